@@ -1,0 +1,123 @@
+"""Named workloads: detector geometry, generator settings and build cuts.
+
+The barrel follows the paper's initial scenario (section 3): concentric
+cylinders, uniform longitudinal field, Gaussian-smeared hits, a particle gun
+flat in pT between 0.5 and 10 GeV.  The workloads:
+
+* ``fit_small``   -- fit, 1 event x 1 000 tracks, 10 layers at r = 4..40 cm;
+* ``fit_scale``   -- fit, 200 events x 20 000 tracks, 17 layers to r = 68 cm;
+* ``build``       -- combinatorial build, 20 000 tracks + 20 % noise per layer,
+  63 phi x 16 z bins, up to 6 candidates per seed, chi2 < 30, one hole;
+* ``batch``       -- 64 events, tracks per event log-uniform in [500, 50 000],
+  noise fraction U[0.05, 0.30] per (event, layer);
+* ``learned``     -- build workload with the learned search window.
+
+Every physical constant is rounded to FP32 before use so that the simulation
+(FP64), the oracle (FP64) and the GPU library (FP32 geometry block) see the
+same numbers.
+"""
+from __future__ import annotations
+
+import dataclasses
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_BASE = 1711065710
+
+
+def f32(v: float) -> float:
+    return float(np.float32(v))
+
+
+@dataclass
+class Geometry:
+    n_layers: int = 10
+    r: list = field(default_factory=lambda: [4.0 * (i + 1) for i in range(10)])
+    z_half: float = 100.0
+    bz: float = f32(3.8)
+    x_over_x0: float = f32(0.02)
+    mass: float = f32(0.13957)
+
+    def __post_init__(self):
+        self.r = [f32(v) for v in self.r]
+        self.z_half = f32(self.z_half)
+        self.bz = f32(self.bz)
+        self.x_over_x0 = f32(self.x_over_x0)
+        self.mass = f32(self.mass)
+
+    def replace(self, **kw) -> "Geometry":
+        return dataclasses.replace(self, **kw)
+
+
+def barrel(n_layers: int, **kw) -> Geometry:
+    return Geometry(n_layers=n_layers, r=[4.0 * (i + 1) for i in range(n_layers)], **kw)
+
+
+@dataclass
+class GenSettings:
+    sig_rphi: float = f32(0.01)
+    sig_z: float = f32(0.1)
+    pt_min: float = 0.5
+    pt_max: float = 10.0
+    eta_max: float = 1.0
+    vtx_sxy: float = 0.01
+    vtx_sz: float = 5.0
+    noise_lo: float = 0.0
+    noise_hi: float = 0.0
+    smear: bool = True
+    seed: int = SEED_BASE + 1
+
+
+@dataclass
+class BuildCuts:
+    chi2_cut: float = 30.0
+    max_holes: int = 1
+    cand_cap: int = 6
+    nsigma: float = 3.0
+    win_sig_rphi: float = f32(0.01)
+    win_sig_z: float = f32(0.1)
+    first_layer: int = 3
+    n_phi_bins: int = 63
+    n_z_bins: int = 16
+
+
+@dataclass
+class Workload:
+    name: str
+    geometry: Geometry
+    gen: GenSettings
+    n_events: int
+    n_tracks: int
+    cuts: BuildCuts = field(default_factory=BuildCuts)
+    tracks_lo: int = 0
+    tracks_hi: int = 0
+
+
+def fit_small() -> Workload:
+    return Workload("fit_small: 1 event x 1000 tracks, 10 layers r=4..40 cm, Bz=3.8 T",
+                    barrel(10), GenSettings(seed=SEED_BASE + 1), 1, 1000)
+
+
+def fit_scale() -> Workload:
+    return Workload("fit_scale: 200 events x 20000 tracks, 17 layers r=4..68 cm, Bz=3.8 T",
+                    barrel(17), GenSettings(seed=SEED_BASE + 2), 200, 20000)
+
+
+def build() -> Workload:
+    return Workload("build: 1 event x 20000 tracks + 20% noise/layer, 17 layers, 63x16 bins, cap 6, chi2<30, 1 hole",
+                    barrel(17), GenSettings(seed=SEED_BASE + 3, noise_lo=0.2, noise_hi=0.2), 1, 20000)
+
+
+def batch() -> Workload:
+    return Workload("batch: 64 events, tracks log-uniform [500,50000], noise U[0.05,0.30]/layer/event, 17 layers",
+                    barrel(17), GenSettings(seed=SEED_BASE + 4, noise_lo=0.05, noise_hi=0.30), 64, 0,
+                    tracks_lo=500, tracks_hi=50000)
+
+
+def learned() -> Workload:
+    return Workload("learned: build workload, MLP 27-64-64-2 search window",
+                    barrel(17), GenSettings(seed=SEED_BASE + 5, noise_lo=0.2, noise_hi=0.2), 1, 20000)
+
+
+ALL = {"fit_small": fit_small, "fit_scale": fit_scale, "build": build, "batch": batch, "learned": learned}

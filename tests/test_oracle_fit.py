@@ -1,0 +1,218 @@
+"""Oracle pins for the seed and the track fit: zero-noise exactness, covariance
+structure, chi2 = ndof with statistically consistent seeds, and equality with
+a batch Gauss-Newton least-squares fit of the same hits."""
+import dataclasses
+
+import numpy as np
+import pytest
+from scipy.optimize import least_squares
+
+import oracle
+from paper_1711_06571_amd import datagen, presets
+
+from conftest import full_from_upper, upper_from_full
+
+
+def _zero_noise_event(w, n, x0=0.0):
+    gen = dataclasses.replace(w.gen, smear=False)
+    g = w.geometry.replace(x_over_x0=x0)
+    ev = datagen.generate(g, gen, 0, n, truth=True)
+    return g, ev
+
+
+@pytest.mark.parametrize("wl", [presets.fit_small, presets.fit_scale])
+def test_zero_noise_fit_returns_generating_helix(wl):
+    w = wl()
+    g, ev = _zero_noise_event(w, 400)
+    n = ev.n_tracks
+    H = datagen.track_hits(ev, dtype=np.float64)
+    sd = oracle.seed64(g, H, n)
+    assert np.all(sd["status"][:n] == 0)
+    assert np.array_equal(sd["q"][:n], ev.q)
+    # the seed itself is the truth at layer 2
+    tr2 = ev.truth[2]
+    assert np.abs(sd["par64"][:3, :n] - tr2[:3]).max() < 1e-10 * 12
+    o = oracle.fit64(g, 3, H, sd["par64"], sd["cov64"], sd["q"], n)
+    tr = ev.truth[-1]
+    rp = np.linalg.norm(o["par"][:3, :n] - tr[:3], axis=0) / np.linalg.norm(tr[:3], axis=0)
+    rm = np.linalg.norm(o["par"][3:, :n] - tr[3:], axis=0) / np.linalg.norm(tr[3:], axis=0)
+    assert rp.max() < 1e-10 and rm.max() < 1e-10
+    assert o["chi2"][:n].max() < 1e-12
+    assert np.all(o["ndof"][:n] == 2 * (g.n_layers - 3))
+
+
+def test_fit_covariance_structure():
+    w = presets.fit_scale()
+    ev = datagen.generate(w.geometry, w.gen, 1, 1000, truth=True)
+    n = ev.n_tracks
+    H = datagen.track_hits(ev)
+    sd = oracle.seed(w.geometry, H, n)
+    o = oracle.fit(w.geometry, 3, H, sd["par"], sd["cov"], sd["q"], n)
+    ok = o["status"][:n] == 0
+    assert ok.mean() > 0.9
+    P = full_from_upper(o["cov"][:, :n])[ok]
+    X = o["par"][:, :n].T[ok]
+    nvec = np.zeros((P.shape[0], 6))
+    r = np.hypot(X[:, 0], X[:, 1])
+    nvec[:, 0] = X[:, 0] / r
+    nvec[:, 1] = X[:, 1] / r
+    # P has one null vector: the radial direction n at the predicted point of
+    # the last layer.  The update moves the state along the tangent there, so
+    # the updated transverse position projects onto n at exactly r = R.
+    w_, V = np.linalg.eigh(P)
+    assert np.all(np.abs(w_[:, 0]) <= 1e-12 * w_[:, -1])
+    v = V[:, :, 0]
+    assert np.all(np.abs(v[:, 2:]).max(axis=1) < 1e-6)
+    proj = np.abs(v[:, 0] * X[:, 0] + v[:, 1] * X[:, 1]) / np.hypot(v[:, 0], v[:, 1])
+    assert np.all(np.abs(proj - w.geometry.r[-1]) < 1e-6)
+    assert np.all(w_[:, 1] > 0)  # PD on the complement of the null vector
+    assert np.allclose(P, np.transpose(P, (0, 2, 1)))
+
+
+def _consistent_seeds(g, ev, rng, alpha):
+    """Seeds drawn from N(truth at layer 2, alpha * P), with P the three-hit
+    seed covariance: the seed error matches the stated covariance exactly."""
+    n = ev.n_tracks
+    H = datagen.track_hits(ev, dtype=np.float64)
+    sd = oracle.seed64(g, H, n)
+    P = full_from_upper(sd["cov64"][:, :n]) * alpha
+    tr = ev.truth[2]
+    X = np.zeros_like(sd["par64"])
+    for t in range(n):
+        w_, V = np.linalg.eigh(P[t])
+        w_ = np.clip(w_, 0, None)
+        X[:, t] = tr[:, t] + V @ (np.sqrt(w_) * rng.normal(size=6))
+    C = np.zeros_like(sd["cov64"])
+    C[:, :n] = upper_from_full(P)
+    q = np.zeros_like(sd["q"])
+    q[:n] = ev.q  # the seed is drawn around the truth, charge included
+    return H, X, C, q
+
+
+@pytest.mark.parametrize("x0", [0.0, float(np.float32(0.02))])
+def test_chi2_averages_ndof_and_pulls_are_unit(x0, rng):
+    # pT below 2 GeV keeps the three-hit curvature resolution (and so the
+    # drawn seed error) small enough for the linearised filter
+    w = presets.fit_scale()
+    g = w.geometry.replace(x_over_x0=x0)
+    gen = dataclasses.replace(w.gen, pt_max=2.0)
+    ev = datagen.generate(g, gen, 11, 6000, truth=True)
+    n = ev.n_tracks
+    H, X, C, q = _consistent_seeds(g, ev, rng, 0.01)
+    o = oracle.fit64(g, 3, H, X, C, q, n)
+    ok = o["status"][:n] == 0
+    assert ok.mean() > 0.999
+    ndof = 2 * (g.n_layers - 3)
+    c2 = o["chi2"][:n][ok]
+    sig = np.sqrt(2.0 * ndof / ok.sum())
+    assert abs(c2.mean() - ndof) < 3.5 * sig, (c2.mean(), ndof, sig)
+    # pulls at the last layer: tangential position, z, and the momentum
+    tr = ev.truth[-1][:, ok]
+    par = o["par"][:, :n][:, ok]
+    P = full_from_upper(o["cov"][:, :n][:, ok])
+    r = np.hypot(par[0], par[1])
+    t = np.stack([-par[1] / r, par[0] / r])
+    d = par - tr
+    pulls = {
+        "t": (t[0] * d[0] + t[1] * d[1]) /
+             np.sqrt(t[0] ** 2 * P[:, 0, 0] + 2 * t[0] * t[1] * P[:, 0, 1] + t[1] ** 2 * P[:, 1, 1]),
+        "z": d[2] / np.sqrt(P[:, 2, 2]),
+        "px": d[3] / np.sqrt(P[:, 3, 3]),
+        "py": d[4] / np.sqrt(P[:, 4, 4]),
+        "pz": d[5] / np.sqrt(P[:, 5, 5]),
+    }
+    m = ok.sum()
+    for k, v in pulls.items():
+        assert abs(v.mean()) < 4 / np.sqrt(m), (k, v.mean())
+        assert abs(v.std() - 1) < 4 / np.sqrt(2 * m), (k, v.std())
+
+
+def _kf_vs_least_squares(noise_scale):
+    """Largest relative difference, over tracks, between the filter's state at
+    the last layer and the batch least-squares solution propagated there."""
+    w = presets.fit_small()
+    g = w.geometry.replace(x_over_x0=0.0)
+    gen = dataclasses.replace(w.gen, pt_max=3.0, sig_rphi=w.gen.sig_rphi * noise_scale,
+                              sig_z=w.gen.sig_z * noise_scale)
+    ev = datagen.generate(g, gen, 5, 12, truth=True)
+    n = ev.n_tracks
+    H64, Xseed, Cseed, qq = _consistent_seeds(g, ev, np.random.default_rng(7), 0.01)
+    o = oracle.fit64(g, 3, H64, Xseed, Cseed, qq, n)
+    R2 = g.r[2]
+    worst = 0.0
+    worst_c2 = 0.0
+    for t in range(n):
+        assert o["status"][t] == 0
+        q = int(qq[t])
+        Xs = Xseed[:, t]
+        Ps = full_from_upper(Cseed[:, t:t + 1])[0]
+
+        def to_X(u):  # the layer-2 state on its cylinder: u = (phi, z, px, py, pz)
+            return np.array([R2 * np.cos(u[0]), R2 * np.sin(u[0]), u[1], u[2], u[3], u[4]])
+        us = np.array([np.arctan2(Xs[1], Xs[0]), Xs[2], Xs[3], Xs[4], Xs[5]])
+        A = np.zeros((5, 6))
+        A[0, 0] = -Xs[1] / (Xs[0] ** 2 + Xs[1] ** 2)
+        A[0, 1] = Xs[0] / (Xs[0] ** 2 + Xs[1] ** 2)
+        A[1:, 2:] = np.eye(4)
+        Lp = np.linalg.cholesky(np.linalg.inv(A @ Ps @ A.T))
+
+        def model(u):
+            X = to_X(u)
+            res = []
+            for l in range(3, g.n_layers):
+                rc, X, _, _ = oracle.propagate(X, q, g.r[l], g.bz)
+                h = H64[l, :, t]
+                r_ = np.hypot(X[0], X[1])
+                tt = np.array([-X[1] / r_, X[0] / r_, 0.0])
+                V = np.array([[h[3], h[4], h[5]], [h[4], h[6], h[7]], [h[5], h[7], h[8]]])
+                F = np.array([tt, [0, 0, 1.0]])
+                rr = np.array([tt @ (h[:3] - X[:3]), h[2] - X[2]])
+                res.append(np.linalg.cholesky(np.linalg.inv(F @ V @ F.T)).T @ rr)
+            res.append(Lp.T @ (u - us))
+            return np.concatenate(res)
+
+        sol = least_squares(model, us, method="lm", xtol=1e-15, ftol=1e-15, gtol=1e-15, x_scale="jac")
+        X = to_X(sol.x)
+        for l in range(3, g.n_layers):
+            rc, X, _, _ = oracle.propagate(X, q, g.r[l], g.bz)
+        kf = o["par"][:, t]
+        worst = max(worst, np.linalg.norm(X[:3] - kf[:3]) / np.linalg.norm(kf[:3]),
+                    np.linalg.norm(X[3:] - kf[3:]) / np.linalg.norm(kf[3:]))
+        worst_c2 = max(worst_c2, abs(np.sum(sol.fun ** 2) - o["chi2"][t]) / o["chi2"][t])
+    return worst, worst_c2
+
+
+def test_kalman_equals_batch_least_squares():
+    """Without scattering the filter equals the minimiser of the hit
+    residuals plus the seed prior (Gauss-Newton to convergence with
+    finite-difference derivatives of the propagation), up to the second-order
+    effect of linearising each step at the prediction: shrinking every error
+    tenfold must shrink the difference about a hundredfold."""
+    d1, c1 = _kf_vs_least_squares(1.0)
+    d01, c01 = _kf_vs_least_squares(0.1)
+    assert d1 < 2e-3 and c1 < 0.05
+    assert d01 < 3e-2 * d1, (d1, d01)
+    assert c01 < 0.2 * c1, (c1, c01)
+
+
+def test_failed_step_freezes_track():
+    w = presets.fit_small()
+    ev = datagen.generate(w.geometry, w.gen, 0, 64)
+    H = datagen.track_hits(ev)
+    sd = oracle.seed(w.geometry, H, 64)
+    # a track whose momentum is too small to reach r = 16 cm: crossing fails at layer 3
+    sp = sd["par"].copy()
+    sp[3:6, 0] = np.float32([0.01, 0.0, 0.0])
+    sp[0:3, 0] = np.float32([12.0, 0.0, 0.0])
+    # a non-finite hit on layer 5 for track 1
+    H2 = H.copy()
+    H2[5, 0, 1] = np.nan
+    o = oracle.fit(w.geometry, 3, H2, sp, sd["cov"], sd["q"], 64)
+    assert o["status"][0] == oracle.TRK_NO_CROSSING and o["ndof"][0] == 0
+    assert np.allclose(o["par"][:, 0], sp[:, 0].astype(np.float64))
+    assert o["status"][1] == oracle.TRK_NONFINITE and o["ndof"][1] == 4
+    # hole mask skips updates
+    hm = np.zeros(H.shape[2], dtype=np.uint32)
+    hm[2] = (1 << 4) | (1 << 7)
+    o2 = oracle.fit(w.geometry, 3, H, sd["par"], sd["cov"], sd["q"], 64, hole_mask=hm)
+    assert o2["ndof"][2] == 2 * (w.geometry.n_layers - 3 - 2)
