@@ -1,0 +1,217 @@
+/*
+ * libkftrack — Kalman-filter track fitting and combinatorial track building
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Cerati et al., "Parallelized Kalman-Filter-Based
+ * Reconstruction of Particle Tracks on Many-Core Architectures":
+ *   - section 2: seeding, building and fitting.  Seeds are given (seeding is
+ *     outside the method); building projects each candidate outward layer by
+ *     layer, uses the Kalman filter to select compatible hits and branches
+ *     into several candidates per seed; fitting reapplies the filter over the
+ *     fixed hit list without branching.
+ *   - section 2.1 and 4.3: data are matrix-major (structure of arrays), so
+ *     consecutive lanes read consecutive addresses.
+ *   - section 3: ideal barrel of concentric cylinders, uniform field along z.
+ *   - section 3.1: hit selection uses a binned hit structure.
+ *   - section 4.1: Kalman updates on the plane tangent to the hit radius.
+ *   - section 4.3: a fixed number of candidate slots per seed, ranked so the
+ *     best candidates are identified quickly; several events in flight.
+ *
+ * Conventions (all entry points):
+ *   - State X = (x, y, z, px, py, pz) in cm and GeV; charge q = +1 or -1.
+ *   - A symmetric 6x6 covariance is stored as its 21 upper-triangle entries
+ *     in row order (00,01,02,03,04,05,11,12,...,15,22,...,55).
+ *   - A hit is (x, y, z) plus its 3x3 covariance as (xx, xy, xz, yy, yz, zz).
+ *   - Arrays are structure of arrays: component c of item i is at
+ *     [c * ld + i]; ld >= n.  Arrays per layer: [layer][component][ld].
+ *   - Layers are 0-based; layer l is the cylinder of radius geometry.r[l].
+ *   - Every pointer argument is a DEVICE pointer, except the descriptor
+ *     structs (kf_geometry, kf_build_params, kf_hits, kf_build_extra), which
+ *     live in host memory and whose pointer fields are device pointers.
+ *   - `stream` is a hipStream_t passed as void* (NULL: the null stream).
+ *     Every call only enqueues work and returns; outputs are valid once the
+ *     stream is synchronised.  The library allocates no device memory: the
+ *     caller owns every buffer, including workspaces sized with the
+ *     *_workspace_bytes queries.  No caller pointer is kept after return.
+ *   - Return value: a kf_status.  On KF_E_HIP, kf_last_error() gives the
+ *     HIP message (thread-local).  The library never aborts or throws.
+ */
+#ifndef LIBKFTRACK_H
+#define LIBKFTRACK_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* call status */
+#define KF_OK 0
+#define KF_E_INVALID_ARG 1 /* null pointer with n > 0, n < 0, ld < n, bad layer range, bad sizes */
+#define KF_E_WORKSPACE 2   /* workspace missing or smaller than the query returned */
+#define KF_E_HIP 3         /* a HIP launch or runtime error; see kf_last_error */
+#define KF_E_UNSUPPORTED 4 /* a parameter outside what the kernels implement */
+
+/* per-track status bits (outputs); a flagged track keeps its last good state */
+#define KF_TRK_NO_CROSSING 1 /* the helix does not reach the next cylinder */
+#define KF_TRK_OUT_OF_Z 2    /* the crossing lies beyond |z| = z_half */
+#define KF_TRK_NONFINITE 4   /* a non-finite input or intermediate */
+#define KF_TRK_S_NOT_PD 8    /* the 2x2 innovation covariance is not positive definite */
+#define KF_TRK_CAP_TRUNC 16  /* build: children were dropped by the candidate cap */
+
+typedef struct {
+  int32_t n_layers; /* 1..32 */
+  float r[32];      /* layer radii, cm, increasing */
+  float z_half;     /* barrel half length, cm */
+  float bz;         /* field, tesla (non-zero) */
+  float x_over_x0;  /* material per layer at normal incidence (0: no scattering) */
+  float mass;       /* GeV, sets beta in the scattering width */
+} kf_geometry;
+
+const char* kf_status_string(int status);
+/* Copies the last HIP error message of this thread into buf (NUL-terminated,
+ * truncated to n bytes); returns its full length. */
+int kf_last_error(char* buf, size_t n);
+
+/*
+ * kf_seed — starting state from the hits on layers 0, 1, 2 (a convention of
+ * this library; the paper treats seeding as given, section 2).  Circle
+ * through the three transverse points -> pT, charge and direction at hit 0;
+ * tan(lambda) from the z change over the arc; then an FP64 Kalman filter over
+ * the three hits from a broad prior (1 cm tangential, 10 cm in z, |p| per
+ * momentum component).  Output: state and covariance at layer 2, rounded to
+ * FP32.
+ *   hits     [n_layers][9][ld] FP32 (only layers 0..2 are read)
+ *   q_out    [ld] int8, seed_par [6][ld], seed_cov [21][ld], status [ld]
+ */
+int kf_seed(const kf_geometry* g, int32_t n, int32_t ld, const float* hits, int8_t* q_out, float* seed_par,
+            float* seed_cov, int32_t* status, void* stream);
+
+/*
+ * kf_fit — Kalman-filter fit over a fixed hit list (section 2), one lane per
+ * track, FP32.  From the seed, for every layer l in [first_layer, n_layers):
+ * propagate along the helix to r[l] (first crossing), transport the
+ * covariance with the surface-constrained Jacobian, add Highland scattering
+ * noise, then update on the tangent plane with the track's hit on l unless
+ * bit l of hole_mask[i] is set (hole_mask may be NULL).
+ *   hits     [n_layers][9][ld] FP32
+ *   seed_par [6][ld], seed_cov [21][ld], q [ld]
+ *   out_par [6][ld], out_cov [21][ld], out_chi2 [ld] (sum over hits),
+ *   out_ndof [ld] (2 per hit used), out_status [ld]
+ * In-place use (out_par == seed_par, out_cov == seed_cov) is allowed.
+ */
+int kf_fit(const kf_geometry* g, int32_t n, int32_t ld, int32_t first_layer, const float* hits,
+           const uint32_t* hole_mask, const float* seed_par, const float* seed_cov, const int8_t* q,
+           float* out_par, float* out_cov, float* out_chi2, int32_t* out_ndof, int32_t* out_status, void* stream);
+
+/*
+ * Binned hits (section 3.1): per event and layer, n_z x n_phi bins,
+ * bin = iz * n_phi + iphi with phi = atan2(y, x) in [0, 2 pi) computed in
+ * FP64 and rounded to FP32, iphi = min(n_phi-1, floor(phi * n_phi / 2pi)),
+ * iz = clamp(floor((z + z_half) * n_z / (2 z_half)), 0, n_z-1).  Hits are
+ * ordered by (event, layer, bin, phi, original index).
+ */
+typedef struct {
+  int32_t n_events;
+  int32_t n_layers;
+  int32_t n_phi, n_z;
+  int32_t n_hits;         /* total over events */
+  const int32_t* offsets; /* [n_events][n_layers][n_phi*n_z + 1]: first sorted position of each bin; the
+                             last entry closes the layer */
+  const float* x;         /* [n_hits] sorted */
+  const float* y;
+  const float* z;
+  const float* phi;
+  const float* cov;       /* [6][n_hits] sorted */
+  const int32_t* orig;    /* [n_hits] event-local original index of each sorted hit */
+} kf_hits;
+
+/* Workspace bytes for hit_bin. */
+size_t hit_bin_workspace_bytes(int32_t n_events, int32_t n_layers, int32_t n_phi, int32_t n_z, int32_t n_hits);
+
+/*
+ * hit_bin — counting sort of the hits of n_events events into the binned
+ * layout above.  Events are concatenated: event e owns input hits
+ * [event_offsets[e], event_offsets[e+1]) (event_offsets may be NULL when
+ * n_events == 1); a hit's original index is its position minus the event's
+ * first position.
+ *   layer [n_hits] int32 (hits with a layer outside [0, n_layers) are
+ *   rejected with KF_E_INVALID_ARG by a device-side check reported via
+ *   out_bad (int32 count, may be NULL)), xyz [3][n_hits], cov [6][n_hits]
+ *   outputs: offsets [E][L][nb+1], sorted x,y,z,phi [4][n_hits] (x block,
+ *   then y, z, phi), sorted cov [6][n_hits], orig [n_hits]
+ */
+int hit_bin(const kf_geometry* g, int32_t n_events, const int32_t* event_offsets, int32_t n_phi, int32_t n_z,
+            int32_t n_hits, const int32_t* layer, const float* xyz, const float* cov, int32_t* offsets,
+            float* sorted_xyzphi, float* sorted_cov, int32_t* sorted_orig, int32_t* out_bad, void* ws,
+            size_t ws_bytes, void* stream);
+
+typedef struct {
+  float chi2_cut;      /* accept a hit iff chi2 < chi2_cut (2 degrees of freedom) */
+  int32_t max_holes;   /* a hole child is added while holes < max_holes */
+  int32_t cand_cap;    /* candidates kept per seed, 1..8 */
+  float nsigma;        /* plain window: nsigma * sqrt(S) per coordinate */
+  float win_sig_rphi;  /* nominal hit resolution used in the window's S, cm */
+  float win_sig_z;
+  int32_t first_layer; /* first layer searched; seeds sit on first_layer - 1 */
+  int32_t window_mode; /* 0 plain; 1 learned (mlp must point to a network block) */
+  const void* mlp;     /* device pointer to the window network block (kf_mlp_block_bytes) */
+  int32_t lanes_per_block; /* 64, 128, 256 (0: 256) */
+  int32_t persistent_blocks; /* blocks of the persistent grid (0: one per CU per resident slot) */
+} kf_build_params;
+
+/* Optional build inputs and outputs (all fields may be NULL / 0). */
+typedef struct {
+  const int32_t* seed_event;  /* [n_seeds] event of each seed (NULL: all event 0) */
+  const int32_t* seed_order;  /* [n_seeds] order in which seeds are taken (NULL: 0..n-1) */
+  const int32_t* event_n_seeds; /* [n_events] seeds per event, needed for event_done_ticks */
+  int64_t* event_done_ticks;  /* [n_events] wall-clock tick when the event's last seed finished */
+  int64_t* start_tick;        /* [1] earliest wall-clock tick seen by any wave of the launch */
+  /* training-data dump: for every candidate whose hits so far are all true
+     (or holes) and whose seed has a true hit on the layer, the 27 features
+     (predicted state and covariance) and the 2 labels (|arc| and |dz| to the
+     true hit) as 29 floats per row */
+  const int32_t* true_hits;   /* [n_layers][ld] true original hit index per seed and layer */
+  float* dump;                /* [dump_capacity][29] */
+  int32_t* dump_count;        /* [1] rows written (rows beyond capacity are counted, not written) */
+  int32_t dump_capacity;
+} kf_build_extra;
+
+/* Workspace bytes for kf_build. */
+size_t kf_build_workspace_bytes(int32_t n_seeds, int32_t n_events);
+
+/*
+ * kf_build — combinatorial Kalman-filter building (sections 2, 3.1, 4.3),
+ * one lane per candidate slot, eight slots per seed, one persistent launch
+ * over all seeds of all events (an atomic queue hands out groups of seeds).
+ * For each seed, from its state on layer first_layer-1, layer by layer:
+ *   1. predict every candidate (a failed crossing or |z| > z_half stops it);
+ *   2. window: plain = nsigma*sqrt(S) per coordinate with S = H P H^T +
+ *      diag(win_sig_rphi^2, win_sig_z^2) (dphi = w_rphi / r, dz = w_z), or
+ *      the learned widths where they are not below their floors;
+ *   3. every hit of the layer with |wrap(phi_h - phi_p)| <= dphi and
+ *      |z_h - z_p| <= dz is tested; accepted iff its update chi2 < chi2_cut;
+ *   4. children: one updated child per accepted hit plus a hole child
+ *      (predicted state) while holes < max_holes;
+ *   5. the seed's children are ranked (nhits desc, chi2 asc, parent slot asc,
+ *      hit index asc, hole last) and the first cand_cap kept;
+ *   6. a candidate with no child competes for the seed's best-finished
+ *      record (nhits desc, chi2 asc; replaces only when strictly better).
+ * Result per seed: the best of the active candidates (slot order) then the
+ * finished record.  nhits counts hits on the searched layers.
+ *   seed_par [6][ld], seed_cov [21][ld], q [ld]: states on layer first_layer-1
+ *   out_hits [n_layers - first_layer][ld]: event-local original hit index per
+ *     searched layer, -1 for a hole or a layer not reached
+ *   out_par [6][ld], out_cov [21][ld], out_chi2, out_nhits, out_status [ld]
+ * Results do not depend on lanes_per_block, persistent_blocks or the order of
+ * the seeds.
+ */
+int kf_build(const kf_geometry* g, const kf_build_params* bp, const kf_hits* hits, int32_t n_seeds, int32_t ld,
+             const float* seed_par, const float* seed_cov, const int8_t* q, int32_t* out_hits, float* out_par,
+             float* out_cov, float* out_chi2, int32_t* out_nhits, int32_t* out_status,
+             const kf_build_extra* extra, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,292 @@
+// Device-side Kalman-filter arithmetic for barrel tracking on gfx950.
+//
+// Everything here works on one candidate held in registers of one lane:
+// state X[6] = (x, y, z, px, py, pz), covariance P[21] (upper triangle, row
+// order).  The functions are templated on the scalar type: the fit and build
+// kernels use float, the seed kernel double.
+//
+// Formulation choices for FP32 (the FP64 oracle uses textbook closed forms):
+//   - the crossing with the cylinder is solved for tan(alpha/2) of the turning
+//     angle from a quadratic whose coefficients carry no large cancelling
+//     terms (the circle-intersection form cancels |C|^2 - rho^2 ~ 1e6 cm^2 at
+//     10 GeV);
+//   - the transverse displacement is written with sin(alpha)/h and
+//     2 sin^2(alpha/2)/h, so it stays accurate as h -> 0;
+//   - the Jacobian uses only nonzero blocks; the covariance update touches
+//     only the upper triangle.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kfdev {
+
+constexpr int KF_NO_CROSSING = 1;
+constexpr int KF_OUT_OF_Z = 2;
+constexpr int KF_NONFINITE = 4;
+constexpr int KF_S_NOT_PD = 8;
+constexpr int KF_CAP_TRUNC = 16;
+
+// GeV / (T cm): pT = KAPPA * B * rho
+template <typename T> __device__ constexpr T kappa() { return T(0.299792458e-2); }
+
+// index of (i, j), i <= j, in the 21-entry upper triangle
+__host__ __device__ constexpr int ut(int i, int j) {
+  return i <= j ? i * 6 - i * (i - 1) / 2 + (j - i) : j * 6 - j * (j - 1) / 2 + (i - j);
+}
+
+template <typename T> __device__ inline T sq(T v) { return v * v; }
+
+__device__ inline float k_sqrt(float v) { return __builtin_sqrtf(v); }
+__device__ inline double k_sqrt(double v) { return __builtin_sqrt(v); }
+__device__ inline void k_sincos(float a, float* s, float* c) { sincosf(a, s, c); }
+__device__ inline void k_sincos(double a, double* s, double* c) { sincos(a, s, c); }
+__device__ inline float k_atan2(float y, float x) { return atan2f(y, x); }
+__device__ inline double k_atan2(double y, double x) { return atan2(y, x); }
+__device__ inline float k_log(float v) { return __logf(v); }
+__device__ inline double k_log(double v) { return log(v); }
+__device__ inline bool k_finite(float v) { return __builtin_isfinite(v); }
+__device__ inline bool k_finite(double v) { return __builtin_isfinite(v); }
+
+// Helix in B = bz * zhat after a turn alpha = h*s (h = -q*KAPPA*bz/pT,
+// s = transverse path):
+//   pos(s) = pos + t * sin(a)/h + n * (1 - cos(a))/h,   t = p_T/pT, n = zhat x t
+//   p_T(s) = rotation of p_T by a,   z(s) = z + pz * s / pT.
+// Crossing with r = R.  With u = pos.t, v = pos.n, D = R^2 - r0^2, the
+// condition |pos(s)|^2 = R^2 becomes, for tau = tan(alpha/2),
+//   (2b - c) tau^2 + 2 a tau - c = 0,  a = h u, b = 1 + h v, c = h^2 D / 2.
+// The root with the sign of h is the first crossing along the motion; it is
+// taken in the form that avoids cancellation, as an angle via atan2 so that
+// turns beyond pi stay representable.
+template <typename T> struct Step {
+  T s;      // transverse path
+  T alpha;  // turning angle
+  T sa, ca; // sin(alpha), cos(alpha)
+  T A, B;   // sin(alpha)/h, (1 - cos(alpha))/h
+  T h, pt;
+};
+
+template <typename T>
+__device__ inline int propagate(const T X[6], int q, T R, T bz, T Xo[6], Step<T>& st) {
+  const T px = X[3], py = X[4], pz = X[5];
+  const T pt2 = px * px + py * py;
+  const T pt = k_sqrt(pt2);
+  if (!(pt > T(0))) return KF_NO_CROSSING;
+  const T h = -T(q) * kappa<T>() * bz / pt;
+  const T tx = px / pt, ty = py / pt;
+  const T u = X[0] * tx + X[1] * ty;
+  const T v = -X[0] * ty + X[1] * tx;
+  const T r02 = X[0] * X[0] + X[1] * X[1];
+  const T D = R * R - r02;
+  const T a = h * u;
+  const T b = T(1) + h * v;
+  const T c = T(0.5) * h * h * D;
+  const T A2 = T(2) * b - c;
+  const T disc = a * a + c * A2;
+  if (!(disc >= T(0))) return KF_NO_CROSSING;
+  const T sd = k_sqrt(disc);
+  const T sg = h > T(0) ? T(1) : T(-1);
+  T num, den;
+  if (a * sg >= T(0)) {  // root c / (a + sg*sd): both terms of the denominator share a sign
+    num = sg * c;
+    den = sg * a + sd;
+  } else {               // root (sg*sd - a) / (2b - c)
+    num = sg * sd - a;
+    den = A2;
+  }
+  const T half = k_atan2(num, den);
+  const T alpha = T(2) * half;
+  T sh, chh;
+  k_sincos(half, &sh, &chh);
+  const T sa = T(2) * sh * chh;
+  const T omc = T(2) * sh * sh;  // 1 - cos(alpha)
+  const T ca = T(1) - omc;
+  const T s = alpha / h;
+  if (!(s > T(0))) return KF_NO_CROSSING;
+  const T Ah = sa / h, Bh = omc / h;
+  Xo[0] = X[0] + tx * Ah - ty * Bh;
+  Xo[1] = X[1] + ty * Ah + tx * Bh;
+  Xo[2] = X[2] + pz * s / pt;
+  Xo[3] = px * ca - py * sa;
+  Xo[4] = py * ca + px * sa;
+  Xo[5] = pz;
+  st.s = s; st.alpha = alpha; st.sa = sa; st.ca = ca; st.A = Ah; st.B = Bh; st.h = h; st.pt = pt;
+  return 0;
+}
+
+// Covariance transport P <- J P J^T for the map "state -> state at the
+// crossing" (J = Js + w g^T: Js at fixed path, w = dX/ds, g = ds/dX keeps the
+// end point on the cylinder), then + Q (Highland scattering at the new point).
+// Nonzero pattern of J: rows x, y, px, py use columns {x, y, px, py}; row z
+// uses all six; row pz is the identity.
+template <typename T>
+__device__ inline void transport(const T X0[6], const T X1[6], const Step<T>& st, T P[21], T x_over_x0, T mass) {
+  const T px = X0[3], py = X0[4], pz = X0[5];
+  const T pt = st.pt, pt2 = pt * pt, pt3 = pt2 * pt;
+  const T s = st.s;
+  const T px1 = X1[3], py1 = X1[4];
+  const T aox = st.alpha / pt2;  // d(alpha)/d(px) = -aox*px
+  // Js entries (rows x, y, z, px, py at columns px, py, pz)
+  const T j03 = st.A / pt - px1 * px * s / pt3;
+  const T j04 = -st.B / pt - px1 * py * s / pt3;
+  const T j13 = st.B / pt - py1 * px * s / pt3;
+  const T j14 = st.A / pt - py1 * py * s / pt3;
+  const T j23 = -pz * s * px / pt3;
+  const T j24 = -pz * s * py / pt3;
+  const T j25 = s / pt;
+  const T j33 = st.ca + py1 * aox * px;
+  const T j34 = -st.sa + py1 * aox * py;
+  const T j43 = st.sa - px1 * aox * px;
+  const T j44 = st.ca - px1 * aox * py;
+  // surface term
+  const T w0 = px1 / pt, w1 = py1 / pt, w2 = pz / pt, w3 = -st.h * py1, w4 = st.h * px1;
+  const T r = k_sqrt(X1[0] * X1[0] + X1[1] * X1[1]);
+  const T nx = X1[0] / r, ny = X1[1] / r;
+  const T den = nx * w0 + ny * w1;
+  const T g0 = -nx / den, g1 = -ny / den;
+  const T g3 = -(nx * j03 + ny * j13) / den, g4 = -(nx * j04 + ny * j14) / den;
+  // J rows as (c0, c1, c3, c4) for rows 0, 1, 3, 4; row 2 has all six columns
+  const T J0[4] = {T(1) + w0 * g0, w0 * g1, j03 + w0 * g3, j04 + w0 * g4};
+  const T J1[4] = {w1 * g0, T(1) + w1 * g1, j13 + w1 * g3, j14 + w1 * g4};
+  const T J3[4] = {w3 * g0, w3 * g1, j33 + w3 * g3, j34 + w3 * g4};
+  const T J4[4] = {w4 * g0, w4 * g1, j43 + w4 * g3, j44 + w4 * g4};
+  const T J2[6] = {w2 * g0, w2 * g1, T(1), j23 + w2 * g3, j24 + w2 * g4, j25};
+  // full copy of P (symmetric)
+  T F[6][6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) F[i][j] = P[ut(i, j)];
+  // Tm = J P (rows 0..5)
+  constexpr int c4[4] = {0, 1, 3, 4};
+  T Tm[6][6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    T a0 = 0, a1 = 0, a3 = 0, a4 = 0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      a0 += J0[m] * F[c4[m]][k];
+      a1 += J1[m] * F[c4[m]][k];
+      a3 += J3[m] * F[c4[m]][k];
+      a4 += J4[m] * F[c4[m]][k];
+    }
+    Tm[0][k] = a0; Tm[1][k] = a1; Tm[3][k] = a3; Tm[4][k] = a4;
+    T a2 = 0;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) a2 += J2[m] * F[m][k];
+    Tm[2][k] = a2;
+    Tm[5][k] = F[5][k];
+  }
+  // P' = Tm J^T, upper triangle
+  const T* Jr[6] = {J0, J1, J2, J3, J4, nullptr};
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+#pragma unroll
+    for (int j = i; j < 6; ++j) {
+      T acc = 0;
+      if (j == 2) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m) acc += Tm[i][m] * J2[m];
+      } else if (j == 5) {
+        acc = Tm[i][5];
+      } else {
+        const T* Jj = j == 0 ? J0 : j == 1 ? J1 : j == 3 ? J3 : J4;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc += Tm[i][c4[m]] * Jj[m];
+      }
+      P[ut(i, j)] = acc;
+    }
+  }
+  (void)Jr;
+  // Highland multiple scattering at the crossing (momentum block)
+  if (x_over_x0 > T(0)) {
+    const T p2 = X1[3] * X1[3] + X1[4] * X1[4] + X1[5] * X1[5];
+    const T p = k_sqrt(p2);
+    const T cospsi = fabs((X1[0] * X1[3] + X1[1] * X1[4]) / (r * p));
+    const T xe = x_over_x0 / cospsi;
+    const T beta2 = p2 / (p2 + mass * mass);
+    const T beta = k_sqrt(beta2);
+    const T th0 = T(0.0136) / (beta * p) * k_sqrt(xe) * (T(1) + T(0.038) * k_log(xe / beta2));
+    const T t2 = th0 * th0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i; j < 3; ++j) P[ut(3 + i, 3 + j)] += t2 * ((i == j ? p2 : T(0)) - X1[3 + i] * X1[3 + j]);
+  }
+}
+
+// Predict: propagate + transport.  Returns a status bit or 0.
+template <typename T>
+__device__ inline int predict(const T X[6], const T P[21], int q, T R, T bz, T z_half, T x_over_x0, T mass,
+                              T Xo[6], T Po[21]) {
+  Step<T> st;
+  int rc = propagate(X, q, R, bz, Xo, st);
+  if (rc) return rc;
+  if (fabs(Xo[2]) > z_half) return KF_OUT_OF_Z;
+#pragma unroll
+  for (int i = 0; i < 21; ++i) Po[i] = P[i];
+  transport(X, Xo, st, Po, x_over_x0, mass);
+  return 0;
+}
+
+// Measurement frame on the plane tangent to the cylinder at the predicted
+// point (section 4.1): u along t = (-y, x)/r, w along z.
+template <typename T> struct Innov {
+  T r0, r1;          // residual (t.(m - pos), m_z - z)
+  T S00, S01, S11;   // innovation covariance
+  T det;
+  T tx, ty;
+};
+
+template <typename T>
+__device__ inline int innovation(const T X[6], const T P[21], T mx, T my, T mz, const T V[6], Innov<T>& in) {
+  const T r = k_sqrt(X[0] * X[0] + X[1] * X[1]);
+  const T tx = -X[1] / r, ty = X[0] / r;
+  in.tx = tx; in.ty = ty;
+  in.r0 = tx * (mx - X[0]) + ty * (my - X[1]);
+  in.r1 = mz - X[2];
+  const T Vuu = tx * tx * V[0] + T(2) * tx * ty * V[1] + ty * ty * V[3];
+  const T Vuw = tx * V[2] + ty * V[4];
+  const T Vww = V[5];
+  in.S00 = tx * tx * P[ut(0, 0)] + T(2) * tx * ty * P[ut(0, 1)] + ty * ty * P[ut(1, 1)] + Vuu;
+  in.S01 = tx * P[ut(0, 2)] + ty * P[ut(1, 2)] + Vuw;
+  in.S11 = P[ut(2, 2)] + Vww;
+  in.det = in.S00 * in.S11 - in.S01 * in.S01;
+  if (!(in.S00 > T(0)) || !(in.det > T(0))) return KF_S_NOT_PD;
+  return 0;
+}
+
+template <typename T> __device__ inline T chi2_of(const Innov<T>& in) {
+  const T i00 = in.S11 / in.det, i01 = -in.S01 / in.det, i11 = in.S00 / in.det;
+  return in.r0 * (i00 * in.r0 + i01 * in.r1) + in.r1 * (i01 * in.r0 + i11 * in.r1);
+}
+
+// Kalman update: K = P H^T S^-1, X += K r, P -= K (H P) (upper triangle).
+template <typename T> __device__ inline void apply_update(T X[6], T P[21], const Innov<T>& in) {
+  const T i00 = in.S11 / in.det, i01 = -in.S01 / in.det, i11 = in.S00 / in.det;
+  T U[6], W[6];  // columns of P H^T: U = P t, W = P zhat
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    U[i] = in.tx * P[ut(i, 0)] + in.ty * P[ut(i, 1)];
+    W[i] = P[ut(i, 2)];
+  }
+  T K0[6], K1[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    K0[i] = U[i] * i00 + W[i] * i01;
+    K1[i] = U[i] * i01 + W[i] * i11;
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) X[i] += K0[i] * in.r0 + K1[i] * in.r1;
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i; j < 6; ++j) P[ut(i, j)] -= K0[i] * U[j] + K1[i] * W[j];
+}
+
+template <typename T> __device__ inline bool all_finite(const T* a, int n) {
+  bool ok = true;
+  for (int i = 0; i < n; ++i) ok = ok && k_finite(a[i]);
+  return ok;
+}
+
+}  // namespace kfdev

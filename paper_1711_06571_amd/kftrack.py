@@ -1,0 +1,254 @@
+"""Python binding of libkftrack (ctypes).  Argument marshalling only: every
+step runs in the library's HIP kernels.  Tensors are torch CUDA (HIP)
+tensors; calls are enqueued on torch's current stream unless one is given.
+
+The library must be built (see build_lib.py); importing this module on a
+machine without it raises immediately instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkftrack.so")
+
+KF_OK = 0
+KF_E_INVALID_ARG = 1
+KF_E_WORKSPACE = 2
+KF_E_HIP = 3
+KF_E_UNSUPPORTED = 4
+
+TRK_NO_CROSSING = 1
+TRK_OUT_OF_Z = 2
+TRK_NONFINITE = 4
+TRK_S_NOT_PD = 8
+TRK_CAP_TRUNC = 16
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("n_layers", ctypes.c_int32), ("r", ctypes.c_float * 32), ("z_half", ctypes.c_float),
+                ("bz", ctypes.c_float), ("x_over_x0", ctypes.c_float), ("mass", ctypes.c_float)]
+
+
+class Hits(ctypes.Structure):
+    _fields_ = [("n_events", ctypes.c_int32), ("n_layers", ctypes.c_int32), ("n_phi", ctypes.c_int32),
+                ("n_z", ctypes.c_int32), ("n_hits", ctypes.c_int32), ("offsets", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p), ("phi", ctypes.c_void_p),
+                ("cov", ctypes.c_void_p), ("orig", ctypes.c_void_p)]
+
+
+class BuildParams(ctypes.Structure):
+    _fields_ = [("chi2_cut", ctypes.c_float), ("max_holes", ctypes.c_int32), ("cand_cap", ctypes.c_int32),
+                ("nsigma", ctypes.c_float), ("win_sig_rphi", ctypes.c_float), ("win_sig_z", ctypes.c_float),
+                ("first_layer", ctypes.c_int32), ("window_mode", ctypes.c_int32), ("mlp", ctypes.c_void_p),
+                ("lanes_per_block", ctypes.c_int32), ("persistent_blocks", ctypes.c_int32)]
+
+
+class BuildExtra(ctypes.Structure):
+    _fields_ = [("seed_event", ctypes.c_void_p), ("seed_order", ctypes.c_void_p),
+                ("event_n_seeds", ctypes.c_void_p), ("event_done_ticks", ctypes.c_void_p),
+                ("start_tick", ctypes.c_void_p), ("true_hits", ctypes.c_void_p), ("dump", ctypes.c_void_p),
+                ("dump_count", ctypes.c_void_p), ("dump_capacity", ctypes.c_int32)]
+
+
+class KFError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise KFError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(there is no fallback implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        I = ctypes.c_int32
+        L.kf_status_string.restype = ctypes.c_char_p
+        L.kf_status_string.argtypes = [ctypes.c_int]
+        L.kf_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+        L.kf_seed.argtypes = [ctypes.POINTER(Geometry), I, I, P, P, P, P, P, P]
+        L.kf_fit.argtypes = [ctypes.POINTER(Geometry), I, I, I, P, P, P, P, P, P, P, P, P, P, P]
+        if hasattr(L, "hit_bin"):
+            L.hit_bin_workspace_bytes.restype = ctypes.c_size_t
+            L.hit_bin_workspace_bytes.argtypes = [I, I, I, I, I]
+            L.hit_bin.argtypes = [ctypes.POINTER(Geometry), I, P, I, I, I, P, P, P, P, P, P, P, P, P,
+                                  ctypes.c_size_t, P]
+        if hasattr(L, "kf_build"):
+            L.kf_build_workspace_bytes.restype = ctypes.c_size_t
+            L.kf_build_workspace_bytes.argtypes = [I, I]
+            L.kf_build.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(BuildParams), ctypes.POINTER(Hits), I,
+                                   I, P, P, P, P, P, P, P, P, P, ctypes.POINTER(BuildExtra), P, ctypes.c_size_t, P]
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return lib()
+
+
+def _check(rc):
+    if rc != KF_OK:
+        msg = lib().kf_status_string(rc).decode()
+        if rc == KF_E_HIP:
+            buf = ctypes.create_string_buffer(512)
+            lib().kf_last_error(buf, 512)
+            msg += ": " + buf.value.decode()
+        raise KFError(f"libkftrack status {rc}: {msg}")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise KFError("tensors passed to libkftrack must live on the GPU")
+    if not t.is_contiguous():
+        raise KFError("tensors passed to libkftrack must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def geometry(g) -> Geometry:
+    """From a presets.Geometry."""
+    o = Geometry()
+    o.n_layers = g.n_layers
+    for i, v in enumerate(g.r):
+        o.r[i] = v
+    o.z_half, o.bz, o.x_over_x0, o.mass = g.z_half, g.bz, g.x_over_x0, g.mass
+    return o
+
+
+def kf_seed(g, n, hits, stream=None):
+    """hits: [L][9][ld] float32 -> dict(q, par [6][ld], cov [21][ld], status)."""
+    ld = hits.shape[2]
+    dev = hits.device
+    out = dict(q=torch.zeros(ld, dtype=torch.int8, device=dev),
+               par=torch.zeros((6, ld), dtype=torch.float32, device=dev),
+               cov=torch.zeros((21, ld), dtype=torch.float32, device=dev),
+               status=torch.zeros(ld, dtype=torch.int32, device=dev))
+    gg = geometry(g)
+    _check(lib().kf_seed(ctypes.byref(gg), n, ld, _ptr(hits), _ptr(out["q"]), _ptr(out["par"]), _ptr(out["cov"]),
+                         _ptr(out["status"]), _stream(stream)))
+    return out
+
+
+def kf_fit(g, n, first_layer, hits, seed_par, seed_cov, q, hole_mask=None, out=None, stream=None):
+    ld = hits.shape[2]
+    dev = hits.device
+    if out is None:
+        out = dict(par=torch.empty((6, ld), dtype=torch.float32, device=dev),
+                   cov=torch.empty((21, ld), dtype=torch.float32, device=dev),
+                   chi2=torch.empty(ld, dtype=torch.float32, device=dev),
+                   ndof=torch.empty(ld, dtype=torch.int32, device=dev),
+                   status=torch.empty(ld, dtype=torch.int32, device=dev))
+    gg = geometry(g)
+    _check(lib().kf_fit(ctypes.byref(gg), n, ld, first_layer, _ptr(hits), _ptr(hole_mask), _ptr(seed_par),
+                        _ptr(seed_cov), _ptr(q), _ptr(out["par"]), _ptr(out["cov"]), _ptr(out["chi2"]),
+                        _ptr(out["ndof"]), _ptr(out["status"]), _stream(stream)))
+    return out
+
+
+# ----------------------------------------------------------------- binning
+
+class BinnedHits:
+    """Device buffers produced by hit_bin (the kf_hits descriptor)."""
+
+    def __init__(self, n_events, n_layers, n_phi, n_z, n_hits, device):
+        nb = n_phi * n_z
+        self.n_events, self.n_layers, self.n_phi, self.n_z, self.n_hits = n_events, n_layers, n_phi, n_z, n_hits
+        self.offsets = torch.zeros((n_events, n_layers, nb + 1), dtype=torch.int32, device=device)
+        self.xyzphi = torch.zeros((4, max(n_hits, 1)), dtype=torch.float32, device=device)
+        self.cov = torch.zeros((6, max(n_hits, 1)), dtype=torch.float32, device=device)
+        self.orig = torch.zeros(max(n_hits, 1), dtype=torch.int32, device=device)
+        self.bad = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def descriptor(self) -> Hits:
+        h = Hits()
+        h.n_events, h.n_layers, h.n_phi, h.n_z, h.n_hits = (self.n_events, self.n_layers, self.n_phi, self.n_z,
+                                                            self.n_hits)
+        h.offsets = self.offsets.data_ptr()
+        stride = self.xyzphi.shape[1] * 4
+        base = self.xyzphi.data_ptr()
+        h.x, h.y, h.z, h.phi = base, base + stride, base + 2 * stride, base + 3 * stride
+        h.cov = self.cov.data_ptr()
+        h.orig = self.orig.data_ptr()
+        return h
+
+
+def hit_bin_workspace_bytes(n_events, n_layers, n_phi, n_z, n_hits):
+    return int(lib().hit_bin_workspace_bytes(n_events, n_layers, n_phi, n_z, n_hits))
+
+
+def hit_bin(g, n_phi, n_z, layer, xyz, cov, event_offsets=None, out=None, ws=None, stream=None):
+    """layer [n] int32, xyz [3][n], cov [6][n] float32 on the GPU; several
+    events are concatenated and delimited by event_offsets [E+1] int32."""
+    n = layer.shape[0]
+    E = 1 if event_offsets is None else event_offsets.shape[0] - 1
+    dev = layer.device
+    if out is None:
+        out = BinnedHits(E, g.n_layers, n_phi, n_z, n, dev)
+    need = hit_bin_workspace_bytes(E, g.n_layers, n_phi, n_z, n)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    gg = geometry(g)
+    _check(lib().hit_bin(ctypes.byref(gg), E, _ptr(event_offsets), n_phi, n_z, n, _ptr(layer), _ptr(xyz), _ptr(cov),
+                         _ptr(out.offsets), _ptr(out.xyzphi), _ptr(out.cov), _ptr(out.orig), _ptr(out.bad),
+                         _ptr(ws), ctypes.c_size_t(need), _stream(stream)))
+    return out
+
+
+# ------------------------------------------------------------------- build
+
+def build_params(cuts, window_mode=0, mlp_block=None, lanes_per_block=0, persistent_blocks=0, cap=None):
+    bp = BuildParams()
+    bp.chi2_cut = cuts.chi2_cut
+    bp.max_holes = cuts.max_holes
+    bp.cand_cap = cuts.cand_cap if cap is None else cap
+    bp.nsigma = cuts.nsigma
+    bp.win_sig_rphi = cuts.win_sig_rphi
+    bp.win_sig_z = cuts.win_sig_z
+    bp.first_layer = cuts.first_layer
+    bp.window_mode = window_mode
+    bp.mlp = None if mlp_block is None else mlp_block.data_ptr()
+    bp.lanes_per_block = lanes_per_block
+    bp.persistent_blocks = persistent_blocks
+    return bp
+
+
+def kf_build_workspace_bytes(n_seeds, n_events):
+    return int(lib().kf_build_workspace_bytes(n_seeds, n_events))
+
+
+def kf_build(g, bp, binned: BinnedHits, n_seeds, seed_par, seed_cov, q, extra=None, out=None, ws=None,
+             stream=None):
+    ld = seed_par.shape[1]
+    dev = seed_par.device
+    F = bp.first_layer
+    if out is None:
+        out = dict(hits=torch.empty((g.n_layers - F, ld), dtype=torch.int32, device=dev),
+                   par=torch.empty((6, ld), dtype=torch.float32, device=dev),
+                   cov=torch.empty((21, ld), dtype=torch.float32, device=dev),
+                   chi2=torch.empty(ld, dtype=torch.float32, device=dev),
+                   nhits=torch.empty(ld, dtype=torch.int32, device=dev),
+                   status=torch.empty(ld, dtype=torch.int32, device=dev))
+    need = kf_build_workspace_bytes(n_seeds, binned.n_events)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    gg = geometry(g)
+    hd = binned.descriptor()
+    ex = extra if extra is not None else BuildExtra()
+    _check(lib().kf_build(ctypes.byref(gg), ctypes.byref(bp), ctypes.byref(hd), n_seeds, ld, _ptr(seed_par),
+                          _ptr(seed_cov), _ptr(q), _ptr(out["hits"]), _ptr(out["par"]), _ptr(out["cov"]),
+                          _ptr(out["chi2"]), _ptr(out["nhits"]), _ptr(out["status"]), ctypes.byref(ex), _ptr(ws),
+                          ctypes.c_size_t(need), _stream(stream)))
+    return out

@@ -1,0 +1,44 @@
+"""kf_fit at the full fit_scale size (200 events x 20 000 tracks, 17 layers),
+in the launch configuration the benchmark times; parity on tracks sampled
+across all events, which the oracle computes one by one."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_06571_amd import presets, workloads
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from gpu_common import assert_fit_parity, host, to_dev  # noqa: E402
+
+
+def test_fit_scale_sampled_parity():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1711_06571_amd import kftrack
+    w = presets.fit_scale()
+    fb = workloads.fit_batch(w)
+    assert fb.n == 4_000_000
+    Hd = to_dev(fb.hits)
+    sg = kftrack.kf_seed(w.geometry, fb.n, Hd)
+    g = kftrack.kf_fit(w.geometry, fb.n, 3, Hd, sg["par"], sg["cov"], sg["q"])
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(2)
+    idx = np.sort(rng.choice(fb.n, 3000, replace=False))
+    idx = np.concatenate([idx, [0, fb.n - 1]])
+    Hs = np.ascontiguousarray(fb.hits[:, :, idx])
+    m = idx.size
+    Hp = np.zeros((Hs.shape[0], 9, ((m + 63) // 64) * 64), dtype=np.float32)
+    Hp[:, :, :m] = Hs
+    so = oracle.seed(w.geometry, Hp, m)
+    o = oracle.fit(w.geometry, 3, Hp, so["par"], so["cov"], so["q"], m)
+    gs = {k: host(v)[..., idx] for k, v in g.items()}
+    sgs = {k: host(v)[..., idx] for k, v in sg.items()}
+    assert np.array_equal(sgs["q"], so["q"][:m])
+    errs = assert_fit_parity(gs, o, m, "fit_scale")
+    print("fit_scale sampled parity", errs)
+    # every track fitted: the status histogram has no unexpected bits
+    st = host(g["status"])[: fb.n]
+    assert np.all((st & ~0x0F) == 0)
+    assert np.mean(st == 0) > 0.9
