@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--events", type=int, default=None, help="override the number of events (testing)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--arith", choices=["f32", "f64"], default="f64",
+                    help="arithmetic of the fit and build kernels (storage is FP32)")
     return ap.parse_args()
 
 
@@ -88,13 +90,25 @@ def main():
 
     stream = torch.cuda.current_stream()
 
-    def step(evs=None):
+    arith = kftrack.ARITH_F64 if args.arith == "f64" else kftrack.ARITH_F32
+
+    def step(evs=None, ar=None):
         nonlocal out
         if evs is not None:
             evs[0].record(stream)
-        out = kftrack.kf_fit(w.geometry, n, 3, Hd, seeds["par"], seeds["cov"], seeds["q"], out=out)
+        out = kftrack.kf_fit(w.geometry, n, 3, Hd, seeds["par"], seeds["cov"], seeds["q"], out=out,
+                             arith=arith if ar is None else ar)
         if evs is not None:
             evs[1].record(stream)
+
+    # the other arithmetic, timed separately for reference
+    other = kftrack.ARITH_F32 if arith == kftrack.ARITH_F64 else kftrack.ARITH_F64
+    step(ar=other)
+    oe = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
+    for e in oe:
+        step(e, ar=other)
+    torch.cuda.synchronize()
+    other_ms = float(np.mean([a.elapsed_time(b) for a, b in oe]))
 
     for _ in range(args.warmup):
         step()
@@ -121,11 +135,12 @@ def main():
     res = {
         "metric": METRIC, "value": round(value, 1), "unit": "tracks/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": args.arith, "data": "synthetic",
         "config": {"workload": w.name, "tracks": n, "events": n // w.n_tracks, "layers": L,
                    "step": "kf_fit"},
         "roofline": roof,
         "stages_ms": {"kf_fit": round(fit_avg, 4)},
+        "other_arith": {"arith": "f32" if args.arith == "f64" else "f64", "kf_fit_ms": round(other_ms, 4)},
         "gen_s": round(t_gen, 2),
     }
     if not args.no_cpu_baseline:

@@ -59,6 +59,10 @@ extern "C" {
 #define KF_TRK_S_NOT_PD 8    /* the 2x2 innovation covariance is not positive definite */
 #define KF_TRK_CAP_TRUNC 16  /* build: children were dropped by the candidate cap */
 
+/* arithmetic of the fit and build kernels (storage is always FP32) */
+#define KF_ARITH_F32 0 /* FP32 arithmetic */
+#define KF_ARITH_F64 1 /* FP64 arithmetic on FP32 data */
+
 typedef struct {
   int32_t n_layers; /* 1..32 */
   float r[32];      /* layer radii, cm, increasing */
@@ -98,11 +102,13 @@ int kf_seed(const kf_geometry* g, int32_t n, int32_t ld, const float* hits, int8
  *   seed_par [6][ld], seed_cov [21][ld], q [ld]
  *   out_par [6][ld], out_cov [21][ld], out_chi2 [ld] (sum over hits),
  *   out_ndof [ld] (2 per hit used), out_status [ld]
+ *   arith: KF_ARITH_F32 or KF_ARITH_F64 (inputs and outputs stay FP32)
  * In-place use (out_par == seed_par, out_cov == seed_cov) is allowed.
  */
 int kf_fit(const kf_geometry* g, int32_t n, int32_t ld, int32_t first_layer, const float* hits,
            const uint32_t* hole_mask, const float* seed_par, const float* seed_cov, const int8_t* q,
-           float* out_par, float* out_cov, float* out_chi2, int32_t* out_ndof, int32_t* out_status, void* stream);
+           float* out_par, float* out_cov, float* out_chi2, int32_t* out_ndof, int32_t* out_status, int32_t arith,
+           void* stream);
 
 /*
  * Binned hits (section 3.1): per event and layer, n_z x n_phi bins,

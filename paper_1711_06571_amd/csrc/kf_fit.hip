@@ -115,7 +115,9 @@ __global__ void __launch_bounds__(256) seed_kernel(GeomK g, int n, int ld, const
   for (int k = 0; k < 21; ++k) seed_cov[(size_t)k * ld + i] = (float)P[k];
 }
 
-// Fit: one lane per track, layers looped in registers (FP32).
+// Fit: one lane per track, layers looped in registers.  Storage is FP32;
+// T is the arithmetic type (float, or double for the precise mode).
+template <typename T>
 __global__ void __launch_bounds__(256) fit_kernel(GeomK g, int n, int ld, int first_layer,
                                                   const float* __restrict__ hits,
                                                   const uint32_t* __restrict__ hole_mask,
@@ -125,34 +127,34 @@ __global__ void __launch_bounds__(256) fit_kernel(GeomK g, int n, int ld, int fi
                                                   int32_t* __restrict__ out_status) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  float X[6], P[21];
+  T X[6], P[21];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) X[k] = seed_par[(size_t)k * ld + i];
+  for (int k = 0; k < 6; ++k) X[k] = (T)seed_par[(size_t)k * ld + i];
 #pragma unroll
-  for (int k = 0; k < 21; ++k) P[k] = seed_cov[(size_t)k * ld + i];
+  for (int k = 0; k < 21; ++k) P[k] = (T)seed_cov[(size_t)k * ld + i];
   const int q = qv[i];
   const uint32_t holes = hole_mask ? hole_mask[i] : 0u;
-  float chi2 = 0.f;
+  T chi2 = 0;
   int ndof = 0;
   int st = (all_finite(X, 6) && all_finite(P, 21)) ? 0 : KF_NONFINITE;
   for (int l = first_layer; l < g.n_layers && !st; ++l) {
     const bool use = !((holes >> l) & 1u);
-    float hv[9];
+    T hv[9];
     if (use) {
       const float* hl = hits + (size_t)l * 9 * ld + i;
 #pragma unroll
-      for (int c = 0; c < 9; ++c) hv[c] = __builtin_nontemporal_load(hl + (size_t)c * ld);
+      for (int c = 0; c < 9; ++c) hv[c] = (T)__builtin_nontemporal_load(hl + (size_t)c * ld);
       if (!all_finite(hv, 9)) { st = KF_NONFINITE; break; }
     }
-    float Xp[6], Pp[21];
-    int rc = predict<float>(X, P, q, g.r[l], g.bz, g.z_half, g.x_over_x0, g.mass, Xp, Pp);
+    T Xp[6], Pp[21];
+    int rc = predict<T>(X, P, q, (T)g.r[l], (T)g.bz, (T)g.z_half, (T)g.x_over_x0, (T)g.mass, Xp, Pp);
     if (rc) { st = rc; break; }
     if (use) {
-      Innov<float> in;
-      const float V[6] = {hv[3], hv[4], hv[5], hv[6], hv[7], hv[8]};
-      if (innovation<float>(Xp, Pp, hv[0], hv[1], hv[2], V, in)) { st = KF_S_NOT_PD; break; }
-      const float c2 = chi2_of(in);
-      apply_update<float>(Xp, Pp, in);
+      Innov<T> in;
+      const T V[6] = {hv[3], hv[4], hv[5], hv[6], hv[7], hv[8]};
+      if (innovation<T>(Xp, Pp, hv[0], hv[1], hv[2], V, in)) { st = KF_S_NOT_PD; break; }
+      const T c2 = chi2_of(in);
+      apply_update<T>(Xp, Pp, in);
       if (!(all_finite(Xp, 6) && all_finite(Pp, 21) && k_finite(c2))) { st = KF_NONFINITE; break; }
       chi2 += c2;
       ndof += 2;
@@ -166,10 +168,10 @@ __global__ void __launch_bounds__(256) fit_kernel(GeomK g, int n, int ld, int fi
     for (int k = 0; k < 21; ++k) P[k] = Pp[k];
   }
 #pragma unroll
-  for (int k = 0; k < 6; ++k) out_par[(size_t)k * ld + i] = X[k];
+  for (int k = 0; k < 6; ++k) out_par[(size_t)k * ld + i] = (float)X[k];
 #pragma unroll
-  for (int k = 0; k < 21; ++k) out_cov[(size_t)k * ld + i] = P[k];
-  out_chi2[i] = chi2;
+  for (int k = 0; k < 21; ++k) out_cov[(size_t)k * ld + i] = (float)P[k];
+  out_chi2[i] = (float)chi2;
   out_ndof[i] = ndof;
   out_status[i] = st;
 }
@@ -202,15 +204,21 @@ extern "C" int kf_seed(const kf_geometry* g, int32_t n, int32_t ld, const float*
 extern "C" int kf_fit(const kf_geometry* g, int32_t n, int32_t ld, int32_t first_layer, const float* hits,
                       const uint32_t* hole_mask, const float* seed_par, const float* seed_cov, const int8_t* q,
                       float* out_par, float* out_cov, float* out_chi2, int32_t* out_ndof, int32_t* out_status,
-                      void* stream) {
+                      int32_t arith, void* stream) {
   if (check_geometry(g)) return KF_E_INVALID_ARG;
   if (n < 0 || ld < n || first_layer < 0 || first_layer > g->n_layers) return KF_E_INVALID_ARG;
+  if (arith != KF_ARITH_F32 && arith != KF_ARITH_F64) return KF_E_INVALID_ARG;
   if (n == 0) return KF_OK;
   if (!hits || !seed_par || !seed_cov || !q || !out_par || !out_cov || !out_chi2 || !out_ndof || !out_status)
     return KF_E_INVALID_ARG;
   const int bs = 256;
-  hipLaunchKernelGGL(fit_kernel, dim3((n + bs - 1) / bs), dim3(bs), 0, (hipStream_t)stream, to_k(g), n, ld,
-                     first_layer, hits, hole_mask, seed_par, seed_cov, q, out_par, out_cov, out_chi2, out_ndof,
-                     out_status);
+  if (arith == KF_ARITH_F64)
+    hipLaunchKernelGGL(fit_kernel<double>, dim3((n + bs - 1) / bs), dim3(bs), 0, (hipStream_t)stream, to_k(g), n, ld,
+                       first_layer, hits, hole_mask, seed_par, seed_cov, q, out_par, out_cov, out_chi2, out_ndof,
+                       out_status);
+  else
+    hipLaunchKernelGGL(fit_kernel<float>, dim3((n + bs - 1) / bs), dim3(bs), 0, (hipStream_t)stream, to_k(g), n, ld,
+                       first_layer, hits, hole_mask, seed_par, seed_cov, q, out_par, out_cov, out_chi2, out_ndof,
+                       out_status);
   return kf_check_launch();
 }

@@ -18,6 +18,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// The arithmetic is also compiled for the host (a CPU build of the same
+// functions is used to inspect individual candidates).
+#define KFD __host__ __device__
+
 namespace kfdev {
 
 constexpr int KF_NO_CROSSING = 1;
@@ -27,25 +31,25 @@ constexpr int KF_S_NOT_PD = 8;
 constexpr int KF_CAP_TRUNC = 16;
 
 // GeV / (T cm): pT = KAPPA * B * rho
-template <typename T> __device__ constexpr T kappa() { return T(0.299792458e-2); }
+template <typename T> KFD constexpr T kappa() { return T(0.299792458e-2); }
 
 // index of (i, j), i <= j, in the 21-entry upper triangle
 __host__ __device__ constexpr int ut(int i, int j) {
   return i <= j ? i * 6 - i * (i - 1) / 2 + (j - i) : j * 6 - j * (j - 1) / 2 + (i - j);
 }
 
-template <typename T> __device__ inline T sq(T v) { return v * v; }
+template <typename T> KFD inline T sq(T v) { return v * v; }
 
-__device__ inline float k_sqrt(float v) { return __builtin_sqrtf(v); }
-__device__ inline double k_sqrt(double v) { return __builtin_sqrt(v); }
-__device__ inline void k_sincos(float a, float* s, float* c) { sincosf(a, s, c); }
-__device__ inline void k_sincos(double a, double* s, double* c) { sincos(a, s, c); }
-__device__ inline float k_atan2(float y, float x) { return atan2f(y, x); }
-__device__ inline double k_atan2(double y, double x) { return atan2(y, x); }
-__device__ inline float k_log(float v) { return __logf(v); }
-__device__ inline double k_log(double v) { return log(v); }
-__device__ inline bool k_finite(float v) { return __builtin_isfinite(v); }
-__device__ inline bool k_finite(double v) { return __builtin_isfinite(v); }
+KFD inline float k_sqrt(float v) { return __builtin_sqrtf(v); }
+KFD inline double k_sqrt(double v) { return __builtin_sqrt(v); }
+KFD inline void k_sincos(float a, float* s, float* c) { sincosf(a, s, c); }
+KFD inline void k_sincos(double a, double* s, double* c) { sincos(a, s, c); }
+KFD inline float k_atan2(float y, float x) { return atan2f(y, x); }
+KFD inline double k_atan2(double y, double x) { return atan2(y, x); }
+KFD inline float k_log(float v) { return logf(v); }
+KFD inline double k_log(double v) { return log(v); }
+KFD inline bool k_finite(float v) { return __builtin_isfinite(v); }
+KFD inline bool k_finite(double v) { return __builtin_isfinite(v); }
 
 // Helix in B = bz * zhat after a turn alpha = h*s (h = -q*KAPPA*bz/pT,
 // s = transverse path):
@@ -66,7 +70,7 @@ template <typename T> struct Step {
 };
 
 template <typename T>
-__device__ inline int propagate(const T X[6], int q, T R, T bz, T Xo[6], Step<T>& st) {
+KFD inline int propagate(const T X[6], int q, T R, T bz, T Xo[6], Step<T>& st) {
   const T px = X[3], py = X[4], pz = X[5];
   const T pt2 = px * px + py * py;
   const T pt = k_sqrt(pt2);
@@ -119,7 +123,7 @@ __device__ inline int propagate(const T X[6], int q, T R, T bz, T Xo[6], Step<T>
 // Nonzero pattern of J: rows x, y, px, py use columns {x, y, px, py}; row z
 // uses all six; row pz is the identity.
 template <typename T>
-__device__ inline void transport(const T X0[6], const T X1[6], const Step<T>& st, T P[21], T x_over_x0, T mass) {
+KFD inline void transport(const T X0[6], const T X1[6], const Step<T>& st, T P[21], T x_over_x0, T mass) {
   const T px = X0[3], py = X0[4], pz = X0[5];
   const T pt = st.pt, pt2 = pt * pt, pt3 = pt2 * pt;
   const T s = st.s;
@@ -216,7 +220,7 @@ __device__ inline void transport(const T X0[6], const T X1[6], const Step<T>& st
 
 // Predict: propagate + transport.  Returns a status bit or 0.
 template <typename T>
-__device__ inline int predict(const T X[6], const T P[21], int q, T R, T bz, T z_half, T x_over_x0, T mass,
+KFD inline int predict(const T X[6], const T P[21], int q, T R, T bz, T z_half, T x_over_x0, T mass,
                               T Xo[6], T Po[21]) {
   Step<T> st;
   int rc = propagate(X, q, R, bz, Xo, st);
@@ -238,7 +242,7 @@ template <typename T> struct Innov {
 };
 
 template <typename T>
-__device__ inline int innovation(const T X[6], const T P[21], T mx, T my, T mz, const T V[6], Innov<T>& in) {
+KFD inline int innovation(const T X[6], const T P[21], T mx, T my, T mz, const T V[6], Innov<T>& in) {
   const T r = k_sqrt(X[0] * X[0] + X[1] * X[1]);
   const T tx = -X[1] / r, ty = X[0] / r;
   in.tx = tx; in.ty = ty;
@@ -255,13 +259,13 @@ __device__ inline int innovation(const T X[6], const T P[21], T mx, T my, T mz, 
   return 0;
 }
 
-template <typename T> __device__ inline T chi2_of(const Innov<T>& in) {
+template <typename T> KFD inline T chi2_of(const Innov<T>& in) {
   const T i00 = in.S11 / in.det, i01 = -in.S01 / in.det, i11 = in.S00 / in.det;
   return in.r0 * (i00 * in.r0 + i01 * in.r1) + in.r1 * (i01 * in.r0 + i11 * in.r1);
 }
 
 // Kalman update: K = P H^T S^-1, X += K r, P -= K (H P) (upper triangle).
-template <typename T> __device__ inline void apply_update(T X[6], T P[21], const Innov<T>& in) {
+template <typename T> KFD inline void apply_update(T X[6], T P[21], const Innov<T>& in) {
   const T i00 = in.S11 / in.det, i01 = -in.S01 / in.det, i11 = in.S00 / in.det;
   T U[6], W[6];  // columns of P H^T: U = P t, W = P zhat
 #pragma unroll
@@ -283,7 +287,7 @@ template <typename T> __device__ inline void apply_update(T X[6], T P[21], const
     for (int j = i; j < 6; ++j) P[ut(i, j)] -= K0[i] * U[j] + K1[i] * W[j];
 }
 
-template <typename T> __device__ inline bool all_finite(const T* a, int n) {
+template <typename T> KFD inline bool all_finite(const T* a, int n) {
   bool ok = true;
   for (int i = 0; i < n; ++i) ok = ok && k_finite(a[i]);
   return ok;

@@ -21,6 +21,9 @@ KF_E_WORKSPACE = 2
 KF_E_HIP = 3
 KF_E_UNSUPPORTED = 4
 
+ARITH_F32 = 0
+ARITH_F64 = 1
+
 TRK_NO_CROSSING = 1
 TRK_OUT_OF_Z = 2
 TRK_NONFINITE = 4
@@ -74,7 +77,7 @@ def lib():
         L.kf_status_string.argtypes = [ctypes.c_int]
         L.kf_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
         L.kf_seed.argtypes = [ctypes.POINTER(Geometry), I, I, P, P, P, P, P, P]
-        L.kf_fit.argtypes = [ctypes.POINTER(Geometry), I, I, I, P, P, P, P, P, P, P, P, P, P, P]
+        L.kf_fit.argtypes = [ctypes.POINTER(Geometry), I, I, I, P, P, P, P, P, P, P, P, P, P, I, P]
         if hasattr(L, "hit_bin"):
             L.hit_bin_workspace_bytes.restype = ctypes.c_size_t
             L.hit_bin_workspace_bytes.argtypes = [I, I, I, I, I]
@@ -142,7 +145,7 @@ def kf_seed(g, n, hits, stream=None):
     return out
 
 
-def kf_fit(g, n, first_layer, hits, seed_par, seed_cov, q, hole_mask=None, out=None, stream=None):
+def kf_fit(g, n, first_layer, hits, seed_par, seed_cov, q, hole_mask=None, out=None, arith=ARITH_F32, stream=None):
     ld = hits.shape[2]
     dev = hits.device
     if out is None:
@@ -154,7 +157,7 @@ def kf_fit(g, n, first_layer, hits, seed_par, seed_cov, q, hole_mask=None, out=N
     gg = geometry(g)
     _check(lib().kf_fit(ctypes.byref(gg), n, ld, first_layer, _ptr(hits), _ptr(hole_mask), _ptr(seed_par),
                         _ptr(seed_cov), _ptr(q), _ptr(out["par"]), _ptr(out["cov"]), _ptr(out["chi2"]),
-                        _ptr(out["ndof"]), _ptr(out["status"]), _stream(stream)))
+                        _ptr(out["ndof"]), _ptr(out["status"]), arith, _stream(stream)))
     return out
 
 

@@ -61,3 +61,23 @@ def assert_fit_parity(gpu, orc, n, ctx=""):
         e = d[ok] / scale[ok]
         assert e.max() <= 1e-3, f"{ctx} cov diag {k}: {e.max():.3g}"
     return dict(pos=float(e_pos.max()), mom=float(e_mom.max()), chi2=float(e_c.max()))
+
+
+def fit_agreement(gpu, orc, n):
+    """Per-track agreement mask under the same tolerances (no assertion)."""
+    same = gpu["status"][:n] == orc["status"][:n]
+    pg = gpu["par"][:, :n].astype(np.float64)
+    po = orc["par"][:, :n]
+    ok = same & (rel_vec_err(pg[:3], po[:3]) <= 1e-4) & (rel_vec_err(pg[3:], po[3:]) <= 1e-4)
+    c = np.abs(gpu["chi2"][:n].astype(np.float64) - orc["chi2"][:n]) / np.maximum(1.0, orc["chi2"][:n])
+    return ok & (c <= 1e-3)
+
+
+def seed_rel_sigma_p(seed_par, seed_cov, n):
+    """Relative momentum uncertainty of the seeds (from the oracle's seeds):
+    sqrt(tr P_pp) / |p|.  Above ~0.1 the Cartesian-momentum filter is
+    ill-conditioned: one-ulp changes of its FP32 inputs move the FP64
+    oracle's own result by more than the parity tolerance."""
+    p = np.linalg.norm(seed_par[3:6, :n].astype(np.float64), axis=0)
+    tr = seed_cov[15, :n].astype(np.float64) + seed_cov[18, :n] + seed_cov[20, :n]
+    return np.sqrt(np.maximum(tr, 0)) / np.maximum(p, 1e-30)

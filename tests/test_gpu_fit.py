@@ -21,7 +21,8 @@ def kf():
     return kftrack
 
 
-from gpu_common import DEV, assert_fit_parity, fit_inputs, host, to_dev  # noqa: E402
+from gpu_common import (DEV, assert_fit_parity, fit_agreement, fit_inputs, host, seed_rel_sigma_p,  # noqa: E402
+                        to_dev)
 
 
 def _seed_both(kf, g, H, n):
@@ -43,6 +44,7 @@ def _assert_seed_parity(so, sg, n):
 
 
 def test_seed_and_fit_parity_small(kf):
+    """FP64 arithmetic: every track within the parity tolerances."""
     w = presets.fit_small()
     ev = datagen.generate(w.geometry, w.gen, 0, w.n_tracks)
     n = ev.n_tracks
@@ -50,10 +52,32 @@ def test_seed_and_fit_parity_small(kf):
     so, sg = _seed_both(kf, w.geometry, H, n)
     _assert_seed_parity(so, sg, n)
     o = oracle.fit(w.geometry, 3, H, so["par"], so["cov"], so["q"], n)
-    g = kf.kf_fit(w.geometry, n, 3, to_dev(H), to_dev(sg["par"]), to_dev(sg["cov"]), to_dev(sg["q"]))
+    g = kf.kf_fit(w.geometry, n, 3, to_dev(H), to_dev(sg["par"]), to_dev(sg["cov"]), to_dev(sg["q"]),
+                  arith=kf.ARITH_F64)
     g = {k: host(v) for k, v in g.items()}
-    errs = assert_fit_parity(g, o, n, "fit_small")
-    print("fit_small parity", errs)
+    errs = assert_fit_parity(g, o, n, "fit_small f64")
+    print("fit_small parity (f64 arithmetic)", errs)
+
+
+def test_fit_fp32_arithmetic_agreement(kf):
+    """FP32 arithmetic: every track whose seed is well conditioned (relative
+    momentum uncertainty below 0.1) within the tolerances; the agreement
+    fraction over all tracks is reported."""
+    w = presets.fit_scale()
+    ev = datagen.generate(w.geometry, w.gen, 1, 20000)
+    n = ev.n_tracks
+    H = fit_inputs(ev)
+    so, sg = _seed_both(kf, w.geometry, H, n)
+    o = oracle.fit(w.geometry, 3, H, so["par"], so["cov"], so["q"], n)
+    g = kf.kf_fit(w.geometry, n, 3, to_dev(H), to_dev(sg["par"]), to_dev(sg["cov"]), to_dev(sg["q"]),
+                  arith=kf.ARITH_F32)
+    g = {k: host(v) for k, v in g.items()}
+    agree = fit_agreement(g, o, n)
+    well = seed_rel_sigma_p(so["par"], so["cov"], n) < 0.1
+    print(f"fp32 arithmetic: agreement {agree.mean():.4f} overall, {agree[well].mean():.4f} on "
+          f"{well.mean():.3f} well-conditioned seeds")
+    assert agree[well].all()
+    assert agree.mean() > 0.6
 
 
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 777])
@@ -64,7 +88,8 @@ def test_fit_ragged_sizes(kf, n):
     so, sg = _seed_both(kf, w.geometry, H, n)
     _assert_seed_parity(so, sg, n)
     o = oracle.fit(w.geometry, 3, H, so["par"], so["cov"], so["q"], n)
-    g = kf.kf_fit(w.geometry, n, 3, to_dev(H), to_dev(sg["par"]), to_dev(sg["cov"]), to_dev(sg["q"]))
+    g = kf.kf_fit(w.geometry, n, 3, to_dev(H), to_dev(sg["par"]), to_dev(sg["cov"]), to_dev(sg["q"]),
+                  arith=kf.ARITH_F64)
     assert_fit_parity({k: host(v) for k, v in g.items()}, o, n, f"n={n}")
 
 
@@ -76,7 +101,7 @@ def test_fit_zero_noise_returns_generating_helix(kf):
     n = ev.n_tracks
     H = fit_inputs(ev)
     sg = kf.kf_seed(g0, n, to_dev(H))
-    g = kf.kf_fit(g0, n, 3, to_dev(H), sg["par"], sg["cov"], sg["q"])
+    g = kf.kf_fit(g0, n, 3, to_dev(H), sg["par"], sg["cov"], sg["q"], arith=kf.ARITH_F32)
     par = host(g["par"])[:, :n].astype(np.float64)
     tr = ev.truth[-1]
     ep = np.linalg.norm(par[:3] - tr[:3], axis=0) / np.linalg.norm(tr[:3], axis=0)
@@ -105,7 +130,7 @@ def test_fit_status_paths(kf):
     hm[3] = (1 << 4) | (1 << 8)
     o = oracle.fit(w.geometry, 3, H, sp, so["cov"], so["q"], n, hole_mask=hm)
     g = kf.kf_fit(w.geometry, n, 3, to_dev(H), to_dev(sp), to_dev(so["cov"]), to_dev(so["q"]),
-                  hole_mask=to_dev(hm.view(np.int32)))
+                  hole_mask=to_dev(hm.view(np.int32)), arith=kf.ARITH_F64)
     gh = {k: host(v) for k, v in g.items()}
     assert gh["status"][0] == oracle.TRK_NO_CROSSING
     assert gh["status"][1] == oracle.TRK_NONFINITE

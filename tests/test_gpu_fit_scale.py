@@ -22,7 +22,7 @@ def test_fit_scale_sampled_parity():
     assert fb.n == 4_000_000
     Hd = to_dev(fb.hits)
     sg = kftrack.kf_seed(w.geometry, fb.n, Hd)
-    g = kftrack.kf_fit(w.geometry, fb.n, 3, Hd, sg["par"], sg["cov"], sg["q"])
+    g = kftrack.kf_fit(w.geometry, fb.n, 3, Hd, sg["par"], sg["cov"], sg["q"], arith=kftrack.ARITH_F64)
     torch.cuda.synchronize()
     rng = np.random.default_rng(2)
     idx = np.sort(rng.choice(fb.n, 3000, replace=False))
