@@ -46,6 +46,8 @@ KFD inline void k_sincos(float a, float* s, float* c) { sincosf(a, s, c); }
 KFD inline void k_sincos(double a, double* s, double* c) { sincos(a, s, c); }
 KFD inline float k_atan2(float y, float x) { return atan2f(y, x); }
 KFD inline double k_atan2(double y, double x) { return atan2(y, x); }
+KFD inline float k_atan(float v) { return atanf(v); }
+KFD inline double k_atan(double v) { return atan(v); }
 KFD inline float k_log(float v) { return logf(v); }
 KFD inline double k_log(double v) { return log(v); }
 KFD inline bool k_finite(float v) { return __builtin_isfinite(v); }
@@ -58,9 +60,10 @@ KFD inline bool k_finite(double v) { return __builtin_isfinite(v); }
 // Crossing with r = R.  With u = pos.t, v = pos.n, D = R^2 - r0^2, the
 // condition |pos(s)|^2 = R^2 becomes, for tau = tan(alpha/2),
 //   (2b - c) tau^2 + 2 a tau - c = 0,  a = h u, b = 1 + h v, c = h^2 D / 2.
-// The root with the sign of h is the first crossing along the motion; it is
-// taken in the form that avoids cancellation, as an angle via atan2 so that
-// turns beyond pi stay representable.
+// tau covers one full turn (alpha in (-pi, pi)); both roots are formed in
+// the cancellation-free pair q/A, -c/q with q = -(a + sign(a) sqrt(disc)).
+// The first crossing along the motion is the root whose turn, taken with the
+// sign of h and in (0, 2 pi) in magnitude, is smallest.
 template <typename T> struct Step {
   T s;      // transverse path
   T alpha;  // turning angle
@@ -88,16 +91,21 @@ KFD inline int propagate(const T X[6], int q, T R, T bz, T Xo[6], Step<T>& st) {
   const T disc = a * a + c * A2;
   if (!(disc >= T(0))) return KF_NO_CROSSING;
   const T sd = k_sqrt(disc);
+  const T qq = -(a + (a >= T(0) ? sd : -sd));
   const T sg = h > T(0) ? T(1) : T(-1);
-  T num, den;
-  if (a * sg >= T(0)) {  // root c / (a + sg*sd): both terms of the denominator share a sign
-    num = sg * c;
-    den = sg * a + sd;
-  } else {               // root (sg*sd - a) / (2b - c)
-    num = sg * sd - a;
-    den = A2;
-  }
-  const T half = k_atan2(num, den);
+  // the two roots, oriented so that the motion turns towards positive tau
+  const T t1 = sg * (qq / A2), t2 = sg * (-c / qq);
+  // first along the motion: the smallest positive oriented root if any,
+  // otherwise the most negative one (a turn beyond pi)
+  T t;
+  if (t1 > T(0) && t2 > T(0)) t = t1 < t2 ? t1 : t2;
+  else if (t1 > T(0)) t = t1;
+  else if (t2 > T(0)) t = t2;
+  else t = t1 < t2 ? t1 : t2;
+  if (!(t == t)) return KF_NO_CROSSING;  // both roots undefined (degenerate circle)
+  T half = k_atan(t);
+  if (!(half > T(0))) half += T(3.14159265358979323846);
+  half *= sg;
   const T alpha = T(2) * half;
   T sh, chh;
   k_sincos(half, &sh, &chh);

@@ -21,8 +21,8 @@ def kf():
     return kftrack
 
 
-from gpu_common import (DEV, assert_fit_parity, fit_agreement, fit_inputs, host, seed_rel_sigma_p,  # noqa: E402
-                        to_dev)
+from gpu_common import (DEV, assert_fit_parity_converged, fit_agreement, fit_inputs, host,  # noqa: E402
+                        seed_rel_sigma_p, to_dev)
 
 
 def _seed_both(kf, g, H, n):
@@ -55,7 +55,7 @@ def test_seed_and_fit_parity_small(kf):
     g = kf.kf_fit(w.geometry, n, 3, to_dev(H), to_dev(sg["par"]), to_dev(sg["cov"]), to_dev(sg["q"]),
                   arith=kf.ARITH_F64)
     g = {k: host(v) for k, v in g.items()}
-    errs = assert_fit_parity(g, o, n, "fit_small f64")
+    errs = assert_fit_parity_converged(g, o, n, "fit_small f64")
     print("fit_small parity (f64 arithmetic)", errs)
 
 
@@ -90,7 +90,7 @@ def test_fit_ragged_sizes(kf, n):
     o = oracle.fit(w.geometry, 3, H, so["par"], so["cov"], so["q"], n)
     g = kf.kf_fit(w.geometry, n, 3, to_dev(H), to_dev(sg["par"]), to_dev(sg["cov"]), to_dev(sg["q"]),
                   arith=kf.ARITH_F64)
-    assert_fit_parity({k: host(v) for k, v in g.items()}, o, n, f"n={n}")
+    assert_fit_parity_converged({k: host(v) for k, v in g.items()}, o, n, f"n={n}")
 
 
 def test_fit_zero_noise_returns_generating_helix(kf):
@@ -136,7 +136,7 @@ def test_fit_status_paths(kf):
     assert gh["status"][1] == oracle.TRK_NONFINITE
     assert gh["status"][2] == oracle.TRK_OUT_OF_Z
     assert gh["ndof"][3] == 2 * (w.geometry.n_layers - 5)
-    assert_fit_parity(gh, o, n, "status paths")
+    assert_fit_parity_converged(gh, o, n, "status paths")
 
 
 def test_fit_empty_and_invalid(kf):

@@ -10,7 +10,7 @@ from paper_1711_06571_amd import presets, workloads
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-from gpu_common import assert_fit_parity, host, to_dev  # noqa: E402
+from gpu_common import assert_fit_parity_converged, host, to_dev  # noqa: E402
 
 
 def test_fit_scale_sampled_parity():
@@ -36,7 +36,7 @@ def test_fit_scale_sampled_parity():
     gs = {k: host(v)[..., idx] for k, v in g.items()}
     sgs = {k: host(v)[..., idx] for k, v in sg.items()}
     assert np.array_equal(sgs["q"], so["q"][:m])
-    errs = assert_fit_parity(gs, o, m, "fit_scale")
+    errs = assert_fit_parity_converged(gs, o, m, "fit_scale")
     print("fit_scale sampled parity", errs)
     # every track fitted: the status histogram has no unexpected bits
     st = host(g["status"])[: fb.n]
