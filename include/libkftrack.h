@@ -155,7 +155,7 @@ int hit_bin(const kf_geometry* g, int32_t n_events, const int32_t* event_offsets
 typedef struct {
   float chi2_cut;      /* accept a hit iff chi2 < chi2_cut (2 degrees of freedom) */
   int32_t max_holes;   /* a hole child is added while holes < max_holes */
-  int32_t cand_cap;    /* candidates kept per seed, 1..8 */
+  int32_t cand_cap;    /* candidates kept per seed, 1..8 (8 slots per seed; 4 when cap <= 4) */
   float nsigma;        /* plain window: nsigma * sqrt(S) per coordinate */
   float win_sig_rphi;  /* nominal hit resolution used in the window's S, cm */
   float win_sig_z;
@@ -163,7 +163,8 @@ typedef struct {
   int32_t window_mode; /* 0 plain; 1 learned (mlp must point to a network block) */
   const void* mlp;     /* device pointer to the window network block (kf_mlp_block_bytes) */
   int32_t lanes_per_block; /* 64, 128, 256 (0: 256) */
-  int32_t persistent_blocks; /* blocks of the persistent grid (0: one per CU per resident slot) */
+  int32_t persistent_blocks; /* blocks of the persistent grid (0: CUs x resident blocks per CU) */
+  int32_t arith;       /* KF_ARITH_F32 or KF_ARITH_F64 */
 } kf_build_params;
 
 /* Optional build inputs and outputs (all fields may be NULL / 0). */
@@ -178,7 +179,8 @@ typedef struct {
      (predicted state and covariance) and the 2 labels (|arc| and |dz| to the
      true hit) as 29 floats per row */
   const int32_t* true_hits;   /* [n_layers][ld] true original hit index per seed and layer */
-  float* dump;                /* [dump_capacity][29] */
+  const float* true_xyz;      /* [n_layers][3][ld] position of that true hit */
+  float* dump;                /* [dump_capacity][32] */
   int32_t* dump_count;        /* [1] rows written (rows beyond capacity are counted, not written) */
   int32_t dump_capacity;
 } kf_build_extra;

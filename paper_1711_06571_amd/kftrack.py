@@ -47,13 +47,15 @@ class BuildParams(ctypes.Structure):
     _fields_ = [("chi2_cut", ctypes.c_float), ("max_holes", ctypes.c_int32), ("cand_cap", ctypes.c_int32),
                 ("nsigma", ctypes.c_float), ("win_sig_rphi", ctypes.c_float), ("win_sig_z", ctypes.c_float),
                 ("first_layer", ctypes.c_int32), ("window_mode", ctypes.c_int32), ("mlp", ctypes.c_void_p),
-                ("lanes_per_block", ctypes.c_int32), ("persistent_blocks", ctypes.c_int32)]
+                ("lanes_per_block", ctypes.c_int32), ("persistent_blocks", ctypes.c_int32),
+                ("arith", ctypes.c_int32)]
 
 
 class BuildExtra(ctypes.Structure):
     _fields_ = [("seed_event", ctypes.c_void_p), ("seed_order", ctypes.c_void_p),
                 ("event_n_seeds", ctypes.c_void_p), ("event_done_ticks", ctypes.c_void_p),
-                ("start_tick", ctypes.c_void_p), ("true_hits", ctypes.c_void_p), ("dump", ctypes.c_void_p),
+                ("start_tick", ctypes.c_void_p), ("true_hits", ctypes.c_void_p), ("true_xyz", ctypes.c_void_p),
+                ("dump", ctypes.c_void_p),
                 ("dump_count", ctypes.c_void_p), ("dump_capacity", ctypes.c_int32)]
 
 
@@ -212,7 +214,8 @@ def hit_bin(g, n_phi, n_z, layer, xyz, cov, event_offsets=None, out=None, ws=Non
 
 # ------------------------------------------------------------------- build
 
-def build_params(cuts, window_mode=0, mlp_block=None, lanes_per_block=0, persistent_blocks=0, cap=None):
+def build_params(cuts, window_mode=0, mlp_block=None, lanes_per_block=0, persistent_blocks=0, cap=None,
+                 arith=ARITH_F32):
     bp = BuildParams()
     bp.chi2_cut = cuts.chi2_cut
     bp.max_holes = cuts.max_holes
@@ -225,6 +228,7 @@ def build_params(cuts, window_mode=0, mlp_block=None, lanes_per_block=0, persist
     bp.mlp = None if mlp_block is None else mlp_block.data_ptr()
     bp.lanes_per_block = lanes_per_block
     bp.persistent_blocks = persistent_blocks
+    bp.arith = arith
     return bp
 
 
