@@ -263,9 +263,11 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
     grp = __shfl(grp, 0, 64);
     if (grp >= A.n_groups) break;
     const int gi = grp * SEEDS + sidx;
-    const bool seed_ok = gi < A.n_seeds;
-    const int seed = seed_ok ? (A.seed_order ? A.seed_order[gi] : gi) : 0;
-    const int ev = (seed_ok && A.seed_event) ? A.seed_event[seed] : 0;
+    int seed = gi < A.n_seeds ? (A.seed_order ? A.seed_order[gi] : gi) : -1;
+    int ev = (seed >= 0 && seed < A.n_seeds && A.seed_event) ? A.seed_event[seed] : 0;
+    // caller-supplied indices outside their ranges: the seed is skipped
+    const bool seed_ok = seed >= 0 && seed < A.n_seeds && ev >= 0 && ev < A.n_events;
+    if (!seed_ok) { seed = 0; ev = 0; }
     const int q = seed_ok ? A.q[seed] : 1;
     // candidate state
     T X[6], P[21];

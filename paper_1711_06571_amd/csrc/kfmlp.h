@@ -54,7 +54,7 @@ __device__ inline float softplus(float o) { return o > 30.f ? o : log1pf(__expf(
 // One lane evaluates the network for its own candidate (FP32 accumulation in
 // index order).  Returns kappa * widths.
 template <typename T>
-__device__ inline void mlp_window_lane(const float* __restrict__ blk, const T Xp[6], const T Pp[21], float w[2]) {
+__device__ __noinline__ void mlp_window_lane(const float* __restrict__ blk, const T Xp[6], const T Pp[21], float w[2]) {
   const uint16_t* W = (const uint16_t*)(blk + KFMLP_HEADER_FLOATS);
   float xh[27];
   for (int k = 0; k < 6; ++k) xh[k] = bf16_round(((float)Xp[k] - blk[KFMLP_OFF_MU + k]) * blk[KFMLP_OFF_ISD + k]);
