@@ -1,15 +1,15 @@
 """Throughput benchmark: Kalman-filter track building and fitting on one GPU.
 
 Workload (fit_scale): 200 events x 20 000 tracks, 17 barrel layers at
-r = 4..68 cm, Bz = 3.8 T, seeded synthetic events (inputs resident in HBM
-before timing).  One step = one pass of the hot path over the whole batch:
+r = 4..68 cm, Bz = 3.8 T, seeded synthetic events; inputs resident in HBM
+before timing.  One step = one pass of the hot path over the whole batch:
   hit_bin (all 200 events) -> kf_build (all 4 M seeds, one persistent launch)
-  -> kf_fit (all 4 M tracks over their hit lists).
+  -> kf_gather_hits -> kf_fit (all 4 M built tracks).
 value = tracks per second through the step (each track built and fitted).
 
-Prints one JSON line.  Per-kernel durations are measured with HIP events on
-the stream the kernels run on.  The CPU baseline is the FP64 oracle timed on
-a bounded sample of the same workload on this host.
+Prints one JSON line.  Per-kernel durations come from HIP events recorded on
+the stream the kernels run on.  The CPU baseline is the FP64 oracle (brute-
+force build, then fit) timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -26,47 +26,76 @@ sys.path.insert(0, ROOT)
 
 METRIC = "KF tracks/s (fit & build) on 1 GPU; learned-window vs plain at equal efficiency"
 
-# Algorithmic work per candidate-layer of the fit formulation (see kfdev.h):
-# propagate 60, transport + scattering 550, innovation 37, chi2 10, update 165
-FIT_FLOP_PER_TRACK_LAYER = 822
-# bytes per fitted track: 14 hit rows of 9 floats, seed (27 floats + q),
-# outputs (27 floats + chi2 + ndof + status)
-FIT_BYTES_PER_TRACK_14 = 14 * 36 + (27 * 4 + 1) + (27 * 4 + 12)
-PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (published)
+# Algorithmic FP work (FMA = 2 flops) of the formulation in kfdev.h
+FLOP_PREDICT = 610      # helix crossing 60 + surface Jacobian, transport and scattering noise 550
+FLOP_WINDOW = 25        # window half-widths from the predicted covariance
+FLOP_WINDOW_TEST = 8    # exact phi/z test of one scanned hit
+FLOP_CHI2 = 47          # innovation + chi2 of one in-window hit
+FLOP_UPDATE = 202       # innovation + Kalman gain and state/covariance update
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X vector peaks (published)
 PEAK_HBM_GBS = 8000.0
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--events", type=int, default=None, help="override the number of events (testing)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--arith", choices=["f32", "f64"], default="f64",
                     help="arithmetic of the fit and build kernels (storage is FP32)")
+    ap.add_argument("--no-other-arith", action="store_true")
     return ap.parse_args()
 
 
-def cpu_baseline(w, fb, seconds):
-    """FP64 oracle on a bounded sample of the same tracks (single thread)."""
+def cpu_baseline(w, eb, seconds):
+    """FP64 oracle: brute-force build then fit, seed by seed, on event 0."""
     import oracle
     L = w.geometry.n_layers
-    chunk = 2000
+    F = w.cuts.first_layer
+    h0, h1 = int(eb.hit_offsets[0]), int(eb.hit_offsets[1])
+    n0 = int(eb.seed_offsets[1])
+    xyz = np.ascontiguousarray(eb.xyz[:, h0:h1])
+    cov = np.ascontiguousarray(eb.cov[:, h0:h1])
+    layer = np.ascontiguousarray(eb.layer[h0:h1])
+    ld = ((n0 + 63) // 64) * 64
+    Hs = np.zeros((3, 9, ld), dtype=np.float32)
+    Hs[:, :, :n0] = eb.seed_hits[:, :, :n0]
+    so = oracle.seed(w.geometry, Hs, n0)
     done = 0
+    chunk = 8
     t0 = time.perf_counter()
     k = 0
     while time.perf_counter() - t0 < seconds:
-        lo = (k * 7919 * chunk) % max(fb.n - chunk, 1)
-        H = np.ascontiguousarray(fb.hits[:, :, lo:lo + chunk])
-        so = oracle.seed(w.geometry, H, chunk)
-        oracle.fit(w.geometry, 3, H, so["par"], so["cov"], so["q"], chunk)
-        done += chunk
+        lst = (np.arange(chunk) * 2503 + k * chunk * 7919) % n0
+        ob = oracle.build(w.geometry, w.cuts, layer, xyz, cov, so["par"], so["cov"], so["q"], n0, seed_list=lst)
+        # fit the built tracks from their seeds
+        m = lst.size
+        Hf = np.zeros((L, 9, 64), dtype=np.float32)
+        hm = np.zeros(64, dtype=np.uint32)
+        for j in range(m):
+            for l in range(F, L):
+                h = ob["hits"][l - F, j]
+                if h < 0:
+                    hm[j] |= 1 << l
+                else:
+                    Hf[l, 0:3, j] = xyz[:, h]
+                    Hf[l, 3:9, j] = cov[:, h]
+        sp = np.zeros((6, 64), np.float32)
+        sc = np.zeros((21, 64), np.float32)
+        q = np.ones(64, np.int8)
+        sp[:, :m] = so["par"][:, lst]
+        sc[:, :m] = so["cov"][:, lst]
+        q[:m] = so["q"][lst]
+        oracle.fit(w.geometry, F, Hf, sp, sc, q, m, hole_mask=hm)
+        done += m
         k += 1
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "tracks/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} fit_scale tracks (seed + fit, {L} layers), FP64 oracle, single thread, {dt:.1f} s"}
+            "sample": f"{done} seeds of fit_scale event 0 (20000 tracks): brute-force build over {L} layers "
+                      f"then fit, FP64 oracle, single thread, {dt:.1f} s"}
 
 
 def main():
@@ -75,76 +104,134 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
-    from paper_1711_06571_amd import kftrack, presets, workloads
+    from paper_1711_06571_amd import kftrack as kf
+    from paper_1711_06571_amd import presets, workloads
 
     dev = "cuda:0"
     w = presets.fit_scale()
+    g = w.geometry
+    cuts = w.cuts
+    E = w.n_events if args.events is None else args.events
     t_gen = time.perf_counter()
-    fb = workloads.fit_batch(w, n_events=args.events)
+    eb = workloads.event_batch(w, range(E), seed_layers=3)
     t_gen = time.perf_counter() - t_gen
-    n = fb.n
-    Hd = torch.from_numpy(fb.hits).to(dev)
-    seeds = kftrack.kf_seed(w.geometry, n, Hd)
-    out = None
+    n = eb.n_seeds
+    L = g.n_layers
+    F = cuts.first_layer
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    layer, xyz, cov = T(eb.layer), T(eb.xyz), T(eb.cov)
+    hoff, sev = T(eb.hit_offsets), T(eb.seed_event)
+    seeds = kf.kf_seed(g, n, T(eb.seed_hits))
+    nb = cuts.n_phi_bins * cuts.n_z_bins
+    binned = kf.BinnedHits(E, L, cuts.n_phi_bins, cuts.n_z_bins, xyz.shape[1], dev)
+    ws_bin = torch.empty(kf.hit_bin_workspace_bytes(E, L, cuts.n_phi_bins, cuts.n_z_bins, xyz.shape[1]),
+                         dtype=torch.uint8, device=dev)
+    ws_build = torch.empty(kf.kf_build_workspace_bytes(n, E), dtype=torch.uint8, device=dev)
+    ld = seeds["par"].shape[1]
+    bout = dict(hits=torch.empty((L - F, ld), dtype=torch.int32, device=dev),
+                par=torch.empty((6, ld), dtype=torch.float32, device=dev),
+                cov=torch.empty((21, ld), dtype=torch.float32, device=dev),
+                chi2=torch.empty(ld, dtype=torch.float32, device=dev),
+                nhits=torch.empty(ld, dtype=torch.int32, device=dev),
+                status=torch.empty(ld, dtype=torch.int32, device=dev))
+    fit_hits = torch.zeros((L, 9, ld), dtype=torch.float32, device=dev)
+    hole = torch.zeros(ld, dtype=torch.int32, device=dev)
+    fout = None
+    ex = kf.BuildExtra()
+    ex.seed_event = sev.data_ptr()
     torch.cuda.synchronize()
-
     stream = torch.cuda.current_stream()
 
-    arith = kftrack.ARITH_F64 if args.arith == "f64" else kftrack.ARITH_F32
+    def step(arith, ev=None, extra=ex):
+        nonlocal fout
+        rec = (lambda i: ev[i].record(stream)) if ev is not None else (lambda i: None)
+        rec(0)
+        kf.hit_bin(g, cuts.n_phi_bins, cuts.n_z_bins, layer, xyz, cov, event_offsets=hoff, out=binned, ws=ws_bin)
+        rec(1)
+        bp = kf.build_params(cuts, arith=arith)
+        kf.kf_build(g, bp, binned, n, seeds["par"], seeds["cov"], seeds["q"], extra=extra, out=bout, ws=ws_build)
+        rec(2)
+        kf.kf_gather_hits(L, F, n, bout["hits"], xyz, cov, seed_event=sev, event_offsets=hoff, fit_hits=fit_hits,
+                          hole_mask=hole)
+        rec(3)
+        fout = kf.kf_fit(g, n, F, fit_hits, seeds["par"], seeds["cov"], seeds["q"], hole_mask=hole, out=fout,
+                         arith=arith)
+        rec(4)
 
-    def step(evs=None, ar=None):
-        nonlocal out
-        if evs is not None:
-            evs[0].record(stream)
-        out = kftrack.kf_fit(w.geometry, n, 3, Hd, seeds["par"], seeds["cov"], seeds["q"], out=out,
-                             arith=arith if ar is None else ar)
-        if evs is not None:
-            evs[1].record(stream)
+    def timed(arith, steps):
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            step(arith, evs[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = np.array([[evs[k][i].elapsed_time(evs[k][i + 1]) for i in range(4)] for k in range(steps)])
+        return wall * 1e3 / steps, st.mean(axis=0)
 
-    # the other arithmetic, timed separately for reference
-    other = kftrack.ARITH_F32 if arith == kftrack.ARITH_F64 else kftrack.ARITH_F64
-    step(ar=other)
-    oe = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
-    for e in oe:
-        step(e, ar=other)
-    torch.cuda.synchronize()
-    other_ms = float(np.mean([a.elapsed_time(b) for a, b in oe]))
-
+    arith = kf.ARITH_F64 if args.arith == "f64" else kf.ARITH_F32
     for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(evs[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    fit_ms = np.array([a.elapsed_time(b) for a, b in evs])
-    ms_per_step = wall * 1e3 / args.steps
+        step(arith)
+    ms_per_step, stages = timed(arith, args.steps)
     value = n / (ms_per_step * 1e-3)
 
-    L = w.geometry.n_layers
-    flop = n * (L - 3) * FIT_FLOP_PER_TRACK_LAYER
-    fit_avg = float(fit_ms.mean())
-    achieved = flop / (fit_avg * 1e-3) / 1e12
-    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None, "kernel": "fit_kernel",
-            "avg_ms": round(fit_avg, 4),
-            "hbm_GBs_algorithmic": round(n * FIT_BYTES_PER_TRACK_14 / (fit_avg * 1e-3) / 1e9, 1)}
+    # work counters (separate, untimed pass)
+    cnt = torch.zeros(4, dtype=torch.int64, device=dev)
+    exc = kf.BuildExtra()
+    exc.seed_event = sev.data_ptr()
+    exc.counters = cnt.data_ptr()
+    step(arith, extra=exc)
+    torch.cuda.synchronize()
+    n_pred, n_scan, n_chi2, n_upd = [int(v) for v in cnt.cpu().numpy()]
+    build_flop = (n_pred * (FLOP_PREDICT + FLOP_WINDOW) + n_scan * FLOP_WINDOW_TEST + n_chi2 * FLOP_CHI2 +
+                  n_upd * FLOP_UPDATE)
+    ndof = fout["ndof"].cpu().numpy()[:n]
+    st = fout["status"].cpu().numpy()[:n]
+    n_upd_fit = int(ndof.sum() // 2)
+    n_pred_fit = n * (L - F)  # upper bound: frozen tracks stop early
+    fit_flop = n_pred_fit * FLOP_PREDICT + n_upd_fit * FLOP_UPDATE
+    names = ["hit_bin", "kf_build", "kf_gather_hits", "kf_fit"]
+    stage_ms = {k: round(float(v), 4) for k, v in zip(names, stages)}
+    dom = names[int(np.argmax(stages))]
+    peak = PEAK_TFLOPS[args.arith]
+    flop_of = {"kf_build": build_flop, "kf_fit": fit_flop}
+    if dom in flop_of:
+        ach = flop_of[dom] / (stage_ms[dom] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(ach / peak, 4), "traffic": None, "kernel": dom, "avg_ms": stage_ms[dom]}
+    else:
+        roof = {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
+                "traffic": None, "kernel": dom, "avg_ms": stage_ms[dom]}
+    # physics: fraction of seeds whose built list holds >= 75 % of their true hits
+    hits = bout["hits"].cpu().numpy()[:, :n]
+    eff = float(np.mean((hits == eb.true_hits[F:, :n]).mean(axis=0) >= 0.75))
     res = {
         "metric": METRIC, "value": round(value, 1), "unit": "tracks/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.arith, "data": "synthetic",
-        "config": {"workload": w.name, "tracks": n, "events": n // w.n_tracks, "layers": L,
-                   "step": "kf_fit"},
+        "config": {"workload": w.name, "tracks": n, "events": E, "layers": L,
+                   "step": "hit_bin -> kf_build -> kf_gather_hits -> kf_fit", "window": "plain",
+                   "cand_cap": cuts.cand_cap, "chi2_cut": cuts.chi2_cut, "storage": "f32"},
         "roofline": roof,
-        "stages_ms": {"kf_fit": round(fit_avg, 4)},
-        "other_arith": {"arith": "f32" if args.arith == "f64" else "f64", "kf_fit_ms": round(other_ms, 4)},
+        "stages_ms": stage_ms,
+        "work": {"build_cand_layers": n_pred, "build_hits_tested": n_scan, "build_chi2": n_chi2,
+                 "build_updates": n_upd, "build_gflop": round(build_flop / 1e9, 3),
+                 "fit_gflop": round(fit_flop / 1e9, 3),
+                 "build_tflops": round(build_flop / (stage_ms["kf_build"] * 1e-3) / 1e12, 3),
+                 "fit_tflops": round(fit_flop / (stage_ms["kf_fit"] * 1e-3) / 1e12, 3)},
+        "efficiency_75pct": round(eff, 4),
+        "fit_status_ok": round(float(np.mean(st == 0)), 4),
         "gen_s": round(t_gen, 2),
     }
+    if not args.no_other_arith:
+        other = "f32" if args.arith == "f64" else "f64"
+        oa = kf.ARITH_F32 if other == "f32" else kf.ARITH_F64
+        step(oa)
+        oms, ost = timed(oa, max(2, args.steps // 2))
+        res["other_arith"] = {"arith": other, "ms_per_step": round(oms, 4), "tracks_per_s": round(n / (oms * 1e-3), 1),
+                              "stages_ms": {k: round(float(v), 4) for k, v in zip(names, ost)}}
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(w, fb, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(w, eb, args.cpu_seconds)
     print(json.dumps(res), flush=True)
 
 

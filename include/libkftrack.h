@@ -183,6 +183,9 @@ typedef struct {
   float* dump;                /* [dump_capacity][32] */
   int32_t* dump_count;        /* [1] rows written (rows beyond capacity are counted, not written) */
   int32_t dump_capacity;
+  /* work counters, added to (not cleared): candidate-layers predicted, hits
+     window-tested, hits given a chi2, Kalman updates applied */
+  uint64_t* counters;         /* [4] */
 } kf_build_extra;
 
 /* Workspace bytes for kf_build. */
@@ -218,6 +221,21 @@ int kf_build(const kf_geometry* g, const kf_build_params* bp, const kf_hits* hit
              const float* seed_par, const float* seed_cov, const int8_t* q, int32_t* out_hits, float* out_par,
              float* out_cov, float* out_chi2, int32_t* out_nhits, int32_t* out_status,
              const kf_build_extra* extra, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * kf_gather_hits — the hit rows of built tracks in the fit layout (the final
+ * fit after building, section 2).  For seed i and layer l >= first_layer:
+ * built_hits[(l - first_layer) * ld + i] is an event-local original index
+ * (or -1); the row is copied from the unsorted event hits xyz [3][n_hits],
+ * cov [6][n_hits] at event_offsets[seed_event[i]] + index; a missing hit
+ * sets bit l of hole_mask[i] and zeroes the row.  seed_event and
+ * event_offsets may be NULL for a single event.  Rows of layers below
+ * first_layer are not written.
+ *   fit_hits [n_layers][9][ld], hole_mask [ld]
+ */
+int kf_gather_hits(int32_t n_layers, int32_t first_layer, int32_t n_seeds, int32_t ld, const int32_t* built_hits,
+                   const int32_t* seed_event, int32_t n_events, const int32_t* event_offsets, int32_t n_hits,
+                   const float* xyz, const float* cov, float* fit_hits, uint32_t* hole_mask, void* stream);
 
 #ifdef __cplusplus
 }

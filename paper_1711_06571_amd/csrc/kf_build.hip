@@ -71,6 +71,7 @@ struct BuildArgs {
   float* dump;
   int32_t* dump_count;
   int dump_capacity;
+  unsigned long long* counters;
   // workspace
   int32_t* queue;
   int32_t* event_done;
@@ -136,6 +137,7 @@ template <typename T, int CAPMAX> struct TopList {
   uint32_t orig[CAPMAX];
   int n;    // entries held (<= cap)
   int tot;  // accepted hits seen
+  int scanned, tested;  // hits window-tested, hits given a chi2 (work counters)
 };
 
 template <typename T, int CAPMAX>
@@ -181,6 +183,7 @@ __device__ inline void scan_range(const BuildArgs& A, int b0, int b1, float plo,
   int p = lower_bound_phi(A.hphi, b0, b1, plo);
   for (; p < b1; ++p) {
     if (A.hphi[p] > phi_hi) break;
+    tl.scanned += 1;
     const T hx = (T)A.hx[p], hy = (T)A.hy[p], hz = (T)A.hz[p];
     const T cr = Xp[0] * hy - Xp[1] * hx, dt = Xp[0] * hx + Xp[1] * hy;
     const T dph = k_atan2(cr, dt);
@@ -189,6 +192,7 @@ __device__ inline void scan_range(const BuildArgs& A, int b0, int b1, float plo,
 #pragma unroll
     for (int c = 0; c < 6; ++c) V[c] = (T)A.hcov[(size_t)c * A.n_hits + p];
     Innov<T> in;
+    tl.tested += 1;
     if (innovation<T>(Xp, Pp, hx, hy, hz, V, in)) continue;
     const T c2 = chi2_of(in);
     if (!(c2 < (T)A.chi2_cut)) continue;
@@ -292,6 +296,7 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
       n_active = 0;
     }
     T fin_chi2_reg = 0;  // chi2 of the finished record, kept by slot 0 of the seed
+    unsigned cnt_pred = 0, cnt_scan = 0, cnt_chi2 = 0, cnt_upd = 0;
     int last_l = A.first_layer - 1;
     for (int l = A.first_layer; l < A.n_layers; ++l) {
       // all seeds of the wave done?
@@ -312,6 +317,8 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
       TopList<T, CAPMAX> tl;
       tl.n = 0;
       tl.tot = 0;
+      tl.scanned = 0;
+      tl.tested = 0;
 #pragma unroll
       for (int k = 0; k < CAPMAX; ++k) { tl.c2[k] = 0; tl.pos[k] = 0; tl.orig[k] = 0; }
       if (pok) {
@@ -350,6 +357,9 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
         }
         scan_window<T, CAPMAX>(A, ev, l, Xp, Pp, w_rphi / R, w_z, tl);
       }
+      cnt_pred += live ? 1u : 0u;
+      cnt_scan += (unsigned)tl.scanned;
+      cnt_chi2 += (unsigned)tl.tested;
       const bool hole_ok = pok && holes < A.max_holes;
       const int nchild = tl.tot + (hole_ok ? 1 : 0);
       // finished candidates of this layer (live, no child) compete for the record
@@ -438,6 +448,7 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
           Innov<T> in;
           innovation<T>(Xn, Pn, hx, hy, hz, V, in);
           apply_update<T>(Xn, Pn, in);
+          cnt_upd += 1;
         }
 #pragma unroll
         for (int k = 0; k < 6; ++k) X[k] = Xn[k];
@@ -453,6 +464,16 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
         hist[(l - A.first_layer) * 64 + lane] = pack_hist(my_parent, my_orig);
       }
       n_active = n_new;
+    }
+    if (A.counters) {
+      unsigned long long c[4] = {cnt_pred, cnt_scan, cnt_chi2, cnt_upd};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        unsigned long long v = c[k];
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
+        if (lane == 0) atomicAdd(&A.counters[k], v);
+      }
     }
     // final choice: best active (slot order), then the finished record
     {
@@ -569,7 +590,7 @@ extern "C" int kf_build(const kf_geometry* g, const kf_build_params* bp, const k
   if (bp->window_mode == 1 && !bp->mlp) return KF_E_INVALID_ARG;
   if (hits->n_layers != g->n_layers || hits->n_events < 1 || hits->n_phi < 1 || hits->n_z < 1 || hits->n_hits < 0)
     return KF_E_INVALID_ARG;
-  if (hits->n_hits > kMaxOrig) return KF_E_UNSUPPORTED;
+  (void)kMaxOrig;  // hit indices are event-local: each event must hold fewer than 2^24 - 1 hits
   if (n_seeds == 0) return KF_OK;
   if (!seed_par || !seed_cov || !q || !out_hits || !out_par || !out_cov || !out_chi2 || !out_nhits || !out_status)
     return KF_E_INVALID_ARG;
@@ -606,6 +627,7 @@ extern "C" int kf_build(const kf_geometry* g, const kf_build_params* bp, const k
   A.event_n_seeds = ex.event_n_seeds; A.event_done_ticks = ex.event_done_ticks; A.start_tick = ex.start_tick;
   A.true_hits = ex.true_hits; A.true_xyz = ex.true_xyz; A.dump = ex.dump; A.dump_count = ex.dump_count;
   A.dump_capacity = ex.dump_capacity;
+  A.counters = (unsigned long long*)ex.counters;
   A.queue = (int32_t*)ws;
   A.event_done = (int32_t*)((char*)ws + 256);
   hipStream_t s = (hipStream_t)stream;

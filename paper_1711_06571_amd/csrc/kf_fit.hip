@@ -222,3 +222,54 @@ extern "C" int kf_fit(const kf_geometry* g, int32_t n, int32_t ld, int32_t first
                        out_status);
   return kf_check_launch();
 }
+
+namespace {
+
+// Gather the hit rows of built tracks into the fit layout.  Layer l of seed i
+// takes the built hit (event-local index) or, if none, a hole bit.
+__global__ void __launch_bounds__(256) gather_kernel(int n_layers, int first_layer, int n, int ld,
+                                                     const int32_t* __restrict__ built,
+                                                     const int32_t* __restrict__ seed_event,
+                                                     const int32_t* __restrict__ event_offsets, int n_events,
+                                                     int n_hits, const float* __restrict__ xyz,
+                                                     const float* __restrict__ cov, float* __restrict__ fit_hits,
+                                                     uint32_t* __restrict__ hole_mask) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int e = seed_event ? seed_event[i] : 0;
+  const bool ev_ok = e >= 0 && e < n_events;
+  const int base = (ev_ok && event_offsets) ? event_offsets[e] : 0;
+  const int end = (ev_ok && event_offsets) ? event_offsets[e + 1] : n_hits;
+  uint32_t holes = 0;
+  for (int l = first_layer; l < n_layers; ++l) {
+    const int h = built[(size_t)(l - first_layer) * ld + i];
+    const int g = base + h;
+    float* row = fit_hits + (size_t)l * 9 * ld + i;
+    if (!ev_ok || h < 0 || g >= end) {
+      holes |= 1u << l;
+      for (int c = 0; c < 9; ++c) row[(size_t)c * ld] = 0.f;
+      continue;
+    }
+    for (int c = 0; c < 3; ++c) row[(size_t)c * ld] = xyz[(size_t)c * n_hits + g];
+    for (int c = 0; c < 6; ++c) row[(size_t)(3 + c) * ld] = cov[(size_t)c * n_hits + g];
+  }
+  hole_mask[i] = holes;
+}
+
+}  // namespace
+
+extern "C" int kf_gather_hits(int32_t n_layers, int32_t first_layer, int32_t n_seeds, int32_t ld,
+                              const int32_t* built_hits, const int32_t* seed_event, int32_t n_events,
+                              const int32_t* event_offsets, int32_t n_hits, const float* xyz, const float* cov,
+                              float* fit_hits, uint32_t* hole_mask, void* stream) {
+  if (n_layers < 1 || n_layers > 32 || first_layer < 0 || first_layer >= n_layers) return KF_E_INVALID_ARG;
+  if (n_seeds < 0 || ld < n_seeds || n_events < 1 || n_hits < 0) return KF_E_INVALID_ARG;
+  if (n_events > 1 && (!seed_event || !event_offsets)) return KF_E_INVALID_ARG;
+  if (n_seeds == 0) return KF_OK;
+  if (!built_hits || !fit_hits || !hole_mask || (n_hits > 0 && (!xyz || !cov))) return KF_E_INVALID_ARG;
+  const int bs = 256;
+  hipLaunchKernelGGL(gather_kernel, dim3((n_seeds + bs - 1) / bs), dim3(bs), 0, (hipStream_t)stream, n_layers,
+                     first_layer, n_seeds, ld, built_hits, seed_event, event_offsets, n_events, n_hits, xyz, cov,
+                     fit_hits, hole_mask);
+  return kf_check_launch();
+}

@@ -56,7 +56,7 @@ class BuildExtra(ctypes.Structure):
                 ("event_n_seeds", ctypes.c_void_p), ("event_done_ticks", ctypes.c_void_p),
                 ("start_tick", ctypes.c_void_p), ("true_hits", ctypes.c_void_p), ("true_xyz", ctypes.c_void_p),
                 ("dump", ctypes.c_void_p),
-                ("dump_count", ctypes.c_void_p), ("dump_capacity", ctypes.c_int32)]
+                ("dump_count", ctypes.c_void_p), ("dump_capacity", ctypes.c_int32), ("counters", ctypes.c_void_p)]
 
 
 class KFError(RuntimeError):
@@ -85,6 +85,7 @@ def lib():
             L.hit_bin_workspace_bytes.argtypes = [I, I, I, I, I]
             L.hit_bin.argtypes = [ctypes.POINTER(Geometry), I, P, I, I, I, P, P, P, P, P, P, P, P, P,
                                   ctypes.c_size_t, P]
+        L.kf_gather_hits.argtypes = [I, I, I, I, P, P, I, P, I, P, P, P, P, P]
         if hasattr(L, "kf_build"):
             L.kf_build_workspace_bytes.restype = ctypes.c_size_t
             L.kf_build_workspace_bytes.argtypes = [I, I]
@@ -259,3 +260,20 @@ def kf_build(g, bp, binned: BinnedHits, n_seeds, seed_par, seed_cov, q, extra=No
                           _ptr(out["chi2"]), _ptr(out["nhits"]), _ptr(out["status"]), ctypes.byref(ex), _ptr(ws),
                           ctypes.c_size_t(need), _stream(stream)))
     return out
+
+
+def kf_gather_hits(n_layers, first_layer, n_seeds, built_hits, xyz, cov, seed_event=None, event_offsets=None,
+                   fit_hits=None, hole_mask=None, stream=None):
+    """Built hit lists -> fit rows [L][9][ld] and hole mask [ld] (int32 view)."""
+    ld = built_hits.shape[1]
+    dev = built_hits.device
+    if fit_hits is None:
+        fit_hits = torch.zeros((n_layers, 9, ld), dtype=torch.float32, device=dev)
+    if hole_mask is None:
+        hole_mask = torch.zeros(ld, dtype=torch.int32, device=dev)
+    E = 1 if event_offsets is None else event_offsets.shape[0] - 1
+    n_hits = xyz.shape[1]
+    _check(lib().kf_gather_hits(n_layers, first_layer, n_seeds, ld, _ptr(built_hits), _ptr(seed_event), E,
+                                _ptr(event_offsets), n_hits, _ptr(xyz), _ptr(cov), _ptr(fit_hits), _ptr(hole_mask),
+                                _stream(stream)))
+    return fit_hits, hole_mask

@@ -54,35 +54,54 @@ class EventBatch:
     track_of_hit: np.ndarray  # [n_hits] int32 (-1 noise), event-local track index
 
 
-def event_batch(w: Workload, events, n_tracks=None) -> EventBatch:
+def _event_tracks(w: Workload, e: int, n_tracks=None) -> int:
+    if n_tracks is not None:
+        return n_tracks
+    return w.n_tracks if w.tracks_hi == 0 else datagen.event_tracks(w.gen, e, w.tracks_lo, w.tracks_hi)
+
+
+def event_batch(w: Workload, events, n_tracks=None, seed_layers=None) -> EventBatch:
+    """Generate events into concatenated FP32 arrays, one event at a time.
+    seed_hits keeps the first `seed_layers` layers of each track's hits (all
+    layers by default)."""
+    import ctypes
     events = list(events)
-    evs = []
-    for e in events:
-        T = n_tracks if n_tracks is not None else (
-            w.n_tracks if w.tracks_hi == 0 else datagen.event_tracks(w.gen, e, w.tracks_lo, w.tracks_hi))
-        evs.append(datagen.generate(w.geometry, w.gen, e, T))
     L = w.geometry.n_layers
-    nh = [ev.n_hits for ev in evs]
-    ns = [ev.n_tracks for ev in evs]
+    SL = L if seed_layers is None else seed_layers
+    nts = [_event_tracks(w, e, n_tracks) for e in events]
+    cfg = datagen._cfg(w.geometry, w.gen)
+    nh = []
+    cnt = np.zeros(32, dtype=np.int64)
+    for e, T in zip(events, nts):
+        datagen.lib().kfg_layer_counts(ctypes.byref(cfg), e, T, cnt.ctypes.data)
+        nh.append(int(cnt[:L].sum()))
     hoff = np.concatenate([[0], np.cumsum(nh)]).astype(np.int64)
-    soff = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    soff = np.concatenate([[0], np.cumsum(nts)]).astype(np.int64)
     if hoff[-1] >= 2 ** 31:
         raise ValueError("too many hits for int32 offsets")
     n_seeds = int(soff[-1])
     ld = datagen.padded(n_seeds)
-    xyz = np.concatenate([ev.xyz for ev in evs], axis=1).astype(np.float32)
-    cov = np.concatenate([ev.cov for ev in evs], axis=1).astype(np.float32)
-    layer = np.concatenate([ev.layer for ev in evs]).astype(np.int32)
-    trk = np.concatenate([ev.track for ev in evs]).astype(np.int32)
-    H = np.zeros((L, 9, ld), dtype=np.float32)
+    xyz = np.zeros((3, hoff[-1]), dtype=np.float32)
+    cov = np.zeros((6, hoff[-1]), dtype=np.float32)
+    layer = np.zeros(hoff[-1], dtype=np.int32)
+    trk = np.zeros(hoff[-1], dtype=np.int32)
+    H = np.zeros((SL, 9, ld), dtype=np.float32)
     TH = np.full((L, ld), -1, dtype=np.int32)
     sev = np.zeros(n_seeds, dtype=np.int32)
-    for k, ev in enumerate(evs):
+    for k, (e, T) in enumerate(zip(events, nts)):
+        ev = datagen.generate(w.geometry, w.gen, e, T)
+        hs = slice(hoff[k], hoff[k + 1])
+        xyz[:, hs] = ev.xyz
+        cov[:, hs] = ev.cov
+        layer[hs] = ev.layer
+        trk[hs] = ev.track
         sl = slice(soff[k], soff[k + 1])
         for l in range(L):
             idx = ev.trk_hits[l]
-            H[l, 0:3, sl] = ev.xyz[:, idx]
-            H[l, 3:9, sl] = ev.cov[:, idx]
+            if l < SL:
+                H[l, 0:3, sl] = ev.xyz[:, idx]
+                H[l, 3:9, sl] = ev.cov[:, idx]
             TH[l, sl] = idx
         sev[sl] = k
+        del ev
     return EventBatch(xyz, cov, layer, hoff.astype(np.int32), H, TH, sev, soff.astype(np.int32), n_seeds, ld, trk)
