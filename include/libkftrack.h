@@ -223,6 +223,31 @@ int kf_build(const kf_geometry* g, const kf_build_params* bp, const kf_hits* hit
              const kf_build_extra* extra, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Learned search window (an addition to the method: the paper sizes the hit
+ * search from the covariance).  A device block of kf_mlp_block_bytes() bytes
+ * holds the network: standardisation (mean, 1/std of the 27 features), FP32
+ * biases, output scales, kappa and the two floors, then BF16 weights
+ * (layout: the library's kfmlp.h).  Rows of data are 32 floats: the 27
+ * features (predicted state, 21 covariance entries), the 2 labels (|arc| at
+ * the layer radius and |dz| to the true hit), then 3 words not read here.
+ */
+size_t kf_mlp_block_bytes(void);
+/* widths [n_rows][2] (kappa applied) and, if out_logits is not NULL, the
+ * head's pre-softplus outputs [n_rows][2] */
+int kf_mlp_forward(const void* block, int32_t n_rows, const float* rows, float* out, float* out_logits,
+                   void* stream);
+size_t kf_mlp_grad_workspace_bytes(int32_t n_rows);
+/* grad [n_params + 1]: gradient of the mean loss over rows and both outputs
+ * (order: W1 [64][27], b1, W2 [64][64], b2, W3 [2][64], b3), then the loss
+ * 20 * max(0, d - w) + max(0, w - d) averaged the same way */
+int kf_mlp_grad(const void* block, int32_t n_rows, const float* rows, float* grad, void* ws, size_t ws_bytes,
+                void* stream);
+/* one Adam step (step counts from 1) on the FP32 master vector [n_params]
+ * with moments m, v; refreshes the block's BF16 weights and FP32 biases */
+int kf_mlp_adam(void* block, float* master, float* m, float* v, const float* grad, int32_t step, float lr,
+                float beta1, float beta2, float eps, void* stream);
+
+/*
  * kf_gather_hits — the hit rows of built tracks in the fit layout (the final
  * fit after building, section 2).  For seed i and layer l >= first_layer:
  * built_hits[(l - first_layer) * ld + i] is an event-local original index

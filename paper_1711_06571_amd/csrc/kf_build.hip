@@ -26,7 +26,6 @@
 #include "kfmlp.h"
 
 using namespace kfdev;
-using kfmlp::mlp_window_lane;
 
 namespace {
 
@@ -257,6 +256,9 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
   const size_t fin_off = (hist_words * 4 + 15) & ~(size_t)15;
   T* fin = (T*)((char*)lds + fin_off) + (size_t)wave * SEEDS * 27;
   int32_t* finm = (int32_t*)((char*)lds + fin_off + (size_t)nwaves * SEEDS * 27 * sizeof(T)) + (size_t)wave * SEEDS * 5;
+  const size_t mlp_off = (fin_off + (size_t)nwaves * SEEDS * 27 * sizeof(T) + (size_t)nwaves * SEEDS * 5 * 4 + 15) &
+                         ~(size_t)15;
+  uint16_t* mlp_buf = (uint16_t*)((char*)lds + mlp_off) + (size_t)wave * (KFMLP_LDS_BYTES / 2);
   const int sidx = lane / S, slot = lane % S, sbase = sidx * S;
 
   if (A.start_tick && lane == 0) atomicMin((unsigned long long*)A.start_tick, (unsigned long long)wall_clock64());
@@ -321,6 +323,19 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
       tl.tested = 0;
 #pragma unroll
       for (int k = 0; k < CAPMAX; ++k) { tl.c2[k] = 0; tl.pos[k] = 0; tl.orig[k] = 0; }
+      // learned window: the whole wave evaluates the network on its 64 slots
+      float wl[2] = {0.f, 0.f};
+      if (A.window_mode == 1) {
+        float feat[27];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) feat[k] = pok ? (float)Xp[k] : 0.f;
+#pragma unroll
+        for (int k = 0; k < 21; ++k) feat[6 + k] = pok ? (float)Pp[k] : 0.f;
+        kfmlp::wave_forward(A.mlp, mlp_buf, feat, wl);
+        const float kap = A.mlp[KFMLP_OFF_KAPPA];
+        wl[0] *= kap;
+        wl[1] *= kap;
+      }
       if (pok) {
         const T R = (T)A.r[l];
         const T rr = k_sqrt(Xp[0] * Xp[0] + Xp[1] * Xp[1]);
@@ -330,8 +345,6 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
         const T Sww = Pp[ut(2, 2)] + (T)A.win_sig_z * (T)A.win_sig_z;
         T w_rphi = (T)A.nsigma * k_sqrt(Suu), w_z = (T)A.nsigma * k_sqrt(Sww);
         if (A.window_mode == 1) {
-          float wl[2];
-          mlp_window_lane(A.mlp, Xp, Pp, wl);
           if (!(wl[0] < A.mlp[KFMLP_OFF_FLOOR])) w_rphi = (T)wl[0];
           if (!(wl[1] < A.mlp[KFMLP_OFF_FLOOR + 1])) w_z = (T)wl[1];
         }
@@ -541,16 +554,18 @@ __global__ void build_clear(int32_t* queue, int32_t* event_done, int n_events, i
   for (int e = i; e < n_events; e += gridDim.x * blockDim.x) event_done[e] = 0;
 }
 
-size_t lds_bytes(int LB, int nwaves, int S, size_t tsize) {
+size_t lds_bytes(int LB, int nwaves, int S, size_t tsize, bool learned) {
   const int seeds = 64 / S;
   const size_t fin_off = ((size_t)nwaves * LB * 64 * 4 + 15) & ~(size_t)15;
-  return fin_off + (size_t)nwaves * seeds * 27 * tsize + (size_t)nwaves * seeds * 5 * 4;
+  const size_t end = fin_off + (size_t)nwaves * seeds * 27 * tsize + (size_t)nwaves * seeds * 5 * 4;
+  if (!learned) return end;
+  return ((end + 15) & ~(size_t)15) + (size_t)nwaves * KFMLP_LDS_BYTES;
 }
 
 template <typename T, int S>
 int launch(const BuildArgs& A, int lanes, int blocks, hipStream_t s) {
   const int nwaves = lanes / 64;
-  const size_t lds = lds_bytes(A.n_layers - A.first_layer, nwaves, S, sizeof(T));
+  const size_t lds = lds_bytes(A.n_layers - A.first_layer, nwaves, S, sizeof(T), A.window_mode == 1);
   if (lds > 64 * 1024) return KF_E_UNSUPPORTED;
   if (blocks <= 0) {
     int dev = 0, cus = 0, per = 0;

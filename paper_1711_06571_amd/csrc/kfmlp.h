@@ -1,8 +1,16 @@
-// Search-window network (an addition to the paper's method): 27 inputs (the
-// predicted state and the 21 covariance entries) -> 64 -> GELU -> 64 -> GELU
-// -> 2, softplus head times a per-output scale, giving the half-width of the
-// hit window as an arc at the layer radius (cm) and in z (cm).  Weights and
-// the activations that feed products are BF16; products accumulate in FP32.
+// Search-window network (an addition to the paper's method, which sizes its
+// hit search from the covariance): 27 inputs (the predicted state and its 21
+// covariance entries) -> 64 -> GELU -> 64 -> GELU -> 2, softplus head times
+// a per-output scale, giving the half-width of the hit window as an arc at
+// the layer radius (cm) and in z (cm).  Weights and the activations that feed
+// products are BF16; every product runs on the matrix cores
+// (v_mfma_f32_16x16x32_bf16) and accumulates in FP32.
+//
+// A wave evaluates 64 rows at once (one per lane): the rows of the wave are
+// four 16-row tiles; for each tile, layer 1 (K = 32, the 27 inputs padded),
+// layer 2 (K = 64) and the head (N padded 2 -> 16) run back to back through
+// one 64 x 72 BF16 LDS buffer (a tile's rows are overwritten only after they
+// have been consumed).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -17,18 +25,34 @@
 #define KFMLP_OFF_KAPPA 186
 #define KFMLP_OFF_FLOOR 187
 #define KFMLP_HEADER_FLOATS 192
-// BF16 weights after the header (offsets in bf16 elements from the weights
-// start): W1 [64][32] (input padded 27 -> 32 with zeros), W2 [64][64],
-// W3 [16][64] (rows 2..15 zero)
+// BF16 weights after the header (offsets in bf16 elements): W1 [64][32]
+// (inputs padded 27 -> 32 with zeros), W2 [64][64], W3 [16][64] (rows 2..15
+// zero), W2T [64][64] (W2 transposed, for the backward pass)
 #define KFMLP_W1 0
 #define KFMLP_W2 (64 * 32)
 #define KFMLP_W3 (64 * 32 + 64 * 64)
-#define KFMLP_WEIGHTS (64 * 32 + 64 * 64 + 16 * 64)
+#define KFMLP_W2T (64 * 32 + 64 * 64 + 16 * 64)
+#define KFMLP_WEIGHTS (64 * 32 + 64 * 64 + 16 * 64 + 64 * 64)
 #define KFMLP_BLOCK_BYTES (KFMLP_HEADER_FLOATS * 4 + KFMLP_WEIGHTS * 2)
-// one row of the training-data dump: 27 features, 2 labels, seed, layer, slot
+// trainable parameters (FP32 master vector): W1 [64][27], b1 [64], W2 [64][64],
+// b2 [64], W3 [2][64], b3 [2]
+#define KFMLP_P_W1 0
+#define KFMLP_P_B1 (64 * 27)
+#define KFMLP_P_W2 (KFMLP_P_B1 + 64)
+#define KFMLP_P_B2 (KFMLP_P_W2 + 64 * 64)
+#define KFMLP_P_W3 (KFMLP_P_B2 + 64)
+#define KFMLP_P_B3 (KFMLP_P_W3 + 2 * 64)
+#define KFMLP_NPARAM (KFMLP_P_B3 + 2)
+// one row of training data: 27 features, 2 labels, then seed, layer, slot
 #define KFMLP_DUMP_ROW 32
+// LDS row pitch of the activation buffer (bf16 elements; 64 + 8 padding)
+#define KFMLP_PITCH 72
+#define KFMLP_LDS_BYTES (64 * KFMLP_PITCH * 2)
 
 namespace kfmlp {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __host__ __device__ inline float bf16_to_f(uint16_t h) {
   uint32_t u = (uint32_t)h << 16;
@@ -49,34 +73,118 @@ __host__ __device__ inline uint16_t f_to_bf16(float f) {
 __host__ __device__ inline float bf16_round(float f) { return bf16_to_f(f_to_bf16(f)); }
 
 __device__ inline float gelu(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
+__device__ inline float gelu_grad(float z) {
+  return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
+}
 __device__ inline float softplus(float o) { return o > 30.f ? o : log1pf(__expf(o)); }
+__device__ inline float sigmoid(float o) { return 1.f / (1.f + __expf(-o)); }
 
-// One lane evaluates the network for its own candidate (FP32 accumulation in
-// index order).  Returns kappa * widths.
-template <typename T>
-__device__ __noinline__ void mlp_window_lane(const float* __restrict__ blk, const T Xp[6], const T Pp[21], float w[2]) {
+// 8 consecutive bf16 (16 bytes, 16-byte aligned) as an MFMA operand
+__device__ inline bf16x8 load8(const uint16_t* p) {
+  uint4 v = *(const uint4*)p;
+  return __builtin_bit_cast(bf16x8, v);
+}
+
+__device__ inline f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Operand layout of v_mfma_f32_16x16x32_bf16 (wave64), lane l:
+//   A (16 x 32): row l % 16, k = 8 (l / 16) .. + 7
+//   B (32 x 16): k = 8 (l / 16) .. + 7, column l % 16
+//   C (16 x 16): rows 4 (l / 16) .. + 3, column l % 16
+//
+// Forward of the 64 rows of a wave.  x: this lane's 27 raw features (its row
+// is the lane index); buf: the wave's LDS buffer [64][KFMLP_PITCH] bf16.
+// Writes the two widths (without kappa) of this lane's row into w.  Must be
+// called by all 64 lanes.
+__device__ inline void wave_forward(const float* __restrict__ blk, uint16_t* buf, const float x[27], float w[2],
+                                    float* o_out = nullptr) {
+  const int lane = threadIdx.x & 63;
   const uint16_t* W = (const uint16_t*)(blk + KFMLP_HEADER_FLOATS);
-  float xh[27];
-  for (int k = 0; k < 6; ++k) xh[k] = bf16_round(((float)Xp[k] - blk[KFMLP_OFF_MU + k]) * blk[KFMLP_OFF_ISD + k]);
-  for (int k = 0; k < 21; ++k)
-    xh[6 + k] = bf16_round(((float)Pp[k] - blk[KFMLP_OFF_MU + 6 + k]) * blk[KFMLP_OFF_ISD + 6 + k]);
-  float h1[64];
-  for (int j = 0; j < 64; ++j) {
-    float s = 0.f;
-    for (int k = 0; k < 27; ++k) s += bf16_to_f(W[KFMLP_W1 + j * 32 + k]) * xh[k];
-    h1[j] = bf16_round(gelu(s + blk[KFMLP_OFF_B1 + j]));
+  // standardised inputs, BF16, columns 0..31 of this lane's row
+  uint16_t* row = buf + lane * KFMLP_PITCH;
+#pragma unroll
+  for (int k = 0; k < 27; ++k) row[k] = f_to_bf16((x[k] - blk[KFMLP_OFF_MU + k]) * blk[KFMLP_OFF_ISD + k]);
+#pragma unroll
+  for (int k = 27; k < 32; ++k) row[k] = 0;
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
+  const int r16 = lane & 15, kq = lane >> 4;
+  float head[2] = {0.f, 0.f};
+  for (int mt = 0; mt < 4; ++mt) {
+    uint16_t* tile = buf + (mt * 16) * KFMLP_PITCH;
+    // layer 1: Z1 = Xh W1^T, 4 column tiles, one k step
+    f32x4 acc1[4];
+    const bf16x8 a1 = load8(tile + r16 * KFMLP_PITCH + 8 * kq);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const bf16x8 b = load8(W + KFMLP_W1 + (nt * 16 + r16) * 32 + 8 * kq);
+      acc1[nt] = mfma(a1, b, f32x4{0.f, 0.f, 0.f, 0.f});
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int col = nt * 16 + r16;
+      const float bias = blk[KFMLP_OFF_B1 + col];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) tile[(4 * kq + i) * KFMLP_PITCH + col] = f_to_bf16(gelu(acc1[nt][i] + bias));
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    // layer 2: Z2 = H1 W2^T, K = 64 in two steps
+    f32x4 acc2[4];
+    const bf16x8 a20 = load8(tile + r16 * KFMLP_PITCH + 8 * kq);
+    const bf16x8 a21 = load8(tile + r16 * KFMLP_PITCH + 32 + 8 * kq);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const uint16_t* wr = W + KFMLP_W2 + (nt * 16 + r16) * 64;
+      acc2[nt] = mfma(a20, load8(wr + 8 * kq), f32x4{0.f, 0.f, 0.f, 0.f});
+      acc2[nt] = mfma(a21, load8(wr + 32 + 8 * kq), acc2[nt]);
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int col = nt * 16 + r16;
+      const float bias = blk[KFMLP_OFF_B2 + col];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) tile[(4 * kq + i) * KFMLP_PITCH + col] = f_to_bf16(gelu(acc2[nt][i] + bias));
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    // head: O = H2 W3^T (columns 0, 1 of a 16-wide tile)
+    const bf16x8 a30 = load8(tile + r16 * KFMLP_PITCH + 8 * kq);
+    const bf16x8 a31 = load8(tile + r16 * KFMLP_PITCH + 32 + 8 * kq);
+    const uint16_t* w3 = W + KFMLP_W3 + r16 * 64;
+    f32x4 acc3 = mfma(a30, load8(w3 + 8 * kq), f32x4{0.f, 0.f, 0.f, 0.f});
+    acc3 = mfma(a31, load8(w3 + 32 + 8 * kq), acc3);
+    __builtin_amdgcn_wave_barrier();
+    // lanes holding columns 0 and 1 of rows 4kq..4kq+3 park the head in the
+    // first two floats of those rows (as raw bits, 4 halves)
+    if (r16 < 2) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t bits = __float_as_uint(acc3[i]);
+        uint16_t* dst = tile + (4 * kq + i) * KFMLP_PITCH + 2 * r16;
+        dst[0] = (uint16_t)bits;
+        dst[1] = (uint16_t)(bits >> 16);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    if ((lane >> 4) == mt) {
+      const uint16_t* src = buf + lane * KFMLP_PITCH;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) head[j] = __uint_as_float((uint32_t)src[2 * j] | ((uint32_t)src[2 * j + 1] << 16));
+    }
+    __builtin_amdgcn_wave_barrier();
   }
-  float o0 = 0.f, o1 = 0.f;
-  for (int j = 0; j < 64; ++j) {
-    float s = 0.f;
-    for (int k = 0; k < 64; ++k) s += bf16_to_f(W[KFMLP_W2 + j * 64 + k]) * h1[k];
-    const float h2 = bf16_round(gelu(s + blk[KFMLP_OFF_B2 + j]));
-    o0 += bf16_to_f(W[KFMLP_W3 + 0 * 64 + j]) * h2;
-    o1 += bf16_to_f(W[KFMLP_W3 + 1 * 64 + j]) * h2;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const float o = head[j] + blk[KFMLP_OFF_B3 + j];
+    if (o_out) o_out[j] = o;
+    w[j] = blk[KFMLP_OFF_SCALE + j] * softplus(o);
   }
-  const float kap = blk[KFMLP_OFF_KAPPA];
-  w[0] = kap * blk[KFMLP_OFF_SCALE] * softplus(o0 + blk[KFMLP_OFF_B3]);
-  w[1] = kap * blk[KFMLP_OFF_SCALE + 1] * softplus(o1 + blk[KFMLP_OFF_B3 + 1]);
 }
 
 }  // namespace kfmlp

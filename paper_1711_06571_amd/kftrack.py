@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -86,6 +87,12 @@ def lib():
             L.hit_bin.argtypes = [ctypes.POINTER(Geometry), I, P, I, I, I, P, P, P, P, P, P, P, P, P,
                                   ctypes.c_size_t, P]
         L.kf_gather_hits.argtypes = [I, I, I, I, P, P, I, P, I, P, P, P, P, P]
+        L.kf_mlp_block_bytes.restype = ctypes.c_size_t
+        L.kf_mlp_grad_workspace_bytes.restype = ctypes.c_size_t
+        L.kf_mlp_grad_workspace_bytes.argtypes = [I]
+        L.kf_mlp_forward.argtypes = [P, I, P, P, P, P]
+        L.kf_mlp_grad.argtypes = [P, I, P, P, P, ctypes.c_size_t, P]
+        L.kf_mlp_adam.argtypes = [P, P, P, P, P, I, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P]
         if hasattr(L, "kf_build"):
             L.kf_build_workspace_bytes.restype = ctypes.c_size_t
             L.kf_build_workspace_bytes.argtypes = [I, I]
@@ -277,3 +284,94 @@ def kf_gather_hits(n_layers, first_layer, n_seeds, built_hits, xyz, cov, seed_ev
                                 _ptr(event_offsets), n_hits, _ptr(xyz), _ptr(cov), _ptr(fit_hits), _ptr(hole_mask),
                                 _stream(stream)))
     return fit_hits, hole_mask
+
+
+# ------------------------------------------------------------ window network
+
+MLP_NPARAM = 64 * 27 + 64 + 64 * 64 + 64 + 2 * 64 + 2
+MLP_ROW = 32
+_MLP_HDR = 192
+
+
+def _bf16_bits(a):
+    """FP32 -> bfloat16 bit patterns, round to nearest even (packing only)."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return r.astype(np.uint16)
+
+
+def mlp_split(master):
+    """FP32 master vector -> dict of W1 (64,27), b1, W2 (64,64), b2, W3 (2,64), b3."""
+    m = np.asarray(master, dtype=np.float32)
+    o = 0
+    out = {}
+    for k, shp in (("W1", (64, 27)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (2, 64)),
+                   ("b3", (2,))):
+        n = int(np.prod(shp))
+        out[k] = m[o:o + n].reshape(shp)
+        o += n
+    return out
+
+
+def mlp_join(p):
+    return np.concatenate([np.asarray(p[k], dtype=np.float32).ravel() for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+
+
+def mlp_block(master, mu, sd, scale, kappa=1.0, floor_rphi=0.01, floor_z=0.1, device="cuda:0"):
+    """Pack the device block: FP32 header then BF16 weights (W1 padded to 32
+    inputs, W2, W3 padded to 16 rows, W2 transposed)."""
+    p = mlp_split(master)
+    hdr = np.zeros(_MLP_HDR, dtype=np.float32)
+    hdr[0:27] = mu
+    hdr[27:54] = 1.0 / np.asarray(sd, dtype=np.float64)
+    hdr[54:118] = p["b1"]
+    hdr[118:182] = p["b2"]
+    hdr[182:184] = p["b3"]
+    hdr[184:186] = scale
+    hdr[186] = kappa
+    hdr[187] = floor_rphi
+    hdr[188] = floor_z
+    W1 = np.zeros((64, 32), dtype=np.float32)
+    W1[:, :27] = p["W1"]
+    W3 = np.zeros((16, 64), dtype=np.float32)
+    W3[:2] = p["W3"]
+    w = np.concatenate([_bf16_bits(W1).ravel(), _bf16_bits(p["W2"]).ravel(), _bf16_bits(W3).ravel(),
+                        _bf16_bits(np.ascontiguousarray(p["W2"].T)).ravel()])
+    raw = np.concatenate([hdr.view(np.uint8), w.view(np.uint8)])
+    assert raw.size == int(lib().kf_mlp_block_bytes())
+    return torch.from_numpy(raw.view(np.float32).copy()).to(device)
+
+
+def mlp_set_header(block, kappa=None, floor_rphi=None, floor_z=None):
+    if kappa is not None:
+        block[186] = kappa
+    if floor_rphi is not None:
+        block[187] = floor_rphi
+    if floor_z is not None:
+        block[188] = floor_z
+
+
+def kf_mlp_forward(block, rows, n=None, logits=False, stream=None):
+    n = rows.shape[0] if n is None else n
+    out = torch.empty((max(n, 1), 2), dtype=torch.float32, device=rows.device)
+    lo = torch.empty((max(n, 1), 2), dtype=torch.float32, device=rows.device) if logits else None
+    _check(lib().kf_mlp_forward(_ptr(block), n, _ptr(rows), _ptr(out), _ptr(lo), _stream(stream)))
+    return (out, lo) if logits else out
+
+
+def kf_mlp_grad(block, rows, n=None, grad=None, ws=None, stream=None):
+    n = rows.shape[0] if n is None else n
+    if grad is None:
+        grad = torch.empty(MLP_NPARAM + 1, dtype=torch.float32, device=rows.device)
+    need = int(lib().kf_mlp_grad_workspace_bytes(n))
+    if ws is None or ws.numel() * ws.element_size() < need:
+        ws = torch.empty(need // 4 + 1, dtype=torch.float32, device=rows.device)
+    _check(lib().kf_mlp_grad(_ptr(block), n, _ptr(rows), _ptr(grad), _ptr(ws), ctypes.c_size_t(need),
+                             _stream(stream)))
+    return grad
+
+
+def kf_mlp_adam(block, master, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().kf_mlp_adam(_ptr(block), _ptr(master), _ptr(m), _ptr(v), _ptr(grad), step, ctypes.c_float(lr),
+                             ctypes.c_float(beta1), ctypes.c_float(beta2), ctypes.c_float(eps), _stream(stream)))
