@@ -1,0 +1,199 @@
+"""Learned search window: data collection with the plain builder, training
+with the library's GPU kernels, calibration, and the plain-vs-learned
+comparison.  Orchestration only: every network and build computation runs in
+libkftrack's kernels.
+
+Data: for every candidate of the plain build whose hits so far are its
+track's true hits or holes, and whose track has a hit on the layer, one row
+of 27 features (predicted state and covariance) and the two labels (|arc| at
+the layer radius and |dz| from the prediction to the true hit).
+
+Training: asymmetric quantile loss (a missed true hit costs 20 times a unit
+of extra width), Adam on FP32 master weights, BF16 working weights.
+
+Calibration: the widths are multiplied by kappa >= 1, chosen on validation
+events as the smallest value whose build efficiency stays within the target
+of the plain window's; predictions below the floors fall back to the plain
+window (floors: one hit resolution, 0.01 cm arc and 0.1 cm in z).
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import kftrack as kf
+from . import presets, workloads
+
+DEV = "cuda:0"
+SCALE = np.array([0.01, 0.1])   # output scales: arc cm, z cm
+FLOOR = (0.01, 0.1)
+
+
+@dataclass
+class EventOnGPU:
+    eb: workloads.EventBatch
+    binned: kf.BinnedHits
+    seeds: dict
+    xyz: torch.Tensor
+    cov: torch.Tensor
+    hoff: torch.Tensor
+    sev: torch.Tensor
+
+
+def load_events(w, events, n_tracks=None) -> EventOnGPU:
+    eb = workloads.event_batch(w, events, n_tracks=n_tracks, seed_layers=3)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    xyz, cov, layer, hoff = T(eb.xyz), T(eb.cov), T(eb.layer), T(eb.hit_offsets)
+    binned = kf.hit_bin(w.geometry, w.cuts.n_phi_bins, w.cuts.n_z_bins, layer, xyz, cov, event_offsets=hoff)
+    seeds = kf.kf_seed(w.geometry, eb.n_seeds, T(eb.seed_hits))
+    return EventOnGPU(eb, binned, seeds, xyz, cov, hoff, T(eb.seed_event))
+
+
+def build(w, e: EventOnGPU, window_mode=0, block=None, counters=False, arith=kf.ARITH_F32):
+    bp = kf.build_params(w.cuts, window_mode=window_mode, mlp_block=block, arith=arith)
+    ex = kf.BuildExtra()
+    ex.seed_event = e.sev.data_ptr()
+    cnt = None
+    if counters:
+        cnt = torch.zeros(4, dtype=torch.int64, device=DEV)
+        ex.counters = cnt.data_ptr()
+    out = kf.kf_build(w.geometry, bp, e.binned, e.eb.n_seeds, e.seeds["par"], e.seeds["cov"], e.seeds["q"], extra=ex)
+    return out, cnt
+
+
+def efficiency(w, e: EventOnGPU, out) -> float:
+    """Fraction of seeds whose best candidate carries >= 75 % of its track's
+    hits on the searched layers."""
+    F = w.cuts.first_layer
+    n = e.eb.n_seeds
+    hits = out["hits"].cpu().numpy()[:, :n]
+    return float(np.mean((hits == e.eb.true_hits[F:, :n]).mean(axis=0) >= 0.75))
+
+
+def dump_rows(w, e: EventOnGPU, capacity=3_000_000) -> np.ndarray:
+    eb = e.eb
+    L = w.geometry.n_layers
+    n = eb.n_seeds
+    # true hit positions per seed and layer
+    txyz = np.zeros((L, 3, eb.ld), dtype=np.float32)
+    for l in range(L):
+        idx = eb.true_hits[l, :n].astype(np.int64) + eb.hit_offsets[eb.seed_event].astype(np.int64)
+        txyz[l, :, :n] = eb.xyz[:, idx]
+    th = torch.from_numpy(eb.true_hits).to(DEV)
+    tx = torch.from_numpy(txyz).to(DEV)
+    dump = torch.empty((capacity, kf.MLP_ROW), dtype=torch.float32, device=DEV)
+    cnt = torch.zeros(1, dtype=torch.int32, device=DEV)
+    bp = kf.build_params(w.cuts)
+    ex = kf.BuildExtra()
+    ex.seed_event = e.sev.data_ptr()
+    ex.true_hits = th.data_ptr()
+    ex.true_xyz = tx.data_ptr()
+    ex.dump = dump.data_ptr()
+    ex.dump_count = cnt.data_ptr()
+    ex.dump_capacity = capacity
+    kf.kf_build(w.geometry, bp, e.binned, n, e.seeds["par"], e.seeds["cov"], e.seeds["q"], extra=ex)
+    torch.cuda.synchronize()
+    k = min(int(cnt.item()), capacity)
+    rows = dump[:k].cpu().numpy()
+    # a deterministic order (the dump order depends on scheduling)
+    key = rows[:, 29].view(np.int32).astype(np.int64) * 4096 + rows[:, 30].view(np.int32) * 16 + \
+        rows[:, 31].view(np.int32)
+    return rows[np.argsort(key, kind="stable")]
+
+
+def init_master(rng):
+    W1 = rng.normal(0, np.sqrt(2.0 / 27), (64, 27))
+    W2 = rng.normal(0, np.sqrt(2.0 / 64), (64, 64))
+    W3 = rng.normal(0, np.sqrt(1.0 / 64), (2, 64))
+    p = {"W1": W1, "b1": np.zeros(64), "W2": W2, "b2": np.zeros(64), "W3": W3, "b3": np.zeros(2)}
+    m = kf.mlp_join(p).astype(np.float32)
+    # the master starts on BF16 values, so the working copy equals it
+    return (kf._bf16_bits(m).astype(np.uint32) << 16).view(np.float32).copy()
+
+
+def standardisation(rows):
+    x = rows[:, :27].astype(np.float64)
+    mu = x.mean(axis=0)
+    sd = x.std(axis=0)
+    sd[sd <= 0] = 1.0
+    return mu.astype(np.float32), sd.astype(np.float32)
+
+
+@dataclass
+class Trained:
+    master: torch.Tensor
+    block: torch.Tensor
+    mu: np.ndarray
+    sd: np.ndarray
+    losses: list
+    seconds: float
+    steps: int
+
+
+def train(rows: np.ndarray, epochs=4, batch=4096, lr=1e-3, seed=1711065715, log=None) -> Trained:
+    rng = np.random.default_rng(seed)
+    mu, sd = standardisation(rows)
+    master_np = init_master(rng)
+    block = kf.mlp_block(master_np, mu, sd, SCALE, kappa=1.0, floor_rphi=FLOOR[0], floor_z=FLOOR[1])
+    master = torch.from_numpy(master_np).to(DEV)
+    m = torch.zeros_like(master)
+    v = torch.zeros_like(master)
+    data = torch.from_numpy(np.ascontiguousarray(rows)).to(DEV)
+    n = data.shape[0]
+    grad = torch.empty(kf.MLP_NPARAM + 1, dtype=torch.float32, device=DEV)
+    ws = torch.empty(int(kf.lib().kf_mlp_grad_workspace_bytes(batch)) // 4 + 1, dtype=torch.float32, device=DEV)
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(seed)
+    losses = []
+    step = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=gen, device=DEV)
+        shuf = data[perm]
+        acc = torch.zeros((), dtype=torch.float32, device=DEV)
+        nb = n // batch
+        for b in range(nb):
+            chunk = shuf[b * batch:(b + 1) * batch]
+            kf.kf_mlp_grad(block, chunk, grad=grad, ws=ws)
+            step += 1
+            kf.kf_mlp_adam(block, master, m, v, grad, step, lr=lr)
+            acc += grad[-1]
+        losses.append(float(acc.item()) / max(nb, 1))
+        if log:
+            log(f"epoch {ep} loss {losses[-1]:.5f}")
+    torch.cuda.synchronize()
+    return Trained(master, block, mu, sd, losses, time.perf_counter() - t0, step)
+
+
+def calibrate(w, t: Trained, val: EventOnGPU, eff_plain: float, target=0.001, kappas=None):
+    """Smallest kappa whose efficiency on the validation events is within
+    `target` of the plain window's."""
+    kappas = kappas or [1.0, 1.1, 1.2, 1.35, 1.5, 1.75, 2.0, 2.5, 3.0]
+    res = []
+    for kap in kappas:
+        kf.mlp_set_header(t.block, kappa=kap)
+        out, _ = build(w, val, window_mode=1, block=t.block)
+        torch.cuda.synchronize()
+        eff = efficiency(w, val, out)
+        res.append((kap, eff))
+        if eff_plain - eff <= target:
+            return kap, res
+    return kappas[-1], res
+
+
+def time_build(w, e: EventOnGPU, window_mode, block=None, reps=5, arith=kf.ARITH_F32):
+    build(w, e, window_mode, block, arith=arith)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        build(w, e, window_mode, block, arith=arith)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))

@@ -1,0 +1,99 @@
+"""Learned search window: GPU training on rows dumped by the plain builder,
+parity of the learned build with the oracle's (same network, FP64), and the
+learned-vs-plain comparison at matched efficiency."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as omlp
+from paper_1711_06571_amd import datagen, presets
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from gpu_common import host, to_dev  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1711_06571_amd import kftrack as kf
+    from paper_1711_06571_amd import window
+    w = presets.learned()
+    tr = window.load_events(w, [0])
+    rows = window.dump_rows(w, tr)
+    t = window.train(rows, epochs=3)
+    return dict(kf=kf, window=window, w=w, rows=rows, t=t)
+
+
+def oracle_blob(kf, t, kappa):
+    p = kf.mlp_split(host(t.master))
+    blk = host(t.block)
+    isd = blk[27:54].astype(np.float64)
+    q = {k: v.astype(np.float64) for k, v in p.items()}
+    for k in ("W1", "W2", "W3"):  # the BF16 working weights
+        q[k] = omlp.bf16(q[k])
+    q["b1"], q["b2"], q["b3"] = blk[54:118].astype(np.float64), blk[118:182].astype(np.float64), \
+        blk[182:184].astype(np.float64)
+    q["mu"] = blk[0:27].astype(np.float64)
+    q["sd"] = 1.0 / isd
+    q["scale"] = blk[184:186].astype(np.float64)
+    return omlp.blob(q, kappa=kappa, floor_rphi=float(blk[187]), floor_z=float(blk[188]))
+
+
+def test_training_reduces_loss(env):
+    t = env["t"]
+    print("rows", env["rows"].shape[0], "losses", [round(v, 5) for v in t.losses], "seconds", round(t.seconds, 2))
+    assert env["rows"].shape[0] > 100_000
+    assert t.losses[-1] < 0.7 * t.losses[0]
+    # the row labels are what the dump says they are: offsets to the true hit
+    r = env["rows"]
+    assert np.all(r[:, 27] >= 0) and np.all(r[:, 28] >= 0)
+
+
+def test_learned_build_matches_oracle(env):
+    kf, window, w, t = env["kf"], env["window"], env["w"], env["t"]
+    kf.mlp_set_header(t.block, kappa=1.5)
+    ev = datagen.generate(w.geometry, w.gen, 50, 500)
+    n = ev.n_tracks
+    xyz = ev.xyz.astype(np.float32)
+    b = kf.hit_bin(w.geometry, 63, 16, to_dev(ev.layer), to_dev(xyz), to_dev(ev.cov.astype(np.float32)))
+    H = datagen.track_hits(ev)
+    sg = kf.kf_seed(w.geometry, n, to_dev(H))
+    bp = kf.build_params(w.cuts, window_mode=1, mlp_block=t.block, arith=kf.ARITH_F64)
+    out = kf.kf_build(w.geometry, bp, b, n, sg["par"], sg["cov"], sg["q"])
+    torch.cuda.synchronize()
+    g = {k: host(v) for k, v in out.items()}
+    so = oracle.seed(w.geometry, H, n)
+    o = oracle.build(w.geometry, w.cuts, ev.layer, ev.xyz, ev.cov, so["par"], so["cov"], so["q"], n,
+                     window_mode=1, mlp_blob=oracle_blob(kf, t, 1.5))
+    m = o["margin"]
+    # learned widths carry BF16 rounding of activations: window edges further
+    # than 1e-3 cm (a tenth of the arc resolution) decide
+    dec = (m[0] > 1e-3) & (m[1] > 1e-3) & (m[2] > 1e-3)
+    same = np.all(g["hits"][:, :n] == o["hits"], axis=0) & (g["nhits"][:n] == o["nhits"])
+    print(f"learned build: undecidable {1 - dec.mean():.4f}, identical {same.mean():.4f}")
+    assert same[dec].all(), np.where(dec & ~same)[0][:10]
+
+
+def test_learned_vs_plain(env):
+    kf, window, w, t = env["kf"], env["window"], env["w"], env["t"]
+    val = window.load_events(w, [1])
+    test = window.load_events(w, [2])
+    out_p, _ = window.build(w, val)
+    eff_plain_val = window.efficiency(w, val, out_p)
+    kap, trace = window.calibrate(w, t, val, eff_plain_val, target=0.001)
+    kf.mlp_set_header(t.block, kappa=kap)
+    outp, cp = window.build(w, test, counters=True)
+    outl, cl = window.build(w, test, window_mode=1, block=t.block, counters=True)
+    torch.cuda.synchronize()
+    ep, el = window.efficiency(w, test, outp), window.efficiency(w, test, outl)
+    tp = window.time_build(w, test, 0)
+    tl = window.time_build(w, test, 1, t.block)
+    cp, cl = host(cp), host(cl)
+    print(f"kappa {kap} (val trace {trace}); test eff plain {ep:.4f} learned {el:.4f}; "
+          f"hits tested per cand-layer plain {cp[1] / cp[0]:.2f} learned {cl[1] / cl[0]:.2f}; "
+          f"build ms plain {tp:.3f} learned {tl:.3f}")
+    assert ep - el <= 0.002  # calibrated on validation events to 0.1 %; test events disjoint
+    assert cl[1] <= cp[1]
