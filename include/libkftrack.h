@@ -262,6 +262,32 @@ int kf_gather_hits(int32_t n_layers, int32_t first_layer, int32_t n_seeds, int32
                    const int32_t* seed_event, int32_t n_events, const int32_t* event_offsets, int32_t n_hits,
                    const float* xyz, const float* cov, float* fit_hits, uint32_t* hole_mask, void* stream);
 
+/*
+ * Batched building as one replayable HIP graph (several events in flight,
+ * sections 4.2 and 4.3): kf_batch_plan_create captures hit_bin of all events
+ * and the persistent kf_build from `stream` (not the null stream) into a
+ * graph and instantiates it; every pointer and size is fixed at creation
+ * (contents may change between launches).  The captured work clears its own
+ * counters with kernels, so each launch is independent of the previous one.
+ * The arguments are those of hit_bin and kf_build; `binned` describes the
+ * sorted arrays that hit_bin writes (binned_offsets .. sorted_orig).
+ * kf_batch_plan_launch replays the graph on `stream`; kf_batch_plan_destroy
+ * frees the host-side graph objects.
+ */
+typedef struct kf_batch_plan kf_batch_plan;
+int kf_batch_plan_create(const kf_geometry* g, const kf_build_params* bp, int32_t n_events,
+                         const int32_t* event_offsets, int32_t n_hits, const int32_t* layer, const float* xyz,
+                         const float* cov, const kf_hits* binned, int32_t* binned_offsets, float* sorted_xyzphi,
+                         float* sorted_cov, int32_t* sorted_orig, void* bin_ws, size_t bin_ws_bytes,
+                         int32_t n_seeds, int32_t ld, const float* seed_par, const float* seed_cov, const int8_t* q,
+                         int32_t* out_hits, float* out_par, float* out_cov, float* out_chi2, int32_t* out_nhits,
+                         int32_t* out_status, const kf_build_extra* extra, void* build_ws, size_t build_ws_bytes,
+                         void* stream, kf_batch_plan** plan);
+int kf_batch_plan_launch(kf_batch_plan* plan, void* stream);
+int kf_batch_plan_destroy(kf_batch_plan* plan);
+/* frequency of the device wall clock read by the build's completion ticks */
+int kf_wall_clock_khz(int32_t* khz);
+
 #ifdef __cplusplus
 }
 #endif

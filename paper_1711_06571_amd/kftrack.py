@@ -87,6 +87,13 @@ def lib():
             L.hit_bin.argtypes = [ctypes.POINTER(Geometry), I, P, I, I, I, P, P, P, P, P, P, P, P, P,
                                   ctypes.c_size_t, P]
         L.kf_gather_hits.argtypes = [I, I, I, I, P, P, I, P, I, P, P, P, P, P]
+        L.kf_batch_plan_create.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(BuildParams), I, P, I, P, P, P,
+                                           ctypes.POINTER(Hits), P, P, P, P, P, ctypes.c_size_t, I, I, P, P, P, P, P,
+                                           P, P, P, P, ctypes.POINTER(BuildExtra), P, ctypes.c_size_t, P,
+                                           ctypes.POINTER(ctypes.c_void_p)]
+        L.kf_batch_plan_launch.argtypes = [P, P]
+        L.kf_batch_plan_destroy.argtypes = [P]
+        L.kf_wall_clock_khz.argtypes = [P]
         L.kf_mlp_block_bytes.restype = ctypes.c_size_t
         L.kf_mlp_grad_workspace_bytes.restype = ctypes.c_size_t
         L.kf_mlp_grad_workspace_bytes.argtypes = [I]
@@ -375,3 +382,66 @@ def kf_mlp_grad(block, rows, n=None, grad=None, ws=None, stream=None):
 def kf_mlp_adam(block, master, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     _check(lib().kf_mlp_adam(_ptr(block), _ptr(master), _ptr(m), _ptr(v), _ptr(grad), step, ctypes.c_float(lr),
                              ctypes.c_float(beta1), ctypes.c_float(beta2), ctypes.c_float(eps), _stream(stream)))
+
+
+# ------------------------------------------------------------ batched graph
+
+class BatchPlan:
+    """hit_bin + kf_build of a batch of events captured as one HIP graph.
+    Holds references to every buffer the graph uses."""
+
+    def __init__(self, g, bp, layer, xyz, cov, event_offsets, n_phi, n_z, n_seeds, seed_par, seed_cov, q,
+                 extra=None, stream=None):
+        dev = layer.device
+        n_hits = layer.shape[0]
+        E = event_offsets.shape[0] - 1
+        self.binned = BinnedHits(E, g.n_layers, n_phi, n_z, n_hits, dev)
+        self.bin_ws = torch.empty(max(hit_bin_workspace_bytes(E, g.n_layers, n_phi, n_z, n_hits), 1),
+                                  dtype=torch.uint8, device=dev)
+        self.build_ws = torch.empty(max(kf_build_workspace_bytes(n_seeds, E), 1), dtype=torch.uint8, device=dev)
+        ld = seed_par.shape[1]
+        F = bp.first_layer
+        self.out = dict(hits=torch.empty((g.n_layers - F, ld), dtype=torch.int32, device=dev),
+                        par=torch.empty((6, ld), dtype=torch.float32, device=dev),
+                        cov=torch.empty((21, ld), dtype=torch.float32, device=dev),
+                        chi2=torch.empty(ld, dtype=torch.float32, device=dev),
+                        nhits=torch.empty(ld, dtype=torch.int32, device=dev),
+                        status=torch.empty(ld, dtype=torch.int32, device=dev))
+        self._keep = (layer, xyz, cov, event_offsets, seed_par, seed_cov, q)
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.g = geometry(g)
+        self.bp = bp
+        self.extra = extra if extra is not None else BuildExtra()
+        self.hd = self.binned.descriptor()
+        h = ctypes.c_void_p()
+        b = self.binned
+        base = b.xyzphi
+        torch.cuda.synchronize()
+        _check(lib().kf_batch_plan_create(
+            ctypes.byref(self.g), ctypes.byref(self.bp), E, _ptr(event_offsets), n_hits, _ptr(layer), _ptr(xyz),
+            _ptr(cov), ctypes.byref(self.hd), _ptr(b.offsets), _ptr(base), _ptr(b.cov), _ptr(b.orig),
+            _ptr(self.bin_ws), ctypes.c_size_t(self.bin_ws.numel()), n_seeds, ld, _ptr(seed_par), _ptr(seed_cov),
+            _ptr(q), _ptr(self.out["hits"]), _ptr(self.out["par"]), _ptr(self.out["cov"]), _ptr(self.out["chi2"]),
+            _ptr(self.out["nhits"]), _ptr(self.out["status"]), ctypes.byref(self.extra), _ptr(self.build_ws),
+            ctypes.c_size_t(self.build_ws.numel()), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self):
+        _check(lib().kf_batch_plan_launch(self.handle, ctypes.c_void_p(self.stream.cuda_stream)))
+
+    def close(self):
+        if self.handle:
+            lib().kf_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def wall_clock_khz() -> int:
+    v = ctypes.c_int32()
+    _check(lib().kf_wall_clock_khz(ctypes.byref(v)))
+    return int(v.value)
