@@ -126,7 +126,8 @@ def main():
     binned = kf.BinnedHits(E, L, cuts.n_phi_bins, cuts.n_z_bins, xyz.shape[1], dev)
     ws_bin = torch.empty(kf.hit_bin_workspace_bytes(E, L, cuts.n_phi_bins, cuts.n_z_bins, xyz.shape[1]),
                          dtype=torch.uint8, device=dev)
-    ws_build = torch.empty(kf.kf_build_workspace_bytes(n, E), dtype=torch.uint8, device=dev)
+    ws_build = torch.empty(kf.kf_build_workspace_bytes(kf.build_params(cuts), binned, n), dtype=torch.uint8,
+                           device=dev)
     ld = seeds["par"].shape[1]
     bout = dict(hits=torch.empty((L - F, ld), dtype=torch.int32, device=dev),
                 par=torch.empty((6, ld), dtype=torch.float32, device=dev),

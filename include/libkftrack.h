@@ -155,16 +155,17 @@ int hit_bin(const kf_geometry* g, int32_t n_events, const int32_t* event_offsets
 typedef struct {
   float chi2_cut;      /* accept a hit iff chi2 < chi2_cut (2 degrees of freedom) */
   int32_t max_holes;   /* a hole child is added while holes < max_holes */
-  int32_t cand_cap;    /* candidates kept per seed, 1..8 (8 slots per seed; 4 when cap <= 4) */
+  int32_t cand_cap;    /* candidates kept per seed, 1..8 (one lane per candidate slot) */
   float nsigma;        /* plain window: nsigma * sqrt(S) per coordinate */
   float win_sig_rphi;  /* nominal hit resolution used in the window's S, cm */
   float win_sig_z;
   int32_t first_layer; /* first layer searched; seeds sit on first_layer - 1 */
   int32_t window_mode; /* 0 plain; 1 learned (mlp must point to a network block) */
   const void* mlp;     /* device pointer to the window network block (kf_mlp_block_bytes) */
-  int32_t lanes_per_block; /* 64, 128, 256 (0: 256) */
+  int32_t lanes_per_block; /* 64, 128, 256 (0: the widest whose LDS fits) */
   int32_t persistent_blocks; /* blocks of the persistent grid (0: CUs x resident blocks per CU) */
   int32_t arith;       /* KF_ARITH_F32 or KF_ARITH_F64 */
+  int32_t phi_refine;  /* sub-bins per phi bin of the fine index the hit search uses, 1..64 (0: 8) */
 } kf_build_params;
 
 /* Optional build inputs and outputs (all fields may be NULL / 0). */
@@ -188,12 +189,17 @@ typedef struct {
   uint64_t* counters;         /* [4] */
 } kf_build_extra;
 
-/* Workspace bytes for kf_build. */
-size_t kf_build_workspace_bytes(int32_t n_seeds, int32_t n_events);
+/*
+ * Workspace bytes for kf_build: a queue head, per-event counters and the
+ * fine phi index of every (event, layer, z row), n_phi * phi_refine + 1
+ * int32 each, rebuilt by every kf_build call from the binned hits.
+ * Returns 0 for a NULL or malformed descriptor.
+ */
+size_t kf_build_workspace_bytes(const kf_build_params* bp, const kf_hits* hits, int32_t n_seeds);
 
 /*
  * kf_build — combinatorial Kalman-filter building (sections 2, 3.1, 4.3),
- * one lane per candidate slot, eight slots per seed, one persistent launch
+ * one lane per candidate slot, cand_cap slots per seed, one persistent launch
  * over all seeds of all events (an atomic queue hands out groups of seeds).
  * For each seed, from its state on layer first_layer-1, layer by layer:
  *   1. predict every candidate (a failed crossing or |z| > z_half stops it);

@@ -1,9 +1,10 @@
 // Combinatorial Kalman-filter track building (sections 2, 3.1, 4.3).
 //
-// Layout of the work: one lane per candidate slot, S slots per seed
-// (S = 8, or 4 when cand_cap <= 4), 64/S seeds per wave.  One persistent
-// launch: each wave takes groups of 64/S seeds from an atomic queue until the
-// queue is empty, so uneven events and seeds balance across the chip.
+// Layout of the work: one lane per candidate slot, S = cand_cap consecutive
+// lanes per seed, floor(64 / S) seeds per wave (lanes beyond the last seed
+// idle).  One persistent launch: each wave takes groups of seeds from an
+// atomic queue until the queue is empty, so uneven events and seeds balance
+// across the chip.
 //
 // Per layer, per wave:
 //   1. every live slot predicts its candidate (FP32 or FP64 arithmetic);
@@ -51,6 +52,8 @@ struct BuildArgs {
   const float *hx, *hy, *hz, *hphi, *hcov;
   const int32_t* horig;
   int n_hits;
+  int refine;            // sub-bins per phi bin in the fine index
+  const int32_t* fine;   // [events][layers][n_z][n_phi * refine + 1]
   // seeds
   int n_seeds, ld, n_groups;
   const float *seed_par, *seed_cov;
@@ -88,20 +91,28 @@ __device__ inline double shfl_d(double v, int src) {
 __device__ inline float shfl_t(float v, int src) { return __shfl(v, src, 64); }
 __device__ inline double shfl_t(double v, int src) { return shfl_d(v, src); }
 
-// minimum over the S lanes of one seed (S a power of two <= 64)
-template <int S> __device__ inline uint64_t group_min(uint64_t k) {
-#pragma unroll
-  for (int m = 1; m < S; m <<= 1) {
-    uint32_t lo = __shfl_xor((uint32_t)k, m, 64), hi = __shfl_xor((uint32_t)(k >> 32), m, 64);
-    uint64_t o = ((uint64_t)hi << 32) | lo;
+// Reductions over the S lanes base .. base+S-1 of one seed (S <= 8, any
+// value).  The minimum doubles a rotation: after the steps 1, 2, 4 a lane
+// has seen the slots slot .. slot+7 (mod S), which covers the group.  Lanes
+// that hold no seed (used = false) only ever read themselves.
+__device__ inline int rot_lane(int base, int slot, int d, int S, bool used) {
+  const int t = slot + d;
+  return used ? base + (t >= S ? t - S : t) : base + slot;
+}
+__device__ inline uint64_t group_min(uint64_t k, int base, int slot, int S, bool used) {
+  for (int d = 1; d < S; d <<= 1) {
+    const uint64_t o = shfl_u64(k, rot_lane(base, slot, d, S, used));
     k = o < k ? o : k;
   }
   return k;
 }
-template <int S> __device__ inline int group_sum(int v) {
-#pragma unroll
-  for (int m = 1; m < S; m <<= 1) v += __shfl_xor(v, m, 64);
-  return v;
+__device__ inline int group_sum(int v, int base, int slot, int S, bool used) {
+  int acc = v;
+  for (int d = 1; d < S; ++d) {
+    const int o = __shfl(v, rot_lane(base, slot, d, S, used), 64);
+    acc += used ? o : 0;
+  }
+  return acc;
 }
 
 __device__ inline uint32_t chi2_bits(float c) {
@@ -121,72 +132,87 @@ __device__ inline float wrap_2pi(float p) {
   return p;
 }
 
-// first position in [lo, hi) with phi[pos] >= v (phi sorted ascending)
-__device__ inline int lower_bound_phi(const float* __restrict__ phi, int lo, int hi, float v) {
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (phi[mid] < v) lo = mid + 1; else hi = mid;
-  }
-  return lo;
+// Fine phi index of a z row: key(phi) = the sub-bin of a stored phi, with
+// n_phi * refine sub-bins over [0, 2 pi).  The stored phi of a row is
+// non-decreasing along the sorted order (hits are sorted by bin, then phi,
+// and rounding to FP32 keeps the order of the FP64 phi that set the bin), so
+// key is non-decreasing too and fine[j] = first position with key >= j
+// brackets every hit whose stored phi lies in an interval.
+__host__ __device__ inline int fine_key(float phi, float inv, int nf) {
+  const float t = floorf(phi * inv);
+  const int k = t > 0.f ? (int)t : 0;  // also maps NaN to 0
+  return k < nf - 1 ? k : nf - 1;
 }
+__host__ __device__ inline float fine_inv(int nf) { return (float)nf / 6.283185307179586f; }
 
-template <typename T, int CAPMAX> struct TopList {
-  T c2[CAPMAX];
-  int pos[CAPMAX];
-  uint32_t orig[CAPMAX];
+// A lane's accepted hits, best first (chi2 ascending, hit index ascending),
+// at most cap of them.  The entries live in LDS, [cap][64] per wave, so that
+// the list costs no registers; this lane's column starts at c2 / pos / orig.
+template <typename T> struct TopList {
+  T* c2;
+  int32_t* pos;
+  uint32_t* orig;
   int n;    // entries held (<= cap)
   int tot;  // accepted hits seen
   int scanned, tested;  // hits window-tested, hits given a chi2 (work counters)
 };
 
-template <typename T, int CAPMAX>
-__device__ inline void top_insert(TopList<T, CAPMAX>& tl, int cap, T c2, int pos, uint32_t orig) {
+template <typename T>
+__device__ inline bool top_before(T c2, uint32_t orig, T oc2, uint32_t oorig) {
+  return (float)c2 < (float)oc2 || ((float)c2 == (float)oc2 && orig < oorig);
+}
+
+template <typename T>
+__device__ inline void top_insert(TopList<T>& tl, int cap, T c2, int pos, uint32_t orig) {
   tl.tot += 1;
-  // insertion into the sorted list (chi2 asc, index asc), keeping cap entries
-  T cc = c2;
-  int pp = pos;
-  uint32_t oo = orig;
-  bool carry = true;
-#pragma unroll
-  for (int k = 0; k < CAPMAX; ++k) {
-    if (k < cap && carry) {
-      if (k >= tl.n) {
-        tl.c2[k] = cc; tl.pos[k] = pp; tl.orig[k] = oo;
-        carry = false;
-      } else {
-        const bool before = (float)cc < (float)tl.c2[k] || ((float)cc == (float)tl.c2[k] && oo < tl.orig[k]);
-        if (before) {
-          T t0 = tl.c2[k]; int t1 = tl.pos[k]; uint32_t t2 = tl.orig[k];
-          tl.c2[k] = cc; tl.pos[k] = pp; tl.orig[k] = oo;
-          cc = t0; pp = t1; oo = t2;
-        }
-      }
-    }
+  int j = tl.n;
+  if (j == cap) {  // full: the new hit must beat the last entry
+    if (!top_before(c2, orig, tl.c2[(cap - 1) * 64], tl.orig[(cap - 1) * 64])) return;
+    j = cap - 1;
+  } else {
+    tl.n += 1;
   }
-  if (tl.n < cap) tl.n += 1;
+  while (j > 0) {
+    const T pc = tl.c2[(j - 1) * 64];
+    const uint32_t po = tl.orig[(j - 1) * 64];
+    if (!top_before(c2, orig, pc, po)) break;
+    tl.c2[j * 64] = pc;
+    tl.pos[j * 64] = tl.pos[(j - 1) * 64];
+    tl.orig[j * 64] = po;
+    --j;
+  }
+  tl.c2[j * 64] = c2;
+  tl.pos[j * 64] = pos;
+  tl.orig[j * 64] = orig;
 }
 
-template <typename T, int CAPMAX>
-__device__ inline void top_get(const TopList<T, CAPMAX>& tl, int k, T& c2, int& pos, uint32_t& orig) {
-  c2 = tl.c2[0]; pos = tl.pos[0]; orig = tl.orig[0];
-#pragma unroll
-  for (int j = 1; j < CAPMAX; ++j)
-    if (j == k) { c2 = tl.c2[j]; pos = tl.pos[j]; orig = tl.orig[j]; }
+template <typename T>
+__device__ inline void top_get(const TopList<T>& tl, int k, T& c2, int& pos, uint32_t& orig) {
+  c2 = tl.c2[k * 64];
+  pos = tl.pos[k * 64];
+  orig = tl.orig[k * 64];
 }
 
-// Scan one phi-sorted range [b0, b1) of hit positions restricted to stored
-// phi in [plo, phi_hi], testing each hit exactly and collecting children.
-template <typename T, int CAPMAX>
-__device__ inline void scan_range(const BuildArgs& A, int b0, int b1, float plo, float phi_hi, const T Xp[6],
-                                  const T Pp[21], T dphi_w, T dz_w, TopList<T, CAPMAX>& tl) {
-  int p = lower_bound_phi(A.hphi, b0, b1, plo);
-  for (; p < b1; ++p) {
-    if (A.hphi[p] > phi_hi) break;
+// Test the hits at sorted positions [p0, p1) whose stored phi lies in
+// [a, b]: exact window test, then chi2; accepted hits become children.  The
+// position, phi and x, y, z of the next hit are loaded one hit ahead.
+template <typename T>
+__device__ inline void scan_range(const BuildArgs& A, int p0, int p1, float a, float b, const T Xp[6],
+                                  const T Pp[21], T dphi_w, T dz_w, TopList<T>& tl) {
+  if (p0 >= p1) return;
+  float nph = A.hphi[p0], nx = A.hx[p0], ny = A.hy[p0], nz = A.hz[p0];
+  for (int p = p0; p < p1; ++p) {
+    const float ph = nph, fx = nx, fy = ny, fz = nz;
+    if (p + 1 < p1) {
+      nph = A.hphi[p + 1]; nx = A.hx[p + 1]; ny = A.hy[p + 1]; nz = A.hz[p + 1];
+    }
+    if (ph < a) continue;
+    if (ph > b) break;
     tl.scanned += 1;
-    const T hx = (T)A.hx[p], hy = (T)A.hy[p], hz = (T)A.hz[p];
+    const T hx = (T)fx, hy = (T)fy, hz = (T)fz;
+    if (!(fabs(hz - Xp[2]) <= dz_w)) continue;
     const T cr = Xp[0] * hy - Xp[1] * hx, dt = Xp[0] * hx + Xp[1] * hy;
-    const T dph = k_atan2(cr, dt);
-    if (!(fabs(dph) <= dphi_w) || !(fabs(hz - Xp[2]) <= dz_w)) continue;
+    if (!(fabs(k_atan2(cr, dt)) <= dphi_w)) continue;
     T V[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) V[c] = (T)A.hcov[(size_t)c * A.n_hits + p];
@@ -199,14 +225,16 @@ __device__ inline void scan_range(const BuildArgs& A, int b0, int b1, float plo,
   }
 }
 
-template <typename T, int CAPMAX>
+template <typename T>
 __device__ inline void scan_window(const BuildArgs& A, int ev, int l, const T Xp[6], const T Pp[21], T dphi_w,
-                                   T dz_w, TopList<T, CAPMAX>& tl) {
-  const int nphi = A.n_phi, nz = A.n_z, nb = nphi * nz;
-  const int32_t* off = A.offsets + ((size_t)ev * A.n_layers + l) * (nb + 1);
+                                   T dz_w, TopList<T>& tl) {
+  const int nz = A.n_z, nf = A.n_phi * A.refine;
+  const int32_t* frow = A.fine + ((size_t)ev * A.n_layers + l) * nz * (nf + 1);
+  const float inv = fine_inv(nf);
   const float zh = A.z_half;
   const float zp = (float)Xp[2];
-  const float phip = wrap_2pi((float)k_atan2(Xp[1], Xp[0]));
+  const float phip = wrap_2pi(atan2f((float)Xp[1], (float)Xp[0]));  // centre of the conservative interval
+  // conservative stored-value intervals: the exact test decides
   const float eps_phi = 1e-5f, eps_z = 1e-4f;
   const float dphi = (float)dphi_w + eps_phi, dz = (float)dz_w + eps_z;
   int iz0 = (int)floorf((zp - dz + zh) * (float)nz / (2.f * zh));
@@ -224,14 +252,12 @@ __device__ inline void scan_window(const BuildArgs& A, int ev, int l, const T Xp
     else { a0 = lo; b0v = hi; }
   }
   for (int iz = iz0; iz <= iz1; ++iz) {
+    const int32_t* f = frow + (size_t)iz * (nf + 1);
     for (int part = 0; part < 2; ++part) {
       const float a = part ? a1 : a0, b = part ? b1v : b0v;
       if (!(a <= b)) continue;
-      int ip0 = (int)floorf(a * (float)nphi / tp), ip1 = (int)floorf(b * (float)nphi / tp);
-      ip0 = ip0 < 0 ? 0 : (ip0 > nphi - 1 ? nphi - 1 : ip0);
-      ip1 = ip1 < 0 ? 0 : (ip1 > nphi - 1 ? nphi - 1 : ip1);
-      const int p0 = off[iz * nphi + ip0], p1 = off[iz * nphi + ip1 + 1];
-      scan_range<T, CAPMAX>(A, p0, p1, a, b, Xp, Pp, dphi_w, dz_w, tl);
+      const int p0 = f[fine_key(a, inv, nf)], p1 = f[fine_key(b, inv, nf) + 1];
+      scan_range<T>(A, p0, p1, a, b, Xp, Pp, dphi_w, dz_w, tl);
     }
   }
 }
@@ -240,26 +266,63 @@ __device__ inline uint32_t pack_hist(int parent, uint32_t orig24) {
   return ((uint32_t)parent << 24) | (orig24 == kHoleIdx ? 0xFFFFFFu : orig24);
 }
 
-template <typename T, int S>
+// LDS of one block (byte offsets), per wave:
+//   history  [LB][64] u32      back-pointers (parent slot << 24 | hit index)
+//   stash    [27][64] f32      each slot's state before this layer's prediction
+//   record   [SEEDS][27] f32   best finished candidate of each seed
+//   recfield [SEEDS][5] i32    valid, nhits, status, last layer, slot
+//   toplist  [cap][64] T, then [cap][64] i32 positions, [cap][64] u32 indices
+//   mlp      activation buffer of the learned window (the network runs before
+//            the hit search, so the toplists of a learned build live in it)
+struct LdsPlan {
+  size_t hist, stash, rec, recf, tl, tl_stride, mlp, total;
+};
+__host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+__host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsize, bool learned) {
+  const int seeds = 64 / cap;
+  LdsPlan p;
+  p.hist = 0;
+  p.stash = align16(p.hist + (size_t)nwaves * LB * 64 * 4);
+  p.rec = align16(p.stash + (size_t)nwaves * 27 * 64 * 4);
+  p.recf = align16(p.rec + (size_t)nwaves * seeds * 27 * 4);
+  const size_t tl_wave = (size_t)cap * 64 * (tsize + 8);
+  p.tl = align16(p.recf + (size_t)nwaves * seeds * 5 * 4);
+  if (learned) {
+    const size_t per = tl_wave > KFMLP_LDS_BYTES ? tl_wave : (size_t)KFMLP_LDS_BYTES;
+    p.mlp = p.tl;
+    p.total = p.mlp + (size_t)nwaves * per;
+    p.tl_stride = per;
+  } else {
+    p.mlp = p.total = align16(p.tl + (size_t)nwaves * tl_wave);
+    p.tl_stride = tl_wave;
+  }
+  return p;
+}
+
+template <typename T, bool LEARNED>
 __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
-  constexpr int CAPMAX = S;
-  constexpr int SEEDS = 64 / S;
+  const int S = A.cap;           // lanes per seed
+  const int SEEDS = 64 / S;      // seeds per wave
   extern __shared__ __align__(16) uint32_t lds[];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
   const int LB = A.n_layers - A.first_layer;  // searched layers
-  // LDS: history [waves][LB][64] u32 | record states [waves][SEEDS][27] T |
-  //      record fields [waves][SEEDS][5] i32 (valid, nhits, status, last layer, slot)
-  uint32_t* hist = lds + (size_t)wave * LB * 64;
-  const size_t hist_words = (size_t)nwaves * LB * 64;
-  const size_t fin_off = (hist_words * 4 + 15) & ~(size_t)15;
-  T* fin = (T*)((char*)lds + fin_off) + (size_t)wave * SEEDS * 27;
-  int32_t* finm = (int32_t*)((char*)lds + fin_off + (size_t)nwaves * SEEDS * 27 * sizeof(T)) + (size_t)wave * SEEDS * 5;
-  const size_t mlp_off = (fin_off + (size_t)nwaves * SEEDS * 27 * sizeof(T) + (size_t)nwaves * SEEDS * 5 * 4 + 15) &
-                         ~(size_t)15;
-  uint16_t* mlp_buf = (uint16_t*)((char*)lds + mlp_off) + (size_t)wave * (KFMLP_LDS_BYTES / 2);
-  const int sidx = lane / S, slot = lane % S, sbase = sidx * S;
+  const LdsPlan lp = lds_plan(LB, nwaves, S, (int)sizeof(T), LEARNED);
+  char* base = (char*)lds;
+  uint32_t* hist = (uint32_t*)(base + lp.hist) + (size_t)wave * LB * 64;
+  float* stash = (float*)(base + lp.stash) + (size_t)wave * 27 * 64;
+  float* fin = (float*)(base + lp.rec) + (size_t)wave * SEEDS * 27;
+  int32_t* finm = (int32_t*)(base + lp.recf) + (size_t)wave * SEEDS * 5;
+  // per wave: the network buffer, or (after the network has run) the toplists
+  char* wave_tl = base + lp.tl + (size_t)wave * lp.tl_stride;
+  uint16_t* mlp_buf = (uint16_t*)wave_tl;
+  T* tl_c2 = (T*)wave_tl + lane;
+  int32_t* tl_pos = (int32_t*)(wave_tl + (size_t)S * 64 * sizeof(T)) + lane;
+  uint32_t* tl_orig = (uint32_t*)(wave_tl + (size_t)S * 64 * (sizeof(T) + 4)) + lane;
+  (void)mlp_buf;
+  const int sidx = lane / S, slot = lane - (lane / S) * S, sbase = sidx * S;
+  const bool lane_used = sidx < SEEDS;
 
   if (A.start_tick && lane == 0) atomicMin((unsigned long long*)A.start_tick, (unsigned long long)wall_clock64());
 
@@ -269,7 +332,7 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
     grp = __shfl(grp, 0, 64);
     if (grp >= A.n_groups) break;
     const int gi = grp * SEEDS + sidx;
-    int seed = gi < A.n_seeds ? (A.seed_order ? A.seed_order[gi] : gi) : -1;
+    int seed = (lane_used && gi < A.n_seeds) ? (A.seed_order ? A.seed_order[gi] : gi) : -1;
     int ev = (seed >= 0 && seed < A.n_seeds && A.seed_event) ? A.seed_event[seed] : 0;
     // caller-supplied indices outside their ranges: the seed is skipped
     const bool seed_ok = seed >= 0 && seed < A.n_seeds && ev >= 0 && ev < A.n_events;
@@ -286,14 +349,14 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
     bool ontrack = true;
     int n_active = seed_ok ? 1 : 0;
     int seed_status = 0;
-    if (slot == 0) finm[sidx * 5 + 0] = 0;
+    if (lane_used && slot == 0) finm[sidx * 5 + 0] = 0;
     if (seed_ok && !(all_finite(X, 6) && all_finite(P, 21))) {
       // non-finite seed: it is its own (finished) result
       if (slot == 0) {
         finm[sidx * 5 + 0] = 1; finm[sidx * 5 + 1] = 0; finm[sidx * 5 + 2] = KF_NONFINITE;
         finm[sidx * 5 + 3] = A.first_layer - 1; finm[sidx * 5 + 4] = 0;
-        for (int k = 0; k < 6; ++k) fin[sidx * 27 + k] = X[k];
-        for (int k = 0; k < 21; ++k) fin[sidx * 27 + 6 + k] = P[k];
+        for (int k = 0; k < 6; ++k) fin[sidx * 27 + k] = (float)X[k];
+        for (int k = 0; k < 21; ++k) fin[sidx * 27 + 6 + k] = (float)P[k];
       }
       n_active = 0;
     }
@@ -305,27 +368,36 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
       if (!__any(n_active > 0)) break;
       last_l = l;
       const bool live = slot < n_active;
+      // the state before prediction is kept (in the output precision) for
+      // the finished record, so it need not stay in registers
+      if (live) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) stash[k * 64 + lane] = (float)X[k];
+#pragma unroll
+        for (int k = 0; k < 21; ++k) stash[(6 + k) * 64 + lane] = (float)P[k];
+      }
       T Xp[6], Pp[21];
       int rc = 1;
       if (live)
         rc = predict<T>(X, P, q, (T)A.r[l], (T)A.bz, (T)A.z_half, (T)A.x_over_x0, (T)A.mass, Xp, Pp);
       else {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) Xp[k] = X[k];
+        for (int k = 0; k < 6; ++k) Xp[k] = T(0);
 #pragma unroll
-        for (int k = 0; k < 21; ++k) Pp[k] = P[k];
+        for (int k = 0; k < 21; ++k) Pp[k] = T(0);
       }
       const bool pok = live && rc == 0;
-      TopList<T, CAPMAX> tl;
+      TopList<T> tl;
+      tl.c2 = tl_c2;
+      tl.pos = tl_pos;
+      tl.orig = tl_orig;
       tl.n = 0;
       tl.tot = 0;
       tl.scanned = 0;
       tl.tested = 0;
-#pragma unroll
-      for (int k = 0; k < CAPMAX; ++k) { tl.c2[k] = 0; tl.pos[k] = 0; tl.orig[k] = 0; }
       // learned window: the whole wave evaluates the network on its 64 slots
       float wl[2] = {0.f, 0.f};
-      if (A.window_mode == 1) {
+      if constexpr (LEARNED) {
         float feat[27];
 #pragma unroll
         for (int k = 0; k < 6; ++k) feat[k] = pok ? (float)Xp[k] : 0.f;
@@ -344,7 +416,7 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
                       (T)A.win_sig_rphi * (T)A.win_sig_rphi;
         const T Sww = Pp[ut(2, 2)] + (T)A.win_sig_z * (T)A.win_sig_z;
         T w_rphi = (T)A.nsigma * k_sqrt(Suu), w_z = (T)A.nsigma * k_sqrt(Sww);
-        if (A.window_mode == 1) {
+        if constexpr (LEARNED) {
           if (!(wl[0] < A.mlp[KFMLP_OFF_FLOOR])) w_rphi = (T)wl[0];
           if (!(wl[1] < A.mlp[KFMLP_OFF_FLOOR + 1])) w_z = (T)wl[1];
         }
@@ -368,7 +440,7 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
             }
           }
         }
-        scan_window<T, CAPMAX>(A, ev, l, Xp, Pp, w_rphi / R, w_z, tl);
+        scan_window<T>(A, ev, l, Xp, Pp, w_rphi / R, w_z, tl);
       }
       cnt_pred += live ? 1u : 0u;
       cnt_scan += (unsigned)tl.scanned;
@@ -379,7 +451,7 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
       {
         const bool stopped = live && nchild == 0;
         uint64_t fk = stopped ? make_key(nhits, (float)chi2, slot, 0) : kInfKey;
-        const uint64_t best = group_min<S>(fk);
+        const uint64_t best = group_min(fk, sbase, slot, S, lane_used);
         if (best != kInfKey) {
           const int ws = (int)((best >> 24) & 7);
           const int wl_ = sbase + ws;
@@ -393,8 +465,7 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
           const bool take = !fvalid || wn > fn || (wn == fn && wc2 < fc2);
           if (take) {
             if (slot == ws) {
-              for (int k = 0; k < 6; ++k) fin[sidx * 27 + k] = X[k];
-              for (int k = 0; k < 21; ++k) fin[sidx * 27 + 6 + k] = P[k];
+              for (int k = 0; k < 27; ++k) fin[sidx * 27 + k] = stash[k * 64 + lane];
               finm[sidx * 5 + 0] = 1; finm[sidx * 5 + 1] = wn; finm[sidx * 5 + 2] = wst;
               finm[sidx * 5 + 3] = l - 1; finm[sidx * 5 + 4] = ws;
             }
@@ -403,7 +474,7 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
         }
       }
       // merge the children of the seed, best first, into slots 0..cap-1
-      const int tot = group_sum<S>(nchild);
+      const int tot = group_sum(nchild, sbase, slot, S, lane_used);
       if (tot > A.cap) seed_status |= KF_CAP_TRUNC;
       int ptr = 0;
       bool hole_left = hole_ok;
@@ -424,7 +495,7 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
             key = make_key(nhits, (float)chi2, slot, kHoleIdx);
           }
         }
-        const uint64_t win = group_min<S>(key);
+        const uint64_t win = group_min(key, sbase, slot, S, lane_used);
         if (win == kInfKey) continue;  // no more children for this seed
         const int ws = (int)((win >> 24) & 7);
         const int wl_ = sbase + ws;
@@ -492,7 +563,7 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
     {
       const bool act = slot < n_active;
       const uint64_t k = act ? make_key(nhits, (float)chi2, slot, 0) : kInfKey;
-      const uint64_t best = group_min<S>(k);
+      const uint64_t best = group_min(k, sbase, slot, S, lane_used);
       int bslot = -1;
       T bc2 = 0;
       int bn = 0;
@@ -505,8 +576,8 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
         (void)__shfl(nhits, sbase, 64);
       }
       const T fc2 = shfl_t(fin_chi2_reg, sbase);
-      const int fvalid = finm[sidx * 5 + 0];
-      const int fn = finm[sidx * 5 + 1];
+      const int fvalid = lane_used ? finm[sidx * 5 + 0] : 0;
+      const int fn = lane_used ? finm[sidx * 5 + 1] : 0;
       const bool use_fin = fvalid && (bslot < 0 || fn > bn || (fn == bn && fc2 < bc2));
       if (seed_ok) {
         // state: the best lane writes its own; slot 0 writes the record
@@ -518,8 +589,8 @@ __global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
           A.out_status[seed] = seed_status;
         }
         if (use_fin && slot == 0) {
-          for (int k2 = 0; k2 < 6; ++k2) A.out_par[(size_t)k2 * A.ld + seed] = (float)fin[sidx * 27 + k2];
-          for (int k2 = 0; k2 < 21; ++k2) A.out_cov[(size_t)k2 * A.ld + seed] = (float)fin[sidx * 27 + 6 + k2];
+          for (int k2 = 0; k2 < 6; ++k2) A.out_par[(size_t)k2 * A.ld + seed] = fin[sidx * 27 + k2];
+          for (int k2 = 0; k2 < 21; ++k2) A.out_cov[(size_t)k2 * A.ld + seed] = fin[sidx * 27 + 6 + k2];
           A.out_chi2[seed] = (float)fin_chi2_reg;
           A.out_nhits[seed] = fn;
           A.out_status[seed] = finm[sidx * 5 + 2] | seed_status;
@@ -554,39 +625,74 @@ __global__ void build_clear(int32_t* queue, int32_t* event_done, int n_events, i
   for (int e = i; e < n_events; e += gridDim.x * blockDim.x) event_done[e] = 0;
 }
 
-size_t lds_bytes(int LB, int nwaves, int S, size_t tsize, bool learned) {
-  const int seeds = 64 / S;
-  const size_t fin_off = ((size_t)nwaves * LB * 64 * 4 + 15) & ~(size_t)15;
-  const size_t end = fin_off + (size_t)nwaves * seeds * 27 * tsize + (size_t)nwaves * seeds * 5 * 4;
-  if (!learned) return end;
-  return ((end + 15) & ~(size_t)15) + (size_t)nwaves * KFMLP_LDS_BYTES;
+// Fine phi index: one wave per (event, layer, z row).  Entry j of the row is
+// the first sorted position whose key is >= j (the row's end if none).
+__global__ void __launch_bounds__(256) fine_kernel(int n_rows, int n_phi, int n_z, int nf,
+                                                   const int32_t* __restrict__ offsets,
+                                                   const float* __restrict__ phi, int32_t* __restrict__ fine) {
+  const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n_rows) return;
+  const int nb = n_phi * n_z;
+  const int el = row / n_z, iz = row % n_z;
+  const int32_t* off = offsets + (size_t)el * (nb + 1);
+  const int rs = off[iz * n_phi], re = off[(iz + 1) * n_phi];
+  int32_t* f = fine + (size_t)row * (nf + 1);
+  const float inv = fine_inv(nf);
+  for (int p = rs + lane; p < re; p += 64) {
+    const int k = fine_key(phi[p], inv, nf);
+    const int kp = p > rs ? fine_key(phi[p - 1], inv, nf) : -1;
+    for (int j = kp + 1; j <= k; ++j) f[j] = p;
+  }
+  const int kl = re > rs ? fine_key(phi[re - 1], inv, nf) : -1;
+  for (int j = kl + 1 + lane; j <= nf; j += 64) f[j] = re;
 }
 
-template <typename T, int S>
+size_t fine_bytes(int n_events, int n_layers, int n_phi, int n_z, int refine) {
+  return (size_t)n_events * n_layers * n_z * ((size_t)n_phi * refine + 1) * 4;
+}
+
+int refine_of(const kf_build_params* bp) { return bp->phi_refine > 0 ? bp->phi_refine : 8; }
+
+template <typename T, bool LEARNED>
 int launch(const BuildArgs& A, int lanes, int blocks, hipStream_t s) {
+  const int LB = A.n_layers - A.first_layer;
+  int dev = 0, max_lds = 0;
+  if (kf_check(hipGetDevice(&dev))) return KF_E_HIP;
+  if (kf_check(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev))) return KF_E_HIP;
+  auto plan = [&](int ln) { return lds_plan(LB, ln / 64, A.cap, (int)sizeof(T), LEARNED).total; };
+  if (lanes == 0) {  // automatic: the widest block whose LDS fits
+    lanes = 256;
+    while (lanes > 64 && plan(lanes) > (size_t)max_lds) lanes /= 2;
+  }
   const int nwaves = lanes / 64;
-  const size_t lds = lds_bytes(A.n_layers - A.first_layer, nwaves, S, sizeof(T), A.window_mode == 1);
-  if (lds > 64 * 1024) return KF_E_UNSUPPORTED;
+  const size_t lds = plan(lanes);
+  if (lds > (size_t)max_lds) return KF_E_UNSUPPORTED;
+  if (lds > (size_t)64 * 1024 &&
+      kf_check(hipFuncSetAttribute((const void*)build_kernel<T, LEARNED>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)))
+    return KF_E_HIP;
   if (blocks <= 0) {
-    int dev = 0, cus = 0, per = 0;
-    if (kf_check(hipGetDevice(&dev))) return KF_E_HIP;
+    int cus = 0, per = 0;
     if (kf_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev))) return KF_E_HIP;
-    if (kf_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, build_kernel<T, S>, lanes, lds))) return KF_E_HIP;
+    if (kf_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, build_kernel<T, LEARNED>, lanes, lds)))
+      return KF_E_HIP;
     blocks = cus * (per > 0 ? per : 1);
   }
   const int need = (A.n_groups + nwaves - 1) / nwaves;
   if (blocks > need) blocks = need;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL((build_kernel<T, S>), dim3(blocks), dim3(lanes), lds, s, A);
+  hipLaunchKernelGGL((build_kernel<T, LEARNED>), dim3(blocks), dim3(lanes), lds, s, A);
   return kf_check_launch();
 }
 
 }  // namespace
 
-extern "C" size_t kf_build_workspace_bytes(int32_t n_seeds, int32_t n_events) {
+extern "C" size_t kf_build_workspace_bytes(const kf_build_params* bp, const kf_hits* hits, int32_t n_seeds) {
   (void)n_seeds;
-  if (n_events < 1) n_events = 1;
-  return 256 + (((size_t)n_events * 4 + 255) & ~(size_t)255);
+  if (!bp || !hits || hits->n_events < 1 || hits->n_layers < 1 || hits->n_phi < 1 || hits->n_z < 1) return 0;
+  const size_t head = 256 + (((size_t)hits->n_events * 4 + 255) & ~(size_t)255);
+  return head + fine_bytes(hits->n_events, hits->n_layers, hits->n_phi, hits->n_z, refine_of(bp));
 }
 
 extern "C" int kf_build(const kf_geometry* g, const kf_build_params* bp, const kf_hits* hits, int32_t n_seeds,
@@ -600,6 +706,7 @@ extern "C" int kf_build(const kf_geometry* g, const kf_build_params* bp, const k
       !(bp->win_sig_z > 0.f))
     return KF_E_INVALID_ARG;
   if (bp->cand_cap > 8) return KF_E_UNSUPPORTED;
+  if (bp->phi_refine < 0 || bp->phi_refine > 64) return KF_E_INVALID_ARG;
   if (bp->arith != KF_ARITH_F32 && bp->arith != KF_ARITH_F64) return KF_E_INVALID_ARG;
   if (bp->window_mode != 0 && bp->window_mode != 1) return KF_E_INVALID_ARG;
   if (bp->window_mode == 1 && !bp->mlp) return KF_E_INVALID_ARG;
@@ -617,10 +724,12 @@ extern "C" int kf_build(const kf_geometry* g, const kf_build_params* bp, const k
   if (hits->n_events > 1 && !ex.seed_event) return KF_E_INVALID_ARG;
   if (ex.event_done_ticks && !ex.event_n_seeds) return KF_E_INVALID_ARG;
   if (ex.dump && (!ex.dump_count || !ex.true_hits || !ex.true_xyz || ex.dump_capacity < 0)) return KF_E_INVALID_ARG;
-  const size_t need = kf_build_workspace_bytes(n_seeds, hits->n_events);
+  const int refine = refine_of(bp);
+  if ((int64_t)hits->n_phi * refine > (1 << 20)) return KF_E_UNSUPPORTED;
+  const size_t need = kf_build_workspace_bytes(bp, hits, n_seeds);
   if (!ws || ws_bytes < need) return KF_E_WORKSPACE;
-  int lanes = bp->lanes_per_block ? bp->lanes_per_block : 256;
-  if (lanes != 64 && lanes != 128 && lanes != 256) return KF_E_UNSUPPORTED;
+  const int lanes = bp->lanes_per_block;
+  if (lanes != 0 && lanes != 64 && lanes != 128 && lanes != 256) return KF_E_UNSUPPORTED;
 
   BuildArgs A;
   A.n_layers = g->n_layers;
@@ -632,8 +741,10 @@ extern "C" int kf_build(const kf_geometry* g, const kf_build_params* bp, const k
   A.n_events = hits->n_events; A.n_phi = hits->n_phi; A.n_z = hits->n_z; A.offsets = hits->offsets;
   A.hx = hits->x; A.hy = hits->y; A.hz = hits->z; A.hphi = hits->phi; A.hcov = hits->cov; A.horig = hits->orig;
   A.n_hits = hits->n_hits;
-  const int S = bp->cand_cap <= 4 ? 4 : 8;
-  const int seeds_per_wave = 64 / S;
+  A.refine = refine;
+  const size_t fine_off = 256 + (((size_t)hits->n_events * 4 + 255) & ~(size_t)255);
+  A.fine = (const int32_t*)((char*)ws + fine_off);
+  const int seeds_per_wave = 64 / bp->cand_cap;
   A.n_seeds = n_seeds; A.ld = ld; A.n_groups = (n_seeds + seeds_per_wave - 1) / seeds_per_wave;
   A.seed_par = seed_par; A.seed_cov = seed_cov; A.q = q;
   A.seed_event = ex.seed_event; A.seed_order = ex.seed_order;
@@ -648,9 +759,15 @@ extern "C" int kf_build(const kf_geometry* g, const kf_build_params* bp, const k
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(build_clear, dim3(1), dim3(256), 0, s, A.queue, A.event_done, hits->n_events, A.start_tick);
   if (int rc = kf_check_launch()) return rc;
+  {
+    const int n_rows = hits->n_events * hits->n_layers * hits->n_z;
+    hipLaunchKernelGGL(fine_kernel, dim3((n_rows + 3) / 4), dim3(256), 0, s, n_rows, hits->n_phi, hits->n_z,
+                       hits->n_phi * refine, hits->offsets, hits->phi, (int32_t*)A.fine);
+    if (int rc = kf_check_launch()) return rc;
+  }
   if (bp->arith == KF_ARITH_F64)
-    return S == 4 ? launch<double, 4>(A, lanes, bp->persistent_blocks, s)
-                  : launch<double, 8>(A, lanes, bp->persistent_blocks, s);
-  return S == 4 ? launch<float, 4>(A, lanes, bp->persistent_blocks, s)
-                : launch<float, 8>(A, lanes, bp->persistent_blocks, s);
+    return bp->window_mode == 1 ? launch<double, true>(A, lanes, bp->persistent_blocks, s)
+                                : launch<double, false>(A, lanes, bp->persistent_blocks, s);
+  return bp->window_mode == 1 ? launch<float, true>(A, lanes, bp->persistent_blocks, s)
+                              : launch<float, false>(A, lanes, bp->persistent_blocks, s);
 }

@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(256) seed_kernel(GeomK g, int n, int ld, const
 // Fit: one lane per track, layers looped in registers.  Storage is FP32;
 // T is the arithmetic type (float, or double for the precise mode).
 template <typename T>
-__global__ void __launch_bounds__(256) fit_kernel(GeomK g, int n, int ld, int first_layer,
+__global__ void __launch_bounds__(256, (sizeof(T) == 8 ? 2 : 1)) fit_kernel(GeomK g, int n, int ld, int first_layer,
                                                   const float* __restrict__ hits,
                                                   const uint32_t* __restrict__ hole_mask,
                                                   const float* seed_par, const float* seed_cov,
@@ -139,11 +139,11 @@ __global__ void __launch_bounds__(256) fit_kernel(GeomK g, int n, int ld, int fi
   int st = (all_finite(X, 6) && all_finite(P, 21)) ? 0 : KF_NONFINITE;
   for (int l = first_layer; l < g.n_layers && !st; ++l) {
     const bool use = !((holes >> l) & 1u);
-    T hv[9];
+    float hv[9];  // kept in the storage type until the update
     if (use) {
       const float* hl = hits + (size_t)l * 9 * ld + i;
 #pragma unroll
-      for (int c = 0; c < 9; ++c) hv[c] = (T)__builtin_nontemporal_load(hl + (size_t)c * ld);
+      for (int c = 0; c < 9; ++c) hv[c] = __builtin_nontemporal_load(hl + (size_t)c * ld);
       if (!all_finite(hv, 9)) { st = KF_NONFINITE; break; }
     }
     T Xp[6], Pp[21];
@@ -151,8 +151,8 @@ __global__ void __launch_bounds__(256) fit_kernel(GeomK g, int n, int ld, int fi
     if (rc) { st = rc; break; }
     if (use) {
       Innov<T> in;
-      const T V[6] = {hv[3], hv[4], hv[5], hv[6], hv[7], hv[8]};
-      if (innovation<T>(Xp, Pp, hv[0], hv[1], hv[2], V, in)) { st = KF_S_NOT_PD; break; }
+      const T V[6] = {(T)hv[3], (T)hv[4], (T)hv[5], (T)hv[6], (T)hv[7], (T)hv[8]};
+      if (innovation<T>(Xp, Pp, (T)hv[0], (T)hv[1], (T)hv[2], V, in)) { st = KF_S_NOT_PD; break; }
       const T c2 = chi2_of(in);
       apply_update<T>(Xp, Pp, in);
       if (!(all_finite(Xp, 6) && all_finite(Pp, 21) && k_finite(c2))) { st = KF_NONFINITE; break; }

@@ -13,7 +13,9 @@
 //   - the transverse displacement is written with sin(alpha)/h and
 //     2 sin^2(alpha/2)/h, so it stays accurate as h -> 0;
 //   - the Jacobian uses only nonzero blocks; the covariance update touches
-//     only the upper triangle.
+//     only the upper triangle;
+//   - quotients by one denominator share its reciprocal (FP32: the hardware
+//     reciprocal, within 1 ulp; FP64: a correctly rounded 1/x).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -41,6 +43,12 @@ __host__ __device__ constexpr int ut(int i, int j) {
 template <typename T> KFD inline T sq(T v) { return v * v; }
 
 KFD inline float k_sqrt(float v) { return __builtin_sqrtf(v); }
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ inline float k_rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+#else
+inline float k_rcp(float v) { return 1.0f / v; }
+#endif
+KFD inline double k_rcp(double v) { return 1.0 / v; }
 KFD inline double k_sqrt(double v) { return __builtin_sqrt(v); }
 KFD inline void k_sincos(float a, float* s, float* c) { sincosf(a, s, c); }
 KFD inline void k_sincos(double a, double* s, double* c) { sincos(a, s, c); }
@@ -69,7 +77,7 @@ template <typename T> struct Step {
   T alpha;  // turning angle
   T sa, ca; // sin(alpha), cos(alpha)
   T A, B;   // sin(alpha)/h, (1 - cos(alpha))/h
-  T h, pt;
+  T h, pt, ipt;  // ipt = 1 / pt
 };
 
 template <typename T>
@@ -78,8 +86,9 @@ KFD inline int propagate(const T X[6], int q, T R, T bz, T Xo[6], Step<T>& st) {
   const T pt2 = px * px + py * py;
   const T pt = k_sqrt(pt2);
   if (!(pt > T(0))) return KF_NO_CROSSING;
-  const T h = -T(q) * kappa<T>() * bz / pt;
-  const T tx = px / pt, ty = py / pt;
+  const T ipt = k_rcp(pt);
+  const T h = -T(q) * kappa<T>() * bz * ipt;
+  const T tx = px * ipt, ty = py * ipt;
   const T u = X[0] * tx + X[1] * ty;
   const T v = -X[0] * ty + X[1] * tx;
   const T r02 = X[0] * X[0] + X[1] * X[1];
@@ -112,16 +121,17 @@ KFD inline int propagate(const T X[6], int q, T R, T bz, T Xo[6], Step<T>& st) {
   const T sa = T(2) * sh * chh;
   const T omc = T(2) * sh * sh;  // 1 - cos(alpha)
   const T ca = T(1) - omc;
-  const T s = alpha / h;
+  const T ih = k_rcp(h);
+  const T s = alpha * ih;
   if (!(s > T(0))) return KF_NO_CROSSING;
-  const T Ah = sa / h, Bh = omc / h;
+  const T Ah = sa * ih, Bh = omc * ih;
   Xo[0] = X[0] + tx * Ah - ty * Bh;
   Xo[1] = X[1] + ty * Ah + tx * Bh;
-  Xo[2] = X[2] + pz * s / pt;
+  Xo[2] = X[2] + pz * s * ipt;
   Xo[3] = px * ca - py * sa;
   Xo[4] = py * ca + px * sa;
   Xo[5] = pz;
-  st.s = s; st.alpha = alpha; st.sa = sa; st.ca = ca; st.A = Ah; st.B = Bh; st.h = h; st.pt = pt;
+  st.s = s; st.alpha = alpha; st.sa = sa; st.ca = ca; st.A = Ah; st.B = Bh; st.h = h; st.pt = pt; st.ipt = ipt;
   return 0;
 }
 
@@ -133,29 +143,32 @@ KFD inline int propagate(const T X[6], int q, T R, T bz, T Xo[6], Step<T>& st) {
 template <typename T>
 KFD inline void transport(const T X0[6], const T X1[6], const Step<T>& st, T P[21], T x_over_x0, T mass) {
   const T px = X0[3], py = X0[4], pz = X0[5];
-  const T pt = st.pt, pt2 = pt * pt, pt3 = pt2 * pt;
+  const T ipt = st.ipt, ipt2 = ipt * ipt, ipt3 = ipt2 * ipt;
   const T s = st.s;
   const T px1 = X1[3], py1 = X1[4];
-  const T aox = st.alpha / pt2;  // d(alpha)/d(px) = -aox*px
+  const T aox = st.alpha * ipt2;  // d(alpha)/d(px) = -aox*px
   // Js entries (rows x, y, z, px, py at columns px, py, pz)
-  const T j03 = st.A / pt - px1 * px * s / pt3;
-  const T j04 = -st.B / pt - px1 * py * s / pt3;
-  const T j13 = st.B / pt - py1 * px * s / pt3;
-  const T j14 = st.A / pt - py1 * py * s / pt3;
-  const T j23 = -pz * s * px / pt3;
-  const T j24 = -pz * s * py / pt3;
-  const T j25 = s / pt;
+  const T sp3 = s * ipt3;
+  const T j03 = st.A * ipt - px1 * px * sp3;
+  const T j04 = -st.B * ipt - px1 * py * sp3;
+  const T j13 = st.B * ipt - py1 * px * sp3;
+  const T j14 = st.A * ipt - py1 * py * sp3;
+  const T j23 = -pz * px * sp3;
+  const T j24 = -pz * py * sp3;
+  const T j25 = s * ipt;
   const T j33 = st.ca + py1 * aox * px;
   const T j34 = -st.sa + py1 * aox * py;
   const T j43 = st.sa - px1 * aox * px;
   const T j44 = st.ca - px1 * aox * py;
   // surface term
-  const T w0 = px1 / pt, w1 = py1 / pt, w2 = pz / pt, w3 = -st.h * py1, w4 = st.h * px1;
+  const T w0 = px1 * ipt, w1 = py1 * ipt, w2 = pz * ipt, w3 = -st.h * py1, w4 = st.h * px1;
   const T r = k_sqrt(X1[0] * X1[0] + X1[1] * X1[1]);
-  const T nx = X1[0] / r, ny = X1[1] / r;
+  const T ir = k_rcp(r);
+  const T nx = X1[0] * ir, ny = X1[1] * ir;
   const T den = nx * w0 + ny * w1;
-  const T g0 = -nx / den, g1 = -ny / den;
-  const T g3 = -(nx * j03 + ny * j13) / den, g4 = -(nx * j04 + ny * j14) / den;
+  const T mid = -k_rcp(den);
+  const T g0 = nx * mid, g1 = ny * mid;
+  const T g3 = (nx * j03 + ny * j13) * mid, g4 = (nx * j04 + ny * j14) * mid;
   // J rows as (c0, c1, c3, c4) for rows 0, 1, 3, 4; row 2 has all six columns
   const T J0[4] = {T(1) + w0 * g0, w0 * g1, j03 + w0 * g3, j04 + w0 * g4};
   const T J1[4] = {w1 * g0, T(1) + w1 * g1, j13 + w1 * g3, j14 + w1 * g4};
@@ -213,11 +226,12 @@ KFD inline void transport(const T X0[6], const T X1[6], const Step<T>& st, T P[2
   if (x_over_x0 > T(0)) {
     const T p2 = X1[3] * X1[3] + X1[4] * X1[4] + X1[5] * X1[5];
     const T p = k_sqrt(p2);
-    const T cospsi = fabs((X1[0] * X1[3] + X1[1] * X1[4]) / (r * p));
-    const T xe = x_over_x0 / cospsi;
-    const T beta2 = p2 / (p2 + mass * mass);
-    const T beta = k_sqrt(beta2);
-    const T th0 = T(0.0136) / (beta * p) * k_sqrt(xe) * (T(1) + T(0.038) * k_log(xe / beta2));
+    const T ip = k_rcp(p);
+    const T cospsi = fabs((X1[0] * X1[3] + X1[1] * X1[4]) * ir * ip);
+    const T xe = x_over_x0 * k_rcp(cospsi);
+    const T e2 = p2 + mass * mass;             // energy squared
+    const T ibeta2 = e2 * ip * ip;             // 1 / beta^2
+    const T th0 = T(0.0136) * k_sqrt(ibeta2) * ip * k_sqrt(xe) * (T(1) + T(0.038) * k_log(xe * ibeta2));
     const T t2 = th0 * th0;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -252,7 +266,8 @@ template <typename T> struct Innov {
 template <typename T>
 KFD inline int innovation(const T X[6], const T P[21], T mx, T my, T mz, const T V[6], Innov<T>& in) {
   const T r = k_sqrt(X[0] * X[0] + X[1] * X[1]);
-  const T tx = -X[1] / r, ty = X[0] / r;
+  const T ir = k_rcp(r);
+  const T tx = -X[1] * ir, ty = X[0] * ir;
   in.tx = tx; in.ty = ty;
   in.r0 = tx * (mx - X[0]) + ty * (my - X[1]);
   in.r1 = mz - X[2];
@@ -268,13 +283,15 @@ KFD inline int innovation(const T X[6], const T P[21], T mx, T my, T mz, const T
 }
 
 template <typename T> KFD inline T chi2_of(const Innov<T>& in) {
-  const T i00 = in.S11 / in.det, i01 = -in.S01 / in.det, i11 = in.S00 / in.det;
+  const T idet = k_rcp(in.det);
+  const T i00 = in.S11 * idet, i01 = -in.S01 * idet, i11 = in.S00 * idet;
   return in.r0 * (i00 * in.r0 + i01 * in.r1) + in.r1 * (i01 * in.r0 + i11 * in.r1);
 }
 
 // Kalman update: K = P H^T S^-1, X += K r, P -= K (H P) (upper triangle).
 template <typename T> KFD inline void apply_update(T X[6], T P[21], const Innov<T>& in) {
-  const T i00 = in.S11 / in.det, i01 = -in.S01 / in.det, i11 = in.S00 / in.det;
+  const T idet = k_rcp(in.det);
+  const T i00 = in.S11 * idet, i01 = -in.S01 * idet, i11 = in.S00 * idet;
   T U[6], W[6];  // columns of P H^T: U = P t, W = P zhat
 #pragma unroll
   for (int i = 0; i < 6; ++i) {

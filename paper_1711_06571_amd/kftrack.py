@@ -49,7 +49,7 @@ class BuildParams(ctypes.Structure):
                 ("nsigma", ctypes.c_float), ("win_sig_rphi", ctypes.c_float), ("win_sig_z", ctypes.c_float),
                 ("first_layer", ctypes.c_int32), ("window_mode", ctypes.c_int32), ("mlp", ctypes.c_void_p),
                 ("lanes_per_block", ctypes.c_int32), ("persistent_blocks", ctypes.c_int32),
-                ("arith", ctypes.c_int32)]
+                ("arith", ctypes.c_int32), ("phi_refine", ctypes.c_int32)]
 
 
 class BuildExtra(ctypes.Structure):
@@ -102,7 +102,7 @@ def lib():
         L.kf_mlp_adam.argtypes = [P, P, P, P, P, I, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P]
         if hasattr(L, "kf_build"):
             L.kf_build_workspace_bytes.restype = ctypes.c_size_t
-            L.kf_build_workspace_bytes.argtypes = [I, I]
+            L.kf_build_workspace_bytes.argtypes = [ctypes.POINTER(BuildParams), ctypes.POINTER(Hits), I]
             L.kf_build.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(BuildParams), ctypes.POINTER(Hits), I,
                                    I, P, P, P, P, P, P, P, P, P, ctypes.POINTER(BuildExtra), P, ctypes.c_size_t, P]
         _lib = L
@@ -230,7 +230,7 @@ def hit_bin(g, n_phi, n_z, layer, xyz, cov, event_offsets=None, out=None, ws=Non
 # ------------------------------------------------------------------- build
 
 def build_params(cuts, window_mode=0, mlp_block=None, lanes_per_block=0, persistent_blocks=0, cap=None,
-                 arith=ARITH_F32):
+                 arith=ARITH_F32, phi_refine=0):
     bp = BuildParams()
     bp.chi2_cut = cuts.chi2_cut
     bp.max_holes = cuts.max_holes
@@ -244,11 +244,13 @@ def build_params(cuts, window_mode=0, mlp_block=None, lanes_per_block=0, persist
     bp.lanes_per_block = lanes_per_block
     bp.persistent_blocks = persistent_blocks
     bp.arith = arith
+    bp.phi_refine = phi_refine
     return bp
 
 
-def kf_build_workspace_bytes(n_seeds, n_events):
-    return int(lib().kf_build_workspace_bytes(n_seeds, n_events))
+def kf_build_workspace_bytes(bp, binned: "BinnedHits", n_seeds):
+    hd = binned.descriptor()
+    return int(lib().kf_build_workspace_bytes(ctypes.byref(bp), ctypes.byref(hd), n_seeds))
 
 
 def kf_build(g, bp, binned: BinnedHits, n_seeds, seed_par, seed_cov, q, extra=None, out=None, ws=None,
@@ -263,7 +265,7 @@ def kf_build(g, bp, binned: BinnedHits, n_seeds, seed_par, seed_cov, q, extra=No
                    chi2=torch.empty(ld, dtype=torch.float32, device=dev),
                    nhits=torch.empty(ld, dtype=torch.int32, device=dev),
                    status=torch.empty(ld, dtype=torch.int32, device=dev))
-    need = kf_build_workspace_bytes(n_seeds, binned.n_events)
+    need = kf_build_workspace_bytes(bp, binned, n_seeds)
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     gg = geometry(g)
@@ -398,7 +400,8 @@ class BatchPlan:
         self.binned = BinnedHits(E, g.n_layers, n_phi, n_z, n_hits, dev)
         self.bin_ws = torch.empty(max(hit_bin_workspace_bytes(E, g.n_layers, n_phi, n_z, n_hits), 1),
                                   dtype=torch.uint8, device=dev)
-        self.build_ws = torch.empty(max(kf_build_workspace_bytes(n_seeds, E), 1), dtype=torch.uint8, device=dev)
+        self.build_ws = torch.empty(max(kf_build_workspace_bytes(bp, self.binned, n_seeds), 1), dtype=torch.uint8,
+                                    device=dev)
         ld = seed_par.shape[1]
         F = bp.first_layer
         self.out = dict(hits=torch.empty((g.n_layers - F, ld), dtype=torch.int32, device=dev),

@@ -38,8 +38,9 @@ def test_graph_replays_equal_eager(bt):
         torch.cuda.synchronize()
         p.launch()
         p.stream.synchronize()
+        n = b.eb.n_seeds  # columns beyond the seeds are padding, not written
         for k in ref:
-            assert np.array_equal(host(p.out[k]), ref[k]), (rep, k)
+            assert np.array_equal(host(p.out[k])[..., :n], ref[k][..., :n]), (rep, k)
         # eager work between replays
         kf.hit_bin(w.geometry, 63, 16, b.layer, b.xyz, b.cov, event_offsets=b.hoff)
         torch.cuda.synchronize()

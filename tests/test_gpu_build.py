@@ -33,7 +33,7 @@ def decidable(o):
     return (m[0] > 1e-3) & (m[1] > 1e-4) & (m[2] > 1e-3)
 
 
-def gpu_build_event(kf, w, ev, arith, cap=None, lanes=0, blocks=0, order=None, seeds=None):
+def gpu_build_event(kf, w, ev, arith, cap=None, lanes=0, blocks=0, order=None, seeds=None, refine=0):
     xyz = ev.xyz.astype(np.float32)
     cov = ev.cov.astype(np.float32)
     b = kf.hit_bin(w.geometry, w.cuts.n_phi_bins, w.cuts.n_z_bins, to_dev(ev.layer), to_dev(xyz), to_dev(cov))
@@ -41,7 +41,8 @@ def gpu_build_event(kf, w, ev, arith, cap=None, lanes=0, blocks=0, order=None, s
     n = ev.n_tracks
     if seeds is None:
         seeds = kf.kf_seed(w.geometry, n, to_dev(H))
-    bp = kf.build_params(w.cuts, cap=cap, lanes_per_block=lanes, persistent_blocks=blocks, arith=arith)
+    bp = kf.build_params(w.cuts, cap=cap, lanes_per_block=lanes, persistent_blocks=blocks, arith=arith,
+                         phi_refine=refine)
     ex = kf.BuildExtra()
     keep = []
     if order is not None:
@@ -126,7 +127,7 @@ def test_build_fp32_arithmetic_agreement(kf):
     assert same.mean() > 0.6
 
 
-@pytest.mark.parametrize("cap", [1, 4, 8])
+@pytest.mark.parametrize("cap", [1, 3, 4, 5, 8])
 def test_build_other_caps(kf, cap):
     w = presets.build()
     ev = datagen.generate(w.geometry, w.gen, 13, 300)
@@ -144,17 +145,21 @@ def test_build_launch_shape_and_order_invariance(kf):
     n = ev.n_tracks
     ref, sg = gpu_build_event(kf, w, ev, kf.ARITH_F32)
     rng = np.random.default_rng(5)
-    for lanes, blocks, order in [(64, 0, None), (128, 7, None), (256, 1, None), (256, 0, rng.permutation(n))]:
-        g, _ = gpu_build_event(kf, w, ev, kf.ARITH_F32, lanes=lanes, blocks=blocks, order=order, seeds=sg)
+    # launch shape, seed order and the granularity of the fine phi index
+    # (an acceleration structure only) change no output
+    for lanes, blocks, order, refine in [(64, 0, None, 0), (128, 7, None, 1), (256, 1, None, 32),
+                                         (256, 0, rng.permutation(n), 3)]:
+        g, _ = gpu_build_event(kf, w, ev, kf.ARITH_F32, lanes=lanes, blocks=blocks, order=order, seeds=sg,
+                               refine=refine)
         for k in ref:
-            assert np.array_equal(g[k][..., :n], ref[k][..., :n]), (k, lanes, blocks)
+            assert np.array_equal(g[k][..., :n], ref[k][..., :n]), (k, lanes, blocks, refine)
 
 
 def test_build_noise_free_recovers_true_hits(kf):
     w = presets.build()
     g0 = w.geometry.replace(x_over_x0=0.0)
     w0 = dataclasses.replace(w, geometry=g0)
-    gen = dataclasses.replace(w.gen, smear=False, noise_lo=0.0, noise_hi=0.0, pt_max=3.0)
+    gen = dataclasses.replace(w.gen, smear=False, vtx_sxy=0.0, noise_lo=0.0, noise_hi=0.0, pt_max=3.0)
     ev = datagen.generate(g0, gen, 0, 1000)
     g, _ = gpu_build_event(kf, w0, ev, kf.ARITH_F32)
     F = w.cuts.first_layer
