@@ -79,17 +79,24 @@ int kf_last_error(char* buf, size_t n);
 
 /*
  * kf_seed — starting state from the hits on layers 0, 1, 2 (a convention of
- * this library; the paper treats seeding as given, section 2).  Circle
- * through the three transverse points -> pT, charge and direction at hit 0;
- * tan(lambda) from the z change over the arc; then an FP64 Kalman filter over
- * the three hits from a broad prior (1 cm tangential, 10 cm in z, |p| per
- * momentum component).  Output: state and covariance at layer 2, rounded to
- * FP32.
+ * this library; the paper treats seeding as given, section 2).
+ * With a beam spot (beam_sigma > 0, cm: tracks leave the z axis within that
+ * transverse distance): the circle through the axis point and the
+ * transverse points of hits 0 and 2 gives pT, charge and direction at hit 0;
+ * tan(lambda) from the z change over the arc from hit 0 to hit 2; from a
+ * broad prior at hit 0 (1 cm tangential, 10 cm in z, |p| per momentum
+ * component) one Kalman update with "transverse impact parameter = 0"
+ * (variance beam_sigma^2), then the layer-0 scattering and an FP64 Kalman
+ * filter over the three hits.  With beam_sigma = 0 the circle passes through
+ * the three hits and the impact-parameter update is skipped.  Output: state
+ * and covariance at layer 2, rounded to FP32; a failed seed gets a zero state
+ * and covariance, q = +1 and its status bit.
  *   hits     [n_layers][9][ld] FP32 (only layers 0..2 are read)
  *   q_out    [ld] int8, seed_par [6][ld], seed_cov [21][ld], status [ld]
+ * KF_E_INVALID_ARG for a negative or NaN beam_sigma.
  */
-int kf_seed(const kf_geometry* g, int32_t n, int32_t ld, const float* hits, int8_t* q_out, float* seed_par,
-            float* seed_cov, int32_t* status, void* stream);
+int kf_seed(const kf_geometry* g, int32_t n, int32_t ld, const float* hits, float beam_sigma, int8_t* q_out,
+            float* seed_par, float* seed_cov, int32_t* status, void* stream);
 
 /*
  * kf_fit — Kalman-filter fit over a fixed hit list (section 2), one lane per

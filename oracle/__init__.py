@@ -63,8 +63,9 @@ def lib():
         L.orc_ms_cov.restype = None
         L.orc_update.argtypes = [P, P, P, P, P, P]
         L.orc_predict.argtypes = [ctypes.POINTER(Geom), I, P, I, P, P, P, P]
-        L.orc_seed.argtypes = [ctypes.POINTER(Geom), I, I, P, P, P, P, P, P, P]
-        L.orc_seed64.argtypes = [ctypes.POINTER(Geom), I, I, P, P, P, P, P]
+        L.orc_seed.argtypes = [ctypes.POINTER(Geom), I, I, P, D, P, P, P, P, P, P]
+        L.orc_seed64.argtypes = [ctypes.POINTER(Geom), I, I, P, D, P, P, P, P]
+        L.orc_beam_d0.argtypes = [P, I, D, P, P]
         L.orc_fit.argtypes = [ctypes.POINTER(Geom), I, I, I] + [P] * 10
         L.orc_fit64.argtypes = [ctypes.POINTER(Geom), I, I, I] + [P] * 9
         L.orc_hit_bin.argtypes = [ctypes.POINTER(Geom), I, I, I, P, P, P, P, P]
@@ -146,9 +147,24 @@ def predict(g, layer, X, q, P):
 
 # ------------------------------------------------------------------ batches
 
-def seed(g, hits, n):
+def beam_d0(X, q, bz):
+    """Impact parameter |c| - rho of the helix of X and its gradient."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    f = np.zeros(1)
+    H = np.zeros(6)
+    rc = lib().orc_beam_d0(_p(X), int(q), float(bz), _p(f), _p(H))
+    return rc, float(f[0]), H
+
+
+def _beam(g, beam_sigma):
+    return float(getattr(g, "beam_sigma", 0.0)) if beam_sigma is None else float(beam_sigma)
+
+
+def seed(g, hits, n, beam_sigma=None):
     """hits: [L][9][ld] float32.  Returns dict of FP32 seeds (the values both
-    sides consume), their FP64 originals, q and status."""
+    sides consume), their FP64 originals, q and status.  beam_sigma: the
+    beam-spot width (cm) of the seed convention, default the geometry's;
+    0 for the three-hit-only convention."""
     ld = hits.shape[2]
     hits = np.ascontiguousarray(hits, dtype=np.float32)
     q = np.zeros(ld, dtype=np.int8)
@@ -158,13 +174,14 @@ def seed(g, hits, n):
     cov64 = np.zeros((21, ld))
     st = np.zeros(ld, dtype=np.int32)
     gg = geom(g)
-    rc = lib().orc_seed(ctypes.byref(gg), n, ld, _p(hits), _p(q), _p(par), _p(cov), _p(par64), _p(cov64), _p(st))
+    rc = lib().orc_seed(ctypes.byref(gg), n, ld, _p(hits), _beam(g, beam_sigma), _p(q), _p(par), _p(cov), _p(par64),
+                        _p(cov64), _p(st))
     if rc:
         raise ValueError("orc_seed: bad arguments")
     return dict(q=q, par=par, cov=cov, par64=par64, cov64=cov64, status=st)
 
 
-def seed64(g, hits, n):
+def seed64(g, hits, n, beam_sigma=None):
     """FP64 hits [L][9][ld] -> FP64 seeds (no rounding anywhere)."""
     ld = hits.shape[2]
     hits = np.ascontiguousarray(hits, dtype=np.float64)
@@ -173,7 +190,8 @@ def seed64(g, hits, n):
     cov64 = np.zeros((21, ld))
     st = np.zeros(ld, dtype=np.int32)
     gg = geom(g)
-    rc = lib().orc_seed64(ctypes.byref(gg), n, ld, _p(hits), _p(q), _p(par64), _p(cov64), _p(st))
+    rc = lib().orc_seed64(ctypes.byref(gg), n, ld, _p(hits), _beam(g, beam_sigma), _p(q), _p(par64), _p(cov64),
+                          _p(st))
     if rc:
         raise ValueError("orc_seed64: bad arguments")
     return dict(q=q, par64=par64, cov64=cov64, status=st)

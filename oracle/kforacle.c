@@ -248,48 +248,98 @@ static void load_hit(const float* hits, int ld, int layer, int i, double h[9]) {
 /* ------------------------------------------------------------- seed */
 
 /*
+ * Transverse impact parameter of the helix of state X (charge q, field bz),
+ * as the signed distance of the z axis from the circle: f = |c| - rho, with
+ * the circle centre c = (x + py/k, y - px/k), k = q*KAPPA*bz (the helix
+ * above turns about that point) and rho = pT/|k|.  H = df/dX (z and pz do
+ * not enter).  Returns nonzero when the centre sits on the axis.
+ */
+int orc_beam_d0(const double X[6], int q, double bz, double* f, double H[6]) {
+  double k = (double)q * KAPPA * bz;
+  double cx = X[0] + X[4] / k, cy = X[1] - X[3] / k;
+  double cn = sqrt(cx * cx + cy * cy);
+  double pt = sqrt(X[3] * X[3] + X[4] * X[4]);
+  if (!(cn > 0.0) || !(pt > 0.0)) return 1;
+  double ak = fabs(k);
+  *f = cn - pt / ak;
+  H[0] = cx / cn;
+  H[1] = cy / cn;
+  H[2] = 0.0;
+  H[3] = -cy / (k * cn) - X[3] / (pt * ak);
+  H[4] = cx / (k * cn) - X[4] / (pt * ak);
+  H[5] = 0.0;
+  return 0;
+}
+
+/*
  * Seed from the hits on layers 0, 1, 2.  Seeding itself is outside the
  * paper's scope (section 2: seeds are given); this is the test convention
- * that turns three hits into a starting state and covariance:
- *   1. circle through the three transverse points gives the centre and
- *      rho, hence pT = KAPPA*bz*rho; the turning sense gives q;
- *   2. the momentum at hit 0 is tangent to that circle; tan(lambda) from
- *      the z change over the arc from hit 0 to hit 2;
+ * that turns three hits into a starting state and covariance.
+ *
+ * With a beam spot (beam_sigma > 0: the track comes from the z axis within
+ * beam_sigma cm transversely):
+ *   1. the circle through the axis point (0, 0) and the transverse points of
+ *      hits 0 and 2 gives the centre and rho, hence pT = KAPPA*|bz|*rho; its
+ *      turning sense with the sign of bz gives q;
+ *   2. the momentum at hit 0 is tangent to that circle, along the motion;
+ *      tan(lambda) from the z change over the arc from hit 0 to hit 2;
  *   3. starting at hit 0 with a broad prior (1 cm tangential, 10 cm in z,
- *      |p| per momentum component), add the layer-0 scattering and run the
- *      Kalman filter over hits 0, 1, 2;
- *   4. the state and covariance at layer 2 are the seed.
+ *      |p| per momentum component), one Kalman update with the measurement
+ *      "impact parameter = 0" of variance beam_sigma^2 (orc_beam_d0);
+ *   4. add the layer-0 scattering and run the Kalman filter over hits 0, 1,
+ *      2; the state and covariance at layer 2 are the seed.
+ * Without a beam spot (beam_sigma <= 0) step 1 uses the circle through the
+ * three hits and step 3 is skipped.
  */
-static int seed_one(const orc_geometry* g, const double h[3][9], int* q_out, double X[6], double P[36]) {
-  double x1 = h[0][0], y1 = h[0][1], z1 = h[0][2];
-  double bx = h[1][0] - x1, by = h[1][1] - y1;
-  double cx = h[2][0] - x1, cy = h[2][1] - y1;
-  double D = 2.0 * (bx * cy - by * cx);
+static int seed_one(const orc_geometry* g, const double h[3][9], double beam_sigma, int* q_out, double X[6],
+                    double P[36]) {
+  const int beam = beam_sigma > 0.0;
+  /* the three circle points: (0,0), hit 0, hit 2 or hit 0, hit 1, hit 2 */
+  double p0x = beam ? 0.0 : h[0][0], p0y = beam ? 0.0 : h[0][1];
+  double p1x = beam ? h[0][0] : h[1][0], p1y = beam ? h[0][1] : h[1][1];
+  double p2x = h[2][0], p2y = h[2][1];
+  /* centre from |c - p0| = |c - p1| = |c - p2| */
+  double ax = p1x - p0x, ay = p1y - p0y, bx = p2x - p0x, by = p2y - p0y;
+  double D = 2.0 * (ax * by - ay * bx);
   if (!(fabs(D) > 0.0)) return ORC_TRK_NO_CROSSING;
-  double b2 = bx * bx + by * by, c2 = cx * cx + cy * cy;
-  double ux = (cy * b2 - by * c2) / D, uy = (bx * c2 - cx * b2) / D; /* centre relative to hit 0 */
-  double rho = sqrt(ux * ux + uy * uy);
-  double cross = bx * (h[2][1] - h[1][1]) - by * (h[2][0] - h[1][0]);
-  int q = cross < 0.0 ? 1 : -1; /* clockwise seen from +z for q > 0 */
+  double a2 = ax * ax + ay * ay, b2 = bx * bx + by * by;
+  double cx = p0x + (by * a2 - ay * b2) / D, cy = p0y + (ax * b2 - bx * a2) / D;
+  /* hit 0 and hit 2 seen from the centre */
+  double r1x = h[0][0] - cx, r1y = h[0][1] - cy;
+  double r3x = h[2][0] - cx, r3y = h[2][1] - cy;
+  double rho = sqrt(r1x * r1x + r1y * r1y);
+  /* turning sense of p0 -> p1 -> p2: counter-clockwise if cross > 0 */
+  double cross = (p1x - p0x) * (p2y - p1y) - (p1y - p0y) * (p2x - p1x);
   double bz = (double)g->bz;
+  /* the helix turns clockwise (seen from +z) when q*bz > 0 */
+  int q = (cross < 0.0) == (bz > 0.0) ? 1 : -1;
   double pt = KAPPA * fabs(bz) * rho;
-  double r1x = -ux, r1y = -uy; /* hit 0 seen from the centre */
   double tx, ty;
-  if (cross > 0.0) { tx = -r1y / rho; ty = r1x / rho; } /* counter-clockwise */
+  if (cross > 0.0) { tx = -r1y / rho; ty = r1x / rho; }
   else { tx = r1y / rho; ty = -r1x / rho; }
-  double r3x = cx - ux, r3y = cy - uy; /* hit 2 seen from the centre */
   double dalpha = fabs(atan2(r1x * r3y - r1y * r3x, r1x * r3x + r1y * r3y));
-  double tanl = (h[2][2] - z1) / (rho * dalpha);
-  double X0[6] = {x1, y1, z1, pt * tx, pt * ty, pt * tanl};
+  double tanl = (h[2][2] - h[0][2]) / (rho * dalpha);
+  double X0[6] = {h[0][0], h[0][1], h[0][2], pt * tx, pt * ty, pt * tanl};
   double p2 = X0[3] * X0[3] + X0[4] * X0[4] + X0[5] * X0[5];
-  double r0 = sqrt(x1 * x1 + y1 * y1);
-  double ttx = -y1 / r0, tty = x1 / r0;
+  double r0 = sqrt(X0[0] * X0[0] + X0[1] * X0[1]);
+  double ttx = -X0[1] / r0, tty = X0[0] / r0;
   double P0[36];
   memset(P0, 0, sizeof(P0));
   P0[0 * 6 + 0] = ttx * ttx; P0[0 * 6 + 1] = ttx * tty;
   P0[1 * 6 + 0] = ttx * tty; P0[1 * 6 + 1] = tty * tty;
   P0[2 * 6 + 2] = 100.0;
   P0[3 * 6 + 3] = p2; P0[4 * 6 + 4] = p2; P0[5 * 6 + 5] = p2;
+  if (beam) {
+    double f, H[6], PH[6];
+    if (orc_beam_d0(X0, q, bz, &f, H)) return ORC_TRK_NO_CROSSING;
+    matmul(P0, H, PH, 6, 6, 1);
+    double S = beam_sigma * beam_sigma;
+    for (int i = 0; i < 6; ++i) S += H[i] * PH[i];
+    if (!(S > 0.0)) return ORC_TRK_S_NOT_PD;
+    for (int i = 0; i < 6; ++i) X0[i] += PH[i] / S * (0.0 - f);
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) P0[i * 6 + j] -= PH[i] * PH[j] / S;
+  }
   double Q[36];
   orc_ms_cov(X0, (double)g->x_over_x0, (double)g->mass, Q);
   for (int i = 0; i < 36; ++i) P0[i] += Q[i];
@@ -306,8 +356,8 @@ static int seed_one(const orc_geometry* g, const double h[3][9], int* q_out, dou
 }
 
 static int seed_rows(const orc_geometry* g, int n, int ld, const float* hits32, const double* hits64,
-                     int8_t* q_out, float* seed_par, float* seed_cov, double* seed_par64, double* seed_cov64,
-                     int32_t* status) {
+                     double beam_sigma, int8_t* q_out, float* seed_par, float* seed_cov, double* seed_par64,
+                     double* seed_cov64, int32_t* status) {
   if (n < 0 || ld < n || g->n_layers < 3) return 1;
   for (int i = 0; i < n; ++i) {
     double h[3][9];
@@ -317,7 +367,7 @@ static int seed_rows(const orc_geometry* g, int n, int ld, const float* hits32, 
     }
     int q = 1;
     double X[6], P[36], u[21];
-    int st = all_finite(&h[0][0], 27) ? seed_one(g, h, &q, X, P) : ORC_TRK_NONFINITE;
+    int st = all_finite(&h[0][0], 27) ? seed_one(g, h, beam_sigma, &q, X, P) : ORC_TRK_NONFINITE;
     if (st) { for (int c = 0; c < 6; ++c) X[c] = 0.0; for (int c = 0; c < 36; ++c) P[c] = 0.0; }
     upper_from_sym(P, u);
     q_out[i] = (int8_t)q;
@@ -334,14 +384,14 @@ static int seed_rows(const orc_geometry* g, int n, int ld, const float* hits32, 
   return 0;
 }
 
-int orc_seed(const orc_geometry* g, int n, int ld, const float* hits, int8_t* q_out, float* seed_par,
-             float* seed_cov, double* seed_par64, double* seed_cov64, int32_t* status) {
-  return seed_rows(g, n, ld, hits, NULL, q_out, seed_par, seed_cov, seed_par64, seed_cov64, status);
+int orc_seed(const orc_geometry* g, int n, int ld, const float* hits, double beam_sigma, int8_t* q_out,
+             float* seed_par, float* seed_cov, double* seed_par64, double* seed_cov64, int32_t* status) {
+  return seed_rows(g, n, ld, hits, NULL, beam_sigma, q_out, seed_par, seed_cov, seed_par64, seed_cov64, status);
 }
 
-int orc_seed64(const orc_geometry* g, int n, int ld, const double* hits, int8_t* q_out, double* seed_par64,
-               double* seed_cov64, int32_t* status) {
-  return seed_rows(g, n, ld, NULL, hits, q_out, NULL, NULL, seed_par64, seed_cov64, status);
+int orc_seed64(const orc_geometry* g, int n, int ld, const double* hits, double beam_sigma, int8_t* q_out,
+               double* seed_par64, double* seed_cov64, int32_t* status) {
+  return seed_rows(g, n, ld, NULL, hits, beam_sigma, q_out, NULL, NULL, seed_par64, seed_cov64, status);
 }
 
 /* -------------------------------------------------------------- fit */

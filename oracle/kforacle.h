@@ -70,12 +70,13 @@ int orc_update(const double X[6], const double P[36], const double hit[9], doubl
                double* chi2);
 int orc_predict(const orc_geometry* g, int layer, const double X[6], int q, const double P[36], double Xo[6],
                 double Po[36], double* disc);
+int orc_beam_d0(const double X[6], int q, double bz, double* f, double H[6]);
 
 /* --- batch entry points, SoA layouts with leading dimension ld --- */
-int orc_seed(const orc_geometry* g, int n, int ld, const float* hits, int8_t* q_out, float* seed_par,
-             float* seed_cov, double* seed_par64, double* seed_cov64, int32_t* status);
-int orc_seed64(const orc_geometry* g, int n, int ld, const double* hits, int8_t* q_out, double* seed_par64,
-               double* seed_cov64, int32_t* status);
+int orc_seed(const orc_geometry* g, int n, int ld, const float* hits, double beam_sigma, int8_t* q_out,
+             float* seed_par, float* seed_cov, double* seed_par64, double* seed_cov64, int32_t* status);
+int orc_seed64(const orc_geometry* g, int n, int ld, const double* hits, double beam_sigma, int8_t* q_out,
+               double* seed_par64, double* seed_cov64, int32_t* status);
 int orc_fit(const orc_geometry* g, int n, int ld, int first_layer, const float* hits, const uint32_t* hole_mask,
             const float* seed_par, const float* seed_cov, const int8_t* q, double* out_par, double* out_cov,
             double* out_chi2, int32_t* out_ndof, int32_t* out_status);

@@ -23,11 +23,39 @@ GeomK to_k(const kf_geometry* g) {
   return k;
 }
 
-// Seed from layers 0..2 in FP64.  Circle through the three transverse
-// points, direction tangent at hit 0 with the turning sense of the charge,
-// tan(lambda) from the arc between hits 0 and 2, then the Kalman filter over
-// the three hits from a broad prior on the surface.
-__global__ void __launch_bounds__(256) seed_kernel(GeomK g, int n, int ld, const float* __restrict__ hits,
+// Seed from layers 0..2 in FP64.  With a beam spot (bs > 0: tracks leave
+// the z axis within bs cm transversely) the first circle passes through the
+// axis point and hits 0 and 2, and the first Kalman step is the 1-D
+// measurement "transverse impact parameter = 0" (variance bs^2); without it
+// the circle passes through the three hits.  Direction tangent at hit 0 with
+// the turning sense of the charge, tan(lambda) from the arc between hits 0
+// and 2, then the Kalman filter over the three hits from a broad prior on
+// the surface; the state at layer 2 is the seed.
+__device__ inline void beam_constraint(double X[6], double P[21], int q, double bz, double bs, int& st) {
+  // impact parameter f = |c| - rho of the circle about c = (x + py/k, y - px/k)
+  const double k = (double)q * kappa<double>() * bz, ik = 1.0 / k, aik = fabs(ik);
+  const double cx = X[0] + X[4] * ik, cy = X[1] - X[3] * ik;
+  const double cn = sqrt(cx * cx + cy * cy), pt = sqrt(X[3] * X[3] + X[4] * X[4]);
+  if (!(cn > 0.0) || !(pt > 0.0)) { st = KF_NO_CROSSING; return; }
+  const double icn = 1.0 / cn, ipt = 1.0 / pt;
+  const double f = cn - pt * aik;
+  double H[6] = {cx * icn, cy * icn, 0.0, -cy * ik * icn - X[3] * ipt * aik, cx * ik * icn - X[4] * ipt * aik, 0.0};
+  double PH[6];
+  for (int i = 0; i < 6; ++i) {
+    double a = 0.0;
+    for (int j = 0; j < 6; ++j) a += P[ut(i, j)] * H[j];
+    PH[i] = a;
+  }
+  double S = bs * bs;
+  for (int i = 0; i < 6; ++i) S += H[i] * PH[i];
+  if (!(S > 0.0)) { st = KF_S_NOT_PD; return; }
+  const double iS = 1.0 / S;
+  for (int i = 0; i < 6; ++i) X[i] -= PH[i] * iS * f;
+  for (int i = 0; i < 6; ++i)
+    for (int j = i; j < 6; ++j) P[ut(i, j)] -= PH[i] * PH[j] * iS;
+}
+
+__global__ void __launch_bounds__(256) seed_kernel(GeomK g, int n, int ld, const float* __restrict__ hits, double bs,
                                                    int8_t* __restrict__ q_out, float* __restrict__ seed_par,
                                                    float* __restrict__ seed_cov, int32_t* __restrict__ status) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -43,31 +71,32 @@ __global__ void __launch_bounds__(256) seed_kernel(GeomK g, int n, int ld, const
   int q = 1;
   double X[6] = {0, 0, 0, 0, 0, 0}, P[21];
   for (int k = 0; k < 21; ++k) P[k] = 0.0;
+  const bool beam = bs > 0.0;
+  const double bz = (double)g.bz;
   if (!st) {
-    const double x1 = h[0][0], y1 = h[0][1], z1 = h[0][2];
-    const double bx = h[1][0] - x1, by = h[1][1] - y1;
-    const double cx = h[2][0] - x1, cy = h[2][1] - y1;
-    const double D = 2.0 * (bx * cy - by * cx);
+    // circle points A, B, C: the axis point (or hit 0), hit 0 (or hit 1), hit 2
+    const double Ax = beam ? 0.0 : h[0][0], Ay = beam ? 0.0 : h[0][1];
+    const double Bx = beam ? h[0][0] : h[1][0], By = beam ? h[0][1] : h[1][1];
+    const double Cx = h[2][0], Cy = h[2][1];
+    const double e1x = Bx - Ax, e1y = By - Ay, e2x = Cx - Ax, e2y = Cy - Ay;
+    const double D = 2.0 * (e1x * e2y - e1y * e2x);
     if (!(fabs(D) > 0.0)) st = KF_NO_CROSSING;
     if (!st) {
-      const double b2 = bx * bx + by * by, c2 = cx * cx + cy * cy;
-      const double ux = (cy * b2 - by * c2) / D, uy = (bx * c2 - cx * b2) / D;
-      const double rho = sqrt(ux * ux + uy * uy);
-      const double cross = bx * (h[2][1] - h[1][1]) - by * (h[2][0] - h[1][0]);
-      q = cross < 0.0 ? 1 : -1;
-      const double pt = kappa<double>() * fabs((double)g.bz) * rho;
-      const double r1x = -ux, r1y = -uy;
-      double tx, ty;
-      if (cross > 0.0) { tx = -r1y / rho; ty = r1x / rho; }
-      else { tx = r1y / rho; ty = -r1x / rho; }
-      const double r3x = cx - ux, r3y = cy - uy;
+      const double l1 = e1x * e1x + e1y * e1y, l2 = e2x * e2x + e2y * e2y;
+      const double ox = Ax + (e2y * l1 - e1y * l2) / D, oy = Ay + (e1x * l2 - e2x * l1) / D;  // centre
+      const double r1x = h[0][0] - ox, r1y = h[0][1] - oy, r3x = h[2][0] - ox, r3y = h[2][1] - oy;
+      const double rho = sqrt(r1x * r1x + r1y * r1y);
+      const double turn = e1x * (Cy - By) - e1y * (Cx - Bx);  // > 0: counter-clockwise
+      q = ((turn < 0.0) == (bz > 0.0)) ? 1 : -1;
+      const double pt = kappa<double>() * fabs(bz) * rho;
+      const double tx = (turn > 0.0 ? -r1y : r1y) / rho, ty = (turn > 0.0 ? r1x : -r1x) / rho;
       const double dal = fabs(atan2(r1x * r3y - r1y * r3x, r1x * r3x + r1y * r3y));
-      const double tanl = (h[2][2] - z1) / (rho * dal);
-      double X0[6] = {x1, y1, z1, pt * tx, pt * ty, pt * tanl};
-      const double p2 = X0[3] * X0[3] + X0[4] * X0[4] + X0[5] * X0[5];
-      const double r0 = sqrt(x1 * x1 + y1 * y1);
-      const double ttx = -y1 / r0, tty = x1 / r0;
-      for (int k = 0; k < 21; ++k) P[k] = 0.0;
+      const double tanl = (h[2][2] - h[0][2]) / (rho * dal);
+      X[0] = h[0][0]; X[1] = h[0][1]; X[2] = h[0][2];
+      X[3] = pt * tx; X[4] = pt * ty; X[5] = pt * tanl;
+      const double p2 = X[3] * X[3] + X[4] * X[4] + X[5] * X[5];
+      const double r0 = sqrt(X[0] * X[0] + X[1] * X[1]);
+      const double ttx = -X[1] / r0, tty = X[0] / r0;
       P[ut(0, 0)] = ttx * ttx;
       P[ut(0, 1)] = ttx * tty;
       P[ut(1, 1)] = tty * tty;
@@ -75,22 +104,26 @@ __global__ void __launch_bounds__(256) seed_kernel(GeomK g, int n, int ld, const
       P[ut(3, 3)] = p2;
       P[ut(4, 4)] = p2;
       P[ut(5, 5)] = p2;
+      if (beam) beam_constraint(X, P, q, bz, bs, st);
+    }
+    if (!st) {
       // scattering on layer 0 (the prior sits at hit 0)
       if (g.x_over_x0 > 0.f) {
-        const double p = sqrt(p2);
-        const double cospsi = fabs((X0[0] * X0[3] + X0[1] * X0[4]) / (r0 * p));
+        const double pp2 = X[3] * X[3] + X[4] * X[4] + X[5] * X[5];
+        const double p = sqrt(pp2);
+        const double r0 = sqrt(X[0] * X[0] + X[1] * X[1]);
+        const double cospsi = fabs((X[0] * X[3] + X[1] * X[4]) / (r0 * p));
         const double xe = (double)g.x_over_x0 / cospsi;
-        const double beta2 = p2 / (p2 + (double)g.mass * (double)g.mass);
+        const double beta2 = pp2 / (pp2 + (double)g.mass * (double)g.mass);
         const double th0 = 0.0136 / (sqrt(beta2) * p) * sqrt(xe) * (1.0 + 0.038 * log(xe / beta2));
         const double t2 = th0 * th0;
         for (int a = 0; a < 3; ++a)
-          for (int b = a; b < 3; ++b) P[ut(3 + a, 3 + b)] += t2 * ((a == b ? p2 : 0.0) - X0[3 + a] * X0[3 + b]);
+          for (int b = a; b < 3; ++b) P[ut(3 + a, 3 + b)] += t2 * ((a == b ? pp2 : 0.0) - X[3 + a] * X[3 + b]);
       }
-      for (int k = 0; k < 6; ++k) X[k] = X0[k];
       for (int l = 0; l < 3 && !st; ++l) {
         if (l > 0) {
           double Xp[6], Pp[21];
-          int rc = predict<double>(X, P, q, (double)g.r[l], (double)g.bz, (double)g.z_half, (double)g.x_over_x0,
+          int rc = predict<double>(X, P, q, (double)g.r[l], bz, (double)g.z_half, (double)g.x_over_x0,
                                    (double)g.mass, Xp, Pp);
           if (rc) { st = rc; break; }
           for (int k = 0; k < 6; ++k) X[k] = Xp[k];
@@ -189,15 +222,15 @@ int check_geometry(const kf_geometry* g) {
 
 int kf_check_geometry(const kf_geometry* g) { return check_geometry(g); }
 
-extern "C" int kf_seed(const kf_geometry* g, int32_t n, int32_t ld, const float* hits, int8_t* q_out,
-                       float* seed_par, float* seed_cov, int32_t* status, void* stream) {
+extern "C" int kf_seed(const kf_geometry* g, int32_t n, int32_t ld, const float* hits, float beam_sigma,
+                       int8_t* q_out, float* seed_par, float* seed_cov, int32_t* status, void* stream) {
   if (check_geometry(g)) return KF_E_INVALID_ARG;
-  if (n < 0 || ld < n || g->n_layers < 3) return KF_E_INVALID_ARG;
+  if (n < 0 || ld < n || g->n_layers < 3 || !(beam_sigma >= 0.f)) return KF_E_INVALID_ARG;
   if (n == 0) return KF_OK;
   if (!hits || !q_out || !seed_par || !seed_cov || !status) return KF_E_INVALID_ARG;
   const int bs = 256;
   hipLaunchKernelGGL(seed_kernel, dim3((n + bs - 1) / bs), dim3(bs), 0, (hipStream_t)stream, to_k(g), n, ld, hits,
-                     q_out, seed_par, seed_cov, status);
+                     (double)beam_sigma, q_out, seed_par, seed_cov, status);
   return kf_check_launch();
 }
 

@@ -79,7 +79,7 @@ def lib():
         L.kf_status_string.restype = ctypes.c_char_p
         L.kf_status_string.argtypes = [ctypes.c_int]
         L.kf_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
-        L.kf_seed.argtypes = [ctypes.POINTER(Geometry), I, I, P, P, P, P, P, P]
+        L.kf_seed.argtypes = [ctypes.POINTER(Geometry), I, I, P, ctypes.c_float, P, P, P, P, P]
         L.kf_fit.argtypes = [ctypes.POINTER(Geometry), I, I, I, P, P, P, P, P, P, P, P, P, P, I, P]
         if hasattr(L, "hit_bin"):
             L.hit_bin_workspace_bytes.restype = ctypes.c_size_t
@@ -148,8 +148,11 @@ def geometry(g) -> Geometry:
     return o
 
 
-def kf_seed(g, n, hits, stream=None):
-    """hits: [L][9][ld] float32 -> dict(q, par [6][ld], cov [21][ld], status)."""
+def kf_seed(g, n, hits, beam_sigma=None, stream=None):
+    """hits: [L][9][ld] float32 -> dict(q, par [6][ld], cov [21][ld], status).
+    beam_sigma: beam-spot width (cm) of the seed convention, default the
+    geometry's; 0 seeds from the three hits alone."""
+    bs = float(getattr(g, "beam_sigma", 0.0)) if beam_sigma is None else float(beam_sigma)
     ld = hits.shape[2]
     dev = hits.device
     out = dict(q=torch.zeros(ld, dtype=torch.int8, device=dev),
@@ -157,8 +160,8 @@ def kf_seed(g, n, hits, stream=None):
                cov=torch.zeros((21, ld), dtype=torch.float32, device=dev),
                status=torch.zeros(ld, dtype=torch.int32, device=dev))
     gg = geometry(g)
-    _check(lib().kf_seed(ctypes.byref(gg), n, ld, _ptr(hits), _ptr(out["q"]), _ptr(out["par"]), _ptr(out["cov"]),
-                         _ptr(out["status"]), _stream(stream)))
+    _check(lib().kf_seed(ctypes.byref(gg), n, ld, _ptr(hits), ctypes.c_float(bs), _ptr(out["q"]), _ptr(out["par"]),
+                         _ptr(out["cov"]), _ptr(out["status"]), _stream(stream)))
     return out
 
 

@@ -38,6 +38,9 @@ class Geometry:
     bz: float = f32(3.8)
     x_over_x0: float = f32(0.02)
     mass: float = f32(0.13957)
+    # transverse width of the luminous region about the z axis (the
+    # generator's vertex spread), used by the seed convention
+    beam_sigma: float = f32(0.01)
 
     def __post_init__(self):
         self.r = [f32(v) for v in self.r]
@@ -45,6 +48,7 @@ class Geometry:
         self.bz = f32(self.bz)
         self.x_over_x0 = f32(self.x_over_x0)
         self.mass = f32(self.mass)
+        self.beam_sigma = f32(self.beam_sigma)
 
     def replace(self, **kw) -> "Geometry":
         return dataclasses.replace(self, **kw)

@@ -96,7 +96,7 @@ def test_fit_ragged_sizes(kf, n):
 def test_fit_zero_noise_returns_generating_helix(kf):
     w = presets.fit_scale()
     g0 = w.geometry.replace(x_over_x0=0.0)
-    gen = dataclasses.replace(w.gen, smear=False)
+    gen = dataclasses.replace(w.gen, smear=False, vtx_sxy=0.0)
     ev = datagen.generate(g0, gen, 0, 2000, truth=True)
     n = ev.n_tracks
     H = fit_inputs(ev)

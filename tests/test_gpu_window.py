@@ -44,9 +44,10 @@ def oracle_blob(kf, t, kappa):
 
 def test_training_reduces_loss(env):
     t = env["t"]
-    print("rows", env["rows"].shape[0], "losses", [round(v, 5) for v in t.losses], "seconds", round(t.seconds, 2))
+    print("rows", env["rows"].shape[0], "initial loss", round(t.loss0, 5), "epoch losses",
+          [round(v, 5) for v in t.losses], "seconds", round(t.seconds, 2))
     assert env["rows"].shape[0] > 100_000
-    assert t.losses[-1] < 0.7 * t.losses[0]
+    assert t.losses[-1] < 0.5 * t.loss0 and t.losses[-1] <= t.losses[0]
     # the row labels are what the dump says they are: offsets to the true hit
     r = env["rows"]
     assert np.all(r[:, 27] >= 0) and np.all(r[:, 28] >= 0)

@@ -147,7 +147,7 @@ def test_cap_one_equals_greedy():
 def test_noise_free_event_recovers_true_hits():
     w = presets.build()
     g = w.geometry.replace(x_over_x0=0.0)
-    gen = dataclasses.replace(w.gen, smear=False, noise_lo=0.0, noise_hi=0.0, pt_max=3.0)
+    gen = dataclasses.replace(w.gen, smear=False, vtx_sxy=0.0, noise_lo=0.0, noise_hi=0.0, pt_max=3.0)
     ev, sd = _event_and_seeds(g, gen, 300)
     n = ev.n_tracks
     o = oracle.build(g, w.cuts, ev.layer, ev.xyz, ev.cov, sd["par"], sd["cov"], sd["q"], n)

@@ -14,19 +14,21 @@ from conftest import full_from_upper, upper_from_full
 
 
 def _zero_noise_event(w, n, x0=0.0):
-    gen = dataclasses.replace(w.gen, smear=False)
+    # no hit smearing, and every vertex on the z axis (the beam spot centre)
+    gen = dataclasses.replace(w.gen, smear=False, vtx_sxy=0.0)
     g = w.geometry.replace(x_over_x0=x0)
     ev = datagen.generate(g, gen, 0, n, truth=True)
     return g, ev
 
 
-@pytest.mark.parametrize("wl", [presets.fit_small, presets.fit_scale])
-def test_zero_noise_fit_returns_generating_helix(wl):
+@pytest.mark.parametrize("wl,beam", [(presets.fit_small, None), (presets.fit_scale, None), (presets.fit_small, 0.0)])
+def test_zero_noise_fit_returns_generating_helix(wl, beam):
+    """Both seed conventions (with the beam spot, and three hits alone)."""
     w = wl()
     g, ev = _zero_noise_event(w, 400)
     n = ev.n_tracks
     H = datagen.track_hits(ev, dtype=np.float64)
-    sd = oracle.seed64(g, H, n)
+    sd = oracle.seed64(g, H, n, beam_sigma=beam)
     assert np.all(sd["status"][:n] == 0)
     assert np.array_equal(sd["q"][:n], ev.q)
     # the seed itself is the truth at layer 2
@@ -131,7 +133,8 @@ def _kf_vs_least_squares(noise_scale):
     """Largest relative difference, over tracks, between the filter's state at
     the last layer and the batch least-squares solution propagated there."""
     w = presets.fit_small()
-    g = w.geometry.replace(x_over_x0=0.0)
+    # every error scales: the hits' and the beam spot's of the seed convention
+    g = w.geometry.replace(x_over_x0=0.0, beam_sigma=w.geometry.beam_sigma * noise_scale)
     gen = dataclasses.replace(w.gen, pt_max=3.0, sig_rphi=w.gen.sig_rphi * noise_scale,
                               sig_z=w.gen.sig_z * noise_scale)
     ev = datagen.generate(g, gen, 5, 12, truth=True)
