@@ -128,9 +128,10 @@ class Trained:
     block: torch.Tensor
     mu: np.ndarray
     sd: np.ndarray
-    losses: list
+    losses: list      # mean training loss of each epoch
     seconds: float
     steps: int
+    loss0: float = 0.0  # mean loss of the initial network over the first batches
 
 
 def train(rows: np.ndarray, epochs=4, batch=4096, lr=1e-3, seed=1711065715, log=None) -> Trained:
@@ -149,6 +150,13 @@ def train(rows: np.ndarray, epochs=4, batch=4096, lr=1e-3, seed=1711065715, log=
     gen.manual_seed(seed)
     losses = []
     step = 0
+    # loss of the initial network (gradients computed, no step taken)
+    acc0 = torch.zeros((), dtype=torch.float32, device=DEV)
+    nb0 = max(1, min(16, n // batch))
+    for b in range(nb0):
+        kf.kf_mlp_grad(block, data[b * batch:(b + 1) * batch], grad=grad, ws=ws)
+        acc0 += grad[-1]
+    loss0 = float(acc0.item()) / nb0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for ep in range(epochs):
@@ -166,7 +174,7 @@ def train(rows: np.ndarray, epochs=4, batch=4096, lr=1e-3, seed=1711065715, log=
         if log:
             log(f"epoch {ep} loss {losses[-1]:.5f}")
     torch.cuda.synchronize()
-    return Trained(master, block, mu, sd, losses, time.perf_counter() - t0, step)
+    return Trained(master, block, mu, sd, losses, time.perf_counter() - t0, step, loss0)
 
 
 def calibrate(w, t: Trained, val: EventOnGPU, eff_plain: float, target=0.001, kappas=None):
