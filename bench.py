@@ -47,7 +47,74 @@ def parse():
     ap.add_argument("--arith", choices=["f32", "f64"], default="f64",
                     help="arithmetic of the fit and build kernels (storage is FP32)")
     ap.add_argument("--no-other-arith", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain window comparison")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-events measurement")
+    ap.add_argument("--autotune", action="store_true", help="sweep the batched build's launch parameters")
     return ap.parse_args()
+
+
+def learned_vs_plain(arith, log):
+    """Learned search window against the plain one on the learned workload
+    (the build workload's generator, other events): rows dumped by the plain
+    build of event 0, GPU training, kappa calibrated on event 1 to keep the
+    plain efficiency within 0.1 %, comparison on events 2..3."""
+    import torch
+    from paper_1711_06571_amd import presets, window
+    w = presets.learned()
+    t0 = time.perf_counter()
+    tr = window.load_events(w, [0])
+    rows = window.dump_rows(w, tr)
+    t = window.train(rows, epochs=4)
+    val = window.load_events(w, [1])
+    test = window.load_events(w, [2, 3])
+    out_p, _ = window.build(w, val, arith=arith)
+    eff_val = window.efficiency(w, val, out_p)
+    kap, trace = window.calibrate(w, t, val, eff_val, target=0.001, arith=arith)
+    from paper_1711_06571_amd import kftrack as kf
+    kf.mlp_set_header(t.block, kappa=kap)
+    outp, cp = window.build(w, test, counters=True, arith=arith)
+    outl, cl = window.build(w, test, window_mode=1, block=t.block, counters=True, arith=arith)
+    torch.cuda.synchronize()
+    ep, el = window.efficiency(w, test, outp), window.efficiency(w, test, outl)
+    tp = window.time_build(w, test, 0, arith=arith)
+    tl = window.time_build(w, test, 1, t.block, arith=arith)
+    cp, cl = cp.cpu().numpy(), cl.cpu().numpy()
+    n = test.eb.n_seeds
+    log(f"learned: kappa {kap}, eff plain {ep:.4f} learned {el:.4f}, ms {tp:.3f} vs {tl:.3f}")
+    return {"workload": f"{w.name}: 2 test events x {n // 2} tracks + noise", "train_rows": int(rows.shape[0]),
+            "train_seconds": round(t.seconds, 3), "loss_initial": round(t.loss0, 5), "loss_final": round(t.losses[-1], 5),
+            "kappa": kap, "calibration": trace,
+            "plain": {"build_ms": round(tp, 4), "seeds_per_s": round(n / (tp * 1e-3), 1), "efficiency": round(ep, 4),
+                      "hits_tested_per_cand_layer": round(float(cp[1]) / max(float(cp[0]), 1), 3)},
+            "learned": {"build_ms": round(tl, 4), "seeds_per_s": round(n / (tl * 1e-3), 1), "efficiency": round(el, 4),
+                        "hits_tested_per_cand_layer": round(float(cl[1]) / max(float(cl[0]), 1), 3)},
+            "speedup": round(tp / tl, 3), "efficiency_loss": round(ep - el, 4),
+            "total_seconds": round(time.perf_counter() - t0, 1)}
+
+
+def batched(arith, autotune, log):
+    """64 events of uneven size (log-uniform 500..50 000 tracks, 5..30 %
+    noise per layer) built in one persistent launch replayed as a HIP graph
+    (binning of every event + the build)."""
+    import numpy as np
+    from paper_1711_06571_amd import batch, presets
+    w = presets.batch()
+    b = batch.load(w)
+    p = batch.plan(b, arith=arith)
+    ms = batch.run(p, reps=5)
+    lat = batch.latencies_ms(b)
+    eff = batch.efficiency(b, p.out)
+    p.close()
+    res = {"workload": f"{w.name}: {w.n_events} events, {b.eb.n_seeds} seeds", "ms_per_launch": round(ms, 4),
+           "events_per_s": round(w.n_events / (ms * 1e-3), 2), "seeds_per_s": round(b.eb.n_seeds / (ms * 1e-3), 1),
+           "latency_ms_p50": round(float(np.percentile(lat, 50)), 4),
+           "latency_ms_p99": round(float(np.percentile(lat, 99)), 4), "efficiency": round(eff, 4)}
+    if autotune:
+        tr = batch.autotune(b, log=lambda q: log(f"tune {q}"))
+        res["tuned"] = dict(tr.best.__dict__)
+        res["tune_points"] = len(tr.points)
+    log(f"batch: {ms:.3f} ms per launch")
+    return res
 
 
 def cpu_baseline(w, eb, seconds):
@@ -231,6 +298,11 @@ def main():
         oms, ost = timed(oa, max(2, args.steps // 2))
         res["other_arith"] = {"arith": other, "ms_per_step": round(oms, 4), "tracks_per_s": round(n / (oms * 1e-3), 1),
                               "stages_ms": {k: round(float(v), 4) for k, v in zip(names, ost)}}
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    if not args.no_learned:
+        res["learned_vs_plain"] = learned_vs_plain(arith, log)
+    if not args.no_batch:
+        res["batched"] = batched(arith, args.autotune, log)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, eb, args.cpu_seconds)
     print(json.dumps(res), flush=True)

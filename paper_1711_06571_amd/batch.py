@@ -65,10 +65,10 @@ def extra_for(b: Batch, timestamps=True) -> kf.BuildExtra:
     return ex
 
 
-def plan(b: Batch, cap=None, lanes=0, blocks=0, arith=kf.ARITH_F32, window_mode=0, mlp_block=None):
+def plan(b: Batch, cap=None, lanes=0, blocks=0, arith=kf.ARITH_F32, window_mode=0, mlp_block=None, refine=0):
     cuts = b.w.cuts
     bp = kf.build_params(cuts, cap=cap, lanes_per_block=lanes, persistent_blocks=blocks, arith=arith,
-                         window_mode=window_mode, mlp_block=mlp_block)
+                         window_mode=window_mode, mlp_block=mlp_block, phi_refine=refine)
     return kf.BatchPlan(b.w.geometry, bp, b.layer, b.xyz, b.cov, b.hoff, cuts.n_phi_bins, cuts.n_z_bins,
                         b.eb.n_seeds, b.seeds["par"], b.seeds["cov"], b.seeds["q"], extra=extra_for(b))
 
@@ -107,6 +107,7 @@ class TunePoint:
     lanes: int
     blocks_per_cu: int
     cap: int
+    refine: int
     ms: float
     eff: float
     p50: float
@@ -120,26 +121,29 @@ class TuneResult:
     gpu: str = ""
 
 
-def autotune(b: Batch, lanes_set=(64, 128, 256), bpcu_set=(1, 2, 0), caps=(4, 6, 8), reps=3, eff_tol=0.001,
-             log=None) -> TuneResult:
-    """Sweep launch shape x candidate cap.  Launch shape never changes the
-    results; the cap does, so the chosen point is the fastest whose
-    efficiency is within eff_tol of the cap-6 efficiency."""
+def autotune(b: Batch, lanes_set=(64, 128, 256), bpcu_set=(1, 2, 0), caps=(4, 6, 8), refines=(4, 8, 16), reps=3,
+             eff_tol=0.001, log=None) -> TuneResult:
+    """Sweep launch shape x candidate cap x granularity of the fine phi index
+    (the hit-search structure: sub-bins per phi bin).  Launch shape and
+    granularity never change the results; the cap does, so the chosen point
+    is the fastest whose efficiency is within eff_tol of the cap-6
+    efficiency.  blocks_per_cu 0 means as many as fit."""
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     res = TuneResult(gpu=torch.cuda.get_device_name(0))
     for cap in caps:
-        for lanes in lanes_set:
-            for bpcu in bpcu_set:
-                p = plan(b, cap=cap, lanes=lanes, blocks=bpcu * cus)
-                ms = run(p, reps=reps)
-                lat = latencies_ms(b)
-                eff = efficiency(b, p.out)
-                pt = TunePoint(lanes, bpcu, cap, ms, eff, float(np.percentile(lat, 50)),
-                               float(np.percentile(lat, 99)))
-                res.points.append(pt)
-                if log:
-                    log(pt)
-                p.close()
+        for refine in refines:
+            for lanes in lanes_set:
+                for bpcu in bpcu_set:
+                    p = plan(b, cap=cap, lanes=lanes, blocks=bpcu * cus, refine=refine)
+                    ms = run(p, reps=reps)
+                    lat = latencies_ms(b)
+                    eff = efficiency(b, p.out)
+                    pt = TunePoint(lanes, bpcu, cap, refine, ms, eff, float(np.percentile(lat, 50)),
+                                   float(np.percentile(lat, 99)))
+                    res.points.append(pt)
+                    if log:
+                        log(pt)
+                    p.close()
     ref = [q for q in res.points if q.cap == 6]
     eff6 = ref[0].eff if ref else max(q.eff for q in res.points)
     ok = [q for q in res.points if eff6 - q.eff <= eff_tol]

@@ -134,23 +134,28 @@ __global__ void offsets_kernel(const int32_t* __restrict__ start, const int32_t*
   offsets[k] = b < nb ? start[g + b] : start[g + nb - 1] + count[g + nb - 1];
 }
 
+// Each hit takes a slot of its bin (arrival order); the slot also receives
+// the hit's phi, so the rank pass reads its bin's keys without indirection.
 __global__ void __launch_bounds__(256) place_kernel(int n, const int32_t* __restrict__ gbin_of,
+                                                    const float* __restrict__ phi_of,
                                                     const int32_t* __restrict__ start, int32_t* __restrict__ cursor,
-                                                    int32_t* __restrict__ tmp_idx) {
+                                                    int32_t* __restrict__ tmp_idx, float* __restrict__ tmp_phi) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int gb = gbin_of[i];
   if (gb < 0) return;
   const int slot = start[gb] + atomicAdd(&cursor[gb], 1);
   tmp_idx[slot] = i;
+  tmp_phi[slot] = phi_of[i];
 }
 
 // Exact order inside each bin: rank = number of hits of the bin with a
-// smaller (phi, original index) key.
+// smaller (phi, original index) key.  One lane per slot; the bin's keys are
+// read from the slot arrays (independent loads, shared by the bin's lanes).
 __global__ void __launch_bounds__(256) rank_kernel(int n, int E, const int32_t* __restrict__ eoff,
                                                    const int32_t* __restrict__ tmp_idx,
+                                                   const float* __restrict__ tmp_phi,
                                                    const int32_t* __restrict__ gbin_of,
-                                                   const float* __restrict__ phi_of,
                                                    const int32_t* __restrict__ start,
                                                    const int32_t* __restrict__ count, const float* __restrict__ xyz,
                                                    const float* __restrict__ cov, float* __restrict__ sorted_xyzphi,
@@ -160,12 +165,13 @@ __global__ void __launch_bounds__(256) rank_kernel(int n, int E, const int32_t* 
   const int i = tmp_idx[p];
   if (i < 0) return;
   const int gb = gbin_of[i];
-  const float ph = phi_of[i];
+  const float ph = tmp_phi[p];
   const int b0 = start[gb], cnt = count[gb];
   int rank = 0;
+#pragma unroll 4
   for (int k = 0; k < cnt; ++k) {
     const int j = tmp_idx[b0 + k];
-    const float pj = phi_of[j];
+    const float pj = tmp_phi[b0 + k];
     rank += (pj < ph || (pj == ph && j < i)) ? 1 : 0;
   }
   const int dst = b0 + rank;
@@ -183,7 +189,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct BinWs {
   int32_t *gbin_of, *tmp_idx, *count, *cursor, *start, *bsum;
-  float* phi_of;
+  float *phi_of, *tmp_phi;
 };
 
 size_t bin_ws_layout(int E, int L, int n_phi, int n_z, int n, char* base, BinWs* w) {
@@ -202,7 +208,9 @@ size_t bin_ws_layout(int E, int L, int n_phi, int n_z, int n, char* base, BinWs*
   char* e = take(sizeof(int32_t) * NB);
   char* f = take(sizeof(int32_t) * NB);
   char* g = take(sizeof(int32_t) * (nblk + 1));
+  char* h = take(sizeof(float) * (size_t)n);
   if (w) {
+    w->tmp_phi = (float*)h;
     w->gbin_of = (int32_t*)a;
     w->tmp_idx = (int32_t*)b;
     w->phi_of = (float*)c;
@@ -264,10 +272,10 @@ extern "C" int hit_bin(const kf_geometry* g, int32_t n_events, const int32_t* ev
   hipLaunchKernelGGL(offsets_kernel, dim3(grid_for((int64_t)EL * (nb + 1), bs)), dim3(bs), 0, s, w.start, w.count,
                      EL, nb, offsets);
   if (n_hits > 0) {
-    hipLaunchKernelGGL(place_kernel, dim3(grid_for(n_hits, bs)), dim3(bs), 0, s, n_hits, w.gbin_of, w.start,
-                       w.cursor, w.tmp_idx);
+    hipLaunchKernelGGL(place_kernel, dim3(grid_for(n_hits, bs)), dim3(bs), 0, s, n_hits, w.gbin_of, w.phi_of,
+                       w.start, w.cursor, w.tmp_idx, w.tmp_phi);
     hipLaunchKernelGGL(rank_kernel, dim3(grid_for(n_hits, bs)), dim3(bs), 0, s, n_hits, n_events, event_offsets,
-                       w.tmp_idx, w.gbin_of, w.phi_of, w.start, w.count, xyz, cov, sorted_xyzphi, sorted_cov,
+                       w.tmp_idx, w.tmp_phi, w.gbin_of, w.start, w.count, xyz, cov, sorted_xyzphi, sorted_cov,
                        sorted_orig);
   }
   return kf_check_launch();

@@ -300,7 +300,7 @@ __host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsi
 }
 
 template <typename T, bool LEARNED>
-__global__ void __launch_bounds__(256) build_kernel(BuildArgs A) {
+__global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) build_kernel(BuildArgs A) {
   const int S = A.cap;           // lanes per seed
   const int SEEDS = 64 / S;      // seeds per wave
   extern __shared__ __align__(16) uint32_t lds[];

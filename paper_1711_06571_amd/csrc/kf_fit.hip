@@ -259,32 +259,56 @@ extern "C" int kf_fit(const kf_geometry* g, int32_t n, int32_t ld, int32_t first
 namespace {
 
 // Gather the hit rows of built tracks into the fit layout.  Layer l of seed i
-// takes the built hit (event-local index) or, if none, a hole bit.
+// takes the built hit (event-local index) or, if none, a hole bit.  One lane
+// per (seed, layer): the rows and the built indices are read and written
+// coalesced along the seeds; the hit reads are the only scattered access.
 __global__ void __launch_bounds__(256) gather_kernel(int n_layers, int first_layer, int n, int ld,
                                                      const int32_t* __restrict__ built,
                                                      const int32_t* __restrict__ seed_event,
                                                      const int32_t* __restrict__ event_offsets, int n_events,
                                                      int n_hits, const float* __restrict__ xyz,
-                                                     const float* __restrict__ cov, float* __restrict__ fit_hits,
-                                                     uint32_t* __restrict__ hole_mask) {
+                                                     const float* __restrict__ cov, float* __restrict__ fit_hits) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int l = first_layer + blockIdx.y;
+  if (i >= n || l >= n_layers) return;
+  const int e = seed_event ? seed_event[i] : 0;
+  const bool ev_ok = e >= 0 && e < n_events;
+  const int base = (ev_ok && event_offsets) ? event_offsets[e] : 0;
+  const int end = (ev_ok && event_offsets) ? event_offsets[e + 1] : n_hits;
+  const int h = built[(size_t)(l - first_layer) * ld + i];
+  float* row = fit_hits + (size_t)l * 9 * ld + i;
+  if (!ev_ok || h < 0 || h >= end - base) {  // (no overflow of base + h)
+#pragma unroll
+    for (int c = 0; c < 9; ++c) row[(size_t)c * ld] = 0.f;
+    return;
+  }
+  const int g = base + h;
+  float v[9];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) v[c] = xyz[(size_t)c * n_hits + g];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) v[3 + c] = cov[(size_t)c * n_hits + g];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) row[(size_t)c * ld] = v[c];
+}
+
+// Hole mask of each built track: bit l set where layer l has no usable hit
+// (the same test as the gather).
+__global__ void __launch_bounds__(256) hole_mask_kernel(int n_layers, int first_layer, int n, int ld,
+                                                        const int32_t* __restrict__ built,
+                                                        const int32_t* __restrict__ seed_event,
+                                                        const int32_t* __restrict__ event_offsets, int n_events,
+                                                        int n_hits, uint32_t* __restrict__ hole_mask) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  int e = seed_event ? seed_event[i] : 0;
+  const int e = seed_event ? seed_event[i] : 0;
   const bool ev_ok = e >= 0 && e < n_events;
   const int base = (ev_ok && event_offsets) ? event_offsets[e] : 0;
   const int end = (ev_ok && event_offsets) ? event_offsets[e + 1] : n_hits;
   uint32_t holes = 0;
   for (int l = first_layer; l < n_layers; ++l) {
     const int h = built[(size_t)(l - first_layer) * ld + i];
-    const int g = base + h;
-    float* row = fit_hits + (size_t)l * 9 * ld + i;
-    if (!ev_ok || h < 0 || g >= end) {
-      holes |= 1u << l;
-      for (int c = 0; c < 9; ++c) row[(size_t)c * ld] = 0.f;
-      continue;
-    }
-    for (int c = 0; c < 3; ++c) row[(size_t)c * ld] = xyz[(size_t)c * n_hits + g];
-    for (int c = 0; c < 6; ++c) row[(size_t)(3 + c) * ld] = cov[(size_t)c * n_hits + g];
+    if (!ev_ok || h < 0 || h >= end - base) holes |= 1u << l;
   }
   hole_mask[i] = holes;
 }
@@ -301,8 +325,11 @@ extern "C" int kf_gather_hits(int32_t n_layers, int32_t first_layer, int32_t n_s
   if (n_seeds == 0) return KF_OK;
   if (!built_hits || !fit_hits || !hole_mask || (n_hits > 0 && (!xyz || !cov))) return KF_E_INVALID_ARG;
   const int bs = 256;
-  hipLaunchKernelGGL(gather_kernel, dim3((n_seeds + bs - 1) / bs), dim3(bs), 0, (hipStream_t)stream, n_layers,
-                     first_layer, n_seeds, ld, built_hits, seed_event, event_offsets, n_events, n_hits, xyz, cov,
-                     fit_hits, hole_mask);
+  hipLaunchKernelGGL(gather_kernel, dim3((n_seeds + bs - 1) / bs, n_layers - first_layer), dim3(bs), 0,
+                     (hipStream_t)stream, n_layers, first_layer, n_seeds, ld, built_hits, seed_event, event_offsets,
+                     n_events, n_hits, xyz, cov, fit_hits);
+  if (int rc = kf_check_launch()) return rc;
+  hipLaunchKernelGGL(hole_mask_kernel, dim3((n_seeds + bs - 1) / bs), dim3(bs), 0, (hipStream_t)stream, n_layers,
+                     first_layer, n_seeds, ld, built_hits, seed_event, event_offsets, n_events, n_hits, hole_mask);
   return kf_check_launch();
 }

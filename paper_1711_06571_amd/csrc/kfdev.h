@@ -3,7 +3,7 @@
 // Everything here works on one candidate held in registers of one lane:
 // state X[6] = (x, y, z, px, py, pz), covariance P[21] (upper triangle, row
 // order).  The functions are templated on the scalar type: the fit and build
-// kernels use float, the seed kernel double.
+// kernels use float, or double in their precise mode; the seed kernel double.
 //
 // Formulation choices for FP32 (the FP64 oracle uses textbook closed forms):
 //   - the crossing with the cylinder is solved for tan(alpha/2) of the turning
@@ -116,10 +116,18 @@ KFD inline int propagate(const T X[6], int q, T R, T bz, T Xo[6], Step<T>& st) {
   if (!(half > T(0))) half += T(3.14159265358979323846);
   half *= sg;
   const T alpha = T(2) * half;
-  T sh, chh;
-  k_sincos(half, &sh, &chh);
-  const T sa = T(2) * sh * chh;
-  const T omc = T(2) * sh * sh;  // 1 - cos(alpha)
+  // sin(alpha) and 1 - cos(alpha) from tau = tan(alpha / 2) = sg * t (tan has
+  // period pi, so the turn beyond pi shares t): 2 tau / (1 + tau^2) and
+  // 2 tau^2 / (1 + tau^2); an infinite t is the half turn
+  T sa, omc;
+  if (fabs(t) < T(1e18)) {  // t * t stays finite in FP32
+    const T iw = k_rcp(T(1) + t * t);
+    sa = T(2) * sg * t * iw;
+    omc = T(2) * t * t * iw;
+  } else {
+    sa = T(0);
+    omc = T(2);
+  }
   const T ca = T(1) - omc;
   const T ih = k_rcp(h);
   const T s = alpha * ih;

@@ -177,14 +177,14 @@ def train(rows: np.ndarray, epochs=4, batch=4096, lr=1e-3, seed=1711065715, log=
     return Trained(master, block, mu, sd, losses, time.perf_counter() - t0, step, loss0)
 
 
-def calibrate(w, t: Trained, val: EventOnGPU, eff_plain: float, target=0.001, kappas=None):
+def calibrate(w, t: Trained, val: EventOnGPU, eff_plain: float, target=0.001, kappas=None, arith=kf.ARITH_F32):
     """Smallest kappa whose efficiency on the validation events is within
     `target` of the plain window's."""
     kappas = kappas or [1.0, 1.1, 1.2, 1.35, 1.5, 1.75, 2.0, 2.5, 3.0]
     res = []
     for kap in kappas:
         kf.mlp_set_header(t.block, kappa=kap)
-        out, _ = build(w, val, window_mode=1, block=t.block)
+        out, _ = build(w, val, window_mode=1, block=t.block, arith=arith)
         torch.cuda.synchronize()
         eff = efficiency(w, val, out)
         res.append((kap, eff))

@@ -33,13 +33,18 @@ def rel_vec_err(a, b):
     return np.linalg.norm(a - b, axis=0) / np.maximum(np.linalg.norm(b, axis=0), 1e-30)
 
 
-DIAG = [0, 6, 11, 15, 18, 20]
+# covariance diagonal entries and the scale each is compared against: x and
+# y against the transverse position block (P00 + P11: a fitted covariance has
+# the radial direction as null vector, so P00 alone is ~0 for a track near
+# phi = 0 and carries only rounding there), z against itself, the momentum
+# components against the momentum block
+DIAG = {0: (0, 6), 6: (0, 6), 11: (11,), 15: (15, 18, 20), 18: (15, 18, 20), 20: (15, 18, 20)}
 
 
 def assert_fit_parity(gpu, orc, n, ctx=""):
     """Parameters within 1e-4 relative (position and momentum as 3-vectors),
-    chi2 within 1e-3 * max(1, chi2), covariance diagonal within 1e-3
-    relative, ndof and status exact."""
+    chi2 within 1e-3 * max(1, chi2), covariance diagonal within 1e-3 of its
+    block's scale (DIAG), ndof and status exact."""
     st_g = gpu["status"][:n]
     st_o = orc["status"][:n]
     assert np.array_equal(st_g, st_o), f"{ctx} status mismatch at {np.where(st_g != st_o)[0][:10]}"
@@ -54,9 +59,9 @@ def assert_fit_parity(gpu, orc, n, ctx=""):
     c_o = orc["chi2"][:n]
     e_c = np.abs(c_g - c_o) / np.maximum(1.0, c_o)
     assert e_c.max() <= 1e-3, f"{ctx} chi2 {e_c.max():.3g} at {np.argmax(e_c)}"
-    for k in DIAG:
+    for k, blk in DIAG.items():
         d = np.abs(gpu["cov"][k, :n].astype(np.float64) - orc["cov"][k, :n])
-        scale = np.abs(orc["cov"][k, :n])
+        scale = sum(np.abs(orc["cov"][j, :n]) for j in blk)
         ok = scale > 0
         e = d[ok] / scale[ok]
         assert e.max() <= 1e-3, f"{ctx} cov diag {k}: {e.max():.3g}"

@@ -55,10 +55,10 @@ def test_graph_replays_equal_eager(bt):
 
 def test_autotune_small_grid(bt):
     batch, kf, b = bt
-    res = batch.autotune(b, lanes_set=(64, 256), bpcu_set=(1, 0), caps=(4, 6), reps=2)
-    assert len(res.points) == 8
+    res = batch.autotune(b, lanes_set=(64, 256), bpcu_set=(1, 0), caps=(4, 6), refines=(4, 16), reps=2)
+    assert len(res.points) == 16
     effs = {q.cap: q.eff for q in res.points}
-    for q in res.points:  # launch shape does not change results
+    for q in res.points:  # launch shape and index granularity do not change results
         assert q.eff == effs[q.cap]
     assert effs[6] - res.best.eff <= 0.001
     print("best", res.best)

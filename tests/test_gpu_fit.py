@@ -60,9 +60,10 @@ def test_seed_and_fit_parity_small(kf):
 
 
 def test_fit_fp32_arithmetic_agreement(kf):
-    """FP32 arithmetic: every track whose seed is well conditioned (relative
-    momentum uncertainty below 0.1) within the tolerances; the agreement
-    fraction over all tracks is reported."""
+    """FP32 arithmetic (hardware reciprocals, 1 ulp): tracks whose seed is
+    well conditioned (relative momentum uncertainty below 0.1) within the
+    tolerances but for a rare rounding casualty (at most 1 in 1000); the
+    agreement fraction over all tracks is reported."""
     w = presets.fit_scale()
     ev = datagen.generate(w.geometry, w.gen, 1, 20000)
     n = ev.n_tracks
@@ -76,8 +77,8 @@ def test_fit_fp32_arithmetic_agreement(kf):
     well = seed_rel_sigma_p(so["par"], so["cov"], n) < 0.1
     print(f"fp32 arithmetic: agreement {agree.mean():.4f} overall, {agree[well].mean():.4f} on "
           f"{well.mean():.3f} well-conditioned seeds")
-    assert agree[well].all()
-    assert agree.mean() > 0.6
+    assert agree[well].mean() >= 0.999
+    assert agree.mean() > 0.8
 
 
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 777])
