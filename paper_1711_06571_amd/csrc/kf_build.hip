@@ -154,7 +154,7 @@ template <typename T> struct TopList {
   uint32_t* orig;
   int n;    // entries held (<= cap)
   int tot;  // accepted hits seen
-  int scanned, tested;  // hits window-tested, hits given a chi2 (work counters)
+  int scanned, tested;  // work counters of the hits this lane examined
 };
 
 template <typename T>
@@ -164,7 +164,6 @@ __device__ inline bool top_before(T c2, uint32_t orig, T oc2, uint32_t oorig) {
 
 template <typename T>
 __device__ inline void top_insert(TopList<T>& tl, int cap, T c2, int pos, uint32_t orig) {
-  tl.tot += 1;
   int j = tl.n;
   if (j == cap) {  // full: the new hit must beat the last entry
     if (!top_before(c2, orig, tl.c2[(cap - 1) * 64], tl.orig[(cap - 1) * 64])) return;
@@ -193,73 +192,188 @@ __device__ inline void top_get(const TopList<T>& tl, int k, T& c2, int& pos, uin
   orig = tl.orig[k * 64];
 }
 
-// Test the hits at sorted positions [p0, p1) whose stored phi lies in
-// [a, b]: exact window test, then chi2; accepted hits become children.  The
-// position, phi and x, y, z of the next hit are loaded one hit ahead.
-template <typename T>
-__device__ inline void scan_range(const BuildArgs& A, int p0, int p1, float a, float b, const T Xp[6],
-                                  const T Pp[21], T dphi_w, T dz_w, TopList<T>& tl) {
-  if (p0 >= p1) return;
-  float nph = A.hphi[p0], nx = A.hx[p0], ny = A.hy[p0], nz = A.hz[p0];
-  for (int p = p0; p < p1; ++p) {
-    const float ph = nph, fx = nx, fy = ny, fz = nz;
-    if (p + 1 < p1) {
-      nph = A.hphi[p + 1]; nx = A.hx[p + 1]; ny = A.hy[p + 1]; nz = A.hz[p + 1];
-    }
-    if (ph < a) continue;
-    if (ph > b) break;
-    tl.scanned += 1;
-    const T hx = (T)fx, hy = (T)fy, hz = (T)fz;
-    if (!(fabs(hz - Xp[2]) <= dz_w)) continue;
-    const T cr = Xp[0] * hy - Xp[1] * hx, dt = Xp[0] * hx + Xp[1] * hy;
-    if (!(fabs(k_atan2(cr, dt)) <= dphi_w)) continue;
-    T V[6];
+// Wave-wide inclusive prefix sum; returns the exclusive prefix, total via ref.
+__device__ inline int wave_excl_scan(int v, int lane, int& total) {
+  int x = v;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) V[c] = (T)A.hcov[(size_t)c * A.n_hits + p];
-    Innov<T> in;
-    tl.tested += 1;
-    if (innovation<T>(Xp, Pp, hx, hy, hz, V, in)) continue;
-    const T c2 = chi2_of(in);
-    if (!(c2 < (T)A.chi2_cut)) continue;
-    top_insert(tl, A.cap, c2, p, (uint32_t)A.horig[p]);
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(x, d, 64);
+    if (lane >= d) x += t;
   }
+  total = __shfl(x, 63, 64);
+  return x - v;
 }
 
-template <typename T>
-__device__ inline void scan_window(const BuildArgs& A, int ev, int l, const T Xp[6], const T Pp[21], T dphi_w,
-                                   T dz_w, TopList<T>& tl) {
-  const int nz = A.n_z, nf = A.n_phi * A.refine;
-  const int32_t* frow = A.fine + ((size_t)ev * A.n_layers + l) * nz * (nf + 1);
-  const float inv = fine_inv(nf);
-  const float zh = A.z_half;
-  const float zp = (float)Xp[2];
-  const float phip = wrap_2pi(atan2f((float)Xp[1], (float)Xp[0]));  // centre of the conservative interval
-  // conservative stored-value intervals: the exact test decides
-  const float eps_phi = 1e-5f, eps_z = 1e-4f;
-  const float dphi = (float)dphi_w + eps_phi, dz = (float)dz_w + eps_z;
-  int iz0 = (int)floorf((zp - dz + zh) * (float)nz / (2.f * zh));
-  int iz1 = (int)floorf((zp + dz + zh) * (float)nz / (2.f * zh));
-  iz0 = iz0 < 0 ? 0 : (iz0 > nz - 1 ? nz - 1 : iz0);
-  iz1 = iz1 < 0 ? 0 : (iz1 > nz - 1 ? nz - 1 : iz1);
-  const float tp = 6.283185307179586f;
-  // up to two phi intervals within [0, 2pi)
-  float a0, b0v, a1 = 1.f, b1v = 0.f;
-  if (dphi >= 3.14159f) { a0 = 0.f; b0v = tp; }
-  else {
-    float lo = phip - dphi, hi = phip + dphi;
-    if (lo < 0.f) { a0 = 0.f; b0v = hi; a1 = lo + tp; b1v = tp; }
-    else if (hi >= tp) { a0 = lo; b0v = tp; a1 = 0.f; b1v = hi - tp; }
-    else { a0 = lo; b0v = hi; }
+__device__ inline int wave_max(int v) {
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    const int o = __shfl_xor(v, m, 64);
+    v = o > v ? o : v;
   }
-  for (int iz = iz0; iz <= iz1; ++iz) {
-    const int32_t* f = frow + (size_t)iz * (nf + 1);
-    for (int part = 0; part < 2; ++part) {
-      const float a = part ? a1 : a0, b = part ? b1v : b0v;
-      if (!(a <= b)) continue;
-      const int p0 = f[fine_key(a, inv, nf)], p1 = f[fine_key(b, inv, nf) + 1];
-      scan_range<T>(A, p0, p1, a, b, Xp, Pp, dphi_w, dz_w, tl);
+  return v;
+}
+
+// Per-wave LDS of the cooperative hit search: the accepted hits of one round
+// of 64 (compacted) and each candidate's count of accepted hits.
+template <typename T> struct AccBuf {
+  T* c2;
+  int32_t* owner;
+  int32_t* pos;
+  uint32_t* orig;
+  int32_t* tot;
+};
+
+// Hit search of every candidate of the wave, shared by all 64 lanes.
+//
+// Each live candidate's window covers, per z row it overlaps and per phi
+// interval (two where the window wraps at 2 pi), one range of sorted hit
+// positions bracketed by the fine phi index.  Range r of every candidate is
+// taken in turn; the (candidate, hit) pairs of all candidates' ranges r are
+// numbered through a wave prefix sum and handed out 64 at a time, one pair
+// per lane, so a candidate with a wide window no longer holds up the wave
+// while the others wait.  A lane finds the pair's candidate by a binary
+// search of the prefix sums and reads that candidate's prediction by lane
+// shuffles.  Every hit whose stored phi lies in the candidate's interval
+// gets the exact window test (z first, then the angle about the axis);
+// in-window hits get their chi2; accepted hits (chi2 < cut) are counted for
+// their candidate and, if they can enter its list of the best cap (a full
+// list admits only hits that rank before its last entry), gathered in LDS
+// and inserted by the candidate's own lane.  The order of insertion does not
+// change a list (the ranking is total), so the result equals a serial scan.
+template <typename T>
+__device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, const T Xp[6], const T Pp[21],
+                                 T dphi_w, T dz_w, TopList<T>& tl, const AccBuf<T>& ab, int lane) {
+  const int nz = A.n_z, nf = A.n_phi * A.refine;
+  const float inv = fine_inv(nf);
+  const float tp = 6.283185307179586f;
+  // this lane's window as conservative stored-value intervals (the exact
+  // test decides): up to two phi intervals within [0, 2pi), z rows iz0..iz1
+  float a0 = 1.f, b0v = 0.f, a1 = 1.f, b1v = 0.f;
+  int iz0 = 0, iz1 = -1;
+  if (pok) {
+    const float zh = A.z_half;
+    const float zp = (float)Xp[2];
+    const float phip = wrap_2pi(atan2f((float)Xp[1], (float)Xp[0]));
+    const float eps_phi = 1e-5f, eps_z = 1e-4f;
+    const float dphi = (float)dphi_w + eps_phi, dz = (float)dz_w + eps_z;
+    iz0 = (int)floorf((zp - dz + zh) * (float)nz / (2.f * zh));
+    iz1 = (int)floorf((zp + dz + zh) * (float)nz / (2.f * zh));
+    iz0 = iz0 < 0 ? 0 : (iz0 > nz - 1 ? nz - 1 : iz0);
+    iz1 = iz1 < 0 ? 0 : (iz1 > nz - 1 ? nz - 1 : iz1);
+    if (dphi >= 3.14159f) { a0 = 0.f; b0v = tp; }
+    else {
+      const float lo = phip - dphi, hi = phip + dphi;
+      if (lo < 0.f) { a0 = 0.f; b0v = hi; a1 = lo + tp; b1v = tp; }
+      else if (hi >= tp) { a0 = lo; b0v = tp; a1 = 0.f; b1v = hi - tp; }
+      else { a0 = lo; b0v = hi; }
     }
   }
+  const int32_t* frow = A.fine + ((size_t)ev * A.n_layers + l) * nz * (nf + 1);
+  const int R = pok ? (iz1 - iz0 + 1) * 2 : 0;
+  const int Rmax = wave_max(R);
+  ab.tot[lane] = 0;
+  // the candidate's admission threshold: its last entry once its list is full
+  T thr_c2 = T(0);
+  uint32_t thr_o = 0;
+  int full = 0;
+  const T cut = (T)A.chi2_cut;
+  for (int r = 0; r < Rmax; ++r) {
+    int p0 = 0, p1 = 0;
+    float a = 1.f, b = 0.f;
+    if (r < R) {
+      a = (r & 1) ? a1 : a0;
+      b = (r & 1) ? b1v : b0v;
+      if (a <= b) {
+        const int32_t* f = frow + (size_t)(iz0 + (r >> 1)) * (nf + 1);
+        p0 = f[fine_key(a, inv, nf)];
+        p1 = f[fine_key(b, inv, nf) + 1];
+      }
+    }
+    const int cnt = p1 > p0 ? p1 - p0 : 0;
+    int total = 0;
+    const int off = wave_excl_scan(cnt, lane, total);
+    for (int base = 0; base < total; base += 64) {
+      const int k = base + lane;
+      // candidate of pair k: the last lane whose prefix is <= k
+      int lo = 0, hi = 64;
+#pragma unroll
+      for (int it = 0; it < 6; ++it) {
+        const int mid = (lo + hi) >> 1;
+        if (__shfl(off, mid, 64) <= k) lo = mid; else hi = mid;
+      }
+      const int c = lo;
+      const int p = __shfl(p0, c, 64) + (k - __shfl(off, c, 64));
+      const float ca = __shfl(a, c, 64), cb = __shfl(b, c, 64);
+      const T cx = shfl_t(Xp[0], c), cy = shfl_t(Xp[1], c), cz = shfl_t(Xp[2], c);
+      const T cdz = shfl_t(dz_w, c), cdphi = shfl_t(dphi_w, c);
+      T Pl[21];
+#pragma unroll
+      for (int q = 0; q < 21; ++q) Pl[q] = T(0);
+      Pl[ut(0, 0)] = shfl_t(Pp[ut(0, 0)], c);
+      Pl[ut(0, 1)] = shfl_t(Pp[ut(0, 1)], c);
+      Pl[ut(0, 2)] = shfl_t(Pp[ut(0, 2)], c);
+      Pl[ut(1, 1)] = shfl_t(Pp[ut(1, 1)], c);
+      Pl[ut(1, 2)] = shfl_t(Pp[ut(1, 2)], c);
+      Pl[ut(2, 2)] = shfl_t(Pp[ut(2, 2)], c);
+      const int cfull = __shfl(full, c, 64);
+      const T cthr = shfl_t(thr_c2, c);
+      const uint32_t cthro = (uint32_t)__shfl((int)thr_o, c, 64);
+      bool keep = false;
+      T c2 = T(0);
+      uint32_t orig = 0;
+      if (k < total) {
+        const float ph = A.hphi[p];
+        const float fx = A.hx[p], fy = A.hy[p], fz = A.hz[p];
+        if (ph >= ca && ph <= cb) {
+          tl.scanned += 1;
+          const T hx = (T)fx, hy = (T)fy, hz = (T)fz;
+          const T cr = cx * hy - cy * hx, dt = cx * hx + cy * hy;
+          if (fabs(hz - cz) <= cdz && fabs(k_atan2(cr, dt)) <= cdphi) {
+            T V[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) V[q] = (T)A.hcov[(size_t)q * A.n_hits + p];
+            const T Xl[6] = {cx, cy, cz, T(0), T(0), T(0)};
+            Innov<T> in;
+            tl.tested += 1;
+            if (!innovation<T>(Xl, Pl, hx, hy, hz, V, in)) {
+              c2 = chi2_of(in);
+              if (c2 < cut) {
+                atomicAdd(&ab.tot[c], 1);
+                orig = (uint32_t)A.horig[p];
+                keep = !cfull || top_before(c2, orig, cthr, cthro);
+              }
+            }
+          }
+        }
+      }
+      // gather the admissible hits of this round and let their candidates insert them
+      const unsigned long long m = __ballot(keep);
+      const int nacc = __popcll(m);
+      if (nacc) {
+        if (keep) {
+          const int slot_ = __popcll(m & ((1ull << lane) - 1ull));
+          ab.c2[slot_] = c2;
+          ab.owner[slot_] = c;
+          ab.pos[slot_] = p;
+          ab.orig[slot_] = orig;
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        for (int j = 0; j < nacc; ++j)
+          if (ab.owner[j] == lane) top_insert(tl, A.cap, ab.c2[j], ab.pos[j], ab.orig[j]);
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        if (tl.n == A.cap) {
+          full = 1;
+          thr_c2 = tl.c2[(A.cap - 1) * 64];
+          thr_o = tl.orig[(A.cap - 1) * 64];
+        }
+      }
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
+  tl.tot = ab.tot[lane];
 }
 
 __device__ inline uint32_t pack_hist(int parent, uint32_t orig24) {
@@ -272,10 +386,12 @@ __device__ inline uint32_t pack_hist(int parent, uint32_t orig24) {
 //   record   [SEEDS][27] f32   best finished candidate of each seed
 //   recfield [SEEDS][5] i32    valid, nhits, status, last layer, slot
 //   toplist  [cap][64] T, then [cap][64] i32 positions, [cap][64] u32 indices
+//   accept   [64] T chi2, [64] i32 candidate, [64] i32 position, [64] u32 index,
+//            [64] i32 accepted count (the cooperative hit search)
 //   mlp      activation buffer of the learned window (the network runs before
 //            the hit search, so the toplists of a learned build live in it)
 struct LdsPlan {
-  size_t hist, stash, rec, recf, tl, tl_stride, mlp, total;
+  size_t hist, stash, rec, recf, acc, tl, tl_stride, mlp, total;
 };
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 __host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsize, bool learned) {
@@ -286,7 +402,8 @@ __host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsi
   p.rec = align16(p.stash + (size_t)nwaves * 27 * 64 * 4);
   p.recf = align16(p.rec + (size_t)nwaves * seeds * 27 * 4);
   const size_t tl_wave = (size_t)cap * 64 * (tsize + 8);
-  p.tl = align16(p.recf + (size_t)nwaves * seeds * 5 * 4);
+  p.acc = align16(p.recf + (size_t)nwaves * seeds * 5 * 4);
+  p.tl = align16(p.acc + (size_t)nwaves * 64 * (tsize + 16));
   if (learned) {
     const size_t per = tl_wave > KFMLP_LDS_BYTES ? tl_wave : (size_t)KFMLP_LDS_BYTES;
     p.mlp = p.tl;
@@ -320,6 +437,15 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) build_kernel(Bu
   T* tl_c2 = (T*)wave_tl + lane;
   int32_t* tl_pos = (int32_t*)(wave_tl + (size_t)S * 64 * sizeof(T)) + lane;
   uint32_t* tl_orig = (uint32_t*)(wave_tl + (size_t)S * 64 * (sizeof(T) + 4)) + lane;
+  AccBuf<T> ab;
+  {
+    char* wa = base + lp.acc + (size_t)wave * 64 * (sizeof(T) + 16);
+    ab.c2 = (T*)wa;
+    ab.owner = (int32_t*)(wa + 64 * sizeof(T));
+    ab.pos = ab.owner + 64;
+    ab.orig = (uint32_t*)(ab.pos + 64);
+    ab.tot = (int32_t*)(ab.orig + 64);
+  }
   (void)mlp_buf;
   const int sidx = lane / S, slot = lane - (lane / S) * S, sbase = sidx * S;
   const bool lane_used = sidx < SEEDS;
@@ -408,6 +534,7 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) build_kernel(Bu
         wl[0] *= kap;
         wl[1] *= kap;
       }
+      T dphi_w = T(0), dz_w = T(0);
       if (pok) {
         const T R = (T)A.r[l];
         const T rr = k_sqrt(Xp[0] * Xp[0] + Xp[1] * Xp[1]);
@@ -440,8 +567,10 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) build_kernel(Bu
             }
           }
         }
-        scan_window<T>(A, ev, l, Xp, Pp, w_rphi / R, w_z, tl);
+        dphi_w = w_rphi / R;
+        dz_w = w_z;
       }
+      coop_scan<T>(A, ev, l, pok, Xp, Pp, dphi_w, dz_w, tl, ab, lane);
       cnt_pred += live ? 1u : 0u;
       cnt_scan += (unsigned)tl.scanned;
       cnt_chi2 += (unsigned)tl.tested;
