@@ -270,6 +270,22 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
   }
   const int32_t* frow = A.fine + ((size_t)ev * A.n_layers + l) * nz * (nf + 1);
   const int R = pok ? (iz1 - iz0 + 1) * 2 : 0;
+  // Per candidate, what every hit test shares: the exact angle test
+  // |atan2(cross, dot)| <= dphi is, for dphi < pi/2, dot > 0 and
+  // |cross| <= tan(dphi) dot (wider windows keep the angle); the measurement
+  // frame (tangent t at the predicted point) and H P H^T of the prediction.
+  const bool wide = !(dphi_w < T(1.5707963267948966));
+  const T tanw = (pok && !wide) ? k_tan(dphi_w) : T(0);
+  T utx = T(0), uty = T(0), suu = T(0), suw = T(0), sww = T(0);
+  if (pok) {
+    const T rr = k_sqrt(Xp[0] * Xp[0] + Xp[1] * Xp[1]);
+    const T irr = k_rcp(rr);
+    utx = -Xp[1] * irr;
+    uty = Xp[0] * irr;
+    suu = utx * utx * Pp[ut(0, 0)] + T(2) * utx * uty * Pp[ut(0, 1)] + uty * uty * Pp[ut(1, 1)];
+    suw = utx * Pp[ut(0, 2)] + uty * Pp[ut(1, 2)];
+    sww = Pp[ut(2, 2)];
+  }
   const int Rmax = wave_max(R);
   ab.tot[lane] = 0;
   // the candidate's admission threshold: its last entry once its list is full
@@ -305,16 +321,10 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
       const int p = __shfl(p0, c, 64) + (k - __shfl(off, c, 64));
       const float ca = __shfl(a, c, 64), cb = __shfl(b, c, 64);
       const T cx = shfl_t(Xp[0], c), cy = shfl_t(Xp[1], c), cz = shfl_t(Xp[2], c);
-      const T cdz = shfl_t(dz_w, c), cdphi = shfl_t(dphi_w, c);
-      T Pl[21];
-#pragma unroll
-      for (int q = 0; q < 21; ++q) Pl[q] = T(0);
-      Pl[ut(0, 0)] = shfl_t(Pp[ut(0, 0)], c);
-      Pl[ut(0, 1)] = shfl_t(Pp[ut(0, 1)], c);
-      Pl[ut(0, 2)] = shfl_t(Pp[ut(0, 2)], c);
-      Pl[ut(1, 1)] = shfl_t(Pp[ut(1, 1)], c);
-      Pl[ut(1, 2)] = shfl_t(Pp[ut(1, 2)], c);
-      Pl[ut(2, 2)] = shfl_t(Pp[ut(2, 2)], c);
+      const T cdz = shfl_t(dz_w, c), cdphi = shfl_t(dphi_w, c), ctan = shfl_t(tanw, c);
+      const int cwide = __shfl((int)wide, c, 64);
+      const T ctx = shfl_t(utx, c), cty = shfl_t(uty, c);
+      const T csuu = shfl_t(suu, c), csuw = shfl_t(suw, c), csww = shfl_t(sww, c);
       const int cfull = __shfl(full, c, 64);
       const T cthr = shfl_t(thr_c2, c);
       const uint32_t cthro = (uint32_t)__shfl((int)thr_o, c, 64);
@@ -328,15 +338,20 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
           tl.scanned += 1;
           const T hx = (T)fx, hy = (T)fy, hz = (T)fz;
           const T cr = cx * hy - cy * hx, dt = cx * hx + cy * hy;
-          if (fabs(hz - cz) <= cdz && fabs(k_atan2(cr, dt)) <= cdphi) {
+          const bool in_phi = cwide ? fabs(k_atan2(cr, dt)) <= cdphi : (dt > T(0) && fabs(cr) <= ctan * dt);
+          if (fabs(hz - cz) <= cdz && in_phi) {
             T V[6];
 #pragma unroll
             for (int q = 0; q < 6; ++q) V[q] = (T)A.hcov[(size_t)q * A.n_hits + p];
-            const T Xl[6] = {cx, cy, cz, T(0), T(0), T(0)};
-            Innov<T> in;
+            // innovation in the tangent-plane frame and its chi2 (2 dof)
             tl.tested += 1;
-            if (!innovation<T>(Xl, Pl, hx, hy, hz, V, in)) {
-              c2 = chi2_of(in);
+            const T r0 = ctx * (hx - cx) + cty * (hy - cy), r1 = hz - cz;
+            const T s00 = csuu + ctx * ctx * V[0] + T(2) * ctx * cty * V[1] + cty * cty * V[3];
+            const T s01 = csuw + ctx * V[2] + cty * V[4];
+            const T s11 = csww + V[5];
+            const T det = s00 * s11 - s01 * s01;
+            if (s00 > T(0) && det > T(0)) {
+              c2 = (s11 * r0 * r0 - T(2) * s01 * r0 * r1 + s00 * r1 * r1) * k_rcp(det);
               if (c2 < cut) {
                 atomicAdd(&ab.tot[c], 1);
                 orig = (uint32_t)A.horig[p];

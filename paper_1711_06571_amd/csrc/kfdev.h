@@ -54,6 +54,8 @@ KFD inline void k_sincos(float a, float* s, float* c) { sincosf(a, s, c); }
 KFD inline void k_sincos(double a, double* s, double* c) { sincos(a, s, c); }
 KFD inline float k_atan2(float y, float x) { return atan2f(y, x); }
 KFD inline double k_atan2(double y, double x) { return atan2(y, x); }
+KFD inline float k_tan(float v) { return tanf(v); }
+KFD inline double k_tan(double v) { return tan(v); }
 KFD inline float k_atan(float v) { return atanf(v); }
 KFD inline double k_atan(double v) { return atan(v); }
 KFD inline float k_log(float v) { return logf(v); }
