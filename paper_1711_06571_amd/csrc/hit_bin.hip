@@ -150,39 +150,52 @@ __global__ void __launch_bounds__(256) place_kernel(int n, const int32_t* __rest
 }
 
 // Exact order inside each bin: rank = number of hits of the bin with a
-// smaller (phi, original index) key.  One lane per slot; the bin's keys are
-// read from the slot arrays (independent loads, shared by the bin's lanes).
-__global__ void __launch_bounds__(256) rank_kernel(int n, int E, const int32_t* __restrict__ eoff,
+// smaller (phi, original index) key.  One wave per bin: each lane holds one
+// hit of the bin and compares it with every hit of the bin, which the wave
+// passes around by shuffles 64 at a time (bins larger than 64 hits loop over
+// blocks of 64).  The hit is then written to its slot in the sorted arrays.
+__global__ void __launch_bounds__(256) rank_kernel(int NB, int n, int L, int nb_el,
+                                                   const int32_t* __restrict__ eoff,
                                                    const int32_t* __restrict__ tmp_idx,
                                                    const float* __restrict__ tmp_phi,
-                                                   const int32_t* __restrict__ gbin_of,
                                                    const int32_t* __restrict__ start,
                                                    const int32_t* __restrict__ count, const float* __restrict__ xyz,
                                                    const float* __restrict__ cov, float* __restrict__ sorted_xyzphi,
                                                    float* __restrict__ sorted_cov, int32_t* __restrict__ sorted_orig) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const int i = tmp_idx[p];
-  if (i < 0) return;
-  const int gb = gbin_of[i];
-  const float ph = tmp_phi[p];
+  const int gb = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (gb >= NB) return;
   const int b0 = start[gb], cnt = count[gb];
-  int rank = 0;
-#pragma unroll 4
-  for (int k = 0; k < cnt; ++k) {
-    const int j = tmp_idx[b0 + k];
-    const float pj = tmp_phi[b0 + k];
-    rank += (pj < ph || (pj == ph && j < i)) ? 1 : 0;
-  }
-  const int dst = b0 + rank;
-  const int e = eoff ? event_of(eoff, E, i) : 0;
-  sorted_xyzphi[dst] = xyz[i];
-  sorted_xyzphi[(size_t)n + dst] = xyz[(size_t)n + i];
-  sorted_xyzphi[2 * (size_t)n + dst] = xyz[2 * (size_t)n + i];
-  sorted_xyzphi[3 * (size_t)n + dst] = ph;
+  if (cnt == 0) return;
+  // the event of the bin: bins are numbered (event * L + layer) * nb_el + bin
+  const int ev_base = eoff ? eoff[gb / (L * nb_el)] : 0;
+  for (int c0 = 0; c0 < cnt; c0 += 64) {
+    const bool mine = c0 + lane < cnt;
+    const int i = mine ? tmp_idx[b0 + c0 + lane] : 0;
+    const float ph = mine ? tmp_phi[b0 + c0 + lane] : 0.f;
+    int rank = 0;
+    for (int d0 = 0; d0 < cnt; d0 += 64) {
+      const bool theirs = d0 + lane < cnt;
+      const int oi = theirs ? tmp_idx[b0 + d0 + lane] : 0;
+      const float op = theirs ? tmp_phi[b0 + d0 + lane] : 0.f;
+      const int m = cnt - d0 < 64 ? cnt - d0 : 64;
+      for (int t = 0; t < m; ++t) {
+        const float pj = __shfl(op, t, 64);
+        const int j = __shfl(oi, t, 64);
+        rank += (pj < ph || (pj == ph && j < i)) ? 1 : 0;
+      }
+    }
+    if (mine) {
+      const int dst = b0 + rank;
+      sorted_xyzphi[dst] = xyz[i];
+      sorted_xyzphi[(size_t)n + dst] = xyz[(size_t)n + i];
+      sorted_xyzphi[2 * (size_t)n + dst] = xyz[2 * (size_t)n + i];
+      sorted_xyzphi[3 * (size_t)n + dst] = ph;
 #pragma unroll
-  for (int c = 0; c < 6; ++c) sorted_cov[(size_t)c * n + dst] = cov[(size_t)c * n + i];
-  sorted_orig[dst] = i - (eoff ? eoff[e] : 0);
+      for (int c = 0; c < 6; ++c) sorted_cov[(size_t)c * n + dst] = cov[(size_t)c * n + i];
+      sorted_orig[dst] = i - ev_base;
+    }
+  }
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -274,8 +287,8 @@ extern "C" int hit_bin(const kf_geometry* g, int32_t n_events, const int32_t* ev
   if (n_hits > 0) {
     hipLaunchKernelGGL(place_kernel, dim3(grid_for(n_hits, bs)), dim3(bs), 0, s, n_hits, w.gbin_of, w.phi_of,
                        w.start, w.cursor, w.tmp_idx, w.tmp_phi);
-    hipLaunchKernelGGL(rank_kernel, dim3(grid_for(n_hits, bs)), dim3(bs), 0, s, n_hits, n_events, event_offsets,
-                       w.tmp_idx, w.tmp_phi, w.gbin_of, w.start, w.count, xyz, cov, sorted_xyzphi, sorted_cov,
+    hipLaunchKernelGGL(rank_kernel, dim3(grid_for(NB, bs / 64)), dim3(bs), 0, s, (int)NB, n_hits, L, nb,
+                       event_offsets, w.tmp_idx, w.tmp_phi, w.start, w.count, xyz, cov, sorted_xyzphi, sorted_cov,
                        sorted_orig);
   }
   return kf_check_launch();

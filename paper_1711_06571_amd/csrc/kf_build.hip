@@ -89,6 +89,16 @@ __device__ inline double shfl_d(double v, int src) {
   return __longlong_as_double((long long)shfl_u64(b, src));
 }
 __device__ inline float shfl_t(float v, int src) { return __shfl(v, src, 64); }
+// value of lane j (j uniform across the wave)
+__device__ inline float readlane_t(float v, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+__device__ inline double readlane_t(double v, int j) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, j);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), j);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
 __device__ inline double shfl_t(double v, int src) { return shfl_d(v, src); }
 
 // Reductions over the S lanes base .. base+S-1 of one seed (S <= 8, any
@@ -213,13 +223,9 @@ __device__ inline int wave_max(int v) {
   return v;
 }
 
-// Per-wave LDS of the cooperative hit search: the accepted hits of one round
-// of 64 (compacted) and each candidate's count of accepted hits.
+// Per-wave LDS of the cooperative hit search: each candidate's count of
+// accepted hits.
 template <typename T> struct AccBuf {
-  T* c2;
-  int32_t* owner;
-  int32_t* pos;
-  uint32_t* orig;
   int32_t* tot;
 };
 
@@ -332,8 +338,15 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
       T c2 = T(0);
       uint32_t orig = 0;
       if (k < total) {
+        // everything the pair can need, in one round trip (the hits of an
+        // event layer are L2-resident; a second dependent round trip for
+        // the covariance of in-window hits costs more than the bytes)
         const float ph = A.hphi[p];
         const float fx = A.hx[p], fy = A.hy[p], fz = A.hz[p];
+        float fv[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) fv[q] = A.hcov[(size_t)q * A.n_hits + p];
+        const uint32_t forig = (uint32_t)A.horig[p];
         if (ph >= ca && ph <= cb) {
           tl.scanned += 1;
           const T hx = (T)fx, hy = (T)fy, hz = (T)fz;
@@ -342,7 +355,7 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
           if (fabs(hz - cz) <= cdz && in_phi) {
             T V[6];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) V[q] = (T)A.hcov[(size_t)q * A.n_hits + p];
+            for (int q = 0; q < 6; ++q) V[q] = (T)fv[q];
             // innovation in the tangent-plane frame and its chi2 (2 dof)
             tl.tested += 1;
             const T r0 = ctx * (hx - cx) + cty * (hy - cy), r1 = hz - cz;
@@ -354,30 +367,26 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
               c2 = (s11 * r0 * r0 - T(2) * s01 * r0 * r1 + s00 * r1 * r1) * k_rcp(det);
               if (c2 < cut) {
                 atomicAdd(&ab.tot[c], 1);
-                orig = (uint32_t)A.horig[p];
+                orig = forig;
                 keep = !cfull || top_before(c2, orig, cthr, cthro);
               }
             }
           }
         }
       }
-      // gather the admissible hits of this round and let their candidates insert them
-      const unsigned long long m = __ballot(keep);
-      const int nacc = __popcll(m);
-      if (nacc) {
-        if (keep) {
-          const int slot_ = __popcll(m & ((1ull << lane) - 1ull));
-          ab.c2[slot_] = c2;
-          ab.owner[slot_] = c;
-          ab.pos[slot_] = p;
-          ab.orig[slot_] = orig;
+      // the admissible hits of this round, one at a time (in lane order), go
+      // to their candidate's lane, which inserts them into its list
+      unsigned long long m = __ballot(keep);
+      if (m) {
+        while (m) {
+          const int j = __builtin_ctzll(m);
+          m &= m - 1ull;
+          const int jc = __builtin_amdgcn_readlane(c, j);
+          const T jc2 = readlane_t(c2, j);
+          const int jp = __builtin_amdgcn_readlane(p, j);
+          const uint32_t jo = (uint32_t)__builtin_amdgcn_readlane((int)orig, j);
+          if (lane == jc) top_insert(tl, A.cap, jc2, jp, jo);
         }
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
-        for (int j = 0; j < nacc; ++j)
-          if (ab.owner[j] == lane) top_insert(tl, A.cap, ab.c2[j], ab.pos[j], ab.orig[j]);
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
         if (tl.n == A.cap) {
           full = 1;
           thr_c2 = tl.c2[(A.cap - 1) * 64];
@@ -401,8 +410,7 @@ __device__ inline uint32_t pack_hist(int parent, uint32_t orig24) {
 //   record   [SEEDS][27] f32   best finished candidate of each seed
 //   recfield [SEEDS][5] i32    valid, nhits, status, last layer, slot
 //   toplist  [cap][64] T, then [cap][64] i32 positions, [cap][64] u32 indices
-//   accept   [64] T chi2, [64] i32 candidate, [64] i32 position, [64] u32 index,
-//            [64] i32 accepted count (the cooperative hit search)
+//   accept   [64] i32 accepted hits per candidate (the cooperative hit search)
 //   mlp      activation buffer of the learned window (the network runs before
 //            the hit search, so the toplists of a learned build live in it)
 struct LdsPlan {
@@ -418,7 +426,7 @@ __host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsi
   p.recf = align16(p.rec + (size_t)nwaves * seeds * 27 * 4);
   const size_t tl_wave = (size_t)cap * 64 * (tsize + 8);
   p.acc = align16(p.recf + (size_t)nwaves * seeds * 5 * 4);
-  p.tl = align16(p.acc + (size_t)nwaves * 64 * (tsize + 16));
+  p.tl = align16(p.acc + (size_t)nwaves * 64 * 4);
   if (learned) {
     const size_t per = tl_wave > KFMLP_LDS_BYTES ? tl_wave : (size_t)KFMLP_LDS_BYTES;
     p.mlp = p.tl;
@@ -453,14 +461,7 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) build_kernel(Bu
   int32_t* tl_pos = (int32_t*)(wave_tl + (size_t)S * 64 * sizeof(T)) + lane;
   uint32_t* tl_orig = (uint32_t*)(wave_tl + (size_t)S * 64 * (sizeof(T) + 4)) + lane;
   AccBuf<T> ab;
-  {
-    char* wa = base + lp.acc + (size_t)wave * 64 * (sizeof(T) + 16);
-    ab.c2 = (T*)wa;
-    ab.owner = (int32_t*)(wa + 64 * sizeof(T));
-    ab.pos = ab.owner + 64;
-    ab.orig = (uint32_t*)(ab.pos + 64);
-    ab.tot = (int32_t*)(ab.orig + 64);
-  }
+  ab.tot = (int32_t*)(base + lp.acc) + (size_t)wave * 64;
   (void)mlp_buf;
   const int sidx = lane / S, slot = lane - (lane / S) * S, sbase = sidx * S;
   const bool lane_used = sidx < SEEDS;
