@@ -72,9 +72,31 @@ __host__ __device__ inline uint16_t f_to_bf16(float f) {
 
 __host__ __device__ inline float bf16_round(float f) { return bf16_to_f(f_to_bf16(f)); }
 
-__device__ inline float gelu(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
+// erf(x) by Abramowitz & Stegun, Handbook of Mathematical Functions, 7.1.26
+// (after Hastings): 1 - (a1 t + ... + a5 t^5) exp(-x^2), t = 1 / (1 + p|x|),
+// absolute error below 1.5e-7 (the activations are then rounded to BF16,
+// whose resolution is 2^-8).  Branch-free; the caller passes exp(-x^2).
+__device__ inline float erf_as(float x, float e) {
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(1.f + 0.3275911f * ax);
+  float poly = 1.061405429f;
+  poly = fmaf(poly, t, -1.453152027f);
+  poly = fmaf(poly, t, 1.421413741f);
+  poly = fmaf(poly, t, -0.284496736f);
+  poly = fmaf(poly, t, 0.254829592f);
+  const float v = 1.f - poly * t * e;
+  return copysignf(v, x);
+}
+// GELU(z) = z Phi(z) = z (1 + erf(z / sqrt 2)) / 2, and its derivative
+// Phi(z) + z phi(z); exp(-z^2 / 2) serves both erf and phi.
+__device__ inline float gelu(float z) {
+  const float x = z * 0.70710678118654752f;
+  return 0.5f * z * (1.f + erf_as(x, __expf(-x * x)));
+}
 __device__ inline float gelu_grad(float z) {
-  return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
+  const float x = z * 0.70710678118654752f;
+  const float e = __expf(-x * x);
+  return 0.5f * (1.f + erf_as(x, e)) + z * 0.39894228040143268f * e;
 }
 __device__ inline float softplus(float o) { return o > 30.f ? o : log1pf(__expf(o)); }
 __device__ inline float sigmoid(float o) { return 1.f / (1.f + __expf(-o)); }
