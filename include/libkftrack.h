@@ -235,6 +235,19 @@ int kf_build(const kf_geometry* g, const kf_build_params* bp, const kf_hits* hit
              float* out_cov, float* out_chi2, int32_t* out_nhits, int32_t* out_status,
              const kf_build_extra* extra, void* ws, size_t ws_bytes, void* stream);
 
+/* Launch shape chosen by the last kf_build call of the calling host thread
+ * (zeros before the first): lanes per block, blocks of the persistent grid,
+ * dynamic LDS bytes per block, blocks per CU the occupancy calculator allows,
+ * the device's LDS limit per block. */
+typedef struct {
+  int32_t lanes_per_block;
+  int32_t blocks;
+  int32_t lds_bytes;
+  int32_t resident_blocks_per_cu;
+  int32_t max_lds_per_block;
+} kf_build_launch_info;
+int kf_build_last_launch(kf_build_launch_info* info);
+
 /*
  * Learned search window (an addition to the method: the paper sizes the hit
  * search from the covariance).  A device block of kf_mlp_block_bytes() bytes

@@ -17,7 +17,8 @@
 //      shuffles; the winners take the slots 0..cap-1;
 //   5. the new slots pull the parent's predicted state by shuffles and apply
 //      the Kalman update with their hit;
-//   6. back-pointers (parent slot, hit) go to an LDS history table; the best
+//   6. back-pointers (parent slot, hit) go to the wave's history table in the
+//      workspace; the best
 //      hit list is recovered at the end by walking it backwards.
 // Candidates with no child compete for a per-seed best-finished record (LDS).
 #include <stdint.h>
@@ -54,6 +55,7 @@ struct BuildArgs {
   int n_hits;
   int refine;            // sub-bins per phi bin in the fine index
   const int32_t* fine;   // [events][layers][n_z][n_phi * refine + 1]
+  uint32_t* hist;        // [resident waves][searched layers][64] back-pointers
   // seeds
   int n_seeds, ld, n_groups;
   const float *seed_par, *seed_cov;
@@ -158,8 +160,9 @@ __host__ __device__ inline float fine_inv(int nf) { return (float)nf / 6.2831853
 // A lane's accepted hits, best first (chi2 ascending, hit index ascending),
 // at most cap of them.  The entries live in LDS, [cap][64] per wave, so that
 // the list costs no registers; this lane's column starts at c2 / pos / orig.
-template <typename T> struct TopList {
-  T* c2;
+// chi2 is kept in FP32 (the hit search computes it in FP32, see coop_scan).
+struct TopList {
+  float* c2;
   int32_t* pos;
   uint32_t* orig;
   int n;    // entries held (<= cap)
@@ -167,13 +170,11 @@ template <typename T> struct TopList {
   int scanned, tested;  // work counters of the hits this lane examined
 };
 
-template <typename T>
-__device__ inline bool top_before(T c2, uint32_t orig, T oc2, uint32_t oorig) {
-  return (float)c2 < (float)oc2 || ((float)c2 == (float)oc2 && orig < oorig);
+__device__ inline bool top_before(float c2, uint32_t orig, float oc2, uint32_t oorig) {
+  return c2 < oc2 || (c2 == oc2 && orig < oorig);
 }
 
-template <typename T>
-__device__ inline void top_insert(TopList<T>& tl, int cap, T c2, int pos, uint32_t orig) {
+__device__ inline void top_insert(TopList& tl, int cap, float c2, int pos, uint32_t orig) {
   int j = tl.n;
   if (j == cap) {  // full: the new hit must beat the last entry
     if (!top_before(c2, orig, tl.c2[(cap - 1) * 64], tl.orig[(cap - 1) * 64])) return;
@@ -182,7 +183,7 @@ __device__ inline void top_insert(TopList<T>& tl, int cap, T c2, int pos, uint32
     tl.n += 1;
   }
   while (j > 0) {
-    const T pc = tl.c2[(j - 1) * 64];
+    const float pc = tl.c2[(j - 1) * 64];
     const uint32_t po = tl.orig[(j - 1) * 64];
     if (!top_before(c2, orig, pc, po)) break;
     tl.c2[j * 64] = pc;
@@ -195,8 +196,7 @@ __device__ inline void top_insert(TopList<T>& tl, int cap, T c2, int pos, uint32
   tl.orig[j * 64] = orig;
 }
 
-template <typename T>
-__device__ inline void top_get(const TopList<T>& tl, int k, T& c2, int& pos, uint32_t& orig) {
+__device__ inline void top_get(const TopList& tl, int k, float& c2, int& pos, uint32_t& orig) {
   c2 = tl.c2[k * 64];
   pos = tl.pos[k * 64];
   orig = tl.orig[k * 64];
@@ -225,7 +225,7 @@ __device__ inline int wave_max(int v) {
 
 // Per-wave LDS of the cooperative hit search: each candidate's count of
 // accepted hits.
-template <typename T> struct AccBuf {
+struct AccBuf {
   int32_t* tot;
 };
 
@@ -238,17 +238,23 @@ template <typename T> struct AccBuf {
 // numbered through a wave prefix sum and handed out 64 at a time, one pair
 // per lane, so a candidate with a wide window no longer holds up the wave
 // while the others wait.  A lane finds the pair's candidate by a binary
-// search of the prefix sums and reads that candidate's prediction by lane
-// shuffles.  Every hit whose stored phi lies in the candidate's interval
+// search of the prefix sums and reads what that candidate's tests share by
+// lane shuffles.  Every hit whose stored phi lies in the candidate's interval
 // gets the exact window test (z first, then the angle about the axis);
 // in-window hits get their chi2; accepted hits (chi2 < cut) are counted for
 // their candidate and, if they can enter its list of the best cap (a full
-// list admits only hits that rank before its last entry), gathered in LDS
-// and inserted by the candidate's own lane.  The order of insertion does not
+// list admits only hits that rank before its last entry), handed to the
+// candidate's lane, which inserts them.  The order of insertion does not
 // change a list (the ranking is total), so the result equals a serial scan.
+//
+// The tests and chi2 run in FP32 in both arithmetic modes, from the
+// prediction rounded to FP32: their rounding (chi2 ~ 3e-5 at the cut,
+// positions ~ 1e-5 cm) stays far below the chi2 gaps (1e-3) and window-edge
+// distances (1e-4 cm) that separate decisions; the Kalman update of a
+// chosen hit runs in the arithmetic of the mode.
 template <typename T>
 __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, const T Xp[6], const T Pp[21],
-                                 T dphi_w, T dz_w, TopList<T>& tl, const AccBuf<T>& ab, int lane) {
+                                 T dphi_w, T dz_w, TopList& tl, const AccBuf& ab, int lane) {
   const int nz = A.n_z, nf = A.n_phi * A.refine;
   const float inv = fine_inv(nf);
   const float tp = 6.283185307179586f;
@@ -256,14 +262,25 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
   // test decides): up to two phi intervals within [0, 2pi), z rows iz0..iz1
   float a0 = 1.f, b0v = 0.f, a1 = 1.f, b1v = 0.f;
   int iz0 = 0, iz1 = -1;
+  // Per candidate, what every hit test shares: for dphi < pi/2 the angle
+  // test |atan2(cross, dot)| <= dphi is dot > 0 and |cross| <= tan(dphi) dot
+  // (wider windows keep the angle); the measurement frame (tangent t at the
+  // predicted point) and H P H^T of the prediction.
+  float fx = 0.f, fy = 0.f, fz = 0.f, fdz = 0.f, fdphi = 0.f, ftan = 0.f;
+  float utx = 0.f, uty = 0.f, suu = 0.f, suw = 0.f, sww = 0.f;
+  int wide = 0;
   if (pok) {
     const float zh = A.z_half;
-    const float zp = (float)Xp[2];
-    const float phip = wrap_2pi(atan2f((float)Xp[1], (float)Xp[0]));
+    fx = (float)Xp[0];
+    fy = (float)Xp[1];
+    fz = (float)Xp[2];
+    fdz = (float)dz_w;
+    fdphi = (float)dphi_w;
+    const float phip = wrap_2pi(atan2f(fy, fx));
     const float eps_phi = 1e-5f, eps_z = 1e-4f;
-    const float dphi = (float)dphi_w + eps_phi, dz = (float)dz_w + eps_z;
-    iz0 = (int)floorf((zp - dz + zh) * (float)nz / (2.f * zh));
-    iz1 = (int)floorf((zp + dz + zh) * (float)nz / (2.f * zh));
+    const float dphi = fdphi + eps_phi, dz = fdz + eps_z;
+    iz0 = (int)floorf((fz - dz + zh) * (float)nz / (2.f * zh));
+    iz1 = (int)floorf((fz + dz + zh) * (float)nz / (2.f * zh));
     iz0 = iz0 < 0 ? 0 : (iz0 > nz - 1 ? nz - 1 : iz0);
     iz1 = iz1 < 0 ? 0 : (iz1 > nz - 1 ? nz - 1 : iz1);
     if (dphi >= 3.14159f) { a0 = 0.f; b0v = tp; }
@@ -273,32 +290,26 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
       else if (hi >= tp) { a0 = lo; b0v = tp; a1 = 0.f; b1v = hi - tp; }
       else { a0 = lo; b0v = hi; }
     }
+    wide = !(dphi_w < T(1.5707963267948966));
+    ftan = wide ? 0.f : (float)k_tan(dphi_w);
+    const T rr = k_sqrt(Xp[0] * Xp[0] + Xp[1] * Xp[1]);
+    const T irr = k_rcp(rr);
+    const T tx = -Xp[1] * irr, ty = Xp[0] * irr;
+    utx = (float)tx;
+    uty = (float)ty;
+    suu = (float)(tx * tx * Pp[ut(0, 0)] + T(2) * tx * ty * Pp[ut(0, 1)] + ty * ty * Pp[ut(1, 1)]);
+    suw = (float)(tx * Pp[ut(0, 2)] + ty * Pp[ut(1, 2)]);
+    sww = (float)Pp[ut(2, 2)];
   }
   const int32_t* frow = A.fine + ((size_t)ev * A.n_layers + l) * nz * (nf + 1);
   const int R = pok ? (iz1 - iz0 + 1) * 2 : 0;
-  // Per candidate, what every hit test shares: the exact angle test
-  // |atan2(cross, dot)| <= dphi is, for dphi < pi/2, dot > 0 and
-  // |cross| <= tan(dphi) dot (wider windows keep the angle); the measurement
-  // frame (tangent t at the predicted point) and H P H^T of the prediction.
-  const bool wide = !(dphi_w < T(1.5707963267948966));
-  const T tanw = (pok && !wide) ? k_tan(dphi_w) : T(0);
-  T utx = T(0), uty = T(0), suu = T(0), suw = T(0), sww = T(0);
-  if (pok) {
-    const T rr = k_sqrt(Xp[0] * Xp[0] + Xp[1] * Xp[1]);
-    const T irr = k_rcp(rr);
-    utx = -Xp[1] * irr;
-    uty = Xp[0] * irr;
-    suu = utx * utx * Pp[ut(0, 0)] + T(2) * utx * uty * Pp[ut(0, 1)] + uty * uty * Pp[ut(1, 1)];
-    suw = utx * Pp[ut(0, 2)] + uty * Pp[ut(1, 2)];
-    sww = Pp[ut(2, 2)];
-  }
   const int Rmax = wave_max(R);
   ab.tot[lane] = 0;
   // the candidate's admission threshold: its last entry once its list is full
-  T thr_c2 = T(0);
+  float thr_c2 = 0.f;
   uint32_t thr_o = 0;
   int full = 0;
-  const T cut = (T)A.chi2_cut;
+  const float cut = A.chi2_cut;
   for (int r = 0; r < Rmax; ++r) {
     int p0 = 0, p1 = 0;
     float a = 1.f, b = 0.f;
@@ -326,45 +337,41 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
       const int c = lo;
       const int p = __shfl(p0, c, 64) + (k - __shfl(off, c, 64));
       const float ca = __shfl(a, c, 64), cb = __shfl(b, c, 64);
-      const T cx = shfl_t(Xp[0], c), cy = shfl_t(Xp[1], c), cz = shfl_t(Xp[2], c);
-      const T cdz = shfl_t(dz_w, c), cdphi = shfl_t(dphi_w, c), ctan = shfl_t(tanw, c);
-      const int cwide = __shfl((int)wide, c, 64);
-      const T ctx = shfl_t(utx, c), cty = shfl_t(uty, c);
-      const T csuu = shfl_t(suu, c), csuw = shfl_t(suw, c), csww = shfl_t(sww, c);
+      const float cx = __shfl(fx, c, 64), cy = __shfl(fy, c, 64), cz = __shfl(fz, c, 64);
+      const float cdz = __shfl(fdz, c, 64), cdphi = __shfl(fdphi, c, 64), ctan = __shfl(ftan, c, 64);
+      const int cwide = __shfl(wide, c, 64);
+      const float ctx = __shfl(utx, c, 64), cty = __shfl(uty, c, 64);
+      const float csuu = __shfl(suu, c, 64), csuw = __shfl(suw, c, 64), csww = __shfl(sww, c, 64);
       const int cfull = __shfl(full, c, 64);
-      const T cthr = shfl_t(thr_c2, c);
+      const float cthr = __shfl(thr_c2, c, 64);
       const uint32_t cthro = (uint32_t)__shfl((int)thr_o, c, 64);
       bool keep = false;
-      T c2 = T(0);
+      float c2 = 0.f;
       uint32_t orig = 0;
       if (k < total) {
-        // everything the pair can need, in one round trip (the hits of an
-        // event layer are L2-resident; a second dependent round trip for
-        // the covariance of in-window hits costs more than the bytes)
+        // everything the pair can need, in one round trip (a second
+        // dependent round trip for the covariance of in-window hits costs
+        // more than the bytes)
         const float ph = A.hphi[p];
-        const float fx = A.hx[p], fy = A.hy[p], fz = A.hz[p];
-        float fv[6];
+        const float hx = A.hx[p], hy = A.hy[p], hz = A.hz[p];
+        float V[6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) fv[q] = A.hcov[(size_t)q * A.n_hits + p];
+        for (int q = 0; q < 6; ++q) V[q] = A.hcov[(size_t)q * A.n_hits + p];
         const uint32_t forig = (uint32_t)A.horig[p];
         if (ph >= ca && ph <= cb) {
           tl.scanned += 1;
-          const T hx = (T)fx, hy = (T)fy, hz = (T)fz;
-          const T cr = cx * hy - cy * hx, dt = cx * hx + cy * hy;
-          const bool in_phi = cwide ? fabs(k_atan2(cr, dt)) <= cdphi : (dt > T(0) && fabs(cr) <= ctan * dt);
-          if (fabs(hz - cz) <= cdz && in_phi) {
-            T V[6];
-#pragma unroll
-            for (int q = 0; q < 6; ++q) V[q] = (T)fv[q];
+          const float cr = cx * hy - cy * hx, dt = cx * hx + cy * hy;
+          const bool in_phi = cwide ? fabsf(atan2f(cr, dt)) <= cdphi : (dt > 0.f && fabsf(cr) <= ctan * dt);
+          if (fabsf(hz - cz) <= cdz && in_phi) {
             // innovation in the tangent-plane frame and its chi2 (2 dof)
             tl.tested += 1;
-            const T r0 = ctx * (hx - cx) + cty * (hy - cy), r1 = hz - cz;
-            const T s00 = csuu + ctx * ctx * V[0] + T(2) * ctx * cty * V[1] + cty * cty * V[3];
-            const T s01 = csuw + ctx * V[2] + cty * V[4];
-            const T s11 = csww + V[5];
-            const T det = s00 * s11 - s01 * s01;
-            if (s00 > T(0) && det > T(0)) {
-              c2 = (s11 * r0 * r0 - T(2) * s01 * r0 * r1 + s00 * r1 * r1) * k_rcp(det);
+            const float r0 = ctx * (hx - cx) + cty * (hy - cy), r1 = hz - cz;
+            const float s00 = csuu + ctx * ctx * V[0] + 2.f * ctx * cty * V[1] + cty * cty * V[3];
+            const float s01 = csuw + ctx * V[2] + cty * V[4];
+            const float s11 = csww + V[5];
+            const float det = s00 * s11 - s01 * s01;
+            if (s00 > 0.f && det > 0.f) {
+              c2 = (s11 * r0 * r0 - 2.f * s01 * r0 * r1 + s00 * r1 * r1) / det;
               if (c2 < cut) {
                 atomicAdd(&ab.tot[c], 1);
                 orig = forig;
@@ -382,7 +389,7 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
           const int j = __builtin_ctzll(m);
           m &= m - 1ull;
           const int jc = __builtin_amdgcn_readlane(c, j);
-          const T jc2 = readlane_t(c2, j);
+          const float jc2 = readlane_t(c2, j);
           const int jp = __builtin_amdgcn_readlane(p, j);
           const uint32_t jo = (uint32_t)__builtin_amdgcn_readlane((int)orig, j);
           if (lane == jc) top_insert(tl, A.cap, jc2, jp, jo);
@@ -405,26 +412,26 @@ __device__ inline uint32_t pack_hist(int parent, uint32_t orig24) {
 }
 
 // LDS of one block (byte offsets), per wave:
-//   history  [LB][64] u32      back-pointers (parent slot << 24 | hit index)
 //   stash    [27][64] f32      each slot's state before this layer's prediction
 //   record   [SEEDS][27] f32   best finished candidate of each seed
 //   recfield [SEEDS][5] i32    valid, nhits, status, last layer, slot
-//   toplist  [cap][64] T, then [cap][64] i32 positions, [cap][64] u32 indices
+//   toplist  [cap][64] f32 chi2, then [cap][64] i32 positions, [cap][64] u32 indices
 //   accept   [64] i32 accepted hits per candidate (the cooperative hit search)
 //   mlp      activation buffer of the learned window (the network runs before
 //            the hit search, so the toplists of a learned build live in it)
 struct LdsPlan {
-  size_t hist, stash, rec, recf, acc, tl, tl_stride, mlp, total;
+  size_t stash, rec, recf, acc, tl, tl_stride, mlp, total;
 };
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 __host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsize, bool learned) {
   const int seeds = 64 / cap;
   LdsPlan p;
-  p.hist = 0;
-  p.stash = align16(p.hist + (size_t)nwaves * LB * 64 * 4);
+  (void)LB;
+  p.stash = 0;
   p.rec = align16(p.stash + (size_t)nwaves * 27 * 64 * 4);
   p.recf = align16(p.rec + (size_t)nwaves * seeds * 27 * 4);
-  const size_t tl_wave = (size_t)cap * 64 * (tsize + 8);
+  (void)tsize;
+  const size_t tl_wave = (size_t)cap * 64 * 12;
   p.acc = align16(p.recf + (size_t)nwaves * seeds * 5 * 4);
   p.tl = align16(p.acc + (size_t)nwaves * 64 * 4);
   if (learned) {
@@ -449,9 +456,13 @@ __host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsi
 #ifndef KF_BUILD_F64_WAVES
 #define KF_BUILD_F64_WAVES 2
 #endif
+#ifndef KF_BUILD_F64_LEARNED_WAVES
+#define KF_BUILD_F64_LEARNED_WAVES 2
+#endif
 
 template <typename T, bool LEARNED>
-__global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES : KF_BUILD_F64_WAVES))
+__global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
+                                                       : (LEARNED ? KF_BUILD_F64_LEARNED_WAVES : KF_BUILD_F64_WAVES)))
     build_kernel(BuildArgs A) {
   const int S = A.cap;           // lanes per seed
   const int SEEDS = 64 / S;      // seeds per wave
@@ -462,17 +473,19 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES : KF
   const int LB = A.n_layers - A.first_layer;  // searched layers
   const LdsPlan lp = lds_plan(LB, nwaves, S, (int)sizeof(T), LEARNED);
   char* base = (char*)lds;
-  uint32_t* hist = (uint32_t*)(base + lp.hist) + (size_t)wave * LB * 64;
+  // this wave's back-pointer table (written once per new candidate and layer,
+  // read once per seed at the end)
+  uint32_t* hist = A.hist + ((size_t)blockIdx.x * nwaves + wave) * LB * 64;
   float* stash = (float*)(base + lp.stash) + (size_t)wave * 27 * 64;
   float* fin = (float*)(base + lp.rec) + (size_t)wave * SEEDS * 27;
   int32_t* finm = (int32_t*)(base + lp.recf) + (size_t)wave * SEEDS * 5;
   // per wave: the network buffer, or (after the network has run) the toplists
   char* wave_tl = base + lp.tl + (size_t)wave * lp.tl_stride;
   uint16_t* mlp_buf = (uint16_t*)wave_tl;
-  T* tl_c2 = (T*)wave_tl + lane;
-  int32_t* tl_pos = (int32_t*)(wave_tl + (size_t)S * 64 * sizeof(T)) + lane;
-  uint32_t* tl_orig = (uint32_t*)(wave_tl + (size_t)S * 64 * (sizeof(T) + 4)) + lane;
-  AccBuf<T> ab;
+  float* tl_c2 = (float*)wave_tl + lane;
+  int32_t* tl_pos = (int32_t*)(wave_tl + (size_t)S * 64 * 4) + lane;
+  uint32_t* tl_orig = (uint32_t*)(wave_tl + (size_t)S * 64 * 8) + lane;
+  AccBuf ab;
   ab.tot = (int32_t*)(base + lp.acc) + (size_t)wave * 64;
   (void)mlp_buf;
   const int sidx = lane / S, slot = lane - (lane / S) * S, sbase = sidx * S;
@@ -541,7 +554,7 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES : KF
         for (int k = 0; k < 21; ++k) Pp[k] = T(0);
       }
       const bool pok = live && rc == 0;
-      TopList<T> tl;
+      TopList tl;
       tl.c2 = tl_c2;
       tl.pos = tl_pos;
       tl.orig = tl_orig;
@@ -552,12 +565,9 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES : KF
       // learned window: the whole wave evaluates the network on its 64 slots
       float wl[2] = {0.f, 0.f};
       if constexpr (LEARNED) {
-        float feat[27];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) feat[k] = pok ? (float)Xp[k] : 0.f;
-#pragma unroll
-        for (int k = 0; k < 21; ++k) feat[6 + k] = pok ? (float)Pp[k] : 0.f;
-        kfmlp::wave_forward(A.mlp, mlp_buf, feat, wl);
+        // features: the prediction and its 21 covariance entries
+        kfmlp::wave_forward(A.mlp, mlp_buf, [&](int k) { return pok ? (float)(k < 6 ? Xp[k] : Pp[k - 6]) : 0.f; },
+                            wl);
         const float kap = A.mlp[KFMLP_OFF_KAPPA];
         wl[0] *= kap;
         wl[1] *= kap;
@@ -641,13 +651,13 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES : KF
       int n_new = 0;
       for (int r = 0; r < A.cap; ++r) {
         uint64_t key = kInfKey;
-        T hc2 = 0;
+        float hc2 = 0.f;
         int hpos = -1;
         uint32_t horig = kHoleIdx;
         if (pok) {
           if (ptr < tl.n) {
             top_get(tl, ptr, hc2, hpos, horig);
-            key = make_key(nhits + 1, (float)(chi2 + hc2), slot, horig);
+            key = make_key(nhits + 1, (float)(chi2 + (T)hc2), slot, horig);
           } else if (hole_left) {
             key = make_key(nhits, (float)chi2, slot, kHoleIdx);
           }
@@ -657,7 +667,7 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES : KF
         const int ws = (int)((win >> 24) & 7);
         const int wl_ = sbase + ws;
         const int wpos = __shfl(hpos, wl_, 64);
-        const T wc2 = shfl_t(hc2, wl_);
+        const T wc2 = (T)__shfl(hc2, wl_, 64);
         if (slot == ws) {
           if (ptr < tl.n) ptr += 1; else hole_left = false;
         }
@@ -811,8 +821,11 @@ size_t fine_bytes(int n_events, int n_layers, int n_phi, int n_z, int refine) {
 
 int refine_of(const kf_build_params* bp) { return bp->phi_refine > 0 ? bp->phi_refine : 8; }
 
+// the launch shape of the last kf_build call of this host thread
+thread_local kf_build_launch_info g_last_launch = {};
+
 template <typename T, bool LEARNED>
-int launch(const BuildArgs& A, int lanes, int blocks, hipStream_t s) {
+int launch(const BuildArgs& A, int lanes, int blocks, int hist_waves, hipStream_t s) {
   const int LB = A.n_layers - A.first_layer;
   int dev = 0, max_lds = 0;
   if (kf_check(hipGetDevice(&dev))) return KF_E_HIP;
@@ -829,27 +842,52 @@ int launch(const BuildArgs& A, int lanes, int blocks, hipStream_t s) {
       kf_check(hipFuncSetAttribute((const void*)build_kernel<T, LEARNED>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)))
     return KF_E_HIP;
-  if (blocks <= 0) {
-    int cus = 0, per = 0;
-    if (kf_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev))) return KF_E_HIP;
-    if (kf_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, build_kernel<T, LEARNED>, lanes, lds)))
-      return KF_E_HIP;
-    blocks = cus * (per > 0 ? per : 1);
-  }
+  int cus = 0, per = 0;
+  if (kf_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev))) return KF_E_HIP;
+  if (kf_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, build_kernel<T, LEARNED>, lanes, lds)))
+    return KF_E_HIP;
+  if (blocks <= 0) blocks = cus * (per > 0 ? per : 1);
   const int need = (A.n_groups + nwaves - 1) / nwaves;
   if (blocks > need) blocks = need;
-  if (blocks < 1) blocks = 1;
+  if (blocks > hist_waves / nwaves) blocks = hist_waves / nwaves;  // history tables in the workspace
+  if (blocks < 1) return KF_E_WORKSPACE;
+  g_last_launch.lanes_per_block = lanes;
+  g_last_launch.blocks = blocks;
+  g_last_launch.lds_bytes = (int32_t)lds;
+  g_last_launch.resident_blocks_per_cu = per;
+  g_last_launch.max_lds_per_block = max_lds;
   hipLaunchKernelGGL((build_kernel<T, LEARNED>), dim3(blocks), dim3(lanes), lds, s, A);
   return kf_check_launch();
 }
 
+// Workspace: queue head and per-event counters | fine phi index | history
+// tables of the resident waves (8 per CU of the current device: two per SIMD,
+// what the build kernels reach; a grid that would hold more waves is clamped).
+size_t ws_head_bytes(int n_events) { return 256 + (((size_t)n_events * 4 + 255) & ~(size_t)255); }
+int hist_waves_of_device() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                               hipSuccess || cus < 1)
+    cus = 256;
+  return cus * 8;
+}
+
 }  // namespace
+
+extern "C" int kf_build_last_launch(kf_build_launch_info* info) {
+  if (!info) return KF_E_INVALID_ARG;
+  *info = g_last_launch;
+  return KF_OK;
+}
 
 extern "C" size_t kf_build_workspace_bytes(const kf_build_params* bp, const kf_hits* hits, int32_t n_seeds) {
   (void)n_seeds;
   if (!bp || !hits || hits->n_events < 1 || hits->n_layers < 1 || hits->n_phi < 1 || hits->n_z < 1) return 0;
-  const size_t head = 256 + (((size_t)hits->n_events * 4 + 255) & ~(size_t)255);
-  return head + fine_bytes(hits->n_events, hits->n_layers, hits->n_phi, hits->n_z, refine_of(bp));
+  if (bp->first_layer < 1 || bp->first_layer >= hits->n_layers) return 0;
+  const size_t LB = (size_t)(hits->n_layers - bp->first_layer);
+  return ws_head_bytes(hits->n_events) + fine_bytes(hits->n_events, hits->n_layers, hits->n_phi, hits->n_z,
+                                                   refine_of(bp)) +
+         (size_t)hist_waves_of_device() * LB * 64 * 4;
 }
 
 extern "C" int kf_build(const kf_geometry* g, const kf_build_params* bp, const kf_hits* hits, int32_t n_seeds,
@@ -899,8 +937,13 @@ extern "C" int kf_build(const kf_geometry* g, const kf_build_params* bp, const k
   A.hx = hits->x; A.hy = hits->y; A.hz = hits->z; A.hphi = hits->phi; A.hcov = hits->cov; A.horig = hits->orig;
   A.n_hits = hits->n_hits;
   A.refine = refine;
-  const size_t fine_off = 256 + (((size_t)hits->n_events * 4 + 255) & ~(size_t)255);
+  const size_t fine_off = ws_head_bytes(hits->n_events);
   A.fine = (const int32_t*)((char*)ws + fine_off);
+  const size_t hist_off =
+      fine_off + fine_bytes(hits->n_events, hits->n_layers, hits->n_phi, hits->n_z, refine);
+  A.hist = (uint32_t*)((char*)ws + hist_off);
+  const size_t LBw = (size_t)(g->n_layers - bp->first_layer) * 64 * 4;
+  const int hist_waves = (int)((ws_bytes - hist_off) / LBw);
   const int seeds_per_wave = 64 / bp->cand_cap;
   A.n_seeds = n_seeds; A.ld = ld; A.n_groups = (n_seeds + seeds_per_wave - 1) / seeds_per_wave;
   A.seed_par = seed_par; A.seed_cov = seed_cov; A.q = q;
@@ -923,8 +966,8 @@ extern "C" int kf_build(const kf_geometry* g, const kf_build_params* bp, const k
     if (int rc = kf_check_launch()) return rc;
   }
   if (bp->arith == KF_ARITH_F64)
-    return bp->window_mode == 1 ? launch<double, true>(A, lanes, bp->persistent_blocks, s)
-                                : launch<double, false>(A, lanes, bp->persistent_blocks, s);
-  return bp->window_mode == 1 ? launch<float, true>(A, lanes, bp->persistent_blocks, s)
-                              : launch<float, false>(A, lanes, bp->persistent_blocks, s);
+    return bp->window_mode == 1 ? launch<double, true>(A, lanes, bp->persistent_blocks, hist_waves, s)
+                                : launch<double, false>(A, lanes, bp->persistent_blocks, hist_waves, s);
+  return bp->window_mode == 1 ? launch<float, true>(A, lanes, bp->persistent_blocks, hist_waves, s)
+                              : launch<float, false>(A, lanes, bp->persistent_blocks, hist_waves, s);
 }

@@ -7,10 +7,9 @@
 // (v_mfma_f32_16x16x32_bf16) and accumulates in FP32.
 //
 // A wave evaluates 64 rows at once (one per lane): the rows of the wave are
-// four 16-row tiles; for each tile, layer 1 (K = 32, the 27 inputs padded),
-// layer 2 (K = 64) and the head (N padded 2 -> 16) run back to back through
-// one 64 x 72 BF16 LDS buffer (a tile's rows are overwritten only after they
-// have been consumed).
+// four 16-row tiles; layer 1 (K = 32, the 27 inputs padded), layer 2
+// (K = 64) and the head (N padded 2 -> 16) each run over the four tiles with
+// their weights held in registers, through one 64 x 72 BF16 LDS buffer.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -61,13 +60,18 @@ __host__ __device__ inline float bf16_to_f(uint16_t h) {
   return f;
 }
 
-// round to nearest bfloat16, ties to even
+// round to nearest bfloat16, ties to even (on gfx950 one v_cvt_pk_bf16_f32;
+// the host sequence gives the same result for every finite value)
 __host__ __device__ inline uint16_t f_to_bf16(float f) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_bit_cast(uint16_t, (__bf16)f);
+#else
   uint32_t u;
   __builtin_memcpy(&u, &f, 4);
   if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
   u += 0x7fffu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
+#endif
 }
 
 __host__ __device__ inline float bf16_round(float f) { return bf16_to_f(f_to_bf16(f)); }
@@ -116,91 +120,120 @@ __device__ inline f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 //   B (32 x 16): k = 8 (l / 16) .. + 7, column l % 16
 //   C (16 x 16): rows 4 (l / 16) .. + 3, column l % 16
 //
-// Forward of the 64 rows of a wave.  x: this lane's 27 raw features (its row
-// is the lane index); buf: the wave's LDS buffer [64][KFMLP_PITCH] bf16.
-// Writes the two widths (without kappa) of this lane's row into w.  Must be
-// called by all 64 lanes.
-__device__ inline void wave_forward(const float* __restrict__ blk, uint16_t* buf, const float x[27], float w[2],
+// Forward of the 64 rows of a wave, layer by layer over the wave's four
+// 16-row tiles (each layer's weights are fetched once per forward).
+// feature(k): this lane's raw feature k of 27 (its row is the lane index);
+// buf: the wave's LDS buffer [64][KFMLP_PITCH] bf16, which holds the inputs
+// (columns 0..31, the 27 standardised features padded with zeros), then the
+// first hidden layer, then the second, each overwriting its own tile's rows
+// after they have been read.  Writes the two widths (without kappa) of this
+// lane's row into w.  Must be called by all 64 lanes.
+template <typename Feature>
+__device__ inline void wave_forward(const float* __restrict__ blk, uint16_t* buf, Feature feature, float w[2],
                                     float* o_out = nullptr) {
   const int lane = threadIdx.x & 63;
   const uint16_t* W = (const uint16_t*)(blk + KFMLP_HEADER_FLOATS);
-  // standardised inputs, BF16, columns 0..31 of this lane's row
-  uint16_t* row = buf + lane * KFMLP_PITCH;
+  const int r16 = lane & 15, kq = lane >> 4;
+  {
+    uint16_t* row = buf + lane * KFMLP_PITCH;
 #pragma unroll
-  for (int k = 0; k < 27; ++k) row[k] = f_to_bf16((x[k] - blk[KFMLP_OFF_MU + k]) * blk[KFMLP_OFF_ISD + k]);
+    for (int k = 0; k < 27; ++k) row[k] = f_to_bf16((feature(k) - blk[KFMLP_OFF_MU + k]) * blk[KFMLP_OFF_ISD + k]);
 #pragma unroll
-  for (int k = 27; k < 32; ++k) row[k] = 0;
+    for (int k = 27; k < 32; ++k) row[k] = 0;
+  }
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
-  const int r16 = lane & 15, kq = lane >> 4;
-  float head[2] = {0.f, 0.f};
-  for (int mt = 0; mt < 4; ++mt) {
-    uint16_t* tile = buf + (mt * 16) * KFMLP_PITCH;
-    // layer 1: Z1 = Xh W1^T, 4 column tiles, one k step
-    f32x4 acc1[4];
-    const bf16x8 a1 = load8(tile + r16 * KFMLP_PITCH + 8 * kq);
+  // layer 1: Z1 = Xh W1^T (K = 32), 4 column tiles
+  {
+    bf16x8 b1[4];
+    float bias[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      const bf16x8 b = load8(W + KFMLP_W1 + (nt * 16 + r16) * 32 + 8 * kq);
-      acc1[nt] = mfma(a1, b, f32x4{0.f, 0.f, 0.f, 0.f});
+      b1[nt] = load8(W + KFMLP_W1 + (nt * 16 + r16) * 32 + 8 * kq);
+      bias[nt] = blk[KFMLP_OFF_B1 + nt * 16 + r16];
     }
-    __builtin_amdgcn_wave_barrier();
+    for (int mt = 0; mt < 4; ++mt) {
+      uint16_t* tile = buf + (mt * 16) * KFMLP_PITCH;
+      const bf16x8 a = load8(tile + r16 * KFMLP_PITCH + 8 * kq);
+      f32x4 acc[4];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      const int col = nt * 16 + r16;
-      const float bias = blk[KFMLP_OFF_B1 + col];
+      for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma(a, b1[nt], f32x4{0.f, 0.f, 0.f, 0.f});
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
 #pragma unroll
-      for (int i = 0; i < 4; ++i) tile[(4 * kq + i) * KFMLP_PITCH + col] = f_to_bf16(gelu(acc1[nt][i] + bias));
+      for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          tile[(4 * kq + i) * KFMLP_PITCH + nt * 16 + r16] = f_to_bf16(gelu(acc[nt][i] + bias[nt]));
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
-    // layer 2: Z2 = H1 W2^T, K = 64 in two steps
-    f32x4 acc2[4];
-    const bf16x8 a20 = load8(tile + r16 * KFMLP_PITCH + 8 * kq);
-    const bf16x8 a21 = load8(tile + r16 * KFMLP_PITCH + 32 + 8 * kq);
+  }
+  // layer 2: Z2 = H1 W2^T (K = 64 in two steps)
+  {
+    bf16x8 b2[4][2];
+    float bias[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
       const uint16_t* wr = W + KFMLP_W2 + (nt * 16 + r16) * 64;
-      acc2[nt] = mfma(a20, load8(wr + 8 * kq), f32x4{0.f, 0.f, 0.f, 0.f});
-      acc2[nt] = mfma(a21, load8(wr + 32 + 8 * kq), acc2[nt]);
+      b2[nt][0] = load8(wr + 8 * kq);
+      b2[nt][1] = load8(wr + 32 + 8 * kq);
+      bias[nt] = blk[KFMLP_OFF_B2 + nt * 16 + r16];
     }
-    __builtin_amdgcn_wave_barrier();
+    for (int mt = 0; mt < 4; ++mt) {
+      uint16_t* tile = buf + (mt * 16) * KFMLP_PITCH;
+      const bf16x8 a0 = load8(tile + r16 * KFMLP_PITCH + 8 * kq);
+      const bf16x8 a1 = load8(tile + r16 * KFMLP_PITCH + 32 + 8 * kq);
+      f32x4 acc[4];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      const int col = nt * 16 + r16;
-      const float bias = blk[KFMLP_OFF_B2 + col];
+      for (int nt = 0; nt < 4; ++nt) {
+        acc[nt] = mfma(a0, b2[nt][0], f32x4{0.f, 0.f, 0.f, 0.f});
+        acc[nt] = mfma(a1, b2[nt][1], acc[nt]);
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
 #pragma unroll
-      for (int i = 0; i < 4; ++i) tile[(4 * kq + i) * KFMLP_PITCH + col] = f_to_bf16(gelu(acc2[nt][i] + bias));
+      for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          tile[(4 * kq + i) * KFMLP_PITCH + nt * 16 + r16] = f_to_bf16(gelu(acc[nt][i] + bias[nt]));
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
-    // head: O = H2 W3^T (columns 0, 1 of a 16-wide tile)
-    const bf16x8 a30 = load8(tile + r16 * KFMLP_PITCH + 8 * kq);
-    const bf16x8 a31 = load8(tile + r16 * KFMLP_PITCH + 32 + 8 * kq);
+  }
+  // head: O = H2 W3^T (columns 0, 1 of a 16-wide tile)
+  {
     const uint16_t* w3 = W + KFMLP_W3 + r16 * 64;
-    f32x4 acc3 = mfma(a30, load8(w3 + 8 * kq), f32x4{0.f, 0.f, 0.f, 0.f});
-    acc3 = mfma(a31, load8(w3 + 32 + 8 * kq), acc3);
-    __builtin_amdgcn_wave_barrier();
-    // lanes holding columns 0 and 1 of rows 4kq..4kq+3 park the head in the
-    // first two floats of those rows (as raw bits, 4 halves)
-    if (r16 < 2) {
+    const bf16x8 b30 = load8(w3 + 8 * kq), b31 = load8(w3 + 32 + 8 * kq);
+    for (int mt = 0; mt < 4; ++mt) {
+      uint16_t* tile = buf + (mt * 16) * KFMLP_PITCH;
+      const bf16x8 a0 = load8(tile + r16 * KFMLP_PITCH + 8 * kq);
+      const bf16x8 a1 = load8(tile + r16 * KFMLP_PITCH + 32 + 8 * kq);
+      f32x4 acc = mfma(a0, b30, f32x4{0.f, 0.f, 0.f, 0.f});
+      acc = mfma(a1, b31, acc);
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+      // lanes holding columns 0 and 1 of rows 4kq..4kq+3 park the head in
+      // the first two floats of those rows (as raw bits, 4 halves)
+      if (r16 < 2) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const uint32_t bits = __float_as_uint(acc3[i]);
-        uint16_t* dst = tile + (4 * kq + i) * KFMLP_PITCH + 2 * r16;
-        dst[0] = (uint16_t)bits;
-        dst[1] = (uint16_t)(bits >> 16);
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t bits = __float_as_uint(acc[i]);
+          uint16_t* dst = tile + (4 * kq + i) * KFMLP_PITCH + 2 * r16;
+          dst[0] = (uint16_t)bits;
+          dst[1] = (uint16_t)(bits >> 16);
+        }
       }
     }
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
-    if ((lane >> 4) == mt) {
-      const uint16_t* src = buf + lane * KFMLP_PITCH;
-#pragma unroll
-      for (int j = 0; j < 2; ++j) head[j] = __uint_as_float((uint32_t)src[2 * j] | ((uint32_t)src[2 * j + 1] << 16));
-    }
-    __builtin_amdgcn_wave_barrier();
   }
+  const uint16_t* src = buf + lane * KFMLP_PITCH;
+  float head[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) head[j] = __uint_as_float((uint32_t)src[2 * j] | ((uint32_t)src[2 * j + 1] << 16));
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const float o = head[j] + blk[KFMLP_OFF_B3 + j];

@@ -274,7 +274,7 @@ __global__ void adam_kernel(float* __restrict__ blk, float* __restrict__ master,
 
 __global__ void __launch_bounds__(64) infer_kernel(const float* __restrict__ blk, const float* __restrict__ rows,
                                                    int n, float* __restrict__ out, float* __restrict__ out_o) {
-  __shared__ __align__(16) uint16_t buf[64 * P];
+  __shared__ __align__(16) uint16_t buf[KFMLP_LDS_BYTES / 2];
   const int lane = threadIdx.x;
   const int row = blockIdx.x * 64 + lane;
   float x[27];
@@ -282,7 +282,7 @@ __global__ void __launch_bounds__(64) infer_kernel(const float* __restrict__ blk
 #pragma unroll
   for (int k = 0; k < 27; ++k) x[k] = row < n ? src[k] : 0.f;
   float w[2], o[2];
-  wave_forward(blk, buf, x, w, o);
+  wave_forward(blk, buf, [&](int k) { return x[k]; }, w, o);
   if (row < n) {
     const float kap = blk[KFMLP_OFF_KAPPA];
     out[(size_t)row * 2] = kap * w[0];

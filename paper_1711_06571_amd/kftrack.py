@@ -52,6 +52,11 @@ class BuildParams(ctypes.Structure):
                 ("arith", ctypes.c_int32), ("phi_refine", ctypes.c_int32)]
 
 
+class LaunchInfo(ctypes.Structure):
+    _fields_ = [("lanes_per_block", ctypes.c_int32), ("blocks", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
+                ("resident_blocks_per_cu", ctypes.c_int32), ("max_lds_per_block", ctypes.c_int32)]
+
+
 class BuildExtra(ctypes.Structure):
     _fields_ = [("seed_event", ctypes.c_void_p), ("seed_order", ctypes.c_void_p),
                 ("event_n_seeds", ctypes.c_void_p), ("event_done_ticks", ctypes.c_void_p),
@@ -279,6 +284,13 @@ def kf_build(g, bp, binned: BinnedHits, n_seeds, seed_par, seed_cov, q, extra=No
                           _ptr(out["chi2"]), _ptr(out["nhits"]), _ptr(out["status"]), ctypes.byref(ex), _ptr(ws),
                           ctypes.c_size_t(need), _stream(stream)))
     return out
+
+
+def kf_build_last_launch() -> dict:
+    """Launch shape of the last kf_build call of this thread."""
+    info = LaunchInfo()
+    _check(lib().kf_build_last_launch(ctypes.byref(info)))
+    return {k: int(getattr(info, k)) for k, _ in LaunchInfo._fields_}
 
 
 def kf_gather_hits(n_layers, first_layer, n_seeds, built_hits, xyz, cov, seed_event=None, event_offsets=None,
