@@ -6,10 +6,13 @@
 // products are BF16; every product runs on the matrix cores
 // (v_mfma_f32_16x16x32_bf16) and accumulates in FP32.
 //
-// A wave evaluates 64 rows at once (one per lane): the rows of the wave are
-// four 16-row tiles; layer 1 (K = 32, the 27 inputs padded), layer 2
-// (K = 64) and the head (N padded 2 -> 16) each run over the four tiles with
-// their weights held in registers, through one 64 x 72 BF16 LDS buffer.
+// A wave evaluates 64 rows at once (one per lane) in four 16-row tiles, in
+// transposed form: every product is W x X^T (weights as the A operand, the
+// tile's samples as the 16 columns).  Then the outputs a lane holds for a
+// sample (4 units of each 16-unit block) are exactly the K values it must
+// supply for that sample to the next layer, once the next layer's weights
+// are stored with their K index permuted to match (W2P, W3P): the hidden
+// activations never leave registers; only the inputs pass through LDS.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -26,12 +29,16 @@
 #define KFMLP_HEADER_FLOATS 192
 // BF16 weights after the header (offsets in bf16 elements): W1 [64][32]
 // (inputs padded 27 -> 32 with zeros), W2 [64][64], W3 [16][64] (rows 2..15
-// zero), W2T [64][64] (W2 transposed, for the backward pass)
+// zero), W2T [64][64] (W2 transposed, for the backward pass), then W2 and W3
+// in the operand order of the inference (kfmlp_perm): W2P [4][2][16][32],
+// W3P [2][16][32]
 #define KFMLP_W1 0
 #define KFMLP_W2 (64 * 32)
 #define KFMLP_W3 (64 * 32 + 64 * 64)
 #define KFMLP_W2T (64 * 32 + 64 * 64 + 16 * 64)
-#define KFMLP_WEIGHTS (64 * 32 + 64 * 64 + 16 * 64 + 64 * 64)
+#define KFMLP_W2P (KFMLP_W2T + 64 * 64)
+#define KFMLP_W3P (KFMLP_W2P + 64 * 64)
+#define KFMLP_WEIGHTS (KFMLP_W3P + 16 * 64)
 #define KFMLP_BLOCK_BYTES (KFMLP_HEADER_FLOATS * 4 + KFMLP_WEIGHTS * 2)
 // trainable parameters (FP32 master vector): W1 [64][27], b1 [64], W2 [64][64],
 // b2 [64], W3 [2][64], b3 [2]
@@ -49,6 +56,18 @@
 #define KFMLP_LDS_BYTES (64 * KFMLP_PITCH * 2)
 
 namespace kfmlp {
+
+// Hidden unit supplied as K slot j (0..7) of lane group kq (0..3) in K step
+// ks (0..1) of a 64-wide hidden input: the lane's layer outputs for units
+// 16 ot + 4 kq + i (ot = 2 ks + j / 4, i = j % 4).
+__host__ __device__ constexpr int kfmlp_perm(int ks, int kq, int j) {
+  return (2 * ks + (j >> 2)) * 16 + 4 * kq + (j & 3);
+}
+// Position in W2P of W2[out][unit] (and in W3P of W3[out][unit], ot = 0).
+__host__ __device__ constexpr int kfmlp_packed_index(int out, int unit) {
+  return ((((out >> 4) * 2 + (unit >> 5)) * 16 + (out & 15)) * 32) + ((unit & 15) >> 2) * 8 +
+         ((unit >> 4) & 1) * 4 + (unit & 3);
+}
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -120,14 +139,11 @@ __device__ inline f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 //   B (32 x 16): k = 8 (l / 16) .. + 7, column l % 16
 //   C (16 x 16): rows 4 (l / 16) .. + 3, column l % 16
 //
-// Forward of the 64 rows of a wave, layer by layer over the wave's four
-// 16-row tiles (each layer's weights are fetched once per forward).
-// feature(k): this lane's raw feature k of 27 (its row is the lane index);
-// buf: the wave's LDS buffer [64][KFMLP_PITCH] bf16, which holds the inputs
-// (columns 0..31, the 27 standardised features padded with zeros), then the
-// first hidden layer, then the second, each overwriting its own tile's rows
-// after they have been read.  Writes the two widths (without kappa) of this
-// lane's row into w.  Must be called by all 64 lanes.
+// Forward of the 64 rows of a wave.  feature(k): this lane's raw feature k
+// of 27 (its row is the lane index); buf: the wave's LDS buffer
+// [64][KFMLP_PITCH] bf16 for the standardised inputs (columns 0..31, padded
+// with zeros).  Writes the two widths (without kappa) of this lane's row
+// into w.  Must be called by all 64 lanes.
 template <typename Feature>
 __device__ inline void wave_forward(const float* __restrict__ blk, uint16_t* buf, Feature feature, float w[2],
                                     float* o_out = nullptr) {
@@ -143,96 +159,50 @@ __device__ inline void wave_forward(const float* __restrict__ blk, uint16_t* buf
   }
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
-  // layer 1: Z1 = Xh W1^T (K = 32), 4 column tiles
-  {
-    bf16x8 b1[4];
-    float bias[4];
+  float head[2] = {0.f, 0.f};
+  for (int mt = 0; mt < 4; ++mt) {
+    // samples 16 mt .. 16 mt + 15: this lane supplies features 8 kq .. 8 kq + 7
+    // of sample 16 mt + r16
+    const bf16x8 x = load8(buf + (16 * mt + r16) * KFMLP_PITCH + 8 * kq);
+    // layer 1 (K = 32): units 16 ot + 4 kq + i of sample 16 mt + r16
+    f32x4 h1[4];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      b1[nt] = load8(W + KFMLP_W1 + (nt * 16 + r16) * 32 + 8 * kq);
-      bias[nt] = blk[KFMLP_OFF_B1 + nt * 16 + r16];
-    }
-    for (int mt = 0; mt < 4; ++mt) {
-      uint16_t* tile = buf + (mt * 16) * KFMLP_PITCH;
-      const bf16x8 a = load8(tile + r16 * KFMLP_PITCH + 8 * kq);
-      f32x4 acc[4];
+    for (int ot = 0; ot < 4; ++ot)
+      h1[ot] = mfma(load8(W + KFMLP_W1 + (ot * 16 + r16) * 32 + 8 * kq), x, f32x4{0.f, 0.f, 0.f, 0.f});
+    bf16x8 a1[2];
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma(a, b1[nt], f32x4{0.f, 0.f, 0.f, 0.f});
-      __builtin_amdgcn_s_waitcnt(0);
-      __builtin_amdgcn_wave_barrier();
+    for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          tile[(4 * kq + i) * KFMLP_PITCH + nt * 16 + r16] = f_to_bf16(gelu(acc[nt][i] + bias[nt]));
-      __builtin_amdgcn_s_waitcnt(0);
-      __builtin_amdgcn_wave_barrier();
-    }
-  }
-  // layer 2: Z2 = H1 W2^T (K = 64 in two steps)
-  {
-    bf16x8 b2[4][2];
-    float bias[4];
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      const uint16_t* wr = W + KFMLP_W2 + (nt * 16 + r16) * 64;
-      b2[nt][0] = load8(wr + 8 * kq);
-      b2[nt][1] = load8(wr + 32 + 8 * kq);
-      bias[nt] = blk[KFMLP_OFF_B2 + nt * 16 + r16];
-    }
-    for (int mt = 0; mt < 4; ++mt) {
-      uint16_t* tile = buf + (mt * 16) * KFMLP_PITCH;
-      const bf16x8 a0 = load8(tile + r16 * KFMLP_PITCH + 8 * kq);
-      const bf16x8 a1 = load8(tile + r16 * KFMLP_PITCH + 32 + 8 * kq);
-      f32x4 acc[4];
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
-        acc[nt] = mfma(a0, b2[nt][0], f32x4{0.f, 0.f, 0.f, 0.f});
-        acc[nt] = mfma(a1, b2[nt][1], acc[nt]);
+      for (int j = 0; j < 8; ++j) {
+        const int ot = 2 * ks + (j >> 2), i = j & 3;
+        a1[ks][j] = (__bf16)gelu(h1[ot][i] + blk[KFMLP_OFF_B1 + ot * 16 + 4 * kq + i]);
       }
-      __builtin_amdgcn_s_waitcnt(0);
-      __builtin_amdgcn_wave_barrier();
+    // layer 2 (K = 64 in two steps, W2 in permuted order)
+    f32x4 h2[4];
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          tile[(4 * kq + i) * KFMLP_PITCH + nt * 16 + r16] = f_to_bf16(gelu(acc[nt][i] + bias[nt]));
-      __builtin_amdgcn_s_waitcnt(0);
-      __builtin_amdgcn_wave_barrier();
+    for (int ot = 0; ot < 4; ++ot) {
+      h2[ot] = mfma(load8(W + KFMLP_W2P + ((ot * 2 + 0) * 16 + r16) * 32 + 8 * kq), a1[0],
+                    f32x4{0.f, 0.f, 0.f, 0.f});
+      h2[ot] = mfma(load8(W + KFMLP_W2P + ((ot * 2 + 1) * 16 + r16) * 32 + 8 * kq), a1[1], h2[ot]);
     }
-  }
-  // head: O = H2 W3^T (columns 0, 1 of a 16-wide tile)
-  {
-    const uint16_t* w3 = W + KFMLP_W3 + r16 * 64;
-    const bf16x8 b30 = load8(w3 + 8 * kq), b31 = load8(w3 + 32 + 8 * kq);
-    for (int mt = 0; mt < 4; ++mt) {
-      uint16_t* tile = buf + (mt * 16) * KFMLP_PITCH;
-      const bf16x8 a0 = load8(tile + r16 * KFMLP_PITCH + 8 * kq);
-      const bf16x8 a1 = load8(tile + r16 * KFMLP_PITCH + 32 + 8 * kq);
-      f32x4 acc = mfma(a0, b30, f32x4{0.f, 0.f, 0.f, 0.f});
-      acc = mfma(a1, b31, acc);
-      __builtin_amdgcn_s_waitcnt(0);
-      __builtin_amdgcn_wave_barrier();
-      // lanes holding columns 0 and 1 of rows 4kq..4kq+3 park the head in
-      // the first two floats of those rows (as raw bits, 4 halves)
-      if (r16 < 2) {
+    bf16x8 a2[2];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const uint32_t bits = __float_as_uint(acc[i]);
-          uint16_t* dst = tile + (4 * kq + i) * KFMLP_PITCH + 2 * r16;
-          dst[0] = (uint16_t)bits;
-          dst[1] = (uint16_t)(bits >> 16);
-        }
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int ot = 2 * ks + (j >> 2), i = j & 3;
+        a2[ks][j] = (__bf16)gelu(h2[ot][i] + blk[KFMLP_OFF_B2 + ot * 16 + 4 * kq + i]);
       }
+    // head (outputs padded 2 -> 16): outputs 0 and 1 of sample 16 mt + r16
+    // land in lane r16 (kq = 0), elements 0 and 1
+    f32x4 o = mfma(load8(W + KFMLP_W3P + (0 * 16 + r16) * 32 + 8 * kq), a2[0], f32x4{0.f, 0.f, 0.f, 0.f});
+    o = mfma(load8(W + KFMLP_W3P + (1 * 16 + r16) * 32 + 8 * kq), a2[1], o);
+    const float s0 = __shfl(o[0], r16, 64), s1 = __shfl(o[1], r16, 64);
+    if (kq == mt) {
+      head[0] = s0;
+      head[1] = s1;
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
   }
-  const uint16_t* src = buf + lane * KFMLP_PITCH;
-  float head[2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j) head[j] = __uint_as_float((uint32_t)src[2 * j] | ((uint32_t)src[2 * j + 1] << 16));
-  __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
   for (int j = 0; j < 2; ++j) {

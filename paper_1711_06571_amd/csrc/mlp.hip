@@ -237,7 +237,7 @@ __global__ void reduce_kernel(const float* __restrict__ partial, int nblk, float
 }
 
 // Adam (Kingma and Ba) on the FP32 master vector; refreshes the block's BF16
-// weights (and W2 transposed) and FP32 biases.
+// weights (W2 also transposed and permuted, W3 permuted) and FP32 biases.
 __global__ void adam_kernel(float* __restrict__ blk, float* __restrict__ master, float* __restrict__ m,
                             float* __restrict__ v, const float* __restrict__ grad, float bc1, float bc2, float lr,
                             float beta1, float beta2, float eps) {
@@ -262,11 +262,14 @@ __global__ void adam_kernel(float* __restrict__ blk, float* __restrict__ master,
     const uint16_t b = f_to_bf16(val);
     W[KFMLP_W2 + j * 64 + k] = b;
     W[KFMLP_W2T + k * 64 + j] = b;
+    W[KFMLP_W2P + kfmlp_packed_index(j, k)] = b;
   } else if (p < KFMLP_P_W3) {
     blk[KFMLP_OFF_B2 + (p - KFMLP_P_B2)] = val;
   } else if (p < KFMLP_P_B3) {
     const int q = p - KFMLP_P_W3, j = q / 64, k = q % 64;
-    W[KFMLP_W3 + j * 64 + k] = f_to_bf16(val);
+    const uint16_t b = f_to_bf16(val);
+    W[KFMLP_W3 + j * 64 + k] = b;
+    W[KFMLP_W3P + kfmlp_packed_index(j, k)] = b;
   } else {
     blk[KFMLP_OFF_B3 + (p - KFMLP_P_B3)] = val;
   }

@@ -342,9 +342,24 @@ def mlp_join(p):
     return np.concatenate([np.asarray(p[k], dtype=np.float32).ravel() for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
 
 
+def _packed(Wm):
+    """W [rows][64 hidden units] in the inference's operand order: entry
+    (out, unit) at ((((out >> 4) * 2 + (unit >> 5)) * 16 + (out & 15)) * 32)
+    + ((unit & 15) >> 2) * 8 + ((unit >> 4) & 1) * 4 + (unit & 3)."""
+    rows = Wm.shape[0]
+    out = np.arange(rows)[:, None]
+    unit = np.arange(64)[None, :]
+    idx = ((((out >> 4) * 2 + (unit >> 5)) * 16 + (out & 15)) * 32) + ((unit & 15) >> 2) * 8 + \
+        ((unit >> 4) & 1) * 4 + (unit & 3)
+    P = np.zeros(rows * 64, dtype=np.float32)
+    P[idx.ravel()] = np.asarray(Wm, dtype=np.float32).ravel()
+    return P
+
+
 def mlp_block(master, mu, sd, scale, kappa=1.0, floor_rphi=0.01, floor_z=0.1, device="cuda:0"):
     """Pack the device block: FP32 header then BF16 weights (W1 padded to 32
-    inputs, W2, W3 padded to 16 rows, W2 transposed)."""
+    inputs, W2, W3 padded to 16 rows, W2 transposed, then W2 and W3 in the
+    inference's operand order)."""
     p = mlp_split(master)
     hdr = np.zeros(_MLP_HDR, dtype=np.float32)
     hdr[0:27] = mu
@@ -361,7 +376,8 @@ def mlp_block(master, mu, sd, scale, kappa=1.0, floor_rphi=0.01, floor_z=0.1, de
     W3 = np.zeros((16, 64), dtype=np.float32)
     W3[:2] = p["W3"]
     w = np.concatenate([_bf16_bits(W1).ravel(), _bf16_bits(p["W2"]).ravel(), _bf16_bits(W3).ravel(),
-                        _bf16_bits(np.ascontiguousarray(p["W2"].T)).ravel()])
+                        _bf16_bits(np.ascontiguousarray(p["W2"].T)).ravel(),
+                        _bf16_bits(_packed(p["W2"])).ravel(), _bf16_bits(_packed(W3)).ravel()])
     raw = np.concatenate([hdr.view(np.uint8), w.view(np.uint8)])
     assert raw.size == int(lib().kf_mlp_block_bytes())
     return torch.from_numpy(raw.view(np.float32).copy()).to(device)
