@@ -89,45 +89,53 @@ def copy_only(nbytes):
     print(json.dumps({"copy_bytes": n * 4, "reps": 5}), flush=True)
 
 
-def learned_vs_plain(arith, log):
+def learned_vs_plain(ariths, log):
     """Learned search window against the plain one on the learned workload
     (the build workload's generator, other events): rows dumped by the plain
-    build of event 0, GPU training, kappa calibrated on event 1 to keep the
-    plain efficiency within 0.1 %, comparison on events 2..33."""
+    build of event 0, gates at a quantile of their plain widths, GPU training
+    on the gated rows, kappa calibrated on event 1 to keep the plain
+    efficiency within 0.1 %, comparison on events 2..33, in each arithmetic."""
     import torch
+    from paper_1711_06571_amd import kftrack as kf
     from paper_1711_06571_amd import presets, window
     w = presets.learned()
     t0 = time.perf_counter()
     tr = window.load_events(w, [0])
     rows = window.dump_rows(w, tr)
-    t = window.train(rows, epochs=4)
+    t = window.train_gated(w, rows, epochs=4)
     val = window.load_events(w, [1])
     # 32 events (640 k seeds, ~30 seed groups per wave): with only a few groups
     # per wave the build time is the slowest group's, not the throughput
     test = window.load_events(w, list(range(2, 34)))
-    out_p, _ = window.build(w, val, arith=arith)
-    eff_val = window.efficiency(w, val, out_p)
-    kap, trace = window.calibrate(w, t, val, eff_val, target=0.001, arith=arith)
-    from paper_1711_06571_amd import kftrack as kf
-    kf.mlp_set_header(t.block, kappa=kap)
-    outp, cp = window.build(w, test, counters=True, arith=arith)
-    outl, cl = window.build(w, test, window_mode=1, block=t.block, counters=True, arith=arith)
-    torch.cuda.synchronize()
-    ep, el = window.efficiency(w, test, outp), window.efficiency(w, test, outl)
-    tp = window.time_build(w, test, 0, arith=arith)
-    tl = window.time_build(w, test, 1, t.block, arith=arith)
-    cp, cl = cp.cpu().numpy(), cl.cpu().numpy()
     n = test.eb.n_seeds
-    log(f"learned: kappa {kap}, eff plain {ep:.4f} learned {el:.4f}, ms {tp:.3f} vs {tl:.3f}")
-    return {"workload": f"{w.name}: 32 test events x {n // 32} tracks + noise", "train_rows": int(rows.shape[0]),
-            "train_seconds": round(t.seconds, 3), "loss_initial": round(t.loss0, 5), "loss_final": round(t.losses[-1], 5),
+    res = {"workload": f"{w.name}: 32 test events x {n // 32} tracks + noise", "train_rows": int(rows.shape[0]),
+           "gate_quantile": window.GATE_QUANTILE, "gates_cm": [round(v, 5) for v in t.gates],
+           "rows_gated": int(t.rows_used), "train_seconds": round(t.seconds, 3), "loss_initial": round(t.loss0, 5),
+           "loss_final": round(t.losses[-1], 5)}
+    for arith in ariths:
+        name = "f64" if arith == kf.ARITH_F64 else "f32"
+        out_p, _ = window.build(w, val, arith=arith)
+        eff_val = window.efficiency(w, val, out_p)
+        kap, trace = window.calibrate(w, t, val, eff_val, target=0.001, arith=arith)
+        kf.mlp_set_header(t.block, kappa=kap)
+        outp, cp = window.build(w, test, counters=True, arith=arith)
+        outl, cl = window.build(w, test, window_mode=1, block=t.block, counters=True, arith=arith)
+        torch.cuda.synchronize()
+        ep, el = window.efficiency(w, test, outp), window.efficiency(w, test, outl)
+        tp = window.time_build(w, test, 0, arith=arith)
+        tl = window.time_build(w, test, 1, t.block, arith=arith)
+        cp, cl = cp.cpu().numpy(), cl.cpu().numpy()
+        log(f"learned {name}: kappa {kap}, eff plain {ep:.4f} learned {el:.4f}, ms {tp:.3f} vs {tl:.3f}")
+        res[name] = {
             "kappa": kap, "calibration": trace,
             "plain": {"build_ms": round(tp, 4), "seeds_per_s": round(n / (tp * 1e-3), 1), "efficiency": round(ep, 4),
                       "hits_tested_per_cand_layer": round(float(cp[1]) / max(float(cp[0]), 1), 3)},
-            "learned": {"build_ms": round(tl, 4), "seeds_per_s": round(n / (tl * 1e-3), 1), "efficiency": round(el, 4),
+            "learned": {"build_ms": round(tl, 4), "seeds_per_s": round(n / (tl * 1e-3), 1),
+                        "efficiency": round(el, 4),
                         "hits_tested_per_cand_layer": round(float(cl[1]) / max(float(cl[0]), 1), 3)},
-            "speedup": round(tp / tl, 3), "efficiency_loss": round(ep - el, 4),
-            "total_seconds": round(time.perf_counter() - t0, 1)}
+            "speedup": round(tp / tl, 3), "efficiency_loss": round(ep - el, 4)}
+    res["total_seconds"] = round(time.perf_counter() - t0, 1)
+    return res
 
 
 def batched(arith, autotune, log):
@@ -343,7 +351,7 @@ def main():
                               "stages_ms": {k: round(float(v), 4) for k, v in zip(names, ost)}}
     log = lambda m: print(m, file=sys.stderr, flush=True)
     if not args.no_learned:
-        res["learned_vs_plain"] = learned_vs_plain(arith, log)
+        res["learned_vs_plain"] = learned_vs_plain([kf.ARITH_F32, kf.ARITH_F64], log)
     if not args.no_batch:
         res["batched"] = batched(arith, args.autotune, log)
     if not args.no_cpu_baseline:

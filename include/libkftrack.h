@@ -211,8 +211,9 @@ size_t kf_build_workspace_bytes(const kf_build_params* bp, const kf_hits* hits, 
  * For each seed, from its state on layer first_layer-1, layer by layer:
  *   1. predict every candidate (a failed crossing or |z| > z_half stops it);
  *   2. window: plain = nsigma*sqrt(S) per coordinate with S = H P H^T +
- *      diag(win_sig_rphi^2, win_sig_z^2) (dphi = w_rphi / r, dz = w_z), or
- *      the learned widths where they are not below their floors;
+ *      diag(win_sig_rphi^2, win_sig_z^2) (dphi = w_rphi / r, dz = w_z); in
+ *      learned mode, where the plain arc or z half-width exceeds its gate,
+ *      the learned widths replace them where not below their floors;
  *   3. every hit of the layer with |wrap(phi_h - phi_p)| <= dphi and
  *      |z_h - z_p| <= dz is tested; accepted iff its update chi2 < chi2_cut;
  *   4. children: one updated child per accepted hit plus a hole child
@@ -252,7 +253,8 @@ int kf_build_last_launch(kf_build_launch_info* info);
  * Learned search window (an addition to the method: the paper sizes the hit
  * search from the covariance).  A device block of kf_mlp_block_bytes() bytes
  * holds the network: standardisation (mean, 1/std of the 27 features), FP32
- * biases, output scales, kappa and the two floors, then BF16 weights
+ * biases, output scales, kappa, the two floors and the two gates (arc, z;
+ * 0 consults the network for every candidate), then BF16 weights
  * (layout: the library's kfmlp.h).  Rows of data are 32 floats: the 27
  * features (predicted state, 21 covariance entries), the 2 labels (|arc| at
  * the layer radius and |dz| to the true hit), then 3 words not read here.

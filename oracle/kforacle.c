@@ -552,7 +552,7 @@ int orc_hit_bin(const orc_geometry* g, int n_phi, int n_z, int n_hits, const int
 /*
  * Parameter block of the window network (FP64 values of the BF16 weights):
  *   mu[27] sd[27] W1[64][27] b1[64] W2[64][64] b2[64] W3[2][64] b3[2]
- *   scale[2] kappa floor_rphi floor_z
+ *   scale[2] kappa floor_rphi floor_z gate_rphi gate_z
  */
 #define MLP_OFF_MU 0
 #define MLP_OFF_SD 27
@@ -565,7 +565,8 @@ int orc_hit_bin(const orc_geometry* g, int n_phi, int n_z, int n_hits, const int
 #define MLP_OFF_SCALE (MLP_OFF_B3 + 2)
 #define MLP_OFF_KAPPA (MLP_OFF_SCALE + 2)
 #define MLP_OFF_FLOOR (MLP_OFF_KAPPA + 1)
-#define MLP_SIZE (MLP_OFF_FLOOR + 2)
+#define MLP_OFF_GATE (MLP_OFF_FLOOR + 2)
+#define MLP_SIZE (MLP_OFF_GATE + 2)
 
 int orc_mlp_blob_size(void) { return MLP_SIZE; }
 
@@ -656,8 +657,10 @@ static double minf(double a, double b) { return a < b ? a : b; }
  *      |z| > z_half) stops it;
  *   2. window: plain = nsigma * sqrt(S) per coordinate with S = H P H^T +
  *      diag(win_sig_rphi^2, win_sig_z^2), as dphi = w_rphi / R, dz = w_z;
- *      learned = kappa * network widths where they are not below the
- *      floors, the plain width otherwise;
+ *      learned (only where the plain arc half-width exceeds gate_rphi or
+ *      the plain z half-width exceeds gate_z; the plain window elsewhere)
+ *      = kappa * network widths where they are not below the floors, the
+ *      plain width otherwise;
  *   3. scan every hit of the layer in original-index order; a hit is in
  *      the window iff |wrap(phi_h - phi_p)| <= dphi and |z_h - z_p| <= dz;
  *      it is accepted iff its update chi2 < chi2_cut;
@@ -678,7 +681,7 @@ static double minf(double a, double b) { return a < b ? a : b; }
  * hits, chi2 gaps at equal nhits for cap cuts, record replacements and the
  * final choice), [1] window (distance in cm from the window edge of the
  * test that decided: R*| |dphi| - dphi_w | or | |dz| - dz_w |; also learned
- * width vs floor),
+ * width vs floor and plain width vs gate),
  * [2] geometry (normalised crossing discriminant, | |z| - z_half |/z_half).
  */
 int orc_build(const orc_geometry* g, const orc_build_params* bp, int n_hits, const int32_t* layer,
@@ -747,7 +750,17 @@ int orc_build(const orc_geometry* g, const orc_build_params* bp, int n_hits, con
                      (double)bp->win_sig_rphi * (double)bp->win_sig_rphi;
         double Sww = Pp[14] + (double)bp->win_sig_z * (double)bp->win_sig_z;
         double w_rphi = (double)bp->nsigma * sqrt(Suu), w_z = (double)bp->nsigma * sqrt(Sww);
+        /* learned window: consulted where the covariance window is wide (its
+           arc or z half-width above the gate); elsewhere the plain window */
+        int gated = 0;
         if (bp->window_mode == 1) {
+          double dr = w_rphi - bp->mlp[MLP_OFF_GATE], dz = w_z - bp->mlp[MLP_OFF_GATE + 1];
+          gated = dr > 0.0 || dz > 0.0;
+          /* distance of the gate decision from flipping (cm) */
+          double gm = gated ? fmax(dr > 0.0 ? dr : 0.0, dz > 0.0 ? dz : 0.0) : fmin(-dr, -dz);
+          mwin = minf(mwin, gm);
+        }
+        if (gated) {
           double feat[27], wl[2], pu[21];
           for (int k = 0; k < 6; ++k) feat[k] = Xp[k];
           upper_from_sym(Pp, pu);

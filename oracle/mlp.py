@@ -122,9 +122,10 @@ def adam_step(master, grads, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8)
     return work
 
 
-def blob(p, kappa=1.0, floor_rphi=0.01, floor_z=0.1):
+def blob(p, kappa=1.0, floor_rphi=0.01, floor_z=0.1, gate_rphi=0.0, gate_z=0.0):
     """Parameter block of the C oracle (kforacle.c: mu sd W1 b1 W2 b2 W3 b3
-    scale kappa floor_rphi floor_z)."""
+    scale kappa floor_rphi floor_z gate_rphi gate_z).  Zero gates consult the
+    network for every candidate."""
     parts = [p["mu"], p["sd"], p["W1"].ravel(), p["b1"], p["W2"].ravel(), p["b2"], p["W3"].ravel(), p["b3"],
-             p["scale"], [kappa, floor_rphi, floor_z]]
+             p["scale"], [kappa, floor_rphi, floor_z, gate_rphi, gate_z]]
     return np.concatenate([np.asarray(a, dtype=np.float64).ravel() for a in parts])

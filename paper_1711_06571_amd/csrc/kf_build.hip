@@ -562,29 +562,17 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
       tl.tot = 0;
       tl.scanned = 0;
       tl.tested = 0;
-      // learned window: the whole wave evaluates the network on its 64 slots
-      float wl[2] = {0.f, 0.f};
-      if constexpr (LEARNED) {
-        // features: the prediction and its 21 covariance entries
-        kfmlp::wave_forward(A.mlp, mlp_buf, [&](int k) { return pok ? (float)(k < 6 ? Xp[k] : Pp[k - 6]) : 0.f; },
-                            wl);
-        const float kap = A.mlp[KFMLP_OFF_KAPPA];
-        wl[0] *= kap;
-        wl[1] *= kap;
-      }
-      T dphi_w = T(0), dz_w = T(0);
+      // plain window from the predicted covariance
+      T w_rphi = T(0), w_z = T(0);
+      const T R = (T)A.r[l];
       if (pok) {
-        const T R = (T)A.r[l];
         const T rr = k_sqrt(Xp[0] * Xp[0] + Xp[1] * Xp[1]);
         const T tx = -Xp[1] / rr, ty = Xp[0] / rr;
         const T Suu = tx * tx * Pp[ut(0, 0)] + T(2) * tx * ty * Pp[ut(0, 1)] + ty * ty * Pp[ut(1, 1)] +
                       (T)A.win_sig_rphi * (T)A.win_sig_rphi;
         const T Sww = Pp[ut(2, 2)] + (T)A.win_sig_z * (T)A.win_sig_z;
-        T w_rphi = (T)A.nsigma * k_sqrt(Suu), w_z = (T)A.nsigma * k_sqrt(Sww);
-        if constexpr (LEARNED) {
-          if (!(wl[0] < A.mlp[KFMLP_OFF_FLOOR])) w_rphi = (T)wl[0];
-          if (!(wl[1] < A.mlp[KFMLP_OFF_FLOOR + 1])) w_z = (T)wl[1];
-        }
+        w_rphi = (T)A.nsigma * k_sqrt(Suu);
+        w_z = (T)A.nsigma * k_sqrt(Sww);
         if (A.dump && ontrack && A.true_hits) {
           const int th = A.true_hits[(size_t)l * A.ld + seed];
           if (th >= 0) {
@@ -605,9 +593,22 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
             }
           }
         }
-        dphi_w = w_rphi / R;
-        dz_w = w_z;
       }
+      if constexpr (LEARNED) {
+        // learned window where the plain one is wide (either half-width above
+        // its gate): the wave evaluates the network on those slots only
+        const bool gated = pok && (w_rphi > (T)A.mlp[KFMLP_OFF_GATE] || w_z > (T)A.mlp[KFMLP_OFF_GATE + 1]);
+        float wl[2] = {0.f, 0.f};
+        kfmlp::wave_forward(A.mlp, mlp_buf, [&](int k) { return (float)(k < 6 ? Xp[k] : Pp[k - 6]); }, gated, wl);
+        if (gated) {
+          const float kap = A.mlp[KFMLP_OFF_KAPPA];
+          wl[0] *= kap;
+          wl[1] *= kap;
+          if (!(wl[0] < A.mlp[KFMLP_OFF_FLOOR])) w_rphi = (T)wl[0];
+          if (!(wl[1] < A.mlp[KFMLP_OFF_FLOOR + 1])) w_z = (T)wl[1];
+        }
+      }
+      const T dphi_w = pok ? w_rphi / R : T(0), dz_w = pok ? w_z : T(0);
       coop_scan<T>(A, ev, l, pok, Xp, Pp, dphi_w, dz_w, tl, ab, lane);
       cnt_pred += live ? 1u : 0u;
       cnt_scan += (unsigned)tl.scanned;

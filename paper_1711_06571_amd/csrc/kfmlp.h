@@ -6,7 +6,7 @@
 // products are BF16; every product runs on the matrix cores
 // (v_mfma_f32_16x16x32_bf16) and accumulates in FP32.
 //
-// A wave evaluates 64 rows at once (one per lane) in four 16-row tiles, in
+// A wave evaluates up to 64 rows at once (one per lane) in 16-row tiles, in
 // transposed form: every product is W x X^T (weights as the A operand, the
 // tile's samples as the 16 columns).  Then the outputs a lane holds for a
 // sample (4 units of each 16-unit block) are exactly the K values it must
@@ -26,6 +26,7 @@
 #define KFMLP_OFF_SCALE 184
 #define KFMLP_OFF_KAPPA 186
 #define KFMLP_OFF_FLOOR 187
+#define KFMLP_OFF_GATE 189
 #define KFMLP_HEADER_FLOATS 192
 // BF16 weights after the header (offsets in bf16 elements): W1 [64][32]
 // (inputs padded 27 -> 32 with zeros), W2 [64][64], W3 [16][64] (rows 2..15
@@ -139,76 +140,100 @@ __device__ inline f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 //   B (32 x 16): k = 8 (l / 16) .. + 7, column l % 16
 //   C (16 x 16): rows 4 (l / 16) .. + 3, column l % 16
 //
-// Forward of the 64 rows of a wave.  feature(k): this lane's raw feature k
-// of 27 (its row is the lane index); buf: the wave's LDS buffer
-// [64][KFMLP_PITCH] bf16 for the standardised inputs (columns 0..31, padded
-// with zeros).  Writes the two widths (without kappa) of this lane's row
-// into w.  Must be called by all 64 lanes.
+// Forward of the active rows of a wave.  The active lanes are numbered in
+// lane order (rank) and their rows packed into the first ceil(n/16) tiles,
+// so a wave with few active lanes runs few tiles (none when no lane is
+// active).  feature(k): this lane's raw feature k of 27; buf: the wave's LDS
+// buffer [64][KFMLP_PITCH] bf16 for the standardised inputs (columns 0..31,
+// padded with zeros).  Writes the two widths (without kappa) of an active
+// lane's row into w (and the head outputs into o_out); leaves an inactive
+// lane's untouched.  Must be called by all 64 lanes together.
 template <typename Feature>
-__device__ inline void wave_forward(const float* __restrict__ blk, uint16_t* buf, Feature feature, float w[2],
-                                    float* o_out = nullptr) {
+__device__ inline void wave_forward(const float* __restrict__ blk, uint16_t* buf, Feature feature, bool active,
+                                    float w[2], float* o_out = nullptr) {
+  const uint64_t act = __ballot(active);
+  if (act == 0) return;
   const int lane = threadIdx.x & 63;
-  const uint16_t* W = (const uint16_t*)(blk + KFMLP_HEADER_FLOATS);
+  const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+  const int ntile = (__popcll(act) + 15) >> 4;
   const int r16 = lane & 15, kq = lane >> 4;
-  {
-    uint16_t* row = buf + lane * KFMLP_PITCH;
+  if (active) {
+    // standardisation read through an opaque copy of the pointer: hoisted out
+    // of a caller's loop, its 54 constants would occupy registers throughout
+    const float* hk = blk;
+    asm volatile("" : "+s"(hk));
+    uint16_t* row = buf + rank * KFMLP_PITCH;
 #pragma unroll
-    for (int k = 0; k < 27; ++k) row[k] = f_to_bf16((feature(k) - blk[KFMLP_OFF_MU + k]) * blk[KFMLP_OFF_ISD + k]);
+    for (int k = 0; k < 27; ++k) row[k] = f_to_bf16((feature(k) - hk[KFMLP_OFF_MU + k]) * hk[KFMLP_OFF_ISD + k]);
 #pragma unroll
     for (int k = 27; k < 32; ++k) row[k] = 0;
   }
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
   float head[2] = {0.f, 0.f};
-  for (int mt = 0; mt < 4; ++mt) {
-    // samples 16 mt .. 16 mt + 15: this lane supplies features 8 kq .. 8 kq + 7
-    // of sample 16 mt + r16
+  for (int mt = 0; mt < ntile; ++mt) {
+    // the weights and biases are read afresh in every tile (from cache): the
+    // opaque copy of the block pointer keeps the compiler from hoisting them
+    // out of the loop, where they would hold about 90 registers for the whole
+    // loop inside kernels that are already short of them
+    const float* bk = blk;
+    asm volatile("" : "+s"(bk));
+    const uint16_t* W = (const uint16_t*)(bk + KFMLP_HEADER_FLOATS);
+    // samples 16 mt .. 16 mt + 15 (rows past the active count hold stale
+    // values; each sample is its own column, so they touch only their own
+    // outputs, which nobody reads): this lane supplies features
+    // 8 kq .. 8 kq + 7 of sample 16 mt + r16
     const bf16x8 x = load8(buf + (16 * mt + r16) * KFMLP_PITCH + 8 * kq);
-    // layer 1 (K = 32): units 16 ot + 4 kq + i of sample 16 mt + r16
-    f32x4 h1[4];
-#pragma unroll
-    for (int ot = 0; ot < 4; ++ot)
-      h1[ot] = mfma(load8(W + KFMLP_W1 + (ot * 16 + r16) * 32 + 8 * kq), x, f32x4{0.f, 0.f, 0.f, 0.f});
+    // Each stage produces one 8-unit K slice of the next layer's input from
+    // two 16-unit output blocks, so few accumulators are live at a time.
+    // layer 1 (K = 32): units 16 ot + 4 kq + i of sample 16 mt + r16, for
+    // ot = 2 ks, 2 ks + 1, give slice ks of the layer-2 input
     bf16x8 a1[2];
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks)
+    for (int ks = 0; ks < 2; ++ks) {
+      const f32x4 hA = mfma(load8(W + KFMLP_W1 + ((2 * ks) * 16 + r16) * 32 + 8 * kq), x, f32x4{0.f, 0.f, 0.f, 0.f});
+      const f32x4 hB =
+          mfma(load8(W + KFMLP_W1 + ((2 * ks + 1) * 16 + r16) * 32 + 8 * kq), x, f32x4{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int ot = 2 * ks + (j >> 2), i = j & 3;
-        a1[ks][j] = (__bf16)gelu(h1[ot][i] + blk[KFMLP_OFF_B1 + ot * 16 + 4 * kq + i]);
+      for (int i = 0; i < 4; ++i) {
+        a1[ks][i] = (__bf16)gelu(hA[i] + bk[KFMLP_OFF_B1 + (2 * ks) * 16 + 4 * kq + i]);
+        a1[ks][4 + i] = (__bf16)gelu(hB[i] + bk[KFMLP_OFF_B1 + (2 * ks + 1) * 16 + 4 * kq + i]);
       }
-    // layer 2 (K = 64 in two steps, W2 in permuted order)
-    f32x4 h2[4];
-#pragma unroll
-    for (int ot = 0; ot < 4; ++ot) {
-      h2[ot] = mfma(load8(W + KFMLP_W2P + ((ot * 2 + 0) * 16 + r16) * 32 + 8 * kq), a1[0],
-                    f32x4{0.f, 0.f, 0.f, 0.f});
-      h2[ot] = mfma(load8(W + KFMLP_W2P + ((ot * 2 + 1) * 16 + r16) * 32 + 8 * kq), a1[1], h2[ot]);
     }
-    bf16x8 a2[2];
+    // layer 2 (K = 64 in two steps, W2 in permuted order), each slice of its
+    // output feeding the head (outputs padded 2 -> 16) at once
+    f32x4 o = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks)
+    for (int ks = 0; ks < 2; ++ks) {
+      const int oa = 2 * ks, ob = 2 * ks + 1;
+      f32x4 hA = mfma(load8(W + KFMLP_W2P + ((oa * 2 + 0) * 16 + r16) * 32 + 8 * kq), a1[0], f32x4{0.f, 0.f, 0.f, 0.f});
+      hA = mfma(load8(W + KFMLP_W2P + ((oa * 2 + 1) * 16 + r16) * 32 + 8 * kq), a1[1], hA);
+      f32x4 hB = mfma(load8(W + KFMLP_W2P + ((ob * 2 + 0) * 16 + r16) * 32 + 8 * kq), a1[0], f32x4{0.f, 0.f, 0.f, 0.f});
+      hB = mfma(load8(W + KFMLP_W2P + ((ob * 2 + 1) * 16 + r16) * 32 + 8 * kq), a1[1], hB);
+      bf16x8 a2;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int ot = 2 * ks + (j >> 2), i = j & 3;
-        a2[ks][j] = (__bf16)gelu(h2[ot][i] + blk[KFMLP_OFF_B2 + ot * 16 + 4 * kq + i]);
+      for (int i = 0; i < 4; ++i) {
+        a2[i] = (__bf16)gelu(hA[i] + bk[KFMLP_OFF_B2 + oa * 16 + 4 * kq + i]);
+        a2[4 + i] = (__bf16)gelu(hB[i] + bk[KFMLP_OFF_B2 + ob * 16 + 4 * kq + i]);
       }
-    // head (outputs padded 2 -> 16): outputs 0 and 1 of sample 16 mt + r16
-    // land in lane r16 (kq = 0), elements 0 and 1
-    f32x4 o = mfma(load8(W + KFMLP_W3P + (0 * 16 + r16) * 32 + 8 * kq), a2[0], f32x4{0.f, 0.f, 0.f, 0.f});
-    o = mfma(load8(W + KFMLP_W3P + (1 * 16 + r16) * 32 + 8 * kq), a2[1], o);
-    const float s0 = __shfl(o[0], r16, 64), s1 = __shfl(o[1], r16, 64);
-    if (kq == mt) {
+      o = mfma(load8(W + KFMLP_W3P + (ks * 16 + r16) * 32 + 8 * kq), a2, o);
+    }
+    // outputs 0 and 1 of sample 16 mt + c land in lane c (kq = 0), elements
+    // 0 and 1; the lane of rank r takes sample r from lane r % 16 in tile r / 16
+    const float s0 = __shfl(o[0], rank & 15, 64), s1 = __shfl(o[1], rank & 15, 64);
+    if ((rank >> 4) == mt) {
       head[0] = s0;
       head[1] = s1;
     }
   }
   __builtin_amdgcn_wave_barrier();
+  if (active) {
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const float o = head[j] + blk[KFMLP_OFF_B3 + j];
-    if (o_out) o_out[j] = o;
-    w[j] = blk[KFMLP_OFF_SCALE + j] * softplus(o);
+    for (int j = 0; j < 2; ++j) {
+      const float o = head[j] + blk[KFMLP_OFF_B3 + j];
+      if (o_out) o_out[j] = o;
+      w[j] = blk[KFMLP_OFF_SCALE + j] * softplus(o);
+    }
   }
 }
 

@@ -285,7 +285,7 @@ __global__ void __launch_bounds__(64) infer_kernel(const float* __restrict__ blk
 #pragma unroll
   for (int k = 0; k < 27; ++k) x[k] = row < n ? src[k] : 0.f;
   float w[2], o[2];
-  wave_forward(blk, buf, [&](int k) { return x[k]; }, w, o);
+  wave_forward(blk, buf, [&](int k) { return x[k]; }, row < n, w, o);
   if (row < n) {
     const float kap = blk[KFMLP_OFF_KAPPA];
     out[(size_t)row * 2] = kap * w[0];

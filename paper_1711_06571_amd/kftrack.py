@@ -356,7 +356,8 @@ def _packed(Wm):
     return P
 
 
-def mlp_block(master, mu, sd, scale, kappa=1.0, floor_rphi=0.01, floor_z=0.1, device="cuda:0"):
+def mlp_block(master, mu, sd, scale, kappa=1.0, floor_rphi=0.01, floor_z=0.1, gate_rphi=0.0, gate_z=0.0,
+              device="cuda:0"):
     """Pack the device block: FP32 header then BF16 weights (W1 padded to 32
     inputs, W2, W3 padded to 16 rows, W2 transposed, then W2 and W3 in the
     inference's operand order)."""
@@ -371,6 +372,8 @@ def mlp_block(master, mu, sd, scale, kappa=1.0, floor_rphi=0.01, floor_z=0.1, de
     hdr[186] = kappa
     hdr[187] = floor_rphi
     hdr[188] = floor_z
+    hdr[189] = gate_rphi
+    hdr[190] = gate_z
     W1 = np.zeros((64, 32), dtype=np.float32)
     W1[:, :27] = p["W1"]
     W3 = np.zeros((16, 64), dtype=np.float32)
@@ -383,7 +386,14 @@ def mlp_block(master, mu, sd, scale, kappa=1.0, floor_rphi=0.01, floor_z=0.1, de
     return torch.from_numpy(raw.view(np.float32).copy()).to(device)
 
 
-def mlp_set_header(block, kappa=None, floor_rphi=None, floor_z=None):
+def mlp_set_header(block, kappa=None, floor_rphi=None, floor_z=None, gate_rphi=None, gate_z=None):
+    """Rewrite header words of a device block in place (None leaves a word);
+    gates: the network is consulted only where the plain arc or z half-width
+    exceeds them (0: everywhere)."""
+    if gate_rphi is not None:
+        block[189] = gate_rphi
+    if gate_z is not None:
+        block[190] = gate_z
     if kappa is not None:
         block[186] = kappa
     if floor_rphi is not None:

@@ -11,10 +11,15 @@ the layer radius and |dz| from the prediction to the true hit).
 Training: asymmetric quantile loss (a missed true hit costs 20 times a unit
 of extra width), Adam on FP32 master weights, BF16 working weights.
 
-Calibration: the widths are multiplied by kappa >= 1, chosen on validation
-events as the smallest value whose build efficiency stays within the target
-of the plain window's; predictions below the floors fall back to the plain
-window (floors: one hit resolution, 0.01 cm arc and 0.1 cm in z).
+Gating: the network is consulted only where the plain window is wide (a
+plain half-width above its gate, a quantile of the training rows' plain
+widths), where it saves most of the scanned hits; elsewhere the plain window
+stays.  The network is trained on the rows the gates pass.
+
+Calibration: the widths are multiplied by kappa, chosen on validation events
+as the smallest value whose build efficiency stays within the target of the
+plain window's; predictions below the floors fall back to the plain window
+(floors: one hit resolution, 0.01 cm arc and 0.1 cm in z).
 """
 from __future__ import annotations
 
@@ -30,6 +35,11 @@ from . import presets, workloads
 DEV = "cuda:0"
 SCALE = np.array([0.01, 0.1])   # output scales: arc cm, z cm
 FLOOR = (0.01, 0.1)
+# the network is consulted where a plain half-width lies above this quantile
+# of the training rows' (about an eighth of them): the wide windows, which scan
+# most of the hits
+GATE_QUANTILE = 0.9
+KAPPAS = [0.6, 0.7, 0.8, 0.9, 1.0, 1.1, 1.2, 1.35, 1.5, 1.75, 2.0, 2.5, 3.0]
 
 
 @dataclass
@@ -104,6 +114,33 @@ def dump_rows(w, e: EventOnGPU, capacity=3_000_000) -> np.ndarray:
     return rows[np.argsort(key, kind="stable")]
 
 
+def plain_widths(w, rows):
+    """Plain half-widths (arc at the layer radius, z; cm) of dumped rows, from
+    their predicted state and covariance: nsigma * sqrt(H P H^T + diag(
+    win_sig^2)) as the builder forms them (covariance entries in upper-
+    triangle order: 0 = xx, 1 = xy, 6 = yy, 11 = zz)."""
+    c = w.cuts
+    X = rows[:, :6].astype(np.float64)
+    P = rows[:, 6:27].astype(np.float64)
+    rr = np.hypot(X[:, 0], X[:, 1])
+    tx, ty = -X[:, 1] / rr, X[:, 0] / rr
+    suu = tx * tx * P[:, 0] + 2 * tx * ty * P[:, 1] + ty * ty * P[:, 6] + float(c.win_sig_rphi) ** 2
+    sww = P[:, 11] + float(c.win_sig_z) ** 2
+    # FP32 rows of a nearly singular covariance can round the projection
+    # below zero: those count as the narrowest window
+    return float(c.nsigma) * np.sqrt(np.maximum(suu, 0.0)), float(c.nsigma) * np.sqrt(np.maximum(sww, 0.0))
+
+
+def gates(w, rows, quantile):
+    """Gate half-widths (arc, z) at the given quantile of the rows' plain
+    widths: the network is consulted where either plain width lies above its
+    gate (quantile 0: nearly everywhere)."""
+    wr, wz = plain_widths(w, rows)
+    if quantile <= 0:
+        return 0.0, 0.0
+    return float(np.quantile(wr, quantile)), float(np.quantile(wz, quantile))
+
+
 def init_master(rng):
     W1 = rng.normal(0, np.sqrt(2.0 / 27), (64, 27))
     W2 = rng.normal(0, np.sqrt(2.0 / 64), (64, 64))
@@ -132,6 +169,8 @@ class Trained:
     seconds: float
     steps: int
     loss0: float = 0.0  # mean loss of the initial network over the first batches
+    gates: tuple = (0.0, 0.0)  # plain half-widths (arc, z) above which the network is consulted
+    rows_used: int = 0
 
 
 def train(rows: np.ndarray, epochs=4, batch=4096, lr=1e-3, seed=1711065715, log=None) -> Trained:
@@ -174,13 +213,27 @@ def train(rows: np.ndarray, epochs=4, batch=4096, lr=1e-3, seed=1711065715, log=
         if log:
             log(f"epoch {ep} loss {losses[-1]:.5f}")
     torch.cuda.synchronize()
-    return Trained(master, block, mu, sd, losses, time.perf_counter() - t0, step, loss0)
+    return Trained(master, block, mu, sd, losses, time.perf_counter() - t0, step, loss0, (0.0, 0.0), n)
+
+
+def train_gated(w, rows: np.ndarray, quantile=GATE_QUANTILE, epochs=4, **kw) -> Trained:
+    """Gates at `quantile` of the rows' plain widths, then training on the
+    rows the gates pass (the population the network will see), for as many
+    optimiser steps as `epochs` over all rows would take."""
+    gr, gz = gates(w, rows, quantile)
+    wr, wz = plain_widths(w, rows)
+    sel = (wr > gr) | (wz > gz)
+    n_sel = max(int(sel.sum()), 1)
+    t = train(rows[sel], epochs=max(epochs, int(round(epochs * rows.shape[0] / n_sel))), **kw)
+    kf.mlp_set_header(t.block, gate_rphi=gr, gate_z=gz)
+    t.gates = (gr, gz)
+    return t
 
 
 def calibrate(w, t: Trained, val: EventOnGPU, eff_plain: float, target=0.001, kappas=None, arith=kf.ARITH_F32):
     """Smallest kappa whose efficiency on the validation events is within
     `target` of the plain window's."""
-    kappas = kappas or [1.0, 1.1, 1.2, 1.35, 1.5, 1.75, 2.0, 2.5, 3.0]
+    kappas = kappas or KAPPAS
     res = []
     for kap in kappas:
         kf.mlp_set_header(t.block, kappa=kap)

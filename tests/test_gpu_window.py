@@ -39,7 +39,8 @@ def oracle_blob(kf, t, kappa):
     q["mu"] = blk[0:27].astype(np.float64)
     q["sd"] = 1.0 / isd
     q["scale"] = blk[184:186].astype(np.float64)
-    return omlp.blob(q, kappa=kappa, floor_rphi=float(blk[187]), floor_z=float(blk[188]))
+    return omlp.blob(q, kappa=kappa, floor_rphi=float(blk[187]), floor_z=float(blk[188]),
+                     gate_rphi=float(blk[189]), gate_z=float(blk[190]))
 
 
 def test_training_reduces_loss(env):
@@ -53,9 +54,13 @@ def test_training_reduces_loss(env):
     assert np.all(r[:, 27] >= 0) and np.all(r[:, 28] >= 0)
 
 
-def test_learned_build_matches_oracle(env):
+@pytest.mark.parametrize("gate_q", [0.0, 0.6])
+def test_learned_build_matches_oracle(env, gate_q):
+    """Gate quantile 0 consults the network for every candidate; 0.6 for the
+    wide-window ones only (scattered lanes of a wave, compacted into tiles)."""
     kf, window, w, t = env["kf"], env["window"], env["w"], env["t"]
-    kf.mlp_set_header(t.block, kappa=1.5)
+    gr, gz = window.gates(w, env["rows"], gate_q)
+    kf.mlp_set_header(t.block, kappa=1.5, gate_rphi=gr, gate_z=gz)
     ev = datagen.generate(w.geometry, w.gen, 50, 500)
     n = ev.n_tracks
     xyz = ev.xyz.astype(np.float32)
@@ -74,26 +79,35 @@ def test_learned_build_matches_oracle(env):
     # than 1e-3 cm (a tenth of the arc resolution) decide
     dec = (m[0] > 1e-3) & (m[1] > 1e-3) & (m[2] > 1e-3)
     same = np.all(g["hits"][:, :n] == o["hits"], axis=0) & (g["nhits"][:n] == o["nhits"])
-    print(f"learned build: undecidable {1 - dec.mean():.4f}, identical {same.mean():.4f}")
+    print(f"learned build (gates {gr:.4f}, {gz:.4f}): undecidable {1 - dec.mean():.4f}, "
+          f"identical {same.mean():.4f}")
     assert same[dec].all(), np.where(dec & ~same)[0][:10]
 
 
-def test_learned_vs_plain(env):
-    kf, window, w, t = env["kf"], env["window"], env["w"], env["t"]
+@pytest.mark.parametrize("arith", ["f32", "f64"])
+def test_learned_vs_plain(env, arith):
+    """Gated network trained on the rows its gates pass, kappa calibrated on
+    a validation event, compared with the plain window on a disjoint event."""
+    kf, window, w = env["kf"], env["window"], env["w"]
+    a = kf.ARITH_F32 if arith == "f32" else kf.ARITH_F64
+    if "tg" not in env:
+        env["tg"] = window.train_gated(w, env["rows"], epochs=3)
+    t = env["tg"]
+    assert t.gates[0] > 0 and t.gates[1] > 0 and 0 < t.rows_used < env["rows"].shape[0]
     val = window.load_events(w, [1])
     test = window.load_events(w, [2])
-    out_p, _ = window.build(w, val)
+    out_p, _ = window.build(w, val, arith=a)
     eff_plain_val = window.efficiency(w, val, out_p)
-    kap, trace = window.calibrate(w, t, val, eff_plain_val, target=0.001)
+    kap, trace = window.calibrate(w, t, val, eff_plain_val, target=0.001, arith=a)
     kf.mlp_set_header(t.block, kappa=kap)
-    outp, cp = window.build(w, test, counters=True)
-    outl, cl = window.build(w, test, window_mode=1, block=t.block, counters=True)
+    outp, cp = window.build(w, test, counters=True, arith=a)
+    outl, cl = window.build(w, test, window_mode=1, block=t.block, counters=True, arith=a)
     torch.cuda.synchronize()
     ep, el = window.efficiency(w, test, outp), window.efficiency(w, test, outl)
-    tp = window.time_build(w, test, 0)
-    tl = window.time_build(w, test, 1, t.block)
+    tp = window.time_build(w, test, 0, arith=a)
+    tl = window.time_build(w, test, 1, t.block, arith=a)
     cp, cl = host(cp), host(cl)
-    print(f"kappa {kap} (val trace {trace}); test eff plain {ep:.4f} learned {el:.4f}; "
+    print(f"{arith}: gates {t.gates}, kappa {kap} (val trace {trace}); test eff plain {ep:.4f} learned {el:.4f}; "
           f"hits tested per cand-layer plain {cp[1] / cp[0]:.2f} learned {cl[1] / cl[0]:.2f}; "
           f"build ms plain {tp:.3f} learned {tl:.3f}")
     assert ep - el <= 0.002  # calibrated on validation events to 0.1 %; test events disjoint
