@@ -174,26 +174,30 @@ __device__ inline bool top_before(float c2, uint32_t orig, float oc2, uint32_t o
   return c2 < oc2 || (c2 == oc2 && orig < oorig);
 }
 
-__device__ inline void top_insert(TopList& tl, int cap, float c2, int pos, uint32_t orig) {
-  int j = tl.n;
-  if (j == cap) {  // full: the new hit must beat the last entry
-    if (!top_before(c2, orig, tl.c2[(cap - 1) * 64], tl.orig[(cap - 1) * 64])) return;
-    j = cap - 1;
-  } else {
-    tl.n += 1;
+// The list while the hit search fills it: in registers, sorted, slots past
+// the entries hold +inf.  Insertion is branch-free over the cap slots (cap
+// is uniform): every slot keeps its entry, takes the new one or takes its
+// predecessor's.  A full list drops its last entry (the new hit must rank
+// before it: the caller's admission test).
+struct RegTop {
+  float c2[8];
+  int32_t pos[8];
+  uint32_t orig[8];
+};
+
+__device__ inline void reg_insert(RegTop& t, int cap, float c2, int pos, uint32_t orig) {
+  bool lt[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) lt[i] = top_before(t.c2[i], t.orig[i], c2, orig);
+#pragma unroll
+  for (int i = 7; i >= 0; --i) {
+    if (i < cap && !lt[i]) {
+      const bool here = i == 0 || lt[i - 1];
+      t.c2[i] = here ? c2 : t.c2[i > 0 ? i - 1 : 0];
+      t.pos[i] = here ? pos : t.pos[i > 0 ? i - 1 : 0];
+      t.orig[i] = here ? orig : t.orig[i > 0 ? i - 1 : 0];
+    }
   }
-  while (j > 0) {
-    const float pc = tl.c2[(j - 1) * 64];
-    const uint32_t po = tl.orig[(j - 1) * 64];
-    if (!top_before(c2, orig, pc, po)) break;
-    tl.c2[j * 64] = pc;
-    tl.pos[j * 64] = tl.pos[(j - 1) * 64];
-    tl.orig[j * 64] = po;
-    --j;
-  }
-  tl.c2[j * 64] = c2;
-  tl.pos[j * 64] = pos;
-  tl.orig[j * 64] = orig;
 }
 
 __device__ inline void top_get(const TopList& tl, int k, float& c2, int& pos, uint32_t& orig) {
@@ -224,9 +228,10 @@ __device__ inline int wave_max(int v) {
 }
 
 // Per-wave LDS of the cooperative hit search: each candidate's count of
-// accepted hits.
+// accepted hits, and per round the candidate whose pairs start at each lane.
 struct AccBuf {
   int32_t* tot;
+  int32_t* start;
 };
 
 // Hit search of every candidate of the wave, shared by all 64 lanes.
@@ -305,6 +310,14 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
   const int R = pok ? (iz1 - iz0 + 1) * 2 : 0;
   const int Rmax = wave_max(R);
   ab.tot[lane] = 0;
+  RegTop rt;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    rt.c2[i] = __builtin_inff();
+    rt.pos[i] = -1;
+    rt.orig[i] = 0xFFFFFFFFu;
+  }
+  int held = 0;  // entries in the list
   // the candidate's admission threshold: its last entry once its list is full
   float thr_c2 = 0.f;
   uint32_t thr_o = 0;
@@ -325,17 +338,23 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
     const int cnt = p1 > p0 ? p1 - p0 : 0;
     int total = 0;
     const int off = wave_excl_scan(cnt, lane, total);
+    int carry = 0;  // candidate of the previous round's last pair
     for (int base = 0; base < total; base += 64) {
       const int k = base + lane;
-      // candidate of pair k: the last lane whose prefix is <= k
-      int lo = 0, hi = 64;
-#pragma unroll
-      for (int it = 0; it < 6; ++it) {
-        const int mid = (lo + hi) >> 1;
-        if (__shfl(off, mid, 64) <= k) lo = mid; else hi = mid;
-      }
-      const int c = lo;
-      const int p = __shfl(p0, c, 64) + (k - __shfl(off, c, 64));
+      // candidate of pair k: candidates mark the lane where their pairs start
+      // in this round; the pair's candidate is the nearest mark at or below
+      // its lane, else the one whose pairs run on from the previous round
+      ab.start[lane] = -1;
+      if (cnt > 0 && off >= base && off - base < 64) ab.start[off - base] = lane;
+      __builtin_amdgcn_wave_barrier();
+      const int st = ab.start[lane];
+      const unsigned long long sm = __ballot(st >= 0) & ((2ull << lane) - 1ull);
+      const int hb = sm ? 63 - (int)__builtin_clzll(sm) : 0;
+      const int sc = __shfl(st, hb, 64);
+      const int c = sm ? sc : carry;
+      carry = __builtin_amdgcn_readlane(c, 63);
+      const int coff = __shfl(off, c, 64);
+      const int p = __shfl(p0, c, 64) + (k - coff);
       const float ca = __shfl(a, c, 64), cb = __shfl(b, c, 64);
       const float cx = __shfl(fx, c, 64), cy = __shfl(fy, c, 64), cz = __shfl(fz, c, 64);
       const float cdz = __shfl(fdz, c, 64), cdphi = __shfl(fdphi, c, 64), ctan = __shfl(ftan, c, 64);
@@ -358,6 +377,10 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
 #pragma unroll
         for (int q = 0; q < 6; ++q) V[q] = A.hcov[(size_t)q * A.n_hits + p];
         const uint32_t forig = (uint32_t)A.horig[p];
+        // all ten loads in flight before the first test (the compiler would
+        // otherwise wait for phi and issue the rest behind the phi test)
+        asm volatile("" ::"v"(ph), "v"(hx), "v"(hy), "v"(hz), "v"(V[0]), "v"(V[1]), "v"(V[2]), "v"(V[3]),
+                     "v"(V[4]), "v"(V[5]), "v"(forig));
         if (ph >= ca && ph <= cb) {
           tl.scanned += 1;
           const float cr = cx * hy - cy * hx, dt = cx * hx + cy * hy;
@@ -381,27 +404,57 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
           }
         }
       }
-      // the admissible hits of this round, one at a time (in lane order), go
-      // to their candidate's lane, which inserts them into its list
+      // the admissible hits of this round go to their candidates' lanes: in
+      // each step every candidate takes the first pending hit of its own run
+      // of lanes (a candidate's pairs occupy consecutive lanes), so the steps
+      // number the most hits any one candidate has in the round
       unsigned long long m = __ballot(keep);
       if (m) {
-        while (m) {
-          const int j = __builtin_ctzll(m);
-          m &= m - 1ull;
-          const int jc = __builtin_amdgcn_readlane(c, j);
-          const float jc2 = readlane_t(c2, j);
-          const int jp = __builtin_amdgcn_readlane(p, j);
-          const uint32_t jo = (uint32_t)__builtin_amdgcn_readlane((int)orig, j);
-          if (lane == jc) top_insert(tl, A.cap, jc2, jp, jo);
-        }
-        if (tl.n == A.cap) {
+        // this lane's run as a candidate, and the start of its pair's run
+        const int s0 = off - base > 0 ? off - base : 0;
+        const int e0 = off + cnt - base < 64 ? off + cnt - base : 64;
+        const int my_lo = coff - base > 0 ? coff - base : 0;
+        do {
+          int j = 64;
+          if (s0 < e0) {
+            const unsigned long long mm = m >> s0;
+            if (mm) {
+              j = s0 + (int)__builtin_ctzll(mm);
+              if (j >= e0) j = 64;
+            }
+          }
+          const int js = j & 63;
+          const float jc2 = __shfl(c2, js, 64);
+          const int jp = __shfl(p, js, 64);
+          const uint32_t jo = (uint32_t)__shfl((int)orig, js, 64);
+          if (j < 64) {
+            reg_insert(rt, A.cap, jc2, jp, jo);
+            held = held < A.cap ? held + 1 : held;
+          }
+          const bool first = ((m >> lane) & 1ull) && ((m >> my_lo) & ((1ull << (lane - my_lo)) - 1ull)) == 0;
+          m &= ~__ballot(first);
+        } while (m);
+        if (held == A.cap) {
           full = 1;
-          thr_c2 = tl.c2[(A.cap - 1) * 64];
-          thr_o = tl.orig[(A.cap - 1) * 64];
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            if (i == A.cap - 1) {
+              thr_c2 = rt.c2[i];
+              thr_o = rt.orig[i];
+            }
         }
       }
     }
   }
+  // the list goes to LDS for the merge
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+    if (i < held) {
+      tl.c2[i * 64] = rt.c2[i];
+      tl.pos[i * 64] = rt.pos[i];
+      tl.orig[i * 64] = rt.orig[i];
+    }
+  tl.n = held;
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
   tl.tot = ab.tot[lane];
@@ -416,7 +469,8 @@ __device__ inline uint32_t pack_hist(int parent, uint32_t orig24) {
 //   record   [SEEDS][27] f32   best finished candidate of each seed
 //   recfield [SEEDS][5] i32    valid, nhits, status, last layer, slot
 //   toplist  [cap][64] f32 chi2, then [cap][64] i32 positions, [cap][64] u32 indices
-//   accept   [64] i32 accepted hits per candidate (the cooperative hit search)
+//   accept   [64] i32 accepted hits per candidate, [64] i32 run starts (the
+//            cooperative hit search)
 //   mlp      activation buffer of the learned window (the network runs before
 //            the hit search, so the toplists of a learned build live in it)
 struct LdsPlan {
@@ -433,7 +487,7 @@ __host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsi
   (void)tsize;
   const size_t tl_wave = (size_t)cap * 64 * 12;
   p.acc = align16(p.recf + (size_t)nwaves * seeds * 5 * 4);
-  p.tl = align16(p.acc + (size_t)nwaves * 64 * 4);
+  p.tl = align16(p.acc + (size_t)nwaves * 128 * 4);
   if (learned) {
     const size_t per = tl_wave > KFMLP_LDS_BYTES ? tl_wave : (size_t)KFMLP_LDS_BYTES;
     p.mlp = p.tl;
@@ -486,7 +540,8 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
   int32_t* tl_pos = (int32_t*)(wave_tl + (size_t)S * 64 * 4) + lane;
   uint32_t* tl_orig = (uint32_t*)(wave_tl + (size_t)S * 64 * 8) + lane;
   AccBuf ab;
-  ab.tot = (int32_t*)(base + lp.acc) + (size_t)wave * 64;
+  ab.tot = (int32_t*)(base + lp.acc) + (size_t)wave * 128;
+  ab.start = ab.tot + 64;
   (void)mlp_buf;
   const int sidx = lane / S, slot = lane - (lane / S) * S, sbase = sidx * S;
   const bool lane_used = sidx < SEEDS;
