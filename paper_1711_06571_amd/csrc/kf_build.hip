@@ -257,6 +257,9 @@ struct AccBuf {
 // positions ~ 1e-5 cm) stays far below the chi2 gaps (1e-3) and window-edge
 // distances (1e-4 cm) that separate decisions; the Kalman update of a
 // chosen hit runs in the arithmetic of the mode.
+// pairs per lane per round of the hit search
+constexpr int NP = 2;
+
 template <typename T>
 __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, const T Xp[6], const T Pp[21],
                                  T dphi_w, T dz_w, TopList& tl, const AccBuf& ab, int lane) {
@@ -269,11 +272,11 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
   int iz0 = 0, iz1 = -1;
   // Per candidate, what every hit test shares: for dphi < pi/2 the angle
   // test |atan2(cross, dot)| <= dphi is dot > 0 and |cross| <= tan(dphi) dot
-  // (wider windows keep the angle); the measurement frame (tangent t at the
-  // predicted point) and H P H^T of the prediction.
+  // (ftan < 0 marks a wider window, which keeps the angle); the measurement
+  // frame (tangent t = (-y, x) / r at the predicted point, from 1 / r) and
+  // H P H^T of the prediction.
   float fx = 0.f, fy = 0.f, fz = 0.f, fdz = 0.f, fdphi = 0.f, ftan = 0.f;
-  float utx = 0.f, uty = 0.f, suu = 0.f, suw = 0.f, sww = 0.f;
-  int wide = 0;
+  float firr = 0.f, suu = 0.f, suw = 0.f, sww = 0.f;
   if (pok) {
     const float zh = A.z_half;
     fx = (float)Xp[0];
@@ -295,13 +298,11 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
       else if (hi >= tp) { a0 = lo; b0v = tp; a1 = 0.f; b1v = hi - tp; }
       else { a0 = lo; b0v = hi; }
     }
-    wide = !(dphi_w < T(1.5707963267948966));
-    ftan = wide ? 0.f : (float)k_tan(dphi_w);
+    ftan = !(dphi_w < T(1.5707963267948966)) ? -1.f : (float)k_tan(dphi_w);
     const T rr = k_sqrt(Xp[0] * Xp[0] + Xp[1] * Xp[1]);
     const T irr = k_rcp(rr);
     const T tx = -Xp[1] * irr, ty = Xp[0] * irr;
-    utx = (float)tx;
-    uty = (float)ty;
+    firr = (float)irr;
     suu = (float)(tx * tx * Pp[ut(0, 0)] + T(2) * tx * ty * Pp[ut(0, 1)] + ty * ty * Pp[ut(1, 1)]);
     suw = (float)(tx * Pp[ut(0, 2)] + ty * Pp[ut(1, 2)]);
     sww = (float)Pp[ut(2, 2)];
@@ -318,10 +319,10 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
     rt.orig[i] = 0xFFFFFFFFu;
   }
   int held = 0;  // entries in the list
-  // the candidate's admission threshold: its last entry once its list is full
-  float thr_c2 = 0.f;
-  uint32_t thr_o = 0;
-  int full = 0;
+  // the candidate's admission threshold: its last entry once its list is
+  // full (before, +inf admits every accepted hit)
+  float thr_c2 = __builtin_inff();
+  uint32_t thr_o = 0xFFFFFFFFu;
   const float cut = A.chi2_cut;
   for (int r = 0; r < Rmax; ++r) {
     int p0 = 0, p1 = 0;
@@ -338,110 +339,146 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
     const int cnt = p1 > p0 ? p1 - p0 : 0;
     int total = 0;
     const int off = wave_excl_scan(cnt, lane, total);
+    const int pb = p0 - off;  // sorted position of pair k of this candidate: pb + k
     int carry = 0;  // candidate of the previous round's last pair
-    for (int base = 0; base < total; base += 64) {
-      const int k = base + lane;
-      // candidate of pair k: candidates mark the lane where their pairs start
+    // each lane takes NP pairs per round (pair base + 64 h + lane): their
+    // loads share one round trip
+    for (int base = 0; base < total; base += 64 * NP) {
+      // candidate of a pair: candidates mark the slot where their pairs start
       // in this round; the pair's candidate is the nearest mark at or below
-      // its lane, else the one whose pairs run on from the previous round
-      ab.start[lane] = -1;
-      if (cnt > 0 && off >= base && off - base < 64) ab.start[off - base] = lane;
-      __builtin_amdgcn_wave_barrier();
-      const int st = ab.start[lane];
-      const unsigned long long sm = __ballot(st >= 0) & ((2ull << lane) - 1ull);
-      const int hb = sm ? 63 - (int)__builtin_clzll(sm) : 0;
-      const int sc = __shfl(st, hb, 64);
-      const int c = sm ? sc : carry;
-      carry = __builtin_amdgcn_readlane(c, 63);
-      const int coff = __shfl(off, c, 64);
-      const int p = __shfl(p0, c, 64) + (k - coff);
-      const float ca = __shfl(a, c, 64), cb = __shfl(b, c, 64);
-      const float cx = __shfl(fx, c, 64), cy = __shfl(fy, c, 64), cz = __shfl(fz, c, 64);
-      const float cdz = __shfl(fdz, c, 64), cdphi = __shfl(fdphi, c, 64), ctan = __shfl(ftan, c, 64);
-      const int cwide = __shfl(wide, c, 64);
-      const float ctx = __shfl(utx, c, 64), cty = __shfl(uty, c, 64);
-      const float csuu = __shfl(suu, c, 64), csuw = __shfl(suw, c, 64), csww = __shfl(sww, c, 64);
-      const int cfull = __shfl(full, c, 64);
-      const float cthr = __shfl(thr_c2, c, 64);
-      const uint32_t cthro = (uint32_t)__shfl((int)thr_o, c, 64);
-      bool keep = false;
-      float c2 = 0.f;
-      uint32_t orig = 0;
-      if (k < total) {
-        // everything the pair can need, in one round trip (a second
-        // dependent round trip for the covariance of in-window hits costs
-        // more than the bytes)
-        const float ph = A.hphi[p];
-        const float hx = A.hx[p], hy = A.hy[p], hz = A.hz[p];
-        float V[6];
+      // its slot in its half, else the one whose pairs run on from before
 #pragma unroll
-        for (int q = 0; q < 6; ++q) V[q] = A.hcov[(size_t)q * A.n_hits + p];
-        const uint32_t forig = (uint32_t)A.horig[p];
-        // all ten loads in flight before the first test (the compiler would
-        // otherwise wait for phi and issue the rest behind the phi test)
-        asm volatile("" ::"v"(ph), "v"(hx), "v"(hy), "v"(hz), "v"(V[0]), "v"(V[1]), "v"(V[2]), "v"(V[3]),
-                     "v"(V[4]), "v"(V[5]), "v"(forig));
-        if (ph >= ca && ph <= cb) {
+      for (int h = 0; h < NP; ++h) ab.start[h * 64 + lane] = -1;
+      if (cnt > 0 && off >= base && off - base < 64 * NP) ab.start[off - base] = lane;
+      __builtin_amdgcn_wave_barrier();
+      int c[NP], my_lo[NP], p[NP];
+      bool valid[NP];
+      float ca[NP], cb[NP], cx[NP], cy[NP], cz[NP], cdz[NP], cdphi[NP], ctan[NP], cirr[NP], csuu[NP], csuw[NP],
+          csww[NP], cthr[NP];
+      uint32_t cthro[NP];
+#pragma unroll
+      for (int h = 0; h < NP; ++h) {
+        const int st = ab.start[h * 64 + lane];
+        const unsigned long long sm = __ballot(st >= 0) & ((2ull << lane) - 1ull);
+        const int hb = sm ? 63 - (int)__builtin_clzll(sm) : 0;
+        const int sc = __shfl(st, hb, 64);
+        c[h] = sm ? sc : carry;
+        my_lo[h] = sm ? hb : 0;  // first slot of this pair's candidate in the half
+        carry = __builtin_amdgcn_readlane(c[h], 63);
+        const int k = base + 64 * h + lane;
+        valid[h] = k < total;
+        p[h] = __shfl(pb, c[h], 64) + k;
+        ca[h] = __shfl(a, c[h], 64);
+        cb[h] = __shfl(b, c[h], 64);
+        cx[h] = __shfl(fx, c[h], 64);
+        cy[h] = __shfl(fy, c[h], 64);
+        cz[h] = __shfl(fz, c[h], 64);
+        cdz[h] = __shfl(fdz, c[h], 64);
+        cdphi[h] = __shfl(fdphi, c[h], 64);
+        ctan[h] = __shfl(ftan, c[h], 64);
+        cirr[h] = __shfl(firr, c[h], 64);
+        csuu[h] = __shfl(suu, c[h], 64);
+        csuw[h] = __shfl(suw, c[h], 64);
+        csww[h] = __shfl(sww, c[h], 64);
+        cthr[h] = __shfl(thr_c2, c[h], 64);
+        cthro[h] = (uint32_t)__shfl((int)thr_o, c[h], 64);
+      }
+      // everything each pair can need, in one round trip for all NP pairs
+      // (a pair past the end reads the round's first pair, which exists)
+      float ph[NP], hx[NP], hy[NP], hz[NP], V[NP][6];
+      uint32_t forig[NP];
+      const int p_first = __builtin_amdgcn_readfirstlane(__shfl(p[0], 0, 64));
+#pragma unroll
+      for (int h = 0; h < NP; ++h) {
+        const int ps = valid[h] ? p[h] : p_first;
+        ph[h] = A.hphi[ps];
+        hx[h] = A.hx[ps];
+        hy[h] = A.hy[ps];
+        hz[h] = A.hz[ps];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) V[h][q] = A.hcov[(size_t)q * A.n_hits + ps];
+        forig[h] = (uint32_t)A.horig[ps];
+      }
+      // all loads in flight before the first test (the compiler would
+      // otherwise wait for phi and issue the rest behind the phi test)
+#pragma unroll
+      for (int h = 0; h < NP; ++h)
+        asm volatile("" ::"v"(ph[h]), "v"(hx[h]), "v"(hy[h]), "v"(hz[h]), "v"(V[h][0]), "v"(V[h][1]), "v"(V[h][2]),
+                     "v"(V[h][3]), "v"(V[h][4]), "v"(V[h][5]), "v"(forig[h]));
+      bool keep[NP];
+      float c2[NP];
+      uint32_t orig[NP];
+#pragma unroll
+      for (int h = 0; h < NP; ++h) {
+        keep[h] = false;
+        c2[h] = 0.f;
+        orig[h] = 0;
+        if (valid[h] && ph[h] >= ca[h] && ph[h] <= cb[h]) {
           tl.scanned += 1;
-          const float cr = cx * hy - cy * hx, dt = cx * hx + cy * hy;
-          const bool in_phi = cwide ? fabsf(atan2f(cr, dt)) <= cdphi : (dt > 0.f && fabsf(cr) <= ctan * dt);
-          if (fabsf(hz - cz) <= cdz && in_phi) {
+          const float cr = cx[h] * hy[h] - cy[h] * hx[h], dt = cx[h] * hx[h] + cy[h] * hy[h];
+          const bool in_phi =
+              ctan[h] < 0.f ? fabsf(atan2f(cr, dt)) <= cdphi[h] : (dt > 0.f && fabsf(cr) <= ctan[h] * dt);
+          if (fabsf(hz[h] - cz[h]) <= cdz[h] && in_phi) {
             // innovation in the tangent-plane frame and its chi2 (2 dof)
             tl.tested += 1;
-            const float r0 = ctx * (hx - cx) + cty * (hy - cy), r1 = hz - cz;
-            const float s00 = csuu + ctx * ctx * V[0] + 2.f * ctx * cty * V[1] + cty * cty * V[3];
-            const float s01 = csuw + ctx * V[2] + cty * V[4];
-            const float s11 = csww + V[5];
+            const float ctx = -cy[h] * cirr[h], cty = cx[h] * cirr[h];
+            const float r0 = ctx * (hx[h] - cx[h]) + cty * (hy[h] - cy[h]), r1 = hz[h] - cz[h];
+            const float s00 = csuu[h] + ctx * ctx * V[h][0] + 2.f * ctx * cty * V[h][1] + cty * cty * V[h][3];
+            const float s01 = csuw[h] + ctx * V[h][2] + cty * V[h][4];
+            const float s11 = csww[h] + V[h][5];
             const float det = s00 * s11 - s01 * s01;
             if (s00 > 0.f && det > 0.f) {
-              c2 = (s11 * r0 * r0 - 2.f * s01 * r0 * r1 + s00 * r1 * r1) / det;
-              if (c2 < cut) {
-                atomicAdd(&ab.tot[c], 1);
-                orig = forig;
-                keep = !cfull || top_before(c2, orig, cthr, cthro);
+              c2[h] = (s11 * r0 * r0 - 2.f * s01 * r0 * r1 + s00 * r1 * r1) / det;
+              if (c2[h] < cut) {
+                atomicAdd(&ab.tot[c[h]], 1);
+                orig[h] = forig[h];
+                keep[h] = top_before(c2[h], orig[h], cthr[h], cthro[h]);
               }
             }
           }
         }
       }
-      // the admissible hits of this round go to their candidates' lanes: in
+      // the admissible hits of each half go to their candidates' lanes: in
       // each step every candidate takes the first pending hit of its own run
       // of lanes (a candidate's pairs occupy consecutive lanes), so the steps
-      // number the most hits any one candidate has in the round
-      unsigned long long m = __ballot(keep);
-      if (m) {
-        // this lane's run as a candidate, and the start of its pair's run
-        const int s0 = off - base > 0 ? off - base : 0;
-        const int e0 = off + cnt - base < 64 ? off + cnt - base : 64;
-        const int my_lo = coff - base > 0 ? coff - base : 0;
-        do {
-          int j = 64;
-          if (s0 < e0) {
-            const unsigned long long mm = m >> s0;
-            if (mm) {
-              j = s0 + (int)__builtin_ctzll(mm);
-              if (j >= e0) j = 64;
-            }
-          }
-          const int js = j & 63;
-          const float jc2 = __shfl(c2, js, 64);
-          const int jp = __shfl(p, js, 64);
-          const uint32_t jo = (uint32_t)__shfl((int)orig, js, 64);
-          if (j < 64) {
-            reg_insert(rt, A.cap, jc2, jp, jo);
-            held = held < A.cap ? held + 1 : held;
-          }
-          const bool first = ((m >> lane) & 1ull) && ((m >> my_lo) & ((1ull << (lane - my_lo)) - 1ull)) == 0;
-          m &= ~__ballot(first);
-        } while (m);
-        if (held == A.cap) {
-          full = 1;
+      // number the most hits any one candidate has in the half
 #pragma unroll
-          for (int i = 0; i < 8; ++i)
-            if (i == A.cap - 1) {
-              thr_c2 = rt.c2[i];
-              thr_o = rt.orig[i];
+      for (int h = 0; h < NP; ++h) {
+        unsigned long long m = __ballot(keep[h]);
+        if (m) {
+          // this lane's run as a candidate in the half
+          const int bh = base + 64 * h;
+          const int s0 = off - bh > 0 ? off - bh : 0;
+          const int e0 = off + cnt - bh < 64 ? off + cnt - bh : 64;
+          do {
+            int j = 64;
+            if (s0 < e0) {
+              const unsigned long long mm = m >> s0;
+              if (mm) {
+                j = s0 + (int)__builtin_ctzll(mm);
+                if (j >= e0) j = 64;
+              }
             }
+            const int js = j & 63;
+            const float jc2 = __shfl(c2[h], js, 64);
+            const int jp = __shfl(p[h], js, 64);
+            const uint32_t jo = (uint32_t)__shfl((int)orig[h], js, 64);
+            if (j < 64) {
+              reg_insert(rt, A.cap, jc2, jp, jo);
+              held = held < A.cap ? held + 1 : held;
+            }
+            const bool first =
+                ((m >> lane) & 1ull) && ((m >> my_lo[h]) & ((1ull << (lane - my_lo[h])) - 1ull)) == 0;
+            m &= ~__ballot(first);
+          } while (m);
+          if (held == A.cap) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+              if (i == A.cap - 1) {
+                thr_c2 = rt.c2[i];
+                thr_o = rt.orig[i];
+              }
+          }
         }
       }
     }
@@ -469,8 +506,8 @@ __device__ inline uint32_t pack_hist(int parent, uint32_t orig24) {
 //   record   [SEEDS][27] f32   best finished candidate of each seed
 //   recfield [SEEDS][5] i32    valid, nhits, status, last layer, slot
 //   toplist  [cap][64] f32 chi2, then [cap][64] i32 positions, [cap][64] u32 indices
-//   accept   [64] i32 accepted hits per candidate, [64] i32 run starts (the
-//            cooperative hit search)
+//   accept   [64] i32 accepted hits per candidate, [64 NP] i32 run starts
+//            (the cooperative hit search)
 //   mlp      activation buffer of the learned window (the network runs before
 //            the hit search, so the toplists of a learned build live in it)
 struct LdsPlan {
@@ -487,7 +524,7 @@ __host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsi
   (void)tsize;
   const size_t tl_wave = (size_t)cap * 64 * 12;
   p.acc = align16(p.recf + (size_t)nwaves * seeds * 5 * 4);
-  p.tl = align16(p.acc + (size_t)nwaves * 128 * 4);
+  p.tl = align16(p.acc + (size_t)nwaves * (64 + 64 * NP) * 4);
   if (learned) {
     const size_t per = tl_wave > KFMLP_LDS_BYTES ? tl_wave : (size_t)KFMLP_LDS_BYTES;
     p.mlp = p.tl;
@@ -540,7 +577,7 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
   int32_t* tl_pos = (int32_t*)(wave_tl + (size_t)S * 64 * 4) + lane;
   uint32_t* tl_orig = (uint32_t*)(wave_tl + (size_t)S * 64 * 8) + lane;
   AccBuf ab;
-  ab.tot = (int32_t*)(base + lp.acc) + (size_t)wave * 128;
+  ab.tot = (int32_t*)(base + lp.acc) + (size_t)wave * (64 + 64 * NP);
   ab.start = ab.tot + 64;
   (void)mlp_buf;
   const int sidx = lane / S, slot = lane - (lane / S) * S, sbase = sidx * S;
