@@ -200,6 +200,30 @@ __device__ inline void reg_insert(RegTop& t, int cap, float c2, int pos, uint32_
   }
 }
 
+// The same insertion into a lane's LDS column (FP64 builds, which are short
+// of registers): shift the entries that rank after the new hit.
+__device__ inline void lds_insert(TopList& tl, int cap, int& held, float c2, int pos, uint32_t orig) {
+  int j = held;
+  if (j == cap) {
+    if (!top_before(c2, orig, tl.c2[(cap - 1) * 64], tl.orig[(cap - 1) * 64])) return;
+    j = cap - 1;
+  } else {
+    held += 1;
+  }
+  while (j > 0) {
+    const float pc = tl.c2[(j - 1) * 64];
+    const uint32_t po = tl.orig[(j - 1) * 64];
+    if (!top_before(c2, orig, pc, po)) break;
+    tl.c2[j * 64] = pc;
+    tl.pos[j * 64] = tl.pos[(j - 1) * 64];
+    tl.orig[j * 64] = po;
+    --j;
+  }
+  tl.c2[j * 64] = c2;
+  tl.pos[j * 64] = pos;
+  tl.orig[j * 64] = orig;
+}
+
 __device__ inline void top_get(const TopList& tl, int k, float& c2, int& pos, uint32_t& orig) {
   c2 = tl.c2[k * 64];
   pos = tl.pos[k * 64];
@@ -257,12 +281,16 @@ struct AccBuf {
 // positions ~ 1e-5 cm) stays far below the chi2 gaps (1e-3) and window-edge
 // distances (1e-4 cm) that separate decisions; the Kalman update of a
 // chosen hit runs in the arithmetic of the mode.
-// pairs per lane per round of the hit search
+// pairs per lane per round of the hit search (at most; FP64 builds take one)
 constexpr int NP = 2;
 
 template <typename T>
 __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, const T Xp[6], const T Pp[21],
                                  T dphi_w, T dz_w, TopList& tl, const AccBuf& ab, int lane) {
+  // FP32 builds keep the lists in registers and take NP pairs per lane and
+  // round; FP64 builds, short of registers, keep the lists in LDS, one pair
+  constexpr bool REG = sizeof(T) == 4;
+  constexpr int NPT = REG ? NP : 1;
   const int nz = A.n_z, nf = A.n_phi * A.refine;
   const float inv = fine_inv(nf);
   const float tp = 6.283185307179586f;
@@ -312,11 +340,13 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
   const int Rmax = wave_max(R);
   ab.tot[lane] = 0;
   RegTop rt;
+  if constexpr (REG) {
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    rt.c2[i] = __builtin_inff();
-    rt.pos[i] = -1;
-    rt.orig[i] = 0xFFFFFFFFu;
+    for (int i = 0; i < 8; ++i) {
+      rt.c2[i] = __builtin_inff();
+      rt.pos[i] = -1;
+      rt.orig[i] = 0xFFFFFFFFu;
+    }
   }
   int held = 0;  // entries in the list
   // the candidate's admission threshold: its last entry once its list is
@@ -343,21 +373,21 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
     int carry = 0;  // candidate of the previous round's last pair
     // each lane takes NP pairs per round (pair base + 64 h + lane): their
     // loads share one round trip
-    for (int base = 0; base < total; base += 64 * NP) {
+    for (int base = 0; base < total; base += 64 * NPT) {
       // candidate of a pair: candidates mark the slot where their pairs start
       // in this round; the pair's candidate is the nearest mark at or below
       // its slot in its half, else the one whose pairs run on from before
 #pragma unroll
-      for (int h = 0; h < NP; ++h) ab.start[h * 64 + lane] = -1;
-      if (cnt > 0 && off >= base && off - base < 64 * NP) ab.start[off - base] = lane;
+      for (int h = 0; h < NPT; ++h) ab.start[h * 64 + lane] = -1;
+      if (cnt > 0 && off >= base && off - base < 64 * NPT) ab.start[off - base] = lane;
       __builtin_amdgcn_wave_barrier();
-      int c[NP], my_lo[NP], p[NP];
-      bool valid[NP];
-      float ca[NP], cb[NP], cx[NP], cy[NP], cz[NP], cdz[NP], cdphi[NP], ctan[NP], cirr[NP], csuu[NP], csuw[NP],
-          csww[NP], cthr[NP];
-      uint32_t cthro[NP];
+      int c[NPT], my_lo[NPT], p[NPT];
+      bool valid[NPT];
+      float ca[NPT], cb[NPT], cx[NPT], cy[NPT], cz[NPT], cdz[NPT], cdphi[NPT], ctan[NPT], cirr[NPT], csuu[NPT], csuw[NPT],
+          csww[NPT], cthr[NPT];
+      uint32_t cthro[NPT];
 #pragma unroll
-      for (int h = 0; h < NP; ++h) {
+      for (int h = 0; h < NPT; ++h) {
         const int st = ab.start[h * 64 + lane];
         const unsigned long long sm = __ballot(st >= 0) & ((2ull << lane) - 1ull);
         const int hb = sm ? 63 - (int)__builtin_clzll(sm) : 0;
@@ -385,11 +415,11 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
       }
       // everything each pair can need, in one round trip for all NP pairs
       // (a pair past the end reads the round's first pair, which exists)
-      float ph[NP], hx[NP], hy[NP], hz[NP], V[NP][6];
-      uint32_t forig[NP];
+      float ph[NPT], hx[NPT], hy[NPT], hz[NPT], V[NPT][6];
+      uint32_t forig[NPT];
       const int p_first = __builtin_amdgcn_readfirstlane(__shfl(p[0], 0, 64));
 #pragma unroll
-      for (int h = 0; h < NP; ++h) {
+      for (int h = 0; h < NPT; ++h) {
         const int ps = valid[h] ? p[h] : p_first;
         ph[h] = A.hphi[ps];
         hx[h] = A.hx[ps];
@@ -402,14 +432,14 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
       // all loads in flight before the first test (the compiler would
       // otherwise wait for phi and issue the rest behind the phi test)
 #pragma unroll
-      for (int h = 0; h < NP; ++h)
+      for (int h = 0; h < NPT; ++h)
         asm volatile("" ::"v"(ph[h]), "v"(hx[h]), "v"(hy[h]), "v"(hz[h]), "v"(V[h][0]), "v"(V[h][1]), "v"(V[h][2]),
                      "v"(V[h][3]), "v"(V[h][4]), "v"(V[h][5]), "v"(forig[h]));
-      bool keep[NP];
-      float c2[NP];
-      uint32_t orig[NP];
+      bool keep[NPT];
+      float c2[NPT];
+      uint32_t orig[NPT];
 #pragma unroll
-      for (int h = 0; h < NP; ++h) {
+      for (int h = 0; h < NPT; ++h) {
         keep[h] = false;
         c2[h] = 0.f;
         orig[h] = 0;
@@ -443,7 +473,7 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
       // of lanes (a candidate's pairs occupy consecutive lanes), so the steps
       // number the most hits any one candidate has in the half
 #pragma unroll
-      for (int h = 0; h < NP; ++h) {
+      for (int h = 0; h < NPT; ++h) {
         unsigned long long m = __ballot(keep[h]);
         if (m) {
           // this lane's run as a candidate in the half
@@ -464,33 +494,44 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
             const int jp = __shfl(p[h], js, 64);
             const uint32_t jo = (uint32_t)__shfl((int)orig[h], js, 64);
             if (j < 64) {
-              reg_insert(rt, A.cap, jc2, jp, jo);
-              held = held < A.cap ? held + 1 : held;
+              if constexpr (REG) {
+                reg_insert(rt, A.cap, jc2, jp, jo);
+                held = held < A.cap ? held + 1 : held;
+              } else {
+                lds_insert(tl, A.cap, held, jc2, jp, jo);
+              }
             }
             const bool first =
                 ((m >> lane) & 1ull) && ((m >> my_lo[h]) & ((1ull << (lane - my_lo[h])) - 1ull)) == 0;
             m &= ~__ballot(first);
           } while (m);
           if (held == A.cap) {
+            if constexpr (REG) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-              if (i == A.cap - 1) {
-                thr_c2 = rt.c2[i];
-                thr_o = rt.orig[i];
-              }
+              for (int i = 0; i < 8; ++i)
+                if (i == A.cap - 1) {
+                  thr_c2 = rt.c2[i];
+                  thr_o = rt.orig[i];
+                }
+            } else {
+              thr_c2 = tl.c2[(A.cap - 1) * 64];
+              thr_o = tl.orig[(A.cap - 1) * 64];
+            }
           }
         }
       }
     }
   }
   // the list goes to LDS for the merge
+  if constexpr (REG) {
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
-    if (i < held) {
-      tl.c2[i * 64] = rt.c2[i];
-      tl.pos[i * 64] = rt.pos[i];
-      tl.orig[i * 64] = rt.orig[i];
-    }
+    for (int i = 0; i < 8; ++i)
+      if (i < held) {
+        tl.c2[i * 64] = rt.c2[i];
+        tl.pos[i * 64] = rt.pos[i];
+        tl.orig[i * 64] = rt.orig[i];
+      }
+  }
   tl.n = held;
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
