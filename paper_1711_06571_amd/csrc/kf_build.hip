@@ -174,34 +174,9 @@ __device__ inline bool top_before(float c2, uint32_t orig, float oc2, uint32_t o
   return c2 < oc2 || (c2 == oc2 && orig < oorig);
 }
 
-// The list while the hit search fills it: in registers, sorted, slots past
-// the entries hold +inf.  Insertion is branch-free over the cap slots (cap
-// is uniform): every slot keeps its entry, takes the new one or takes its
-// predecessor's.  A full list drops its last entry (the new hit must rank
-// before it: the caller's admission test).
-struct RegTop {
-  float c2[8];
-  int32_t pos[8];
-  uint32_t orig[8];
-};
-
-__device__ inline void reg_insert(RegTop& t, int cap, float c2, int pos, uint32_t orig) {
-  bool lt[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) lt[i] = top_before(t.c2[i], t.orig[i], c2, orig);
-#pragma unroll
-  for (int i = 7; i >= 0; --i) {
-    if (i < cap && !lt[i]) {
-      const bool here = i == 0 || lt[i - 1];
-      t.c2[i] = here ? c2 : t.c2[i > 0 ? i - 1 : 0];
-      t.pos[i] = here ? pos : t.pos[i > 0 ? i - 1 : 0];
-      t.orig[i] = here ? orig : t.orig[i > 0 ? i - 1 : 0];
-    }
-  }
-}
-
-// The same insertion into a lane's LDS column (FP64 builds, which are short
-// of registers): shift the entries that rank after the new hit.
+// Insertion into a lane's list: a full list admits only a hit that ranks
+// before its last entry (which drops out); the entries that rank after the
+// new hit shift down one slot.
 __device__ inline void lds_insert(TopList& tl, int cap, int& held, float c2, int pos, uint32_t orig) {
   int j = held;
   if (j == cap) {
@@ -287,10 +262,9 @@ constexpr int NP = 2;
 template <typename T>
 __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, const T Xp[6], const T Pp[21],
                                  T dphi_w, T dz_w, TopList& tl, const AccBuf& ab, int lane) {
-  // FP32 builds keep the lists in registers and take NP pairs per lane and
-  // round; FP64 builds, short of registers, keep the lists in LDS, one pair
-  constexpr bool REG = sizeof(T) == 4;
-  constexpr int NPT = REG ? NP : 1;
+  // FP32 builds take NP pairs per lane and round, FP64 builds (short of
+  // registers) one
+  constexpr int NPT = sizeof(T) == 4 ? NP : 1;
   const int nz = A.n_z, nf = A.n_phi * A.refine;
   const float inv = fine_inv(nf);
   const float tp = 6.283185307179586f;
@@ -339,15 +313,6 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
   const int R = pok ? (iz1 - iz0 + 1) * 2 : 0;
   const int Rmax = wave_max(R);
   ab.tot[lane] = 0;
-  RegTop rt;
-  if constexpr (REG) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      rt.c2[i] = __builtin_inff();
-      rt.pos[i] = -1;
-      rt.orig[i] = 0xFFFFFFFFu;
-    }
-  }
   int held = 0;  // entries in the list
   // the candidate's admission threshold: its last entry once its list is
   // full (before, +inf admits every accepted hit)
@@ -494,43 +459,19 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
             const int jp = __shfl(p[h], js, 64);
             const uint32_t jo = (uint32_t)__shfl((int)orig[h], js, 64);
             if (j < 64) {
-              if constexpr (REG) {
-                reg_insert(rt, A.cap, jc2, jp, jo);
-                held = held < A.cap ? held + 1 : held;
-              } else {
-                lds_insert(tl, A.cap, held, jc2, jp, jo);
-              }
+              lds_insert(tl, A.cap, held, jc2, jp, jo);
             }
             const bool first =
                 ((m >> lane) & 1ull) && ((m >> my_lo[h]) & ((1ull << (lane - my_lo[h])) - 1ull)) == 0;
             m &= ~__ballot(first);
           } while (m);
           if (held == A.cap) {
-            if constexpr (REG) {
-#pragma unroll
-              for (int i = 0; i < 8; ++i)
-                if (i == A.cap - 1) {
-                  thr_c2 = rt.c2[i];
-                  thr_o = rt.orig[i];
-                }
-            } else {
-              thr_c2 = tl.c2[(A.cap - 1) * 64];
-              thr_o = tl.orig[(A.cap - 1) * 64];
-            }
+            thr_c2 = tl.c2[(A.cap - 1) * 64];
+            thr_o = tl.orig[(A.cap - 1) * 64];
           }
         }
       }
     }
-  }
-  // the list goes to LDS for the merge
-  if constexpr (REG) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-      if (i < held) {
-        tl.c2[i * 64] = rt.c2[i];
-        tl.pos[i * 64] = rt.pos[i];
-        tl.orig[i * 64] = rt.orig[i];
-      }
   }
   tl.n = held;
   __builtin_amdgcn_s_waitcnt(0);
