@@ -121,7 +121,7 @@ class TuneResult:
     gpu: str = ""
 
 
-def autotune(b: Batch, lanes_set=(64, 128, 256), bpcu_set=(1, 2, 0), caps=(4, 6, 8), refines=(4, 8, 16), reps=3,
+def autotune(b: Batch, lanes_set=(64, 128, 256), bpcu_set=(1, 2, 0), caps=(4, 6, 8), refines=(8, 32, 64), reps=3,
              eff_tol=0.001, log=None) -> TuneResult:
     """Sweep launch shape x candidate cap x granularity of the fine phi index
     (the hit-search structure: sub-bins per phi bin).  Launch shape and

@@ -310,7 +310,10 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
     sww = (float)Pp[ut(2, 2)];
   }
   const int32_t* frow = A.fine + ((size_t)ev * A.n_layers + l) * nz * (nf + 1);
-  const int R = pok ? (iz1 - iz0 + 1) * 2 : 0;
+  // ranges: (row, interval) for every row, the second interval only where
+  // the window wraps at 2 pi
+  const int nint = a1 <= b1v ? 2 : 1;
+  const int R = pok ? (iz1 - iz0 + 1) * nint : 0;
   const int Rmax = wave_max(R);
   ab.tot[lane] = 0;
   int held = 0;  // entries in the list
@@ -319,18 +322,31 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
   float thr_c2 = __builtin_inff();
   uint32_t thr_o = 0xFFFFFFFFu;
   const float cut = A.chi2_cut;
-  for (int r = 0; r < Rmax; ++r) {
-    int p0 = 0, p1 = 0;
-    float a = 1.f, b = 0.f;
+  // range r of this candidate: its stored-value interval and its sorted
+  // positions from the fine index (read one range ahead)
+  auto range_of = [&](int r, float& a, float& b, int& q0, int& q1) {
+    a = 1.f;
+    b = 0.f;
+    q0 = 0;
+    q1 = 0;
     if (r < R) {
-      a = (r & 1) ? a1 : a0;
-      b = (r & 1) ? b1v : b0v;
+      const int ri = nint == 2 ? (r & 1) : 0, rr = nint == 2 ? (r >> 1) : r;
+      a = ri ? a1 : a0;
+      b = ri ? b1v : b0v;
       if (a <= b) {
-        const int32_t* f = frow + (size_t)(iz0 + (r >> 1)) * (nf + 1);
-        p0 = f[fine_key(a, inv, nf)];
-        p1 = f[fine_key(b, inv, nf) + 1];
+        const int32_t* f = frow + (size_t)(iz0 + rr) * (nf + 1);
+        q0 = f[fine_key(a, inv, nf)];
+        q1 = f[fine_key(b, inv, nf) + 1];
       }
     }
+  };
+  float an = 1.f, bn = 0.f;
+  int p0n = 0, p1n = 0;
+  range_of(0, an, bn, p0n, p1n);
+  for (int r = 0; r < Rmax; ++r) {
+    const float a = an, b = bn;
+    const int p0 = p0n, p1 = p1n;
+    range_of(r + 1, an, bn, p0n, p1n);
     const int cnt = p1 > p0 ? p1 - p0 : 0;
     int total = 0;
     const int off = wave_excl_scan(cnt, lane, total);
@@ -894,7 +910,7 @@ size_t fine_bytes(int n_events, int n_layers, int n_phi, int n_z, int refine) {
   return (size_t)n_events * n_layers * n_z * ((size_t)n_phi * refine + 1) * 4;
 }
 
-int refine_of(const kf_build_params* bp) { return bp->phi_refine > 0 ? bp->phi_refine : 8; }
+int refine_of(const kf_build_params* bp) { return bp->phi_refine > 0 ? bp->phi_refine : 32; }
 
 // the launch shape of the last kf_build call of this host thread
 thread_local kf_build_launch_info g_last_launch = {};
