@@ -688,10 +688,21 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
         // learned window where the plain one is wide (either half-width above
         // its gate): the wave evaluates the network on those slots only
         const bool gated = pok && (w_rphi > (T)A.mlp[KFMLP_OFF_GATE] || w_z > (T)A.mlp[KFMLP_OFF_GATE + 1]);
-        float wl[2] = {0.f, 0.f};
-        kfmlp::wave_forward(A.mlp, mlp_buf, [&](int k) { return (float)(k < 6 ? Xp[k] : Pp[k - 6]); }, gated, wl);
+        // the features rounded to FP32 first and pinned there by an empty
+        // asm: converted inside the row writes instead, the FP64 build's
+        // register allocation spilled twice as much
+        float feat[27];
+#pragma unroll
+        for (int k = 0; k < 27; ++k) feat[k] = (float)(k < 6 ? Xp[k] : Pp[k - 6]);
+#pragma unroll
+        for (int k = 0; k < 27; ++k) asm volatile("" : "+v"(feat[k]));
+        const uint64_t act = kfmlp::wave_stage(A.mlp, mlp_buf, [&](int k) { return feat[k]; }, gated);
+        float o[2] = {0.f, 0.f};
+        if (act) kfmlp::wave_tiles(A.mlp, mlp_buf, act, o);
         if (gated) {
           const float kap = A.mlp[KFMLP_OFF_KAPPA];
+          float wl[2] = {A.mlp[KFMLP_OFF_SCALE] * kfmlp::softplus(o[0]),
+                         A.mlp[KFMLP_OFF_SCALE + 1] * kfmlp::softplus(o[1])};
           wl[0] *= kap;
           wl[1] *= kap;
           if (!(wl[0] < A.mlp[KFMLP_OFF_FLOOR])) w_rphi = (T)wl[0];

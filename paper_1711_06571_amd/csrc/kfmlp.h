@@ -125,6 +125,18 @@ __device__ inline float gelu_grad(float z) {
 __device__ inline float softplus(float o) { return o > 30.f ? o : log1pf(__expf(o)); }
 __device__ inline float sigmoid(float o) { return 1.f / (1.f + __expf(-o)); }
 
+// A wave-uniform pointer made opaque to the optimiser (the block pointer is
+// the same in every lane; taken as a scalar, reads through it can be
+// neither hoisted out of a loop nor moved across the call site)
+__device__ inline const float* opaque_uniform(const float* p) {
+  const uint64_t u = (uint64_t)p;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+  const float* q = (const float*)(((uint64_t)hi << 32) | lo);
+  asm volatile("" : "+s"(q));
+  return q;
+}
+
 // 8 consecutive bf16 (16 bytes, 16-byte aligned) as an MFMA operand
 __device__ inline bf16x8 load8(const uint16_t* p) {
   uint4 v = *(const uint4*)p;
@@ -140,28 +152,23 @@ __device__ inline f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 //   B (32 x 16): k = 8 (l / 16) .. + 7, column l % 16
 //   C (16 x 16): rows 4 (l / 16) .. + 3, column l % 16
 //
-// Forward of the active rows of a wave.  The active lanes are numbered in
-// lane order (rank) and their rows packed into the first ceil(n/16) tiles,
-// so a wave with few active lanes runs few tiles (none when no lane is
-// active).  feature(k): this lane's raw feature k of 27; buf: the wave's LDS
-// buffer [64][KFMLP_PITCH] bf16 for the standardised inputs (columns 0..31,
-// padded with zeros).  Writes the two widths (without kappa) of an active
-// lane's row into w (and the head outputs into o_out); leaves an inactive
-// lane's untouched.  Must be called by all 64 lanes together.
+// Forward of the active rows of a wave, in two steps.  wave_stage numbers
+// the active lanes in lane order (rank) and writes their standardised rows
+// into the first ceil(n/16) tiles of buf, the wave's LDS buffer [64]
+// [KFMLP_PITCH] bf16 (columns 0..31, inputs padded with zeros); feature(k)
+// is this lane's raw feature k of 27.  It returns the mask of active lanes.
+// wave_tiles runs the network over those tiles only (none when no lane is
+// active) and gives each active lane the head outputs of its row.  Both must
+// be called by all 64 lanes together.
 template <typename Feature>
-__device__ inline void wave_forward(const float* __restrict__ blk, uint16_t* buf, Feature feature, bool active,
-                                    float w[2], float* o_out = nullptr) {
+__device__ inline uint64_t wave_stage(const float* __restrict__ blk, uint16_t* buf, Feature feature, bool active) {
   const uint64_t act = __ballot(active);
-  if (act == 0) return;
-  const int lane = threadIdx.x & 63;
-  const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
-  const int ntile = (__popcll(act) + 15) >> 4;
-  const int r16 = lane & 15, kq = lane >> 4;
   if (active) {
+    const int rank =
+        __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
     // standardisation read through an opaque copy of the pointer: hoisted out
     // of a caller's loop, its 54 constants would occupy registers throughout
-    const float* hk = blk;
-    asm volatile("" : "+s"(hk));
+    const float* hk = opaque_uniform(blk);
     uint16_t* row = buf + rank * KFMLP_PITCH;
 #pragma unroll
     for (int k = 0; k < 27; ++k) row[k] = f_to_bf16((feature(k) - hk[KFMLP_OFF_MU + k]) * hk[KFMLP_OFF_ISD + k]);
@@ -170,14 +177,21 @@ __device__ inline void wave_forward(const float* __restrict__ blk, uint16_t* buf
   }
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
+  return act;
+}
+
+__device__ inline void wave_tiles(const float* __restrict__ blk, const uint16_t* buf, uint64_t act, float out[2]) {
+  const int lane = threadIdx.x & 63;
+  const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+  const int ntile = (__popcll(act) + 15) >> 4;
+  const int r16 = lane & 15, kq = lane >> 4;
   float head[2] = {0.f, 0.f};
   for (int mt = 0; mt < ntile; ++mt) {
     // the weights and biases are read afresh in every tile (from cache): the
     // opaque copy of the block pointer keeps the compiler from hoisting them
     // out of the loop, where they would hold about 90 registers for the whole
     // loop inside kernels that are already short of them
-    const float* bk = blk;
-    asm volatile("" : "+s"(bk));
+    const float* bk = opaque_uniform(blk);
     const uint16_t* W = (const uint16_t*)(bk + KFMLP_HEADER_FLOATS);
     // samples 16 mt .. 16 mt + 15 (rows past the active count hold stale
     // values; each sample is its own column, so they touch only their own
@@ -227,12 +241,24 @@ __device__ inline void wave_forward(const float* __restrict__ blk, uint16_t* buf
     }
   }
   __builtin_amdgcn_wave_barrier();
+  out[0] = head[0] + blk[KFMLP_OFF_B3 + 0];
+  out[1] = head[1] + blk[KFMLP_OFF_B3 + 1];
+}
+
+// Both steps, and the widths (without kappa) of an active lane's row in w
+// (head outputs in o_out); an inactive lane's are left untouched.
+template <typename Feature>
+__device__ inline void wave_forward(const float* __restrict__ blk, uint16_t* buf, Feature feature, bool active,
+                                    float w[2], float* o_out = nullptr) {
+  const uint64_t act = wave_stage(blk, buf, feature, active);
+  if (act == 0) return;
+  float o[2];
+  wave_tiles(blk, buf, act, o);
   if (active) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const float o = head[j] + blk[KFMLP_OFF_B3 + j];
-      if (o_out) o_out[j] = o;
-      w[j] = blk[KFMLP_OFF_SCALE + j] * softplus(o);
+      if (o_out) o_out[j] = o[j];
+      w[j] = blk[KFMLP_OFF_SCALE + j] * softplus(o[j]);
     }
   }
 }
