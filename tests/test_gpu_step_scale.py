@@ -1,0 +1,89 @@
+"""The benchmark's whole step (hit_bin -> kf_build -> kf_gather_hits ->
+kf_fit) at its full size (fit_scale: 200 events x 20 000 tracks, 17 layers),
+in the launch configuration the benchmark times (FP64 arithmetic, default
+launch shape, all events in one build launch).  The oracle builds seeds
+sampled from the first, a middle and the last event one by one, then fits
+the lists it built; the GPU step's lists and fits must agree."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_06571_amd import presets, workloads
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from gpu_common import assert_fit_parity_converged, host, to_dev  # noqa: E402
+from test_gpu_build import compare, decidable  # noqa: E402
+
+
+def test_step_scale_sampled_parity():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1711_06571_amd import kftrack as kf
+    w = presets.fit_scale()
+    g, cuts = w.geometry, w.cuts
+    L, F = g.n_layers, cuts.first_layer
+    eb = workloads.event_batch(w, range(w.n_events), seed_layers=3)
+    n = eb.n_seeds
+    assert n == 4_000_000
+    layer, xyz, cov = to_dev(eb.layer), to_dev(eb.xyz), to_dev(eb.cov)
+    hoff, sev = to_dev(eb.hit_offsets), to_dev(eb.seed_event)
+    binned = kf.hit_bin(g, cuts.n_phi_bins, cuts.n_z_bins, layer, xyz, cov, event_offsets=hoff)
+    seeds = kf.kf_seed(g, n, to_dev(eb.seed_hits))
+    ex = kf.BuildExtra()
+    ex.seed_event = sev.data_ptr()
+    out = kf.kf_build(g, kf.build_params(cuts, arith=kf.ARITH_F64), binned, n, seeds["par"], seeds["cov"],
+                      seeds["q"], extra=ex)
+    ld = seeds["par"].shape[1]
+    fit_hits = torch.zeros((L, 9, ld), dtype=torch.float32, device="cuda:0")
+    hole = torch.zeros(ld, dtype=torch.int32, device="cuda:0")
+    kf.kf_gather_hits(L, F, n, out["hits"], xyz, cov, seed_event=sev, event_offsets=hoff, fit_hits=fit_hits,
+                      hole_mask=hole)
+    fout = kf.kf_fit(g, n, F, fit_hits, seeds["par"], seeds["cov"], seeds["q"], hole_mask=hole,
+                     arith=kf.ARITH_F64)
+    torch.cuda.synchronize()
+    gb = {k: host(v) for k, v in out.items()}
+    gf = {k: host(v) for k, v in fout.items()}
+    for e in (0, w.n_events // 2, w.n_events - 1):
+        h0, h1 = int(eb.hit_offsets[e]), int(eb.hit_offsets[e + 1])
+        s0, s1 = int(eb.seed_offsets[e]), int(eb.seed_offsets[e + 1])
+        ne = s1 - s0
+        xe = np.ascontiguousarray(eb.xyz[:, h0:h1])
+        ce = np.ascontiguousarray(eb.cov[:, h0:h1])
+        le = np.ascontiguousarray(eb.layer[h0:h1])
+        lde = ((ne + 63) // 64) * 64
+        Hs = np.zeros((3, 9, lde), dtype=np.float32)
+        Hs[:, :, :ne] = eb.seed_hits[:, :, s0:s1]
+        so = oracle.seed(g, Hs, ne)
+        lst = np.concatenate([np.arange(0, ne, 613)[:30], np.arange(ne - 3, ne)])
+        ob = oracle.build(g, cuts, le, xe, ce, so["par"], so["cov"], so["q"], ne, seed_list=lst)
+        r = compare(gb, ob, lst.size, cols_g=s0 + lst, ctx=f"event {e}")
+        # the fit of the lists the oracle built, where the GPU built the same
+        m = lst.size
+        same = decidable(ob)[:m] & np.all(gb["hits"][:, s0 + lst] == ob["hits"][:, :m], axis=0)
+        sel = lst[same]
+        k = sel.size
+        ldk = ((k + 63) // 64) * 64
+        Hf = np.zeros((L, 9, ldk), dtype=np.float32)
+        hm = np.zeros(ldk, dtype=np.uint32)
+        obh = ob["hits"][:, :m][:, same]
+        for j in range(k):
+            for l in range(F, L):
+                h = obh[l - F, j]
+                if h < 0:
+                    hm[j] |= 1 << l
+                else:
+                    Hf[l, 0:3, j] = xe[:, h]
+                    Hf[l, 3:9, j] = ce[:, h]
+        sp = np.zeros((6, ldk), np.float32)
+        sc = np.zeros((21, ldk), np.float32)
+        q = np.ones(ldk, np.int8)
+        sp[:, :k] = so["par"][:, sel]
+        sc[:, :k] = so["cov"][:, sel]
+        q[:k] = so["q"][sel]
+        of = oracle.fit(g, F, Hf, sp, sc, q, k, hole_mask=hm)
+        gsub = {kk: v[..., s0 + sel] for kk, v in gf.items()}
+        errs = assert_fit_parity_converged(gsub, of, k, f"event {e} fit")
+        print(f"step at scale, event {e}: build {r}, fit on {k} identical lists {errs}")
+        assert k >= 0.8 * m
