@@ -151,10 +151,15 @@ def batched(arith, autotune, log):
     lat = batch.latencies_ms(b)
     eff = batch.efficiency(b, p.out)
     p.close()
+    # the whole step (binning, build, gather, final fit) as one graph
+    pf = batch.plan(b, arith=arith, fit=True)
+    ms_fit = batch.run(pf, reps=5)
+    pf.close()
     res = {"workload": f"{w.name}: {w.n_events} events, {b.eb.n_seeds} seeds", "ms_per_launch": round(ms, 4),
            "events_per_s": round(w.n_events / (ms * 1e-3), 2), "seeds_per_s": round(b.eb.n_seeds / (ms * 1e-3), 1),
            "latency_ms_p50": round(float(np.percentile(lat, 50)), 4),
-           "latency_ms_p99": round(float(np.percentile(lat, 99)), 4), "efficiency": round(eff, 4)}
+           "latency_ms_p99": round(float(np.percentile(lat, 99)), 4), "efficiency": round(eff, 4),
+           "ms_per_launch_with_fit": round(ms_fit, 4)}
     if autotune:
         tr = batch.autotune(b, log=lambda q: log(f"tune {q}"))
         res["tuned"] = dict(tr.best.__dict__)

@@ -311,6 +311,33 @@ int kf_batch_plan_create(const kf_geometry* g, const kf_build_params* bp, int32_
                          int32_t* out_hits, float* out_par, float* out_cov, float* out_chi2, int32_t* out_nhits,
                          int32_t* out_status, const kf_build_extra* extra, void* build_ws, size_t build_ws_bytes,
                          void* stream, kf_batch_plan** plan);
+/*
+ * The whole step as one graph (section 2: building, then the final fit of
+ * the built tracks): what kf_batch_plan_create captures, then
+ * kf_gather_hits of the built lists (xyz, cov and event_offsets as given to
+ * hit_bin, seed_event from `extra`, first_layer from `bp`) into
+ * fit->fit_hits / fit->hole_mask, then kf_fit from the same seeds in
+ * fit->arith.  fit must not be NULL; every pointer in it is a device pointer
+ * the caller owns.  Launch and destroy as a batch plan.
+ */
+typedef struct {
+  int32_t arith;        /* KF_ARITH_F32 or KF_ARITH_F64 for the fit */
+  float* fit_hits;      /* [n_layers][9][ld], written by the gather */
+  uint32_t* hole_mask;  /* [ld], written by the gather */
+  float* out_par;       /* [6][ld] */
+  float* out_cov;       /* [21][ld] */
+  float* out_chi2;      /* [ld] */
+  int32_t* out_ndof;    /* [ld] */
+  int32_t* out_status;  /* [ld] */
+} kf_fit_stage;
+int kf_step_plan_create(const kf_geometry* g, const kf_build_params* bp, int32_t n_events,
+                        const int32_t* event_offsets, int32_t n_hits, const int32_t* layer, const float* xyz,
+                        const float* cov, const kf_hits* binned, int32_t* binned_offsets, float* sorted_xyzphi,
+                        float* sorted_cov, int32_t* sorted_orig, void* bin_ws, size_t bin_ws_bytes,
+                        int32_t n_seeds, int32_t ld, const float* seed_par, const float* seed_cov, const int8_t* q,
+                        int32_t* out_hits, float* out_par, float* out_cov, float* out_chi2, int32_t* out_nhits,
+                        int32_t* out_status, const kf_build_extra* extra, void* build_ws, size_t build_ws_bytes,
+                        const kf_fit_stage* fit, void* stream, kf_batch_plan** plan);
 int kf_batch_plan_launch(kf_batch_plan* plan, void* stream);
 int kf_batch_plan_destroy(kf_batch_plan* plan);
 /* frequency of the device wall clock read by the build's completion ticks */

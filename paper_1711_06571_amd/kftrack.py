@@ -57,6 +57,12 @@ class LaunchInfo(ctypes.Structure):
                 ("resident_blocks_per_cu", ctypes.c_int32), ("max_lds_per_block", ctypes.c_int32)]
 
 
+class FitStage(ctypes.Structure):
+    _fields_ = [("arith", ctypes.c_int32), ("fit_hits", ctypes.c_void_p), ("hole_mask", ctypes.c_void_p),
+                ("out_par", ctypes.c_void_p), ("out_cov", ctypes.c_void_p), ("out_chi2", ctypes.c_void_p),
+                ("out_ndof", ctypes.c_void_p), ("out_status", ctypes.c_void_p)]
+
+
 class BuildExtra(ctypes.Structure):
     _fields_ = [("seed_event", ctypes.c_void_p), ("seed_order", ctypes.c_void_p),
                 ("event_n_seeds", ctypes.c_void_p), ("event_done_ticks", ctypes.c_void_p),
@@ -96,6 +102,8 @@ def lib():
                                            ctypes.POINTER(Hits), P, P, P, P, P, ctypes.c_size_t, I, I, P, P, P, P, P,
                                            P, P, P, P, ctypes.POINTER(BuildExtra), P, ctypes.c_size_t, P,
                                            ctypes.POINTER(ctypes.c_void_p)]
+        L.kf_step_plan_create.argtypes = list(L.kf_batch_plan_create.argtypes[:-2]) + [
+            ctypes.POINTER(FitStage), P, ctypes.POINTER(ctypes.c_void_p)]
         L.kf_batch_plan_launch.argtypes = [P, P]
         L.kf_batch_plan_destroy.argtypes = [P]
         L.kf_wall_clock_khz.argtypes = [P]
@@ -430,11 +438,13 @@ def kf_mlp_adam(block, master, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999
 # ------------------------------------------------------------ batched graph
 
 class BatchPlan:
-    """hit_bin + kf_build of a batch of events captured as one HIP graph.
-    Holds references to every buffer the graph uses."""
+    """hit_bin + kf_build of a batch of events captured as one HIP graph;
+    with fit_arith set, also kf_gather_hits + kf_fit of the built lists (the
+    whole step), fit outputs in self.fit.  Holds references to every buffer
+    the graph uses."""
 
     def __init__(self, g, bp, layer, xyz, cov, event_offsets, n_phi, n_z, n_seeds, seed_par, seed_cov, q,
-                 extra=None, stream=None):
+                 extra=None, stream=None, fit_arith=None):
         dev = layer.device
         n_hits = layer.shape[0]
         E = event_offsets.shape[0] - 1
@@ -460,14 +470,32 @@ class BatchPlan:
         h = ctypes.c_void_p()
         b = self.binned
         base = b.xyzphi
-        torch.cuda.synchronize()
-        _check(lib().kf_batch_plan_create(
+        args = [
             ctypes.byref(self.g), ctypes.byref(self.bp), E, _ptr(event_offsets), n_hits, _ptr(layer), _ptr(xyz),
             _ptr(cov), ctypes.byref(self.hd), _ptr(b.offsets), _ptr(base), _ptr(b.cov), _ptr(b.orig),
             _ptr(self.bin_ws), ctypes.c_size_t(self.bin_ws.numel()), n_seeds, ld, _ptr(seed_par), _ptr(seed_cov),
             _ptr(q), _ptr(self.out["hits"]), _ptr(self.out["par"]), _ptr(self.out["cov"]), _ptr(self.out["chi2"]),
             _ptr(self.out["nhits"]), _ptr(self.out["status"]), ctypes.byref(self.extra), _ptr(self.build_ws),
-            ctypes.c_size_t(self.build_ws.numel()), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+            ctypes.c_size_t(self.build_ws.numel())]
+        self.fit = None
+        torch.cuda.synchronize()
+        if fit_arith is None:
+            _check(lib().kf_batch_plan_create(*args, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        else:
+            L = g.n_layers
+            self.fit = dict(hits=torch.zeros((L, 9, ld), dtype=torch.float32, device=dev),
+                            hole=torch.zeros(ld, dtype=torch.int32, device=dev),
+                            par=torch.empty((6, ld), dtype=torch.float32, device=dev),
+                            cov=torch.empty((21, ld), dtype=torch.float32, device=dev),
+                            chi2=torch.empty(ld, dtype=torch.float32, device=dev),
+                            ndof=torch.empty(ld, dtype=torch.int32, device=dev),
+                            status=torch.empty(ld, dtype=torch.int32, device=dev))
+            f = self.fit
+            self.fs = FitStage(fit_arith, _ptr(f["hits"]), _ptr(f["hole"]), _ptr(f["par"]), _ptr(f["cov"]),
+                               _ptr(f["chi2"]), _ptr(f["ndof"]), _ptr(f["status"]))
+            torch.cuda.synchronize()
+            _check(lib().kf_step_plan_create(*args, ctypes.byref(self.fs), ctypes.c_void_p(self.stream.cuda_stream),
+                                             ctypes.byref(h)))
         self.handle = h
 
     def launch(self):

@@ -53,6 +53,40 @@ def test_graph_replays_equal_eager(bt):
     p.close()
 
 
+def test_step_graph_replays_equal_eager(bt):
+    """Binning, build, gather and fit in one graph: every replay equals the
+    eager sequence of the same calls bit for bit."""
+    batch, kf, b = bt
+    w = b.w
+    L, F = w.geometry.n_layers, w.cuts.first_layer
+    n = b.eb.n_seeds
+    binned = kf.hit_bin(w.geometry, 63, 16, b.layer, b.xyz, b.cov, event_offsets=b.hoff)
+    bp = kf.build_params(w.cuts, arith=kf.ARITH_F64)
+    out = kf.kf_build(w.geometry, bp, binned, n, b.seeds["par"], b.seeds["cov"], b.seeds["q"],
+                      extra=batch.extra_for(b, timestamps=False))
+    fh, hole = kf.kf_gather_hits(L, F, n, out["hits"], b.xyz, b.cov, seed_event=b.sev, event_offsets=b.hoff)
+    ref = kf.kf_fit(w.geometry, n, F, fh, b.seeds["par"], b.seeds["cov"], b.seeds["q"], hole_mask=hole,
+                    arith=kf.ARITH_F64)
+    torch.cuda.synchronize()
+    ref = {k: host(v) for k, v in ref.items()}
+    ref_hits = host(out["hits"])
+    p = batch.plan(b, arith=kf.ARITH_F64, fit=True)
+    for rep in range(3):
+        for k in p.fit:
+            p.fit[k].zero_()
+        torch.cuda.synchronize()
+        p.launch()
+        p.stream.synchronize()
+        assert np.array_equal(host(p.out["hits"])[:, :n], ref_hits[:, :n]), rep
+        for k in ref:
+            assert np.array_equal(host(p.fit[k])[..., :n], ref[k][..., :n]), (rep, k)
+        kf.hit_bin(w.geometry, 63, 16, b.layer, b.xyz, b.cov, event_offsets=b.hoff)
+        torch.cuda.synchronize()
+    ms = batch.run(p, reps=3)
+    print(f"step graph, 8 events, {n} seeds: {ms:.3f} ms per launch")
+    p.close()
+
+
 def test_autotune_small_grid(bt):
     batch, kf, b = bt
     res = batch.autotune(b, lanes_set=(64, 256), bpcu_set=(1, 0), caps=(4, 6), refines=(4, 16), reps=2)
