@@ -92,11 +92,10 @@ def lib():
         L.kf_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
         L.kf_seed.argtypes = [ctypes.POINTER(Geometry), I, I, P, ctypes.c_float, P, P, P, P, P]
         L.kf_fit.argtypes = [ctypes.POINTER(Geometry), I, I, I, P, P, P, P, P, P, P, P, P, P, I, P]
-        if hasattr(L, "hit_bin"):
-            L.hit_bin_workspace_bytes.restype = ctypes.c_size_t
-            L.hit_bin_workspace_bytes.argtypes = [I, I, I, I, I]
-            L.hit_bin.argtypes = [ctypes.POINTER(Geometry), I, P, I, I, I, P, P, P, P, P, P, P, P, P,
-                                  ctypes.c_size_t, P]
+        L.hit_bin_workspace_bytes.restype = ctypes.c_size_t
+        L.hit_bin_workspace_bytes.argtypes = [I, I, I, I, I]
+        L.hit_bin.argtypes = [ctypes.POINTER(Geometry), I, P, I, I, I, P, P, P, P, P, P, P, P, P,
+                              ctypes.c_size_t, P]
         L.kf_gather_hits.argtypes = [I, I, I, I, P, P, I, P, I, P, P, P, P, P]
         L.kf_batch_plan_create.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(BuildParams), I, P, I, P, P, P,
                                            ctypes.POINTER(Hits), P, P, P, P, P, ctypes.c_size_t, I, I, P, P, P, P, P,
@@ -113,11 +112,10 @@ def lib():
         L.kf_mlp_forward.argtypes = [P, I, P, P, P, P]
         L.kf_mlp_grad.argtypes = [P, I, P, P, P, ctypes.c_size_t, P]
         L.kf_mlp_adam.argtypes = [P, P, P, P, P, I, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P]
-        if hasattr(L, "kf_build"):
-            L.kf_build_workspace_bytes.restype = ctypes.c_size_t
-            L.kf_build_workspace_bytes.argtypes = [ctypes.POINTER(BuildParams), ctypes.POINTER(Hits), I]
-            L.kf_build.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(BuildParams), ctypes.POINTER(Hits), I,
-                                   I, P, P, P, P, P, P, P, P, P, ctypes.POINTER(BuildExtra), P, ctypes.c_size_t, P]
+        L.kf_build_workspace_bytes.restype = ctypes.c_size_t
+        L.kf_build_workspace_bytes.argtypes = [ctypes.POINTER(BuildParams), ctypes.POINTER(Hits), I]
+        L.kf_build.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(BuildParams), ctypes.POINTER(Hits), I,
+                               I, P, P, P, P, P, P, P, P, P, ctypes.POINTER(BuildExtra), P, ctypes.c_size_t, P]
         _lib = L
     return _lib
 
