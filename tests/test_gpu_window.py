@@ -85,6 +85,22 @@ def test_learned_build_matches_oracle(env, gate_q):
 
 
 @pytest.mark.parametrize("arith", ["f32", "f64"])
+def test_closed_gates_build_equals_plain(env, arith):
+    """Gates above every plain window: the learned kernel never runs the
+    network and must return the plain build exactly."""
+    kf, window, w, t = env["kf"], env["window"], env["w"], env["t"]
+    a = kf.ARITH_F32 if arith == "f32" else kf.ARITH_F64
+    ev = window.load_events(w, [3])
+    kf.mlp_set_header(t.block, kappa=1.0, gate_rphi=1e30, gate_z=1e30)
+    outp, _ = window.build(w, ev, arith=a)
+    outl, _ = window.build(w, ev, window_mode=1, block=t.block, arith=a)
+    torch.cuda.synchronize()
+    n = ev.eb.n_seeds
+    for k in outp:
+        assert np.array_equal(host(outl[k])[..., :n], host(outp[k])[..., :n]), k
+
+
+@pytest.mark.parametrize("arith", ["f32", "f64"])
 def test_learned_vs_plain(env, arith):
     """Gated network trained on the rows its gates pass, kappa calibrated on
     a validation event, compared with the plain window on a disjoint event."""

@@ -200,3 +200,47 @@ def test_build_efficiency_and_margins():
     # crossing and barrel-end tests further than 1e-3 relative
     decidable = (o["margin"][0] > 1e-3) & (o["margin"][1] > 1e-4) & (o["margin"][2] > 1e-3)
     assert decidable.mean() > 0.85
+
+
+def _window_network(seed, kappa, gates):
+    """A random window network in the oracle's parameter block whose head is
+    a constant (zero weights, bias 1: widths scale * softplus(1) for every
+    input), with the given kappa and gates (floors 0: its widths are always
+    taken)."""
+    from oracle import mlp
+    rng = np.random.default_rng(seed)
+    p = mlp.init_params(rng, np.zeros(27), np.ones(27), np.array([0.01, 0.1]))
+    p["W3"] = np.zeros_like(p["W3"])
+    p["b3"] = np.ones(2)
+    return mlp.blob(p, kappa=kappa, floor_rphi=0.0, floor_z=0.0, gate_rphi=gates[0], gate_z=gates[1])
+
+
+def test_learned_window_gates_closed_is_plain():
+    """Gates no plain window exceeds: the network is never consulted, so the
+    learned build is the plain build, bit for bit."""
+    w = presets.build()
+    ev, sd = _event_and_seeds(w.geometry, w.gen, 120, event=5)
+    n = ev.n_tracks
+    args = (w.geometry, w.cuts, ev.layer, ev.xyz, ev.cov, sd["par"], sd["cov"], sd["q"], n)
+    plain = oracle.build(*args)
+    learned = oracle.build(*args, window_mode=1, mlp_blob=_window_network(1, 1.0, (1e30, 1e30)))
+    for k in ("hits", "nhits", "status", "chi2", "par", "cov"):
+        assert np.array_equal(learned[k], plain[k]), k
+
+
+def test_learned_window_everything_equals_plain_everything():
+    """Gates open and kappa huge: every learned window covers the whole
+    layer, as does a plain window with a huge nsigma; both builds then test
+    every hit of every layer and must agree exactly."""
+    w = presets.build()
+    ev, sd = _event_and_seeds(w.geometry, w.gen, 60, event=6)
+    n = ev.n_tracks
+    args = (w.geometry, ev.layer, ev.xyz, ev.cov, sd["par"], sd["cov"], sd["q"], n)
+    wide = dataclasses.replace(w.cuts, nsigma=np.float32(1e7))
+    plain = oracle.build(args[0], wide, *args[1:])
+    learned = oracle.build(args[0], w.cuts, *args[1:], window_mode=1,
+                           mlp_blob=_window_network(2, 1e7, (0.0, 0.0)))
+    for k in ("hits", "nhits", "status", "chi2", "par", "cov"):
+        assert np.array_equal(learned[k], plain[k]), k
+    # and the search really was exhaustive: noise hits were tested
+    assert plain["nhits"][:n].mean() > 0
