@@ -963,15 +963,16 @@ int launch(const BuildArgs& A, int lanes, int blocks, int hist_waves, hipStream_
 }
 
 // Workspace: queue head and per-event counters | fine phi index | history
-// tables of the resident waves (8 per CU of the current device: two per SIMD,
-// what the build kernels reach; a grid that would hold more waves is clamped).
+// tables of the resident waves (16 per CU of the current device: four per
+// SIMD, more than the build kernels' register use allows; a grid that would
+// hold more waves is clamped).
 size_t ws_head_bytes(int n_events) { return 256 + (((size_t)n_events * 4 + 255) & ~(size_t)255); }
 int hist_waves_of_device() {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
                                                hipSuccess || cus < 1)
     cus = 256;
-  return cus * 8;
+  return cus * 16;
 }
 
 }  // namespace
