@@ -69,6 +69,16 @@ def lib():
         L.orc_fit.argtypes = [ctypes.POINTER(Geom), I, I, I] + [P] * 10
         L.orc_fit64.argtypes = [ctypes.POINTER(Geom), I, I, I] + [P] * 9
         L.orc_hit_bin.argtypes = [ctypes.POINTER(Geom), I, I, I, P, P, P, P, P]
+        L.orc_hyb_from_cart.argtypes = [P, I, P]
+        L.orc_hyb_from_cart.restype = None
+        L.orc_cart_from_hyb.argtypes = [P, P]
+        L.orc_hyb_jac_cart_from_hyb.argtypes = [P, P]
+        L.orc_hyb_jac_cart_from_hyb.restype = None
+        L.orc_hyb_jac_hyb_from_cart.argtypes = [P, I, P]
+        L.orc_hyb_jac_hyb_from_cart.restype = None
+        L.orc_predict_hyb.argtypes = [ctypes.POINTER(Geom), I, P, P, P, P]
+        L.orc_fit_hybrid.argtypes = [ctypes.POINTER(Geom), I, I, I] + [P] * 10
+        L.orc_fit_hybrid64.argtypes = [ctypes.POINTER(Geom), I, I, I] + [P] * 9
         L.orc_build.argtypes = [ctypes.POINTER(Geom), ctypes.POINTER(BuildParams), I, P, P, P, I, I, P, P, P, I,
                                 P, P, P, P, P, P, P, P]
         L.orc_mlp_forward.argtypes = [P, P, P]
@@ -211,6 +221,77 @@ def fit(g, first_layer, hits, seed_par, seed_cov, q, n, hole_mask=None):
                        _p(out["par"]), _p(out["cov"]), _p(out["chi2"]), _p(out["ndof"]), _p(out["status"]))
     if rc:
         raise ValueError("orc_fit: bad arguments")
+    return out
+
+
+def hyb_from_cart(X, q):
+    """Hybrid state (x, y, z, q/pT, phi, theta) of a Cartesian state."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    Y = np.zeros(6)
+    lib().orc_hyb_from_cart(_p(X), int(q), _p(Y))
+    return Y
+
+
+def cart_from_hyb(Y):
+    """(Cartesian state, charge) of a hybrid state."""
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    X = np.zeros(6)
+    q = lib().orc_cart_from_hyb(_p(Y), _p(X))
+    return X, int(q)
+
+
+def hyb_jacobians(Y):
+    """(d cart / d hyb at Y, d hyb / d cart at the Cartesian image of Y)."""
+    X, q = cart_from_hyb(Y)
+    A = np.zeros(36)
+    B = np.zeros(36)
+    lib().orc_hyb_jac_cart_from_hyb(_p(np.ascontiguousarray(Y, dtype=np.float64)), _p(A))
+    lib().orc_hyb_jac_hyb_from_cart(_p(X), q, _p(B))
+    return A.reshape(6, 6), B.reshape(6, 6)
+
+
+def predict_hyb(g, layer, Y, P):
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    Yo = np.zeros(6)
+    Po = np.zeros(36)
+    gg = geom(g)
+    rc = lib().orc_predict_hyb(ctypes.byref(gg), int(layer), _p(Y), _p(P), _p(Yo), _p(Po))
+    return rc, Yo, Po.reshape(6, 6)
+
+
+def fit_hybrid(g, first_layer, hits, seed_par, seed_cov, q, n, hole_mask=None):
+    """Fit in the hybrid state from Cartesian seeds; outputs (x, y, z, q/pT,
+    phi, theta) and their covariance."""
+    ld = hits.shape[2]
+    out = dict(par=np.zeros((6, ld)), cov=np.zeros((21, ld)), chi2=np.zeros(ld), ndof=np.zeros(ld, np.int32),
+               status=np.zeros(ld, np.int32))
+    hits = np.ascontiguousarray(hits, dtype=np.float32)
+    sp = np.ascontiguousarray(seed_par, dtype=np.float32)
+    sc = np.ascontiguousarray(seed_cov, dtype=np.float32)
+    q = np.ascontiguousarray(q, dtype=np.int8)
+    hm = None if hole_mask is None else np.ascontiguousarray(hole_mask, dtype=np.uint32)
+    gg = geom(g)
+    rc = lib().orc_fit_hybrid(ctypes.byref(gg), n, ld, first_layer, _p(hits), _p(hm), _p(sp), _p(sc), _p(q),
+                              _p(out["par"]), _p(out["cov"]), _p(out["chi2"]), _p(out["ndof"]), _p(out["status"]))
+    if rc:
+        raise ValueError("orc_fit_hybrid: bad arguments")
+    return out
+
+
+def fit_hybrid64(g, first_layer, hits, seed_par, seed_cov, q, n):
+    ld = hits.shape[2]
+    out = dict(par=np.zeros((6, ld)), cov=np.zeros((21, ld)), chi2=np.zeros(ld), ndof=np.zeros(ld, np.int32),
+               status=np.zeros(ld, np.int32))
+    hits = np.ascontiguousarray(hits, dtype=np.float64)
+    sp = np.ascontiguousarray(seed_par, dtype=np.float64)
+    sc = np.ascontiguousarray(seed_cov, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.int8)
+    gg = geom(g)
+    rc = lib().orc_fit_hybrid64(ctypes.byref(gg), n, ld, first_layer, _p(hits), _p(sp), _p(sc), _p(q),
+                                _p(out["par"]), _p(out["cov"]), _p(out["chi2"]), _p(out["ndof"]), _p(out["status"]))
+    if rc:
+        raise ValueError("orc_fit_hybrid64: bad arguments")
     return out
 
 

@@ -440,6 +440,182 @@ static void fit_one(const orc_geometry* g, int first_layer, const double* hitrow
   *status_out = st;
 }
 
+/* ------------------------------------------------- hybrid-state fit */
+
+/*
+ * Hybrid state (section 3: global Cartesian coordinates for the position,
+ * polar coordinates for the momentum): Y = (x, y, z, k, phi, theta) with
+ * k = q / pT (signed, so the charge is a continuous part of the state),
+ * phi the azimuth and theta the polar angle of the momentum:
+ *   px = cos(phi) / |k|, py = sin(phi) / |k|, pz = cos(theta) / (sin(theta) |k|),
+ *   q = sign(k).
+ * The helix depends on the state only through k (its curvature is
+ * proportional to k), the direction and the position, so a prediction is the
+ * Cartesian one taken at the same point: Y -> X (Cartesian), predict,
+ * X' -> Y'; its covariance is carried through the Jacobians of the two
+ * changes of variables (exact linearisation of the composed map).  The
+ * update is the tangent-plane update of section 4.1 applied to Y: it only
+ * measures the position, whose components are common to both states, but
+ * its linear correction now acts on (k, phi, theta), and k may change sign.
+ */
+void orc_hyb_from_cart(const double X[6], int q, double Y[6]) {
+  double pt = sqrt(X[3] * X[3] + X[4] * X[4]);
+  Y[0] = X[0]; Y[1] = X[1]; Y[2] = X[2];
+  Y[3] = (double)q / pt;
+  Y[4] = atan2(X[4], X[3]);
+  Y[5] = atan2(pt, X[5]);
+}
+
+int orc_cart_from_hyb(const double Y[6], double X[6]) {
+  double pt = 1.0 / fabs(Y[3]);
+  X[0] = Y[0]; X[1] = Y[1]; X[2] = Y[2];
+  X[3] = pt * cos(Y[4]);
+  X[4] = pt * sin(Y[4]);
+  X[5] = pt * cos(Y[5]) / sin(Y[5]);
+  return Y[3] > 0.0 ? 1 : -1;
+}
+
+/* d(X)/d(Y) at Y (6x6, row-major): identity on the position, and the
+ * derivatives of (px, py, pz) with respect to (k, phi, theta). */
+void orc_hyb_jac_cart_from_hyb(const double Y[6], double A[36]) {
+  memset(A, 0, sizeof(double) * 36);
+  for (int i = 0; i < 3; ++i) A[i * 6 + i] = 1.0;
+  double k = Y[3], pt = 1.0 / fabs(k), s = k > 0.0 ? 1.0 : -1.0;
+  double cf = cos(Y[4]), sf = sin(Y[4]), ct = cos(Y[5]), st = sin(Y[5]);
+  double dpt = -s * pt * pt; /* d pT / d k */
+  A[3 * 6 + 3] = dpt * cf;  A[3 * 6 + 4] = -pt * sf;  A[3 * 6 + 5] = 0.0;
+  A[4 * 6 + 3] = dpt * sf;  A[4 * 6 + 4] = pt * cf;   A[4 * 6 + 5] = 0.0;
+  A[5 * 6 + 3] = dpt * ct / st; A[5 * 6 + 4] = 0.0;   A[5 * 6 + 5] = -pt / (st * st);
+}
+
+/* d(Y)/d(X) at X (charge q): identity on the position, and the derivatives
+ * of (k, phi, theta) with respect to (px, py, pz). */
+void orc_hyb_jac_hyb_from_cart(const double X[6], int q, double B[36]) {
+  memset(B, 0, sizeof(double) * 36);
+  for (int i = 0; i < 3; ++i) B[i * 6 + i] = 1.0;
+  double px = X[3], py = X[4], pz = X[5];
+  double pt2 = px * px + py * py, pt = sqrt(pt2), p2 = pt2 + pz * pz;
+  double k = (double)q / pt;
+  B[3 * 6 + 3] = -k * px / pt2;       B[3 * 6 + 4] = -k * py / pt2;       B[3 * 6 + 5] = 0.0;
+  B[4 * 6 + 3] = -py / pt2;           B[4 * 6 + 4] = px / pt2;            B[4 * 6 + 5] = 0.0;
+  B[5 * 6 + 3] = px * pz / (pt * p2); B[5 * 6 + 4] = py * pz / (pt * p2); B[5 * 6 + 5] = -pt / p2;
+}
+
+/* M P M^T */
+static void congruence(const double M[36], const double P[36], double Po[36]) {
+  double MT[36], T[36];
+  transpose(M, MT, 6, 6);
+  matmul(M, P, T, 6, 6, 6);
+  matmul(T, MT, Po, 6, 6, 6);
+}
+
+int orc_predict_hyb(const orc_geometry* g, int layer, const double Y[6], const double P[36], double Yo[6],
+                    double Po[36]) {
+  double X[6], A[36], Pc[36], Xo[6], Pco[36], B[36];
+  if (!(Y[3] != 0.0)) return ORC_TRK_NONFINITE;
+  int q = orc_cart_from_hyb(Y, X);
+  orc_hyb_jac_cart_from_hyb(Y, A);
+  congruence(A, P, Pc);
+  int rc = orc_predict(g, layer, X, q, Pc, Xo, Pco, NULL);
+  if (rc) return rc;
+  orc_hyb_from_cart(Xo, q, Yo);
+  orc_hyb_jac_hyb_from_cart(Xo, q, B);
+  congruence(B, Pco, Po);
+  return 0;
+}
+
+/*
+ * Fit in the hybrid state: the Cartesian seed (X, P, q) is converted to Y
+ * (covariance through d(Y)/d(X)), then per layer: hybrid prediction, update
+ * with the hit (or none on a hole).  Outputs are hybrid: (x, y, z, k, phi,
+ * theta) and their covariance (21 upper-triangle entries).
+ */
+static void fit_one_hyb(const orc_geometry* g, int first_layer, const double* hitrows /*[L][9]*/, uint32_t holes,
+                        const double Xs[6], const double Ps[36], int q, double Yout[6], double Pout[36],
+                        double* chi2_out, int* ndof_out, int* status_out) {
+  double B[36], Y[6], P[36];
+  orc_hyb_from_cart(Xs, q, Y);
+  orc_hyb_jac_hyb_from_cart(Xs, q, B);
+  congruence(B, Ps, P);
+  double chi2 = 0.0;
+  int ndof = 0, st = 0;
+  if (!all_finite(Y, 6) || !all_finite(P, 36)) st = ORC_TRK_NONFINITE;
+  for (int l = first_layer; l < g->n_layers && !st; ++l) {
+    const double* h = hitrows + (size_t)l * 9;
+    int use = !((holes >> l) & 1u);
+    if (use && !all_finite(h, 9)) { st = ORC_TRK_NONFINITE; break; }
+    double Yp[6], Pp[36];
+    int rc = orc_predict_hyb(g, l, Y, P, Yp, Pp);
+    if (rc) { st = rc; break; }
+    if (!use) {
+      if (!all_finite(Yp, 6) || !all_finite(Pp, 36)) { st = ORC_TRK_NONFINITE; break; }
+      memcpy(Y, Yp, sizeof(Y)); memcpy(P, Pp, sizeof(P));
+      continue;
+    }
+    double Yu[6], Pu[36], c2;
+    rc = orc_update(Yp, Pp, h, Yu, Pu, &c2);
+    if (rc) { st = rc; break; }
+    if (!all_finite(Yu, 6) || !all_finite(Pu, 36) || !isfinite(c2)) { st = ORC_TRK_NONFINITE; break; }
+    memcpy(Y, Yu, sizeof(Y)); memcpy(P, Pu, sizeof(P));
+    chi2 += c2;
+    ndof += 2;
+  }
+  memcpy(Yout, Y, sizeof(Y));
+  memcpy(Pout, P, sizeof(P));
+  *chi2_out = chi2;
+  *ndof_out = ndof;
+  *status_out = st;
+}
+
+static void store_fit(int ld, int i, const double Y[6], const double P[36], double c2, int ndof, int st,
+                      double* out_par, double* out_cov, double* out_chi2, int32_t* out_ndof, int32_t* out_status) {
+  double u[21];
+  upper_from_sym(P, u);
+  for (int c = 0; c < 6; ++c) out_par[(size_t)c * ld + i] = Y[c];
+  for (int c = 0; c < 21; ++c) out_cov[(size_t)c * ld + i] = u[c];
+  out_chi2[i] = c2;
+  out_ndof[i] = ndof;
+  out_status[i] = st;
+}
+
+int orc_fit_hybrid(const orc_geometry* g, int n, int ld, int first_layer, const float* hits,
+                   const uint32_t* hole_mask, const float* seed_par, const float* seed_cov, const int8_t* q,
+                   double* out_par, double* out_cov, double* out_chi2, int32_t* out_ndof, int32_t* out_status) {
+  if (n < 0 || ld < n || g->n_layers > 32 || first_layer < 0) return 1;
+  double rows[9 * 32];
+  for (int i = 0; i < n; ++i) {
+    for (int l = 0; l < g->n_layers; ++l) load_hit(hits, ld, l, i, rows + l * 9);
+    double Xs[6], u[21], Ps[36], Y[6], P[36], c2;
+    int ndof, st;
+    for (int c = 0; c < 6; ++c) Xs[c] = (double)seed_par[(size_t)c * ld + i];
+    for (int c = 0; c < 21; ++c) u[c] = (double)seed_cov[(size_t)c * ld + i];
+    sym_from_upper(u, Ps);
+    fit_one_hyb(g, first_layer, rows, hole_mask ? hole_mask[i] : 0u, Xs, Ps, q[i], Y, P, &c2, &ndof, &st);
+    store_fit(ld, i, Y, P, c2, ndof, st, out_par, out_cov, out_chi2, out_ndof, out_status);
+  }
+  return 0;
+}
+
+/* FP64 inputs throughout (used by the exactness pins). */
+int orc_fit_hybrid64(const orc_geometry* g, int n, int ld, int first_layer, const double* hits,
+                     const double* seed_par, const double* seed_cov, const int8_t* q, double* out_par,
+                     double* out_cov, double* out_chi2, int32_t* out_ndof, int32_t* out_status) {
+  if (n < 0 || ld < n || g->n_layers > 32 || first_layer < 0) return 1;
+  double rows[9 * 32];
+  for (int i = 0; i < n; ++i) {
+    for (int l = 0; l < g->n_layers; ++l)
+      for (int c = 0; c < 9; ++c) rows[l * 9 + c] = hits[((size_t)l * 9 + c) * (size_t)ld + (size_t)i];
+    double Xs[6], u[21], Ps[36], Y[6], P[36], c2;
+    int ndof, st;
+    for (int c = 0; c < 6; ++c) Xs[c] = seed_par[(size_t)c * ld + i];
+    for (int c = 0; c < 21; ++c) u[c] = seed_cov[(size_t)c * ld + i];
+    sym_from_upper(u, Ps);
+    fit_one_hyb(g, first_layer, rows, 0u, Xs, Ps, q[i], Y, P, &c2, &ndof, &st);
+    store_fit(ld, i, Y, P, c2, ndof, st, out_par, out_cov, out_chi2, out_ndof, out_status);
+  }
+  return 0;
+}
+
 int orc_fit(const orc_geometry* g, int n, int ld, int first_layer, const float* hits, const uint32_t* hole_mask,
             const float* seed_par, const float* seed_cov, const int8_t* q, double* out_par, double* out_cov,
             double* out_chi2, int32_t* out_ndof, int32_t* out_status) {

@@ -83,6 +83,18 @@ int orc_fit(const orc_geometry* g, int n, int ld, int first_layer, const float* 
 int orc_fit64(const orc_geometry* g, int n, int ld, int first_layer, const double* hits,
               const double* seed_par, const double* seed_cov, const int8_t* q, double* out_par, double* out_cov,
               double* out_chi2, int32_t* out_ndof, int32_t* out_status);
+void orc_hyb_from_cart(const double X[6], int q, double Y[6]);
+int orc_cart_from_hyb(const double Y[6], double X[6]);
+void orc_hyb_jac_cart_from_hyb(const double Y[6], double A[36]);
+void orc_hyb_jac_hyb_from_cart(const double X[6], int q, double B[36]);
+int orc_predict_hyb(const orc_geometry* g, int layer, const double Y[6], const double P[36], double Yo[6],
+                    double Po[36]);
+int orc_fit_hybrid(const orc_geometry* g, int n, int ld, int first_layer, const float* hits,
+                   const uint32_t* hole_mask, const float* seed_par, const float* seed_cov, const int8_t* q,
+                   double* out_par, double* out_cov, double* out_chi2, int32_t* out_ndof, int32_t* out_status);
+int orc_fit_hybrid64(const orc_geometry* g, int n, int ld, int first_layer, const double* hits,
+                     const double* seed_par, const double* seed_cov, const int8_t* q, double* out_par,
+                     double* out_cov, double* out_chi2, int32_t* out_ndof, int32_t* out_status);
 int orc_hit_bin(const orc_geometry* g, int n_phi, int n_z, int n_hits, const int32_t* layer, const float* xyz,
                 int32_t* offsets, int32_t* order, float* phi_sorted);
 int orc_build(const orc_geometry* g, const orc_build_params* bp, int n_hits, const int32_t* layer,
