@@ -326,6 +326,19 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
                 "traffic": None, "kernel": dom, "avg_ms": stage_ms[dom]}
+    # the fit stage in the hybrid state (Cartesian position, q/pT, phi, theta)
+    # on the same built lists, timed on its own
+    fh = kf.kf_fit_hybrid(g, n, F, fit_hits, seeds["par"], seeds["cov"], seeds["q"], hole_mask=hole, arith=arith)
+    hts = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        kf.kf_fit_hybrid(g, n, F, fit_hits, seeds["par"], seeds["cov"], seeds["q"], hole_mask=hole, out=fh,
+                         arith=arith)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        hts.append(e0.elapsed_time(e1))
+    fit_hybrid_ms = float(np.median(hts))
     # physics: fraction of seeds whose built list holds >= 75 % of their true hits
     hits = bout["hits"].cpu().numpy()[:, :n]
     eff = float(np.mean((hits == eb.true_hits[F:, :n]).mean(axis=0) >= 0.75))
@@ -345,6 +358,8 @@ def main():
                  "fit_tflops": round(fit_flop / (stage_ms["kf_fit"] * 1e-3) / 1e12, 3)},
         "efficiency_75pct": round(eff, 4),
         "fit_status_ok": round(float(np.mean(st == 0)), 4),
+        "fit_hybrid_ms": round(fit_hybrid_ms, 4),
+        "fit_hybrid_status_ok": round(float(np.mean(fh["status"].cpu().numpy()[:n] == 0)), 4),
         "gen_s": round(t_gen, 2),
     }
     if not args.no_other_arith:

@@ -118,6 +118,23 @@ int kf_fit(const kf_geometry* g, int32_t n, int32_t ld, int32_t first_layer, con
            void* stream);
 
 /*
+ * kf_fit_hybrid — the same fit in the hybrid state of section 3: global
+ * Cartesian position, polar momentum, Y = (x, y, z, k = q/pT, phi, theta).
+ * The seeds are Cartesian as for kf_fit (state, covariance, q) and are
+ * converted on entry; each prediction is the Cartesian one at the same point
+ * with the covariance carried through the changes of variables, and the
+ * update acts on Y, so k may change sign (the charge is not fixed by the
+ * seed).  Outputs are hybrid: out_par [6][ld] = Y, out_cov [21][ld] its
+ * covariance (upper triangle, row order); chi2, ndof, status as kf_fit.  A
+ * state with k = 0 stops with KF_NONFINITE.  Arguments, errors and
+ * arithmetic as kf_fit.
+ */
+int kf_fit_hybrid(const kf_geometry* g, int32_t n, int32_t ld, int32_t first_layer, const float* hits,
+                  const uint32_t* hole_mask, const float* seed_par, const float* seed_cov, const int8_t* q,
+                  float* out_par, float* out_cov, float* out_chi2, int32_t* out_ndof, int32_t* out_status,
+                  int32_t arith, void* stream);
+
+/*
  * Binned hits (section 3.1): per event and layer, n_z x n_phi bins,
  * bin = iz * n_phi + iphi with phi = atan2(y, x) in [0, 2 pi) computed in
  * FP64 and rounded to FP32, iphi = min(n_phi-1, floor(phi * n_phi / 2pi)),

@@ -149,8 +149,10 @@ __global__ void __launch_bounds__(256) seed_kernel(GeomK g, int n, int ld, const
 }
 
 // Fit: one lane per track, layers looped in registers.  Storage is FP32;
-// T is the arithmetic type (float, or double for the precise mode).
-template <typename T>
+// T is the arithmetic type (float, or double for the precise mode).  HYB:
+// the state is the hybrid one (x, y, z, q/pT, phi, theta), entered from the
+// Cartesian seed and returned as it is.
+template <typename T, bool HYB>
 __global__ void __launch_bounds__(256, (sizeof(T) == 8 ? 2 : 1)) fit_kernel(GeomK g, int n, int ld, int first_layer,
                                                   const float* __restrict__ hits,
                                                   const uint32_t* __restrict__ hole_mask,
@@ -166,6 +168,13 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 8 ? 2 : 1)) fit_kernel(Geom
 #pragma unroll
   for (int k = 0; k < 21; ++k) P[k] = (T)seed_cov[(size_t)k * ld + i];
   const int q = qv[i];
+  if constexpr (HYB) {
+    T Y[6], B[9];
+    hyb_from_cart(X, q, Y, B);
+    congruence_mom(P, B);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) X[k] = Y[k];
+  }
   const uint32_t holes = hole_mask ? hole_mask[i] : 0u;
   T chi2 = 0;
   int ndof = 0;
@@ -180,7 +189,11 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 8 ? 2 : 1)) fit_kernel(Geom
       if (!all_finite(hv, 9)) { st = KF_NONFINITE; break; }
     }
     T Xp[6], Pp[21];
-    int rc = predict<T>(X, P, q, (T)g.r[l], (T)g.bz, (T)g.z_half, (T)g.x_over_x0, (T)g.mass, Xp, Pp);
+    int rc;
+    if constexpr (HYB)
+      rc = predict_hyb<T>(X, P, (T)g.r[l], (T)g.bz, (T)g.z_half, (T)g.x_over_x0, (T)g.mass, Xp, Pp);
+    else
+      rc = predict<T>(X, P, q, (T)g.r[l], (T)g.bz, (T)g.z_half, (T)g.x_over_x0, (T)g.mass, Xp, Pp);
     if (rc) { st = rc; break; }
     if (use) {
       Innov<T> in;
@@ -234,10 +247,13 @@ extern "C" int kf_seed(const kf_geometry* g, int32_t n, int32_t ld, const float*
   return kf_check_launch();
 }
 
-extern "C" int kf_fit(const kf_geometry* g, int32_t n, int32_t ld, int32_t first_layer, const float* hits,
-                      const uint32_t* hole_mask, const float* seed_par, const float* seed_cov, const int8_t* q,
-                      float* out_par, float* out_cov, float* out_chi2, int32_t* out_ndof, int32_t* out_status,
-                      int32_t arith, void* stream) {
+namespace {
+
+template <bool HYB>
+int fit_launch(const kf_geometry* g, int32_t n, int32_t ld, int32_t first_layer, const float* hits,
+               const uint32_t* hole_mask, const float* seed_par, const float* seed_cov, const int8_t* q,
+               float* out_par, float* out_cov, float* out_chi2, int32_t* out_ndof, int32_t* out_status,
+               int32_t arith, void* stream) {
   if (check_geometry(g)) return KF_E_INVALID_ARG;
   if (n < 0 || ld < n || first_layer < 0 || first_layer > g->n_layers) return KF_E_INVALID_ARG;
   if (arith != KF_ARITH_F32 && arith != KF_ARITH_F64) return KF_E_INVALID_ARG;
@@ -246,14 +262,32 @@ extern "C" int kf_fit(const kf_geometry* g, int32_t n, int32_t ld, int32_t first
     return KF_E_INVALID_ARG;
   const int bs = 256;
   if (arith == KF_ARITH_F64)
-    hipLaunchKernelGGL(fit_kernel<double>, dim3((n + bs - 1) / bs), dim3(bs), 0, (hipStream_t)stream, to_k(g), n, ld,
-                       first_layer, hits, hole_mask, seed_par, seed_cov, q, out_par, out_cov, out_chi2, out_ndof,
-                       out_status);
+    hipLaunchKernelGGL((fit_kernel<double, HYB>), dim3((n + bs - 1) / bs), dim3(bs), 0, (hipStream_t)stream, to_k(g),
+                       n, ld, first_layer, hits, hole_mask, seed_par, seed_cov, q, out_par, out_cov, out_chi2,
+                       out_ndof, out_status);
   else
-    hipLaunchKernelGGL(fit_kernel<float>, dim3((n + bs - 1) / bs), dim3(bs), 0, (hipStream_t)stream, to_k(g), n, ld,
-                       first_layer, hits, hole_mask, seed_par, seed_cov, q, out_par, out_cov, out_chi2, out_ndof,
-                       out_status);
+    hipLaunchKernelGGL((fit_kernel<float, HYB>), dim3((n + bs - 1) / bs), dim3(bs), 0, (hipStream_t)stream, to_k(g),
+                       n, ld, first_layer, hits, hole_mask, seed_par, seed_cov, q, out_par, out_cov, out_chi2,
+                       out_ndof, out_status);
   return kf_check_launch();
+}
+
+}  // namespace
+
+extern "C" int kf_fit(const kf_geometry* g, int32_t n, int32_t ld, int32_t first_layer, const float* hits,
+                      const uint32_t* hole_mask, const float* seed_par, const float* seed_cov, const int8_t* q,
+                      float* out_par, float* out_cov, float* out_chi2, int32_t* out_ndof, int32_t* out_status,
+                      int32_t arith, void* stream) {
+  return fit_launch<false>(g, n, ld, first_layer, hits, hole_mask, seed_par, seed_cov, q, out_par, out_cov, out_chi2,
+                           out_ndof, out_status, arith, stream);
+}
+
+extern "C" int kf_fit_hybrid(const kf_geometry* g, int32_t n, int32_t ld, int32_t first_layer, const float* hits,
+                             const uint32_t* hole_mask, const float* seed_par, const float* seed_cov,
+                             const int8_t* q, float* out_par, float* out_cov, float* out_chi2, int32_t* out_ndof,
+                             int32_t* out_status, int32_t arith, void* stream) {
+  return fit_launch<true>(g, n, ld, first_layer, hits, hole_mask, seed_par, seed_cov, q, out_par, out_cov, out_chi2,
+                          out_ndof, out_status, arith, stream);
 }
 
 namespace {

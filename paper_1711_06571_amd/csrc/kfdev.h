@@ -328,4 +328,99 @@ template <typename T> KFD inline bool all_finite(const T* a, int n) {
   return ok;
 }
 
+// Hybrid state (section 3: Cartesian position, polar momentum):
+// Y = (x, y, z, k, phi, theta), k = q / pT signed.  The prediction of Y is
+// the Cartesian prediction at the same point with the covariance carried
+// through the changes of variables; they leave the position alone, so only
+// the momentum blocks of their Jacobians are kept (3 x 3, row-major).
+//
+// Y -> Cartesian state; A = d(px, py, pz) / d(k, phi, theta); returns q.
+template <typename T> KFD inline int cart_from_hyb(const T Y[6], T X[6], T A[9]) {
+  const T k = Y[3];
+  const T ak = k < T(0) ? -k : k;
+  const T pt = k_rcp(ak);
+  const T sg = k < T(0) ? T(-1) : T(1);
+  T sf, cf, st, ct;
+  k_sincos(Y[4], &sf, &cf);
+  k_sincos(Y[5], &st, &ct);
+  const T ist = k_rcp(st);
+  const T cot = ct * ist;
+  X[0] = Y[0];
+  X[1] = Y[1];
+  X[2] = Y[2];
+  X[3] = pt * cf;
+  X[4] = pt * sf;
+  X[5] = pt * cot;
+  const T dpt = -sg * pt * pt;  // d pT / d k
+  A[0] = dpt * cf; A[1] = -pt * sf; A[2] = T(0);
+  A[3] = dpt * sf; A[4] = pt * cf;  A[5] = T(0);
+  A[6] = dpt * cot; A[7] = T(0);    A[8] = -pt * ist * ist;
+  return k < T(0) ? -1 : 1;
+}
+
+// Cartesian state (charge q) -> Y; B = d(k, phi, theta) / d(px, py, pz).
+template <typename T> KFD inline void hyb_from_cart(const T X[6], int q, T Y[6], T B[9]) {
+  const T px = X[3], py = X[4], pz = X[5];
+  const T pt2 = px * px + py * py;
+  const T pt = k_sqrt(pt2);
+  const T ipt = k_rcp(pt), ipt2 = ipt * ipt;
+  const T ip2 = k_rcp(pt2 + pz * pz);
+  const T k = (q < 0 ? T(-1) : T(1)) * ipt;
+  Y[0] = X[0];
+  Y[1] = X[1];
+  Y[2] = X[2];
+  Y[3] = k;
+  Y[4] = k_atan2(py, px);
+  Y[5] = k_atan2(pt, pz);
+  B[0] = -k * px * ipt2;       B[1] = -k * py * ipt2;       B[2] = T(0);
+  B[3] = -py * ipt2;           B[4] = px * ipt2;            B[5] = T(0);
+  B[6] = px * pz * ipt * ip2;  B[7] = py * pz * ipt * ip2;  B[8] = -pt * ip2;
+}
+
+// P <- M P M^T with M = diag(I3, Mp) on the 21-entry upper triangle: the
+// position block stays, position-momentum becomes Ppm Mp^T, momentum Mp Pmm Mp^T.
+template <typename T> KFD inline void congruence_mom(T P[21], const T M[9]) {
+  T pm[3][3], mm[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) pm[i][b] = P[ut(i, 3 + b)];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) mm[a][b] = P[ut(3 + a, 3 + b)];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) P[ut(i, 3 + a)] = pm[i][0] * M[a * 3] + pm[i][1] * M[a * 3 + 1] + pm[i][2] * M[a * 3 + 2];
+  // T1 = Mp Pmm, then T1 Mp^T (upper triangle)
+  T t1[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) t1[a][b] = M[a * 3] * mm[0][b] + M[a * 3 + 1] * mm[1][b] + M[a * 3 + 2] * mm[2][b];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = a; c < 3; ++c)
+      P[ut(3 + a, 3 + c)] = t1[a][0] * M[c * 3] + t1[a][1] * M[c * 3 + 1] + t1[a][2] * M[c * 3 + 2];
+}
+
+// Prediction of a hybrid state: to Cartesian, predict, back.
+template <typename T>
+KFD inline int predict_hyb(const T Y[6], const T P[21], T R, T bz, T z_half, T x_over_x0, T mass, T Yo[6],
+                           T Po[21]) {
+  if (!(Y[3] != T(0))) return KF_NONFINITE;
+  T X[6], A[9], Pc[21], Xo[6], B[9];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) Pc[k] = P[k];
+  const int q = cart_from_hyb(Y, X, A);
+  congruence_mom(Pc, A);
+  const int rc = predict<T>(X, Pc, q, R, bz, z_half, x_over_x0, mass, Xo, Po);
+  if (rc) return rc;
+  hyb_from_cart(Xo, q, Yo, B);
+  congruence_mom(Po, B);
+  return 0;
+}
+
 }  // namespace kfdev

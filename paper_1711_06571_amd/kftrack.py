@@ -92,6 +92,7 @@ def lib():
         L.kf_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
         L.kf_seed.argtypes = [ctypes.POINTER(Geometry), I, I, P, ctypes.c_float, P, P, P, P, P]
         L.kf_fit.argtypes = [ctypes.POINTER(Geometry), I, I, I, P, P, P, P, P, P, P, P, P, P, I, P]
+        L.kf_fit_hybrid.argtypes = L.kf_fit.argtypes
         L.hit_bin_workspace_bytes.restype = ctypes.c_size_t
         L.hit_bin_workspace_bytes.argtypes = [I, I, I, I, I]
         L.hit_bin.argtypes = [ctypes.POINTER(Geometry), I, P, I, I, I, P, P, P, P, P, P, P, P, P,
@@ -176,7 +177,7 @@ def kf_seed(g, n, hits, beam_sigma=None, stream=None):
     return out
 
 
-def kf_fit(g, n, first_layer, hits, seed_par, seed_cov, q, hole_mask=None, out=None, arith=ARITH_F32, stream=None):
+def _fit(fn, g, n, first_layer, hits, seed_par, seed_cov, q, hole_mask, out, arith, stream):
     ld = hits.shape[2]
     dev = hits.device
     if out is None:
@@ -186,10 +187,21 @@ def kf_fit(g, n, first_layer, hits, seed_par, seed_cov, q, hole_mask=None, out=N
                    ndof=torch.empty(ld, dtype=torch.int32, device=dev),
                    status=torch.empty(ld, dtype=torch.int32, device=dev))
     gg = geometry(g)
-    _check(lib().kf_fit(ctypes.byref(gg), n, ld, first_layer, _ptr(hits), _ptr(hole_mask), _ptr(seed_par),
-                        _ptr(seed_cov), _ptr(q), _ptr(out["par"]), _ptr(out["cov"]), _ptr(out["chi2"]),
-                        _ptr(out["ndof"]), _ptr(out["status"]), arith, _stream(stream)))
+    _check(fn(ctypes.byref(gg), n, ld, first_layer, _ptr(hits), _ptr(hole_mask), _ptr(seed_par), _ptr(seed_cov),
+              _ptr(q), _ptr(out["par"]), _ptr(out["cov"]), _ptr(out["chi2"]), _ptr(out["ndof"]),
+              _ptr(out["status"]), arith, _stream(stream)))
     return out
+
+
+def kf_fit(g, n, first_layer, hits, seed_par, seed_cov, q, hole_mask=None, out=None, arith=ARITH_F32, stream=None):
+    return _fit(lib().kf_fit, g, n, first_layer, hits, seed_par, seed_cov, q, hole_mask, out, arith, stream)
+
+
+def kf_fit_hybrid(g, n, first_layer, hits, seed_par, seed_cov, q, hole_mask=None, out=None, arith=ARITH_F32,
+                  stream=None):
+    """Fit in the hybrid state; outputs (x, y, z, q/pT, phi, theta) and their
+    covariance."""
+    return _fit(lib().kf_fit_hybrid, g, n, first_layer, hits, seed_par, seed_cov, q, hole_mask, out, arith, stream)
 
 
 # ----------------------------------------------------------------- binning
