@@ -39,7 +39,8 @@ class Geom(ctypes.Structure):
 class BuildParams(ctypes.Structure):
     _fields_ = [("chi2_cut", ctypes.c_float), ("max_holes", ctypes.c_int32), ("cand_cap", ctypes.c_int32),
                 ("nsigma", ctypes.c_float), ("win_sig_rphi", ctypes.c_float), ("win_sig_z", ctypes.c_float),
-                ("first_layer", ctypes.c_int32), ("window_mode", ctypes.c_int32), ("mlp", ctypes.c_void_p)]
+                ("first_layer", ctypes.c_int32), ("window_mode", ctypes.c_int32), ("mlp", ctypes.c_void_p),
+                ("state", ctypes.c_int32)]
 
 
 _lib = None
@@ -76,7 +77,7 @@ def lib():
         L.orc_hyb_jac_cart_from_hyb.restype = None
         L.orc_hyb_jac_hyb_from_cart.argtypes = [P, I, P]
         L.orc_hyb_jac_hyb_from_cart.restype = None
-        L.orc_predict_hyb.argtypes = [ctypes.POINTER(Geom), I, P, P, P, P]
+        L.orc_predict_hyb.argtypes = [ctypes.POINTER(Geom), I, P, P, P, P, P]
         L.orc_fit_hybrid.argtypes = [ctypes.POINTER(Geom), I, I, I] + [P] * 10
         L.orc_fit_hybrid64.argtypes = [ctypes.POINTER(Geom), I, I, I] + [P] * 9
         L.orc_build.argtypes = [ctypes.POINTER(Geom), ctypes.POINTER(BuildParams), I, P, P, P, I, I, P, P, P, I,
@@ -256,7 +257,7 @@ def predict_hyb(g, layer, Y, P):
     Yo = np.zeros(6)
     Po = np.zeros(36)
     gg = geom(g)
-    rc = lib().orc_predict_hyb(ctypes.byref(gg), int(layer), _p(Y), _p(P), _p(Yo), _p(Po))
+    rc = lib().orc_predict_hyb(ctypes.byref(gg), int(layer), _p(Y), _p(P), _p(Yo), _p(Po), None)
     return rc, Yo, Po.reshape(6, 6)
 
 
@@ -328,9 +329,10 @@ def hit_bin(g, n_phi, n_z, layer, xyz):
 
 
 def build(g, cuts, layer, xyz, cov, seed_par, seed_cov, q, n_seeds, seed_list=None, cap=None,
-          window_mode=0, mlp_blob=None, first_layer=None):
+          window_mode=0, mlp_blob=None, first_layer=None, state=0):
     """Brute-force combinatorial build.  seed_list selects seeds; outputs are
-    indexed by position in the list (first len(seed_list) columns)."""
+    indexed by position in the list (first len(seed_list) columns).  state 1
+    builds in the hybrid state (Cartesian seeds converted; hybrid outputs)."""
     ld = seed_par.shape[1]
     lst = None if seed_list is None else np.ascontiguousarray(seed_list, dtype=np.int32)
     nl = n_seeds if lst is None else lst.shape[0]
@@ -350,6 +352,7 @@ def build(g, cuts, layer, xyz, cov, seed_par, seed_cov, q, n_seeds, seed_list=No
     bp.win_sig_z = cuts.win_sig_z
     bp.first_layer = F
     bp.window_mode = window_mode
+    bp.state = state
     blob = None
     if window_mode == 1:
         blob = np.ascontiguousarray(mlp_blob, dtype=np.float64)

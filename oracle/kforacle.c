@@ -510,13 +510,15 @@ static void congruence(const double M[36], const double P[36], double Po[36]) {
 }
 
 int orc_predict_hyb(const orc_geometry* g, int layer, const double Y[6], const double P[36], double Yo[6],
-                    double Po[36]) {
+                    double Po[36], double* disc) {
   double X[6], A[36], Pc[36], Xo[6], Pco[36], B[36];
+  if (disc) *disc = NAN;
   if (!(Y[3] != 0.0)) return ORC_TRK_NONFINITE;
   int q = orc_cart_from_hyb(Y, X);
   orc_hyb_jac_cart_from_hyb(Y, A);
   congruence(A, P, Pc);
-  int rc = orc_predict(g, layer, X, q, Pc, Xo, Pco, NULL);
+  int rc = orc_predict(g, layer, X, q, Pc, Xo, Pco, disc);
+  if (rc == ORC_TRK_OUT_OF_Z) memcpy(Yo, Xo, sizeof(double) * 3); /* the crossing point, for the caller's margin */
   if (rc) return rc;
   orc_hyb_from_cart(Xo, q, Yo);
   orc_hyb_jac_hyb_from_cart(Xo, q, B);
@@ -545,7 +547,7 @@ static void fit_one_hyb(const orc_geometry* g, int first_layer, const double* hi
     int use = !((holes >> l) & 1u);
     if (use && !all_finite(h, 9)) { st = ORC_TRK_NONFINITE; break; }
     double Yp[6], Pp[36];
-    int rc = orc_predict_hyb(g, l, Y, P, Yp, Pp);
+    int rc = orc_predict_hyb(g, l, Y, P, Yp, Pp, NULL);
     if (rc) { st = rc; break; }
     if (!use) {
       if (!all_finite(Yp, 6) || !all_finite(Pp, 36)) { st = ORC_TRK_NONFINITE; break; }
@@ -852,6 +854,12 @@ static double minf(double a, double b) { return a < b ? a : b; }
  * finished record) under (nhits desc, chi2 asc), first wins ties.  nhits
  * counts hits on the searched layers only.
  *
+ * With state = 1 the candidates carry the hybrid state (x, y, z, q/pT, phi,
+ * theta): the seed is converted on entry, predictions are hybrid ones (the
+ * charge follows the sign of q/pT), the update and the window are unchanged
+ * (they use the position and its covariance block), and the outputs are
+ * hybrid.
+ *
  * out_margin[3][ld] records, per seed, the smallest distance of any
  * decision from its threshold: [0] chi2 (absolute: |chi2 - cut| of in-window
  * hits, chi2 gaps at equal nhits for cap cuts, record replacements and the
@@ -869,6 +877,7 @@ int orc_build(const orc_geometry* g, const orc_build_params* bp, int n_hits, con
   if (n_seeds < 0 || ld < n_seeds || L > 32 || F < 0 || F >= L || bp->cand_cap < 1 || n_list < 0 || n_list > ld)
     return 1;
   if (bp->window_mode == 1 && !bp->mlp) return 1;
+  if (bp->state != 0 && bp->state != 1) return 1;
   /* group hit indices by layer, increasing original index */
   int* lay_cnt = (int*)calloc((size_t)L, sizeof(int));
   int* lay_off = (int*)calloc((size_t)L + 1, sizeof(int));
@@ -901,6 +910,14 @@ int orc_build(const orc_geometry* g, const orc_build_params* bp, int n_hits, con
     for (int c = 0; c < 6; ++c) act[0].X[c] = (double)seed_par[(size_t)c * ld + i];
     for (int c = 0; c < 21; ++c) u[c] = (double)seed_cov[(size_t)c * ld + i];
     sym_from_upper(u, act[0].P);
+    if (bp->state == 1) { /* the seed in the hybrid state */
+      double Y[6], B[36], Pc[36];
+      memcpy(Pc, act[0].P, sizeof(Pc));
+      orc_hyb_from_cart(act[0].X, qi, Y);
+      orc_hyb_jac_hyb_from_cart(act[0].X, qi, B);
+      congruence(B, Pc, act[0].P);
+      memcpy(act[0].X, Y, sizeof(Y));
+    }
     for (int l = 0; l < 32; ++l) act[0].hits[l] = -1;
     if (!all_finite(act[0].X, 6) || !all_finite(act[0].P, 36)) {
       act[0].status = ORC_TRK_NONFINITE;
@@ -915,9 +932,10 @@ int orc_build(const orc_geometry* g, const orc_build_params* bp, int n_hits, con
       for (int a = 0; a < n_act; ++a) {
         cand_t* c = &act[a];
         double Xp[6], Pp[36], disc = INFINITY;
-        int rc = orc_predict(g, l, c->X, qi, c->P, Xp, Pp, &disc);
+        int rc = bp->state == 1 ? orc_predict_hyb(g, l, c->X, c->P, Xp, Pp, &disc)
+                                : orc_predict(g, l, c->X, qi, c->P, Xp, Pp, &disc);
         if (isfinite(disc)) mgeo = minf(mgeo, disc);
-        if (rc != ORC_TRK_NO_CROSSING) mgeo = minf(mgeo, fabs(fabs(Xp[2]) - (double)g->z_half) / (double)g->z_half);
+        if (rc != ORC_TRK_NO_CROSSING && rc != ORC_TRK_NONFINITE) mgeo = minf(mgeo, fabs(fabs(Xp[2]) - (double)g->z_half) / (double)g->z_half);
         if (rc) { stopped[n_stop] = a; stop_status[n_stop++] = rc; continue; }
         /* window */
         double rr = sqrt(Xp[0] * Xp[0] + Xp[1] * Xp[1]);

@@ -59,6 +59,7 @@ typedef struct {
   int32_t first_layer;/* first layer searched */
   int32_t window_mode;/* 0 plain, 1 learned */
   const double* mlp;  /* learned-window parameters (oracle layout), or NULL */
+  int32_t state;      /* 0 Cartesian; 1 hybrid (x, y, z, q/pT, phi, theta) */
 } orc_build_params;
 
 /* --- primitives (exposed for the pins) --- */
@@ -88,7 +89,7 @@ int orc_cart_from_hyb(const double Y[6], double X[6]);
 void orc_hyb_jac_cart_from_hyb(const double Y[6], double A[36]);
 void orc_hyb_jac_hyb_from_cart(const double X[6], int q, double B[36]);
 int orc_predict_hyb(const orc_geometry* g, int layer, const double Y[6], const double P[36], double Yo[6],
-                    double Po[36]);
+                    double Po[36], double* disc);
 int orc_fit_hybrid(const orc_geometry* g, int n, int ld, int first_layer, const float* hits,
                    const uint32_t* hole_mask, const float* seed_par, const float* seed_cov, const int8_t* q,
                    double* out_par, double* out_cov, double* out_chi2, int32_t* out_ndof, int32_t* out_status);

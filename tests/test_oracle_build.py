@@ -244,3 +244,40 @@ def test_learned_window_everything_equals_plain_everything():
         assert np.array_equal(learned[k], plain[k]), k
     # and the search really was exhaustive: noise hits were tested
     assert plain["nhits"][:n].mean() > 0
+
+
+def test_hybrid_state_build_noise_free_recovers_true_hits():
+    w = presets.build()
+    g = w.geometry.replace(x_over_x0=0.0)
+    gen = dataclasses.replace(w.gen, smear=False, vtx_sxy=0.0, noise_lo=0.0, noise_hi=0.0, pt_max=3.0)
+    ev, sd = _event_and_seeds(g, gen, 300)
+    n = ev.n_tracks
+    o = oracle.build(g, w.cuts, ev.layer, ev.xyz, ev.cov, sd["par"], sd["cov"], sd["q"], n, state=1)
+    F = w.cuts.first_layer
+    assert np.array_equal(o["hits"], ev.trk_hits[F:, :n])
+    assert np.all(o["nhits"] == g.n_layers - F)
+    assert o["chi2"].max() < 1e-3
+    # hybrid outputs: q/pT of the generating track at the last layer
+    pt = np.hypot(ev.truth[-1][3, :n], ev.truth[-1][4, :n])
+    assert np.allclose(o["par"][3, :n], ev.q / pt, rtol=1e-6)
+
+
+def test_hybrid_state_build_efficiency_not_below_cartesian():
+    """The same search in the hybrid state: on the build workload its best
+    candidates carry their track's hits at least as often as the Cartesian
+    state's, most of all at high pT where seeds can have the wrong charge."""
+    w = presets.build()
+    ev = datagen.generate(w.geometry, w.gen, 0, 20000, truth=True)
+    sd = oracle.seed(w.geometry, datagen.track_hits(ev), ev.n_tracks)
+    n = ev.n_tracks
+    lst = np.arange(0, n, 100)
+    args = (w.geometry, w.cuts, ev.layer, ev.xyz, ev.cov, sd["par"], sd["cov"], sd["q"], n)
+    oc = oracle.build(*args, seed_list=lst)
+    oh = oracle.build(*args, seed_list=lst, state=1)
+    F = w.cuts.first_layer
+    true = ev.trk_hits[F:, lst]
+    ec = (oc["hits"] == true).sum(axis=0) / true.shape[0] >= 0.75
+    eh = (oh["hits"] == true).sum(axis=0) / true.shape[0] >= 0.75
+    print(f"build efficiency on {lst.size} seeds: Cartesian {ec.mean():.3f}, hybrid {eh.mean():.3f}")
+    assert eh.mean() >= ec.mean() - 0.01
+    assert eh.mean() > 0.6
