@@ -549,7 +549,7 @@ __host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsi
 #define KF_BUILD_F64_LEARNED_WAVES 2
 #endif
 
-template <typename T, bool LEARNED>
+template <typename T, bool LEARNED, bool HYB>
 __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
                                                        : (LEARNED ? KF_BUILD_F64_LEARNED_WAVES : KF_BUILD_F64_WAVES)))
     build_kernel(BuildArgs A) {
@@ -601,6 +601,15 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
     for (int k = 0; k < 6; ++k) X[k] = seed_ok ? (T)A.seed_par[(size_t)k * A.ld + seed] : T(0);
 #pragma unroll
     for (int k = 0; k < 21; ++k) P[k] = seed_ok ? (T)A.seed_cov[(size_t)k * A.ld + seed] : T(0);
+    if constexpr (HYB) {  // the seed in the hybrid state
+      if (seed_ok) {
+        T Y[6], B[9];
+        hyb_from_cart(X, q, Y, B);
+        congruence_mom(P, B);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) X[k] = Y[k];
+      }
+    }
     T chi2 = 0;
     int nhits = 0, holes = 0;
     bool ontrack = true;
@@ -635,8 +644,12 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
       }
       T Xp[6], Pp[21];
       int rc = 1;
-      if (live)
-        rc = predict<T>(X, P, q, (T)A.r[l], (T)A.bz, (T)A.z_half, (T)A.x_over_x0, (T)A.mass, Xp, Pp);
+      if (live) {
+        if constexpr (HYB)
+          rc = predict_hyb<T>(X, P, (T)A.r[l], (T)A.bz, (T)A.z_half, (T)A.x_over_x0, (T)A.mass, Xp, Pp);
+        else
+          rc = predict<T>(X, P, q, (T)A.r[l], (T)A.bz, (T)A.z_half, (T)A.x_over_x0, (T)A.mass, Xp, Pp);
+      }
       else {
 #pragma unroll
         for (int k = 0; k < 6; ++k) Xp[k] = T(0);
@@ -926,7 +939,7 @@ int refine_of(const kf_build_params* bp) { return bp->phi_refine > 0 ? bp->phi_r
 // the launch shape of the last kf_build call of this host thread
 thread_local kf_build_launch_info g_last_launch = {};
 
-template <typename T, bool LEARNED>
+template <typename T, bool LEARNED, bool HYB>
 int launch(const BuildArgs& A, int lanes, int blocks, int hist_waves, hipStream_t s) {
   const int LB = A.n_layers - A.first_layer;
   int dev = 0, max_lds = 0;
@@ -941,12 +954,12 @@ int launch(const BuildArgs& A, int lanes, int blocks, int hist_waves, hipStream_
   const size_t lds = plan(lanes);
   if (lds > (size_t)max_lds) return KF_E_UNSUPPORTED;
   if (lds > (size_t)64 * 1024 &&
-      kf_check(hipFuncSetAttribute((const void*)build_kernel<T, LEARNED>,
+      kf_check(hipFuncSetAttribute((const void*)build_kernel<T, LEARNED, HYB>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)))
     return KF_E_HIP;
   int cus = 0, per = 0;
   if (kf_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev))) return KF_E_HIP;
-  if (kf_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, build_kernel<T, LEARNED>, lanes, lds)))
+  if (kf_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, build_kernel<T, LEARNED, HYB>, lanes, lds)))
     return KF_E_HIP;
   if (blocks <= 0) blocks = cus * (per > 0 ? per : 1);
   const int need = (A.n_groups + nwaves - 1) / nwaves;
@@ -958,7 +971,7 @@ int launch(const BuildArgs& A, int lanes, int blocks, int hist_waves, hipStream_
   g_last_launch.lds_bytes = (int32_t)lds;
   g_last_launch.resident_blocks_per_cu = per;
   g_last_launch.max_lds_per_block = max_lds;
-  hipLaunchKernelGGL((build_kernel<T, LEARNED>), dim3(blocks), dim3(lanes), lds, s, A);
+  hipLaunchKernelGGL((build_kernel<T, LEARNED, HYB>), dim3(blocks), dim3(lanes), lds, s, A);
   return kf_check_launch();
 }
 
@@ -1008,6 +1021,8 @@ extern "C" int kf_build(const kf_geometry* g, const kf_build_params* bp, const k
   if (bp->arith != KF_ARITH_F32 && bp->arith != KF_ARITH_F64) return KF_E_INVALID_ARG;
   if (bp->window_mode != 0 && bp->window_mode != 1) return KF_E_INVALID_ARG;
   if (bp->window_mode == 1 && !bp->mlp) return KF_E_INVALID_ARG;
+  if (bp->state != 0 && bp->state != 1) return KF_E_INVALID_ARG;
+  if (bp->state == 1 && bp->window_mode == 1) return KF_E_UNSUPPORTED;  // the network reads Cartesian features
   if (hits->n_layers != g->n_layers || hits->n_events < 1 || hits->n_phi < 1 || hits->n_z < 1 || hits->n_hits < 0)
     return KF_E_INVALID_ARG;
   (void)kMaxOrig;  // hit indices are event-local: each event must hold fewer than 2^24 - 1 hits
@@ -1069,8 +1084,10 @@ extern "C" int kf_build(const kf_geometry* g, const kf_build_params* bp, const k
     if (int rc = kf_check_launch()) return rc;
   }
   if (bp->arith == KF_ARITH_F64)
-    return bp->window_mode == 1 ? launch<double, true>(A, lanes, bp->persistent_blocks, hist_waves, s)
-                                : launch<double, false>(A, lanes, bp->persistent_blocks, hist_waves, s);
-  return bp->window_mode == 1 ? launch<float, true>(A, lanes, bp->persistent_blocks, hist_waves, s)
-                              : launch<float, false>(A, lanes, bp->persistent_blocks, hist_waves, s);
+    return bp->state == 1         ? launch<double, false, true>(A, lanes, bp->persistent_blocks, hist_waves, s)
+           : bp->window_mode == 1 ? launch<double, true, false>(A, lanes, bp->persistent_blocks, hist_waves, s)
+                                  : launch<double, false, false>(A, lanes, bp->persistent_blocks, hist_waves, s);
+  return bp->state == 1         ? launch<float, false, true>(A, lanes, bp->persistent_blocks, hist_waves, s)
+         : bp->window_mode == 1 ? launch<float, true, false>(A, lanes, bp->persistent_blocks, hist_waves, s)
+                                : launch<float, false, false>(A, lanes, bp->persistent_blocks, hist_waves, s);
 }

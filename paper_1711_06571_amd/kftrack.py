@@ -49,7 +49,7 @@ class BuildParams(ctypes.Structure):
                 ("nsigma", ctypes.c_float), ("win_sig_rphi", ctypes.c_float), ("win_sig_z", ctypes.c_float),
                 ("first_layer", ctypes.c_int32), ("window_mode", ctypes.c_int32), ("mlp", ctypes.c_void_p),
                 ("lanes_per_block", ctypes.c_int32), ("persistent_blocks", ctypes.c_int32),
-                ("arith", ctypes.c_int32), ("phi_refine", ctypes.c_int32)]
+                ("arith", ctypes.c_int32), ("phi_refine", ctypes.c_int32), ("state", ctypes.c_int32)]
 
 
 class LaunchInfo(ctypes.Structure):
@@ -255,8 +255,12 @@ def hit_bin(g, n_phi, n_z, layer, xyz, cov, event_offsets=None, out=None, ws=Non
 
 # ------------------------------------------------------------------- build
 
+STATE_CARTESIAN = 0
+STATE_HYBRID = 1
+
+
 def build_params(cuts, window_mode=0, mlp_block=None, lanes_per_block=0, persistent_blocks=0, cap=None,
-                 arith=ARITH_F32, phi_refine=0):
+                 arith=ARITH_F32, phi_refine=0, state=STATE_CARTESIAN):
     bp = BuildParams()
     bp.chi2_cut = cuts.chi2_cut
     bp.max_holes = cuts.max_holes
@@ -271,6 +275,7 @@ def build_params(cuts, window_mode=0, mlp_block=None, lanes_per_block=0, persist
     bp.persistent_blocks = persistent_blocks
     bp.arith = arith
     bp.phi_refine = phi_refine
+    bp.state = state
     return bp
 
 

@@ -227,3 +227,69 @@ def test_build_edge_cases(kf):
     out = kf.kf_build(g, bp, empty, 64, sg["par"], sg["cov"], sg["q"])
     torch.cuda.synchronize()
     assert np.all(host(out["nhits"])[:64] == 0)
+
+
+def _hybrid_param_errors(g, o, cols_g, sel):
+    gp = g["par"][:, cols_g][:, sel].astype(np.float64)
+    op = o["par"][:, sel]
+    ep = rel_vec_err(gp[:3], op[:3])
+    ek = np.abs(gp[3] - op[3]) / np.abs(op[3])
+    da = gp[4:] - op[4:]
+    da[0] = (da[0] + np.pi) % (2 * np.pi) - np.pi
+    return ep, ek, np.abs(da).max(axis=0)
+
+
+@pytest.mark.parametrize("full", [False, True])
+def test_hybrid_state_build_parity(kf, full):
+    """The build in the hybrid state (FP64 arithmetic) against the oracle's:
+    hit lists, nhits and status on every decidable seed; chi2, position,
+    q/pT and angles on the converged ones."""
+    w = presets.build()
+    if full:
+        ev = datagen.generate(w.geometry, w.gen, 0, w.n_tracks)
+    else:
+        ev = datagen.generate(w.geometry, w.gen, 13, 600)
+    n = ev.n_tracks
+    xyz = ev.xyz.astype(np.float32)
+    b = kf.hit_bin(w.geometry, w.cuts.n_phi_bins, w.cuts.n_z_bins, to_dev(ev.layer), to_dev(xyz),
+                   to_dev(ev.cov.astype(np.float32)))
+    H = datagen.track_hits(ev)
+    sg = kf.kf_seed(w.geometry, n, to_dev(H))
+    bp = kf.build_params(w.cuts, arith=kf.ARITH_F64, state=kf.STATE_HYBRID)
+    out = kf.kf_build(w.geometry, bp, b, n, sg["par"], sg["cov"], sg["q"])
+    torch.cuda.synchronize()
+    g = {k: host(v) for k, v in out.items()}
+    so = oracle.seed(w.geometry, H, n)
+    lst = np.concatenate([np.arange(0, n, 97)[:200], np.arange(n - 40, n)]) if full else np.arange(n)
+    o = oracle.build(w.geometry, w.cuts, ev.layer, ev.xyz, ev.cov, so["par"], so["cov"], so["q"], n,
+                     seed_list=lst, state=1)
+    r = compare(g, o, lst.size, cols_g=lst, ctx=f"hybrid {'full' if full else 'small'}", check_params=False)
+    dec = decidable(o)[:lst.size]
+    same = np.all(g["hits"][:, lst] == o["hits"], axis=0) & (g["nhits"][lst] == o["nhits"])
+    conv = dec & same & (o["chi2"] <= 100 * np.maximum(2 * o["nhits"], 1))
+    sel = np.where(conv)[0]
+    ep, ek, ea = _hybrid_param_errors(g, o, lst, sel)
+    assert ep.max(initial=0) <= 1e-4 and ek.max(initial=0) <= 1e-4 and ea.max(initial=0) <= 1e-4, \
+        (ep.max(), ek.max(), ea.max())
+    print(f"build hybrid {'full' if full else 'small'} f64", r, f"params on {sel.size}: pos {ep.max(initial=0):.2g} "
+          f"q/pT {ek.max(initial=0):.2g} angles {ea.max(initial=0):.2g}")
+
+
+def test_hybrid_state_build_efficiency(kf):
+    """On the full build event the hybrid state keeps the true hits of more
+    seeds than the Cartesian state (seeds of the wrong charge recover)."""
+    w = presets.build()
+    ev = datagen.generate(w.geometry, w.gen, 0, w.n_tracks, truth=True)
+    n = ev.n_tracks
+    gc, sg = gpu_build_event(kf, w, ev, kf.ARITH_F64)
+    xyz = ev.xyz.astype(np.float32)
+    b = kf.hit_bin(w.geometry, w.cuts.n_phi_bins, w.cuts.n_z_bins, to_dev(ev.layer), to_dev(xyz),
+                   to_dev(ev.cov.astype(np.float32)))
+    bp = kf.build_params(w.cuts, arith=kf.ARITH_F64, state=kf.STATE_HYBRID)
+    gh = {k: host(v) for k, v in kf.kf_build(w.geometry, bp, b, n, sg["par"], sg["cov"], sg["q"]).items()}
+    F = w.cuts.first_layer
+    true = ev.trk_hits[F:, :n]
+    ec = ((gc["hits"][:, :n] == true).sum(axis=0) / true.shape[0] >= 0.75).mean()
+    eh = ((gh["hits"][:, :n] == true).sum(axis=0) / true.shape[0] >= 0.75).mean()
+    print(f"build efficiency, {n} seeds: Cartesian {ec:.4f}, hybrid {eh:.4f}")
+    assert eh >= ec
