@@ -336,8 +336,8 @@ int kf_batch_plan_create(const kf_geometry* g, const kf_build_params* bp, int32_
  * the built tracks): what kf_batch_plan_create captures, then
  * kf_gather_hits of the built lists (xyz, cov and event_offsets as given to
  * hit_bin, seed_event from `extra`, first_layer from `bp`) into
- * fit->fit_hits / fit->hole_mask, then kf_fit from the same seeds in
- * fit->arith.  fit must not be NULL; every pointer in it is a device pointer
+ * fit->fit_hits / fit->hole_mask, then kf_fit (kf_fit_hybrid when
+ * bp->state is 1) from the same seeds in fit->arith.  fit must not be NULL; every pointer in it is a device pointer
  * the caller owns.  Launch and destroy as a batch plan.
  */
 typedef struct {

@@ -66,12 +66,13 @@ def extra_for(b: Batch, timestamps=True) -> kf.BuildExtra:
 
 
 def plan(b: Batch, cap=None, lanes=0, blocks=0, arith=kf.ARITH_F32, window_mode=0, mlp_block=None, refine=0,
-         fit=False):
+         fit=False, state=kf.STATE_CARTESIAN):
     """The batch's graph: binning and build, and with fit=True also the
-    gather and the final fit of the built lists (in the same arithmetic)."""
+    gather and the final fit of the built lists (in the same arithmetic and
+    state)."""
     cuts = b.w.cuts
     bp = kf.build_params(cuts, cap=cap, lanes_per_block=lanes, persistent_blocks=blocks, arith=arith,
-                         window_mode=window_mode, mlp_block=mlp_block, phi_refine=refine)
+                         window_mode=window_mode, mlp_block=mlp_block, phi_refine=refine, state=state)
     return kf.BatchPlan(b.w.geometry, bp, b.layer, b.xyz, b.cov, b.hoff, cuts.n_phi_bins, cuts.n_z_bins,
                         b.eb.n_seeds, b.seeds["par"], b.seeds["cov"], b.seeds["q"], extra=extra_for(b),
                         fit_arith=arith if fit else None)

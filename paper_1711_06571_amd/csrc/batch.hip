@@ -42,9 +42,10 @@ int plan_create(const kf_geometry* g, const kf_build_params* bp, int32_t n_event
   if (rc == KF_OK && fit)
     rc = kf_gather_hits(g->n_layers, bp->first_layer, n_seeds, ld, out_hits, extra ? extra->seed_event : nullptr,
                         n_events, event_offsets, n_hits, xyz, cov, fit->fit_hits, fit->hole_mask, stream);
-  if (rc == KF_OK && fit)
-    rc = kf_fit(g, n_seeds, ld, bp->first_layer, fit->fit_hits, fit->hole_mask, seed_par, seed_cov, q, fit->out_par,
-                fit->out_cov, fit->out_chi2, fit->out_ndof, fit->out_status, fit->arith, stream);
+  if (rc == KF_OK && fit)  // the fit in the state of the build
+    rc = (bp->state == 1 ? kf_fit_hybrid : kf_fit)(g, n_seeds, ld, bp->first_layer, fit->fit_hits, fit->hole_mask,
+                                                   seed_par, seed_cov, q, fit->out_par, fit->out_cov, fit->out_chi2,
+                                                   fit->out_ndof, fit->out_status, fit->arith, stream);
   hipGraph_t graph = nullptr;
   const int rc_end = kf_check(hipStreamEndCapture(s, &graph));
   if (rc != KF_OK || rc_end != KF_OK) {
