@@ -53,24 +53,28 @@ def test_graph_replays_equal_eager(bt):
     p.close()
 
 
-def test_step_graph_replays_equal_eager(bt):
-    """Binning, build, gather and fit in one graph: every replay equals the
-    eager sequence of the same calls bit for bit."""
+@pytest.mark.parametrize("hybrid", [False, True])
+def test_step_graph_replays_equal_eager(bt, hybrid):
+    """Binning, build, gather and fit in one graph (Cartesian or hybrid
+    state): every replay equals the eager sequence of the same calls bit for
+    bit."""
     batch, kf, b = bt
     w = b.w
     L, F = w.geometry.n_layers, w.cuts.first_layer
     n = b.eb.n_seeds
+    state = kf.STATE_HYBRID if hybrid else kf.STATE_CARTESIAN
     binned = kf.hit_bin(w.geometry, 63, 16, b.layer, b.xyz, b.cov, event_offsets=b.hoff)
-    bp = kf.build_params(w.cuts, arith=kf.ARITH_F64)
+    bp = kf.build_params(w.cuts, arith=kf.ARITH_F64, state=state)
     out = kf.kf_build(w.geometry, bp, binned, n, b.seeds["par"], b.seeds["cov"], b.seeds["q"],
                       extra=batch.extra_for(b, timestamps=False))
     fh, hole = kf.kf_gather_hits(L, F, n, out["hits"], b.xyz, b.cov, seed_event=b.sev, event_offsets=b.hoff)
-    ref = kf.kf_fit(w.geometry, n, F, fh, b.seeds["par"], b.seeds["cov"], b.seeds["q"], hole_mask=hole,
-                    arith=kf.ARITH_F64)
+    fit = kf.kf_fit_hybrid if hybrid else kf.kf_fit
+    ref = fit(w.geometry, n, F, fh, b.seeds["par"], b.seeds["cov"], b.seeds["q"], hole_mask=hole,
+              arith=kf.ARITH_F64)
     torch.cuda.synchronize()
     ref = {k: host(v) for k, v in ref.items()}
     ref_hits = host(out["hits"])
-    p = batch.plan(b, arith=kf.ARITH_F64, fit=True)
+    p = batch.plan(b, arith=kf.ARITH_F64, fit=True, state=state)
     for rep in range(3):
         for k in p.fit:
             p.fit[k].zero_()
@@ -83,7 +87,7 @@ def test_step_graph_replays_equal_eager(bt):
         kf.hit_bin(w.geometry, 63, 16, b.layer, b.xyz, b.cov, event_offsets=b.hoff)
         torch.cuda.synchronize()
     ms = batch.run(p, reps=3)
-    print(f"step graph, 8 events, {n} seeds: {ms:.3f} ms per launch")
+    print(f"step graph ({'hybrid' if hybrid else 'Cartesian'}), 8 events, {n} seeds: {ms:.3f} ms per launch")
     p.close()
 
 
