@@ -319,7 +319,7 @@ def main():
     flop_of = {"kf_build": build_flop, "kf_fit": fit_flop}
     if dom in flop_of:
         ach = flop_of[dom] / (stage_ms[dom] * 1e-3) / 1e12
-        kname = f"build_kernel<{'double' if args.arith == 'f64' else 'float'}, false>" if dom == "kf_build" else dom
+        kname = f"build_kernel<{'double' if args.arith == 'f64' else 'float'}, false, false>" if dom == "kf_build" else dom
         roof = {"bound": "alu", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(ach / peak, 4), "traffic": measured_traffic(kname), "kernel": dom,
                 "avg_ms": stage_ms[dom]}
