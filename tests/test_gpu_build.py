@@ -200,7 +200,8 @@ def test_build_batch_of_events(kf):
         print(f"event {e}", compare(g, o, lst.size, cols_g=s0 + lst, ctx=f"event {e}"))
 
 
-def test_build_edge_cases(kf):
+@pytest.mark.parametrize("state", [0, 1])
+def test_build_edge_cases(kf, state):
     w = presets.build()
     g = w.geometry
     ev = datagen.generate(g, w.gen, 15, 64)
@@ -210,7 +211,7 @@ def test_build_edge_cases(kf):
     sg = kf.kf_seed(g, 64, to_dev(H))
     par = sg["par"].clone()
     par[0, 5] = float("nan")  # a non-finite seed is returned as given, flagged
-    bp = kf.build_params(w.cuts)
+    bp = kf.build_params(w.cuts, state=state)
     out = kf.kf_build(g, bp, b, 64, par, sg["cov"], sg["q"])
     torch.cuda.synchronize()
     st = host(out["status"])
@@ -218,9 +219,17 @@ def test_build_edge_cases(kf):
     assert np.all(host(out["hits"])[:, 5] == -1)
     # no seeds: nothing to do
     kf.kf_build(g, bp, b, 0, par, sg["cov"], sg["q"])
-    # a cap the kernels do not implement
+    # a cap the kernels do not implement; a state that does not exist; the
+    # learned window (Cartesian features) in the hybrid state
     with pytest.raises(kf.KFError):
-        kf.kf_build(g, kf.build_params(w.cuts, cap=9), b, 64, par, sg["cov"], sg["q"])
+        kf.kf_build(g, kf.build_params(w.cuts, cap=9, state=state), b, 64, par, sg["cov"], sg["q"])
+    with pytest.raises(kf.KFError):
+        kf.kf_build(g, kf.build_params(w.cuts, state=2), b, 64, par, sg["cov"], sg["q"])
+    if state == 1:
+        blk = torch.zeros(int(kf.lib().kf_mlp_block_bytes()) // 4, dtype=torch.float32, device="cuda:0")
+        with pytest.raises(kf.KFError):
+            kf.kf_build(g, kf.build_params(w.cuts, window_mode=1, mlp_block=blk, state=1), b, 64, par,
+                        sg["cov"], sg["q"])
     # an event with no hits at all: every seed ends on holes and stops
     empty = kf.hit_bin(g, 63, 16, torch.zeros(0, dtype=torch.int32, device="cuda:0"),
                        torch.zeros((3, 0), device="cuda:0"), torch.zeros((6, 0), device="cuda:0"))

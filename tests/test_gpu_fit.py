@@ -140,17 +140,26 @@ def test_fit_status_paths(kf):
     assert_fit_parity_converged(gh, o, n, "status paths")
 
 
-def test_fit_empty_and_invalid(kf):
+@pytest.mark.parametrize("hybrid", [False, True])
+def test_fit_empty_and_invalid(kf, hybrid):
     w = presets.fit_small()
+    fit = kf.kf_fit_hybrid if hybrid else kf.kf_fit
     H = torch.zeros((10, 9, 64), dtype=torch.float32, device=DEV)
     sp = torch.zeros((6, 64), device=DEV)
     sc = torch.zeros((21, 64), device=DEV)
     q = torch.ones(64, dtype=torch.int8, device=DEV)
-    kf.kf_fit(w.geometry, 0, 3, H, sp, sc, q)  # n = 0: nothing to do
+    fit(w.geometry, 0, 3, H, sp, sc, q)  # n = 0: nothing to do
     with pytest.raises(kf.KFError):
-        kf.kf_fit(w.geometry, -1, 3, H, sp, sc, q)
+        fit(w.geometry, -1, 3, H, sp, sc, q)
     with pytest.raises(kf.KFError):
-        kf.kf_fit(w.geometry, 10, 11, H, sp, sc, q)
+        fit(w.geometry, 10, 11, H, sp, sc, q)
     bad = w.geometry.replace(bz=0.0)
     with pytest.raises(kf.KFError):
-        kf.kf_fit(bad, 10, 3, H, sp, sc, q)
+        fit(bad, 10, 3, H, sp, sc, q)
+    with pytest.raises(kf.KFError):
+        fit(w.geometry, 10, 3, H, sp, sc, q, arith=7)
+    if hybrid:
+        # a zero seed (no momentum) has no hybrid state: flagged, not crashed
+        out = fit(w.geometry, 10, 3, H, sp, sc, q)
+        torch.cuda.synchronize()
+        assert np.all(host(out["status"])[:10] & kf.TRK_NONFINITE)
