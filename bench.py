@@ -94,7 +94,8 @@ def learned_vs_plain(ariths, log):
     (the build workload's generator, other events): rows dumped by the plain
     build of event 0, gates at a quantile of their plain widths, GPU training
     on the gated rows, kappa calibrated on event 1 to keep the plain
-    efficiency within 0.1 %, comparison on events 2..33, in each arithmetic."""
+    efficiency within 0.1 %, comparison on events 2..33, in each arithmetic
+    and in both states (the network reads the Cartesian prediction)."""
     import torch
     from paper_1711_06571_amd import kftrack as kf
     from paper_1711_06571_amd import presets, window
@@ -112,18 +113,18 @@ def learned_vs_plain(ariths, log):
            "gate_quantile": window.GATE_QUANTILE, "gates_cm": [round(v, 5) for v in t.gates],
            "rows_gated": int(t.rows_used), "train_seconds": round(t.seconds, 3), "loss_initial": round(t.loss0, 5),
            "loss_final": round(t.losses[-1], 5)}
-    for arith in ariths:
-        name = "f64" if arith == kf.ARITH_F64 else "f32"
-        out_p, _ = window.build(w, val, arith=arith)
+    for arith, state in [(a, kf.STATE_CARTESIAN) for a in ariths] + [(a, kf.STATE_HYBRID) for a in ariths]:
+        name = ("f64" if arith == kf.ARITH_F64 else "f32") + ("_hybrid" if state == kf.STATE_HYBRID else "")
+        out_p, _ = window.build(w, val, arith=arith, state=state)
         eff_val = window.efficiency(w, val, out_p)
-        kap, trace = window.calibrate(w, t, val, eff_val, target=0.001, arith=arith)
+        kap, trace = window.calibrate(w, t, val, eff_val, target=0.001, arith=arith, state=state)
         kf.mlp_set_header(t.block, kappa=kap)
-        outp, cp = window.build(w, test, counters=True, arith=arith)
-        outl, cl = window.build(w, test, window_mode=1, block=t.block, counters=True, arith=arith)
+        outp, cp = window.build(w, test, counters=True, arith=arith, state=state)
+        outl, cl = window.build(w, test, window_mode=1, block=t.block, counters=True, arith=arith, state=state)
         torch.cuda.synchronize()
         ep, el = window.efficiency(w, test, outp), window.efficiency(w, test, outl)
-        tp = window.time_build(w, test, 0, arith=arith)
-        tl = window.time_build(w, test, 1, t.block, arith=arith)
+        tp = window.time_build(w, test, 0, arith=arith, state=state)
+        tl = window.time_build(w, test, 1, t.block, arith=arith, state=state)
         cp, cl = cp.cpu().numpy(), cl.cpu().numpy()
         log(f"learned {name}: kappa {kap}, eff plain {ep:.4f} learned {el:.4f}, ms {tp:.3f} vs {tl:.3f}")
         res[name] = {

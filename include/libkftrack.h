@@ -192,7 +192,7 @@ typedef struct {
   int32_t phi_refine;  /* sub-bins per phi bin of the fine index the hit search uses, 1..64 (0: 32) */
   int32_t state;       /* 0 Cartesian; 1 hybrid (x, y, z, q/pT, phi, theta; section 3): seeds are
                           converted on entry, the charge follows the sign of q/pT, out_par/out_cov
-                          are hybrid; not with window_mode 1 (KF_E_UNSUPPORTED) */
+                          are hybrid; the learned window still reads the Cartesian prediction */
 } kf_build_params;
 
 /* Optional build inputs and outputs (all fields may be NULL / 0). */

@@ -955,9 +955,20 @@ int orc_build(const orc_geometry* g, const orc_build_params* bp, int n_hits, con
           mwin = minf(mwin, gm);
         }
         if (gated) {
-          double feat[27], wl[2], pu[21];
-          for (int k = 0; k < 6; ++k) feat[k] = Xp[k];
-          upper_from_sym(Pp, pu);
+          /* features: the Cartesian prediction and covariance (a hybrid
+             prediction is converted: state, and covariance through
+             d(X)/d(Y)) */
+          double feat[27], wl[2], pu[21], Xf[6], Pf[36];
+          memcpy(Xf, Xp, sizeof(Xf));
+          memcpy(Pf, Pp, sizeof(Pf));
+          if (bp->state == 1) {
+            double A[36];
+            orc_cart_from_hyb(Xp, Xf);
+            orc_hyb_jac_cart_from_hyb(Xp, A);
+            congruence(A, Pp, Pf);
+          }
+          for (int k = 0; k < 6; ++k) feat[k] = Xf[k];
+          upper_from_sym(Pf, pu);
           for (int k = 0; k < 21; ++k) feat[6 + k] = pu[k];
           orc_mlp_forward(bp->mlp, feat, wl);
           double kap = bp->mlp[MLP_OFF_KAPPA];

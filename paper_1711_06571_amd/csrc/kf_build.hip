@@ -705,8 +705,20 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
         // asm: converted inside the row writes instead, the FP64 build's
         // register allocation spilled twice as much
         float feat[27];
+        if constexpr (HYB) {
+          // the network reads the Cartesian prediction: convert the hybrid
+          // one (state, and covariance through d(X)/d(Y))
+          T Xc[6], Am[9], Pc[21];
+          (void)cart_from_hyb(Xp, Xc, Am);
 #pragma unroll
-        for (int k = 0; k < 27; ++k) feat[k] = (float)(k < 6 ? Xp[k] : Pp[k - 6]);
+          for (int k = 0; k < 21; ++k) Pc[k] = Pp[k];
+          congruence_mom(Pc, Am);
+#pragma unroll
+          for (int k = 0; k < 27; ++k) feat[k] = (float)(k < 6 ? Xc[k] : Pc[k - 6]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 27; ++k) feat[k] = (float)(k < 6 ? Xp[k] : Pp[k - 6]);
+        }
 #pragma unroll
         for (int k = 0; k < 27; ++k) asm volatile("" : "+v"(feat[k]));
         const uint64_t act = kfmlp::wave_stage(A.mlp, mlp_buf, [&](int k) { return feat[k]; }, gated);
@@ -1022,7 +1034,6 @@ extern "C" int kf_build(const kf_geometry* g, const kf_build_params* bp, const k
   if (bp->window_mode != 0 && bp->window_mode != 1) return KF_E_INVALID_ARG;
   if (bp->window_mode == 1 && !bp->mlp) return KF_E_INVALID_ARG;
   if (bp->state != 0 && bp->state != 1) return KF_E_INVALID_ARG;
-  if (bp->state == 1 && bp->window_mode == 1) return KF_E_UNSUPPORTED;  // the network reads Cartesian features
   if (hits->n_layers != g->n_layers || hits->n_events < 1 || hits->n_phi < 1 || hits->n_z < 1 || hits->n_hits < 0)
     return KF_E_INVALID_ARG;
   (void)kMaxOrig;  // hit indices are event-local: each event must hold fewer than 2^24 - 1 hits
@@ -1084,10 +1095,14 @@ extern "C" int kf_build(const kf_geometry* g, const kf_build_params* bp, const k
     if (int rc = kf_check_launch()) return rc;
   }
   if (bp->arith == KF_ARITH_F64)
-    return bp->state == 1         ? launch<double, false, true>(A, lanes, bp->persistent_blocks, hist_waves, s)
-           : bp->window_mode == 1 ? launch<double, true, false>(A, lanes, bp->persistent_blocks, hist_waves, s)
-                                  : launch<double, false, false>(A, lanes, bp->persistent_blocks, hist_waves, s);
-  return bp->state == 1         ? launch<float, false, true>(A, lanes, bp->persistent_blocks, hist_waves, s)
-         : bp->window_mode == 1 ? launch<float, true, false>(A, lanes, bp->persistent_blocks, hist_waves, s)
-                                : launch<float, false, false>(A, lanes, bp->persistent_blocks, hist_waves, s);
+    return bp->state == 1
+               ? (bp->window_mode == 1 ? launch<double, true, true>(A, lanes, bp->persistent_blocks, hist_waves, s)
+                                       : launch<double, false, true>(A, lanes, bp->persistent_blocks, hist_waves, s))
+               : (bp->window_mode == 1 ? launch<double, true, false>(A, lanes, bp->persistent_blocks, hist_waves, s)
+                                       : launch<double, false, false>(A, lanes, bp->persistent_blocks, hist_waves, s));
+  return bp->state == 1
+             ? (bp->window_mode == 1 ? launch<float, true, true>(A, lanes, bp->persistent_blocks, hist_waves, s)
+                                     : launch<float, false, true>(A, lanes, bp->persistent_blocks, hist_waves, s))
+             : (bp->window_mode == 1 ? launch<float, true, false>(A, lanes, bp->persistent_blocks, hist_waves, s)
+                                     : launch<float, false, false>(A, lanes, bp->persistent_blocks, hist_waves, s));
 }

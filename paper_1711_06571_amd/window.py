@@ -62,8 +62,9 @@ def load_events(w, events, n_tracks=None) -> EventOnGPU:
     return EventOnGPU(eb, binned, seeds, xyz, cov, hoff, T(eb.seed_event))
 
 
-def build(w, e: EventOnGPU, window_mode=0, block=None, counters=False, arith=kf.ARITH_F32):
-    bp = kf.build_params(w.cuts, window_mode=window_mode, mlp_block=block, arith=arith)
+def build(w, e: EventOnGPU, window_mode=0, block=None, counters=False, arith=kf.ARITH_F32,
+          state=kf.STATE_CARTESIAN):
+    bp = kf.build_params(w.cuts, window_mode=window_mode, mlp_block=block, arith=arith, state=state)
     ex = kf.BuildExtra()
     ex.seed_event = e.sev.data_ptr()
     cnt = None
@@ -230,14 +231,15 @@ def train_gated(w, rows: np.ndarray, quantile=GATE_QUANTILE, epochs=4, **kw) -> 
     return t
 
 
-def calibrate(w, t: Trained, val: EventOnGPU, eff_plain: float, target=0.001, kappas=None, arith=kf.ARITH_F32):
+def calibrate(w, t: Trained, val: EventOnGPU, eff_plain: float, target=0.001, kappas=None, arith=kf.ARITH_F32,
+              state=kf.STATE_CARTESIAN):
     """Smallest kappa whose efficiency on the validation events is within
     `target` of the plain window's."""
     kappas = kappas or KAPPAS
     res = []
     for kap in kappas:
         kf.mlp_set_header(t.block, kappa=kap)
-        out, _ = build(w, val, window_mode=1, block=t.block, arith=arith)
+        out, _ = build(w, val, window_mode=1, block=t.block, arith=arith, state=state)
         torch.cuda.synchronize()
         eff = efficiency(w, val, out)
         res.append((kap, eff))
@@ -246,14 +248,14 @@ def calibrate(w, t: Trained, val: EventOnGPU, eff_plain: float, target=0.001, ka
     return kappas[-1], res
 
 
-def time_build(w, e: EventOnGPU, window_mode, block=None, reps=5, arith=kf.ARITH_F32):
-    build(w, e, window_mode, block, arith=arith)
+def time_build(w, e: EventOnGPU, window_mode, block=None, reps=5, arith=kf.ARITH_F32, state=kf.STATE_CARTESIAN):
+    build(w, e, window_mode, block, arith=arith, state=state)
     torch.cuda.synchronize()
     ts = []
     for _ in range(reps):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
-        build(w, e, window_mode, block, arith=arith)
+        build(w, e, window_mode, block, arith=arith, state=state)
         b.record()
         torch.cuda.synchronize()
         ts.append(a.elapsed_time(b))

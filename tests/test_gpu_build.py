@@ -219,17 +219,11 @@ def test_build_edge_cases(kf, state):
     assert np.all(host(out["hits"])[:, 5] == -1)
     # no seeds: nothing to do
     kf.kf_build(g, bp, b, 0, par, sg["cov"], sg["q"])
-    # a cap the kernels do not implement; a state that does not exist; the
-    # learned window (Cartesian features) in the hybrid state
+    # a cap the kernels do not implement; a state that does not exist
     with pytest.raises(kf.KFError):
         kf.kf_build(g, kf.build_params(w.cuts, cap=9, state=state), b, 64, par, sg["cov"], sg["q"])
     with pytest.raises(kf.KFError):
         kf.kf_build(g, kf.build_params(w.cuts, state=2), b, 64, par, sg["cov"], sg["q"])
-    if state == 1:
-        blk = torch.zeros(int(kf.lib().kf_mlp_block_bytes()) // 4, dtype=torch.float32, device="cuda:0")
-        with pytest.raises(kf.KFError):
-            kf.kf_build(g, kf.build_params(w.cuts, window_mode=1, mlp_block=blk, state=1), b, 64, par,
-                        sg["cov"], sg["q"])
     # an event with no hits at all: every seed ends on holes and stops
     empty = kf.hit_bin(g, 63, 16, torch.zeros(0, dtype=torch.int32, device="cuda:0"),
                        torch.zeros((3, 0), device="cuda:0"), torch.zeros((6, 0), device="cuda:0"))

@@ -54,10 +54,12 @@ def test_training_reduces_loss(env):
     assert np.all(r[:, 27] >= 0) and np.all(r[:, 28] >= 0)
 
 
-@pytest.mark.parametrize("gate_q", [0.0, 0.6])
-def test_learned_build_matches_oracle(env, gate_q):
+@pytest.mark.parametrize("gate_q,state", [(0.0, 0), (0.6, 0), (0.6, 1)])
+def test_learned_build_matches_oracle(env, gate_q, state):
     """Gate quantile 0 consults the network for every candidate; 0.6 for the
-    wide-window ones only (scattered lanes of a wave, compacted into tiles)."""
+    wide-window ones only (scattered lanes of a wave, compacted into tiles);
+    state 1: the hybrid state, whose prediction the network reads converted
+    to Cartesian."""
     kf, window, w, t = env["kf"], env["window"], env["w"], env["t"]
     gr, gz = window.gates(w, env["rows"], gate_q)
     kf.mlp_set_header(t.block, kappa=1.5, gate_rphi=gr, gate_z=gz)
@@ -67,33 +69,33 @@ def test_learned_build_matches_oracle(env, gate_q):
     b = kf.hit_bin(w.geometry, 63, 16, to_dev(ev.layer), to_dev(xyz), to_dev(ev.cov.astype(np.float32)))
     H = datagen.track_hits(ev)
     sg = kf.kf_seed(w.geometry, n, to_dev(H))
-    bp = kf.build_params(w.cuts, window_mode=1, mlp_block=t.block, arith=kf.ARITH_F64)
+    bp = kf.build_params(w.cuts, window_mode=1, mlp_block=t.block, arith=kf.ARITH_F64, state=state)
     out = kf.kf_build(w.geometry, bp, b, n, sg["par"], sg["cov"], sg["q"])
     torch.cuda.synchronize()
     g = {k: host(v) for k, v in out.items()}
     so = oracle.seed(w.geometry, H, n)
     o = oracle.build(w.geometry, w.cuts, ev.layer, ev.xyz, ev.cov, so["par"], so["cov"], so["q"], n,
-                     window_mode=1, mlp_blob=oracle_blob(kf, t, 1.5))
+                     window_mode=1, mlp_blob=oracle_blob(kf, t, 1.5), state=state)
     m = o["margin"]
     # learned widths carry BF16 rounding of activations: window edges further
     # than 1e-3 cm (a tenth of the arc resolution) decide
     dec = (m[0] > 1e-3) & (m[1] > 1e-3) & (m[2] > 1e-3)
     same = np.all(g["hits"][:, :n] == o["hits"], axis=0) & (g["nhits"][:n] == o["nhits"])
-    print(f"learned build (gates {gr:.4f}, {gz:.4f}): undecidable {1 - dec.mean():.4f}, "
+    print(f"learned build (state {state}, gates {gr:.4f}, {gz:.4f}): undecidable {1 - dec.mean():.4f}, "
           f"identical {same.mean():.4f}")
     assert same[dec].all(), np.where(dec & ~same)[0][:10]
 
 
-@pytest.mark.parametrize("arith", ["f32", "f64"])
-def test_closed_gates_build_equals_plain(env, arith):
+@pytest.mark.parametrize("arith,state", [("f32", 0), ("f64", 0), ("f32", 1), ("f64", 1)])
+def test_closed_gates_build_equals_plain(env, arith, state):
     """Gates above every plain window: the learned kernel never runs the
-    network and must return the plain build exactly."""
+    network and must return the plain build exactly (in either state)."""
     kf, window, w, t = env["kf"], env["window"], env["w"], env["t"]
     a = kf.ARITH_F32 if arith == "f32" else kf.ARITH_F64
     ev = window.load_events(w, [3])
     kf.mlp_set_header(t.block, kappa=1.0, gate_rphi=1e30, gate_z=1e30)
-    outp, _ = window.build(w, ev, arith=a)
-    outl, _ = window.build(w, ev, window_mode=1, block=t.block, arith=a)
+    outp, _ = window.build(w, ev, arith=a, state=state)
+    outl, _ = window.build(w, ev, window_mode=1, block=t.block, arith=a, state=state)
     torch.cuda.synchronize()
     n = ev.eb.n_seeds
     for k in outp:

@@ -215,31 +215,33 @@ def _window_network(seed, kappa, gates):
     return mlp.blob(p, kappa=kappa, floor_rphi=0.0, floor_z=0.0, gate_rphi=gates[0], gate_z=gates[1])
 
 
-def test_learned_window_gates_closed_is_plain():
+@pytest.mark.parametrize("state", [0, 1])
+def test_learned_window_gates_closed_is_plain(state):
     """Gates no plain window exceeds: the network is never consulted, so the
-    learned build is the plain build, bit for bit."""
+    learned build is the plain build, bit for bit (in either state)."""
     w = presets.build()
     ev, sd = _event_and_seeds(w.geometry, w.gen, 120, event=5)
     n = ev.n_tracks
     args = (w.geometry, w.cuts, ev.layer, ev.xyz, ev.cov, sd["par"], sd["cov"], sd["q"], n)
-    plain = oracle.build(*args)
-    learned = oracle.build(*args, window_mode=1, mlp_blob=_window_network(1, 1.0, (1e30, 1e30)))
+    plain = oracle.build(*args, state=state)
+    learned = oracle.build(*args, window_mode=1, mlp_blob=_window_network(1, 1.0, (1e30, 1e30)), state=state)
     for k in ("hits", "nhits", "status", "chi2", "par", "cov"):
         assert np.array_equal(learned[k], plain[k]), k
 
 
-def test_learned_window_everything_equals_plain_everything():
+@pytest.mark.parametrize("state", [0, 1])
+def test_learned_window_everything_equals_plain_everything(state):
     """Gates open and kappa huge: every learned window covers the whole
     layer, as does a plain window with a huge nsigma; both builds then test
-    every hit of every layer and must agree exactly."""
+    every hit of every layer and must agree exactly (in either state)."""
     w = presets.build()
     ev, sd = _event_and_seeds(w.geometry, w.gen, 60, event=6)
     n = ev.n_tracks
     args = (w.geometry, ev.layer, ev.xyz, ev.cov, sd["par"], sd["cov"], sd["q"], n)
     wide = dataclasses.replace(w.cuts, nsigma=np.float32(1e7))
-    plain = oracle.build(args[0], wide, *args[1:])
+    plain = oracle.build(args[0], wide, *args[1:], state=state)
     learned = oracle.build(args[0], w.cuts, *args[1:], window_mode=1,
-                           mlp_blob=_window_network(2, 1e7, (0.0, 0.0)))
+                           mlp_blob=_window_network(2, 1e7, (0.0, 0.0)), state=state)
     for k in ("hits", "nhits", "status", "chi2", "par", "cov"):
         assert np.array_equal(learned[k], plain[k]), k
     # and the search really was exhaustive: noise hits were tested
