@@ -95,7 +95,9 @@ def learned_vs_plain(ariths, log):
     build of event 0, gates at a quantile of their plain widths, GPU training
     on the gated rows, kappa calibrated on event 1 to keep the plain
     efficiency within 0.1 %, comparison on events 2..33, in each arithmetic
-    and in both states (the network reads the Cartesian prediction)."""
+    and in both states (the network reads the Cartesian prediction; in the
+    hybrid state it is trained on rows of the hybrid-state build, whose plain
+    windows are narrower)."""
     import torch
     from paper_1711_06571_amd import kftrack as kf
     from paper_1711_06571_amd import presets, window
@@ -104,6 +106,8 @@ def learned_vs_plain(ariths, log):
     tr = window.load_events(w, [0])
     rows = window.dump_rows(w, tr)
     t = window.train_gated(w, rows, epochs=4)
+    rows_h = window.dump_rows(w, tr, state=kf.STATE_HYBRID)
+    t_h = window.train_gated(w, rows_h, epochs=4)
     val = window.load_events(w, [1])
     # 32 events (640 k seeds, ~30 seed groups per wave): with only a few groups
     # per wave the build time is the slowest group's, not the throughput
@@ -112,19 +116,23 @@ def learned_vs_plain(ariths, log):
     res = {"workload": f"{w.name}: 32 test events x {n // 32} tracks + noise", "train_rows": int(rows.shape[0]),
            "gate_quantile": window.GATE_QUANTILE, "gates_cm": [round(v, 5) for v in t.gates],
            "rows_gated": int(t.rows_used), "train_seconds": round(t.seconds, 3), "loss_initial": round(t.loss0, 5),
-           "loss_final": round(t.losses[-1], 5)}
+           "loss_final": round(t.losses[-1], 5),
+           "hybrid_state_network": {"train_rows": int(rows_h.shape[0]), "gates_cm": [round(v, 5) for v in t_h.gates],
+                                    "rows_gated": int(t_h.rows_used), "loss_initial": round(t_h.loss0, 5),
+                                    "loss_final": round(t_h.losses[-1], 5)}}
     for arith, state in [(a, kf.STATE_CARTESIAN) for a in ariths] + [(a, kf.STATE_HYBRID) for a in ariths]:
         name = ("f64" if arith == kf.ARITH_F64 else "f32") + ("_hybrid" if state == kf.STATE_HYBRID else "")
+        net = t_h if state == kf.STATE_HYBRID else t
         out_p, _ = window.build(w, val, arith=arith, state=state)
         eff_val = window.efficiency(w, val, out_p)
-        kap, trace = window.calibrate(w, t, val, eff_val, target=0.001, arith=arith, state=state)
-        kf.mlp_set_header(t.block, kappa=kap)
+        kap, trace = window.calibrate(w, net, val, eff_val, target=0.001, arith=arith, state=state)
+        kf.mlp_set_header(net.block, kappa=kap)
         outp, cp = window.build(w, test, counters=True, arith=arith, state=state)
-        outl, cl = window.build(w, test, window_mode=1, block=t.block, counters=True, arith=arith, state=state)
+        outl, cl = window.build(w, test, window_mode=1, block=net.block, counters=True, arith=arith, state=state)
         torch.cuda.synchronize()
         ep, el = window.efficiency(w, test, outp), window.efficiency(w, test, outl)
         tp = window.time_build(w, test, 0, arith=arith, state=state)
-        tl = window.time_build(w, test, 1, t.block, arith=arith, state=state)
+        tl = window.time_build(w, test, 1, net.block, arith=arith, state=state)
         cp, cl = cp.cpu().numpy(), cl.cpu().numpy()
         log(f"learned {name}: kappa {kap}, eff plain {ep:.4f} learned {el:.4f}, ms {tp:.3f} vs {tl:.3f}")
         res[name] = {

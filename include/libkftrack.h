@@ -204,7 +204,8 @@ typedef struct {
   int64_t* start_tick;        /* [1] earliest wall-clock tick seen by any wave of the launch */
   /* training-data dump: for every candidate whose hits so far are all true
      (or holes) and whose seed has a true hit on the layer, the 27 features
-     (predicted state and covariance) and the 2 labels (|arc| and |dz| to the
+     (predicted state and covariance, Cartesian in either state: what the
+     learned window reads) and the 2 labels (|arc| and |dz| to the
      true hit) as 29 floats per row */
   const int32_t* true_hits;   /* [n_layers][ld] true original hit index per seed and layer */
   const float* true_xyz;      /* [n_layers][3][ld] position of that true hit */

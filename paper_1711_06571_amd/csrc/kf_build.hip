@@ -682,8 +682,18 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
             const int row = atomicAdd(A.dump_count, 1);
             if (row < A.dump_capacity) {
               float* d = A.dump + (size_t)row * KFMLP_DUMP_ROW;
-              for (int k = 0; k < 6; ++k) d[k] = (float)Xp[k];
-              for (int k = 0; k < 21; ++k) d[6 + k] = (float)Pp[k];
+              if constexpr (HYB) {
+                // the features the network reads: the Cartesian prediction
+                T Xc[6], Am[9], Pc[21];
+                (void)cart_from_hyb(Xp, Xc, Am);
+                for (int k = 0; k < 21; ++k) Pc[k] = Pp[k];
+                congruence_mom(Pc, Am);
+                for (int k = 0; k < 6; ++k) d[k] = (float)Xc[k];
+                for (int k = 0; k < 21; ++k) d[6 + k] = (float)Pc[k];
+              } else {
+                for (int k = 0; k < 6; ++k) d[k] = (float)Xp[k];
+                for (int k = 0; k < 21; ++k) d[6 + k] = (float)Pp[k];
+              }
               const T mx = (T)A.true_xyz[((size_t)l * 3 + 0) * A.ld + seed];
               const T my = (T)A.true_xyz[((size_t)l * 3 + 1) * A.ld + seed];
               const T mz = (T)A.true_xyz[((size_t)l * 3 + 2) * A.ld + seed];

@@ -84,7 +84,9 @@ def efficiency(w, e: EventOnGPU, out) -> float:
     return float(np.mean((hits == e.eb.true_hits[F:, :n]).mean(axis=0) >= 0.75))
 
 
-def dump_rows(w, e: EventOnGPU, capacity=3_000_000) -> np.ndarray:
+def dump_rows(w, e: EventOnGPU, capacity=3_000_000, state=kf.STATE_CARTESIAN) -> np.ndarray:
+    """Training rows from the plain FP32 build in the given state (the
+    features are the Cartesian prediction in either state)."""
     eb = e.eb
     L = w.geometry.n_layers
     n = eb.n_seeds
@@ -97,7 +99,7 @@ def dump_rows(w, e: EventOnGPU, capacity=3_000_000) -> np.ndarray:
     tx = torch.from_numpy(txyz).to(DEV)
     dump = torch.empty((capacity, kf.MLP_ROW), dtype=torch.float32, device=DEV)
     cnt = torch.zeros(1, dtype=torch.int32, device=DEV)
-    bp = kf.build_params(w.cuts)
+    bp = kf.build_params(w.cuts, state=state)
     ex = kf.BuildExtra()
     ex.seed_event = e.sev.data_ptr()
     ex.true_hits = th.data_ptr()

@@ -54,6 +54,32 @@ def test_training_reduces_loss(env):
     assert np.all(r[:, 27] >= 0) and np.all(r[:, 28] >= 0)
 
 
+def test_hybrid_dump_rows_are_cartesian(env):
+    """Rows dumped by the hybrid-state build carry the Cartesian prediction:
+    on the first searched layer (predicted straight from the seed, where the
+    two states' predictions are the same map) they agree with the Cartesian
+    build's rows of the same seed."""
+    kf, window, w = env["kf"], env["window"], env["w"]
+    tr = window.load_events(w, [0])
+    rc, rh = env["rows"], window.dump_rows(w, tr, state=kf.STATE_HYBRID)
+    F = w.cuts.first_layer
+
+    def first(r):
+        lay, slot = r[:, 30].view(np.int32), r[:, 31].view(np.int32)
+        sel = (lay == F) & (slot == 0)
+        return r[sel][np.argsort(r[sel, 29].view(np.int32), kind="stable")]
+    a, b = first(rc), first(rh)
+    assert a.shape[0] > 1000 and np.array_equal(a[:, 29:], b[:, 29:])
+    st = np.sqrt(np.abs(a[:, [6, 12, 17, 21, 24, 26]]))  # sigma of each parameter
+    dx = np.abs(a[:, :6] - b[:, :6]) / np.maximum(st, 1e-30)
+    ds = np.abs(a[:, 6:27] - b[:, 6:27]) / np.maximum(np.abs(a[:, 6:27]), 1e-30)
+    print(f"hybrid vs Cartesian first-layer rows: {a.shape[0]}, max |dX|/sigma {dx.max():.2e}, "
+          f"median rel dP {np.median(ds):.2e}")
+    assert np.median(dx) < 1e-3 and np.percentile(dx, 99) < 1e-2
+    assert np.median(ds) < 1e-3
+    assert np.allclose(a[:, 27:29], b[:, 27:29], rtol=1e-3, atol=1e-5)  # the labels
+
+
 @pytest.mark.parametrize("gate_q,state", [(0.0, 0), (0.6, 0), (0.6, 1)])
 def test_learned_build_matches_oracle(env, gate_q, state):
     """Gate quantile 0 consults the network for every candidate; 0.6 for the
