@@ -48,7 +48,7 @@ extern "C" {
 /* call status */
 #define KF_OK 0
 #define KF_E_INVALID_ARG 1 /* null pointer with n > 0, n < 0, ld < n, bad layer range, bad sizes */
-#define KF_E_WORKSPACE 2   /* workspace missing or smaller than the query returned */
+#define KF_E_WORKSPACE 2   /* workspace missing, smaller than the query returned, or misaligned */
 #define KF_E_HIP 3         /* a HIP launch or runtime error; see kf_last_error */
 #define KF_E_UNSUPPORTED 4 /* a parameter outside what the kernels implement */
 
@@ -218,10 +218,14 @@ typedef struct {
 } kf_build_extra;
 
 /*
- * Workspace bytes for kf_build: a queue head, per-event counters and the
- * fine phi index of every (event, layer, z row), n_phi * phi_refine + 1
- * int32 each, rebuilt by every kf_build call from the binned hits.
- * Returns 0 for a NULL or malformed descriptor.
+ * Workspace bytes for kf_build: a queue head, per-event counters, the fine
+ * phi index of every (event, layer, z row), n_phi * phi_refine + 1 int32
+ * each, a packed copy of the binned hits (48 bytes per hit: phi, x, y, z,
+ * cov, orig, which the hit search reads in one pass) and the per-wave
+ * history tables; the index and the packed hits are rebuilt by every
+ * kf_build call from the binned hits.  The workspace must be 256-byte
+ * aligned (device allocations are).  Returns 0 for a NULL or malformed
+ * descriptor.
  */
 size_t kf_build_workspace_bytes(const kf_build_params* bp, const kf_hits* hits, int32_t n_seeds);
 

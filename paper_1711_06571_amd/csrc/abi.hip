@@ -20,7 +20,7 @@ extern "C" const char* kf_status_string(int status) {
   switch (status) {
     case KF_OK: return "ok";
     case KF_E_INVALID_ARG: return "invalid argument";
-    case KF_E_WORKSPACE: return "workspace missing or too small";
+    case KF_E_WORKSPACE: return "workspace missing, too small or misaligned";
     case KF_E_HIP: return "HIP error";
     case KF_E_UNSUPPORTED: return "unsupported parameter";
     default: return "unknown status";

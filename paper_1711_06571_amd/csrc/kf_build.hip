@@ -50,8 +50,9 @@ struct BuildArgs {
   // hits
   int n_events, n_phi, n_z;
   const int32_t* offsets;
-  const float *hx, *hy, *hz, *hphi, *hcov;
-  const int32_t* horig;
+  // the hits packed per sorted position, three float4 each:
+  // (phi, x, y, z), (cov 0..3), (cov 4, cov 5, orig bits, 0)
+  const float4* hpack;
   int n_hits;
   int refine;            // sub-bins per phi bin in the fine index
   const int32_t* fine;   // [events][layers][n_z][n_phi * refine + 1]
@@ -402,13 +403,19 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
 #pragma unroll
       for (int h = 0; h < NPT; ++h) {
         const int ps = valid[h] ? p[h] : p_first;
-        ph[h] = A.hphi[ps];
-        hx[h] = A.hx[ps];
-        hy[h] = A.hy[ps];
-        hz[h] = A.hz[ps];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) V[h][q] = A.hcov[(size_t)q * A.n_hits + ps];
-        forig[h] = (uint32_t)A.horig[ps];
+        const float4* hp = A.hpack + (size_t)ps * 3;
+        const float4 u0 = hp[0], u1 = hp[1], u2 = hp[2];
+        ph[h] = u0.x;
+        hx[h] = u0.y;
+        hy[h] = u0.z;
+        hz[h] = u0.w;
+        V[h][0] = u1.x;
+        V[h][1] = u1.y;
+        V[h][2] = u1.z;
+        V[h][3] = u1.w;
+        V[h][4] = u2.x;
+        V[h][5] = u2.y;
+        forig[h] = __float_as_uint(u2.z);
       }
       // all loads in flight before the first test (the compiler would
       // otherwise wait for phi and issue the rest behind the phi test)
@@ -829,10 +836,10 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
       if (my_parent >= 0) {
         const bool is_hole = my_orig == kHoleIdx;
         if (!is_hole) {
-          const T hx = (T)A.hx[my_pos], hy = (T)A.hy[my_pos], hz = (T)A.hz[my_pos];
-          T V[6];
-#pragma unroll
-          for (int c = 0; c < 6; ++c) V[c] = (T)A.hcov[(size_t)c * A.n_hits + my_pos];
+          const float4* hp = A.hpack + (size_t)my_pos * 3;
+          const float4 u0 = hp[0], u1 = hp[1], u2 = hp[2];
+          const T hx = (T)u0.y, hy = (T)u0.z, hz = (T)u0.w;
+          const T V[6] = {(T)u1.x, (T)u1.y, (T)u1.z, (T)u1.w, (T)u2.x, (T)u2.y};
           Innov<T> in;
           innovation<T>(Xn, Pn, hx, hy, hz, V, in);
           apply_update<T>(Xn, Pn, in);
@@ -952,6 +959,22 @@ __global__ void __launch_bounds__(256) fine_kernel(int n_rows, int n_phi, int n_
   for (int j = kl + 1 + lane; j <= nf; j += 64) f[j] = re;
 }
 
+// Packed hits for the hit search: one thread per sorted position.
+__global__ void __launch_bounds__(256) pack_kernel(int n_hits, const float* __restrict__ x, const float* __restrict__ y,
+                                                   const float* __restrict__ z, const float* __restrict__ phi,
+                                                   const float* __restrict__ cov, const int32_t* __restrict__ orig,
+                                                   float4* __restrict__ pack) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_hits) return;
+  const size_t n = (size_t)n_hits;
+  float4* o = pack + (size_t)p * 3;
+  o[0] = make_float4(phi[p], x[p], y[p], z[p]);
+  o[1] = make_float4(cov[p], cov[n + p], cov[2 * n + p], cov[3 * n + p]);
+  o[2] = make_float4(cov[4 * n + p], cov[5 * n + p], __int_as_float(orig[p]), 0.f);
+}
+
+size_t pack_bytes(int n_hits) { return (((size_t)n_hits * 48) + 255) & ~(size_t)255; }
+
 size_t fine_bytes(int n_events, int n_layers, int n_phi, int n_z, int refine) {
   return (size_t)n_events * n_layers * n_z * ((size_t)n_phi * refine + 1) * 4;
 }
@@ -997,8 +1020,8 @@ int launch(const BuildArgs& A, int lanes, int blocks, int hist_waves, hipStream_
   return kf_check_launch();
 }
 
-// Workspace: queue head and per-event counters | fine phi index | history
-// tables of the resident waves (16 per CU of the current device: four per
+// Workspace: queue head and per-event counters | fine phi index | packed
+// hits (48 bytes each) | history tables of the resident waves (16 per CU of the current device: four per
 // SIMD, more than the build kernels' register use allows; a grid that would
 // hold more waves is clamped).
 size_t ws_head_bytes(int n_events) { return 256 + (((size_t)n_events * 4 + 255) & ~(size_t)255); }
@@ -1023,9 +1046,10 @@ extern "C" size_t kf_build_workspace_bytes(const kf_build_params* bp, const kf_h
   if (!bp || !hits || hits->n_events < 1 || hits->n_layers < 1 || hits->n_phi < 1 || hits->n_z < 1) return 0;
   if (bp->first_layer < 1 || bp->first_layer >= hits->n_layers) return 0;
   const size_t LB = (size_t)(hits->n_layers - bp->first_layer);
-  return ws_head_bytes(hits->n_events) + fine_bytes(hits->n_events, hits->n_layers, hits->n_phi, hits->n_z,
-                                                   refine_of(bp)) +
-         (size_t)hist_waves_of_device() * LB * 64 * 4;
+  if (hits->n_hits < 0) return 0;
+  return ws_head_bytes(hits->n_events) +
+         ((fine_bytes(hits->n_events, hits->n_layers, hits->n_phi, hits->n_z, refine_of(bp)) + 255) & ~(size_t)255) +
+         pack_bytes(hits->n_hits) + (size_t)hist_waves_of_device() * LB * 64 * 4;
 }
 
 extern "C" int kf_build(const kf_geometry* g, const kf_build_params* bp, const kf_hits* hits, int32_t n_seeds,
@@ -1061,7 +1085,7 @@ extern "C" int kf_build(const kf_geometry* g, const kf_build_params* bp, const k
   const int refine = refine_of(bp);
   if ((int64_t)hits->n_phi * refine > (1 << 20)) return KF_E_UNSUPPORTED;
   const size_t need = kf_build_workspace_bytes(bp, hits, n_seeds);
-  if (!ws || ws_bytes < need) return KF_E_WORKSPACE;
+  if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) return KF_E_WORKSPACE;
   const int lanes = bp->lanes_per_block;
   if (lanes != 0 && lanes != 64 && lanes != 128 && lanes != 256) return KF_E_UNSUPPORTED;
 
@@ -1073,13 +1097,14 @@ extern "C" int kf_build(const kf_geometry* g, const kf_build_params* bp, const k
   A.nsigma = bp->nsigma; A.win_sig_rphi = bp->win_sig_rphi; A.win_sig_z = bp->win_sig_z;
   A.first_layer = bp->first_layer; A.window_mode = bp->window_mode; A.mlp = (const float*)bp->mlp;
   A.n_events = hits->n_events; A.n_phi = hits->n_phi; A.n_z = hits->n_z; A.offsets = hits->offsets;
-  A.hx = hits->x; A.hy = hits->y; A.hz = hits->z; A.hphi = hits->phi; A.hcov = hits->cov; A.horig = hits->orig;
   A.n_hits = hits->n_hits;
   A.refine = refine;
   const size_t fine_off = ws_head_bytes(hits->n_events);
   A.fine = (const int32_t*)((char*)ws + fine_off);
-  const size_t hist_off =
-      fine_off + fine_bytes(hits->n_events, hits->n_layers, hits->n_phi, hits->n_z, refine);
+  const size_t pack_off =
+      fine_off + ((fine_bytes(hits->n_events, hits->n_layers, hits->n_phi, hits->n_z, refine) + 255) & ~(size_t)255);
+  A.hpack = (const float4*)((char*)ws + pack_off);
+  const size_t hist_off = pack_off + pack_bytes(hits->n_hits);
   A.hist = (uint32_t*)((char*)ws + hist_off);
   const size_t LBw = (size_t)(g->n_layers - bp->first_layer) * 64 * 4;
   const int hist_waves = (int)((ws_bytes - hist_off) / LBw);
@@ -1103,6 +1128,11 @@ extern "C" int kf_build(const kf_geometry* g, const kf_build_params* bp, const k
     hipLaunchKernelGGL(fine_kernel, dim3((n_rows + 3) / 4), dim3(256), 0, s, n_rows, hits->n_phi, hits->n_z,
                        hits->n_phi * refine, hits->offsets, hits->phi, (int32_t*)A.fine);
     if (int rc = kf_check_launch()) return rc;
+    if (hits->n_hits > 0) {
+      hipLaunchKernelGGL(pack_kernel, dim3((hits->n_hits + 255) / 256), dim3(256), 0, s, hits->n_hits, hits->x,
+                         hits->y, hits->z, hits->phi, hits->cov, hits->orig, (float4*)A.hpack);
+      if (int rc = kf_check_launch()) return rc;
+    }
   }
   if (bp->arith == KF_ARITH_F64)
     return bp->state == 1

@@ -224,6 +224,12 @@ def test_build_edge_cases(kf, state):
         kf.kf_build(g, kf.build_params(w.cuts, cap=9, state=state), b, 64, par, sg["cov"], sg["q"])
     with pytest.raises(kf.KFError):
         kf.kf_build(g, kf.build_params(w.cuts, state=2), b, 64, par, sg["cov"], sg["q"])
+    # a workspace that is not 256-byte aligned (the packed hits are read as
+    # 16-byte vectors) is refused before any launch
+    need = kf.kf_build_workspace_bytes(bp, b, 64)
+    wsb = torch.empty(need + 256, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(kf.KFError, match="orkspace"):
+        kf.kf_build(g, bp, b, 64, par, sg["cov"], sg["q"], ws=wsb[16:])
     # an event with no hits at all: every seed ends on holes and stops
     empty = kf.hit_bin(g, 63, 16, torch.zeros(0, dtype=torch.int32, device="cuda:0"),
                        torch.zeros((3, 0), device="cuda:0"), torch.zeros((6, 0), device="cuda:0"))
