@@ -4,7 +4,10 @@
 // are assigned by rank, never by atomic arrival order.
 //
 // Kernels: count -> three-phase exclusive scan of bin counts -> offsets ->
-// place (arbitrary order inside each bin) -> rank (exact order) + gather.
+// place (arbitrary order inside each bin, whole hit records) -> rank (exact
+// order inside each bin) and write out.  The hit data moves with the place
+// pass, which reads the input in order, so the scattered accesses are whole
+// 48-byte records rather than one word from each of ten input arrays.
 #include "kfhost.h"
 
 namespace {
@@ -134,33 +137,40 @@ __global__ void offsets_kernel(const int32_t* __restrict__ start, const int32_t*
   offsets[k] = b < nb ? start[g + b] : start[g + nb - 1] + count[g + nb - 1];
 }
 
-// Each hit takes a slot of its bin (arrival order); the slot also receives
-// the hit's phi, so the rank pass reads its bin's keys without indirection.
+// Each hit takes a slot of its bin (arrival order) and writes its whole
+// record there: (x, y, z, phi), (cov 0..3), (cov 4, cov 5, input index, 0).
 __global__ void __launch_bounds__(256) place_kernel(int n, const int32_t* __restrict__ gbin_of,
-                                                    const float* __restrict__ phi_of,
+                                                    const float* __restrict__ phi_of, const float* __restrict__ xyz,
+                                                    const float* __restrict__ cov,
                                                     const int32_t* __restrict__ start, int32_t* __restrict__ cursor,
-                                                    int32_t* __restrict__ tmp_idx, float* __restrict__ tmp_phi) {
+                                                    float4* __restrict__ rec) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int gb = gbin_of[i];
   if (gb < 0) return;
+  const size_t N = (size_t)n;
+  const float4 r0 = make_float4(xyz[i], xyz[N + i], xyz[2 * N + i], phi_of[i]);
+  const float4 r1 = make_float4(cov[i], cov[N + i], cov[2 * N + i], cov[3 * N + i]);
+  const float4 r2 = make_float4(cov[4 * N + i], cov[5 * N + i], __int_as_float(i), 0.f);
   const int slot = start[gb] + atomicAdd(&cursor[gb], 1);
-  tmp_idx[slot] = i;
-  tmp_phi[slot] = phi_of[i];
+  float4* r = rec + (size_t)slot * 3;
+  r[0] = r0;
+  r[1] = r1;
+  r[2] = r2;
 }
 
 // Exact order inside each bin: rank = number of hits of the bin with a
 // smaller (phi, original index) key.  One wave per bin: each lane holds one
-// hit of the bin and compares it with every hit of the bin, which the wave
-// passes around by shuffles 64 at a time (bins larger than 64 hits loop over
-// blocks of 64).  The hit is then written to its slot in the sorted arrays.
+// hit record of the bin and compares it with every hit of the bin, whose keys
+// the wave passes around by shuffles 64 at a time (bins larger than 64 hits
+// loop over blocks of 64).  The hit is then written to its slot in the sorted
+// arrays.
 __global__ void __launch_bounds__(256) rank_kernel(int NB, int n, int L, int nb_el,
                                                    const int32_t* __restrict__ eoff,
-                                                   const int32_t* __restrict__ tmp_idx,
-                                                   const float* __restrict__ tmp_phi,
+                                                   const float4* __restrict__ rec,
                                                    const int32_t* __restrict__ start,
-                                                   const int32_t* __restrict__ count, const float* __restrict__ xyz,
-                                                   const float* __restrict__ cov, float* __restrict__ sorted_xyzphi,
+                                                   const int32_t* __restrict__ count,
+                                                   float* __restrict__ sorted_xyzphi,
                                                    float* __restrict__ sorted_cov, int32_t* __restrict__ sorted_orig) {
   const int gb = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -171,13 +181,16 @@ __global__ void __launch_bounds__(256) rank_kernel(int NB, int n, int L, int nb_
   const int ev_base = eoff ? eoff[gb / (L * nb_el)] : 0;
   for (int c0 = 0; c0 < cnt; c0 += 64) {
     const bool mine = c0 + lane < cnt;
-    const int i = mine ? tmp_idx[b0 + c0 + lane] : 0;
-    const float ph = mine ? tmp_phi[b0 + c0 + lane] : 0.f;
+    const float4* r = rec + (size_t)(b0 + c0 + (mine ? lane : 0)) * 3;
+    const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+    const int i = __float_as_int(r2.z);
+    const float ph = r0.w;
     int rank = 0;
     for (int d0 = 0; d0 < cnt; d0 += 64) {
       const bool theirs = d0 + lane < cnt;
-      const int oi = theirs ? tmp_idx[b0 + d0 + lane] : 0;
-      const float op = theirs ? tmp_phi[b0 + d0 + lane] : 0.f;
+      const float4* o = rec + (size_t)(b0 + d0 + (theirs ? lane : 0)) * 3;
+      const int oi = d0 == c0 ? i : __float_as_int(o[2].z);
+      const float op = d0 == c0 ? ph : o[0].w;
       const int m = cnt - d0 < 64 ? cnt - d0 : 64;
       for (int t = 0; t < m; ++t) {
         const float pj = __shfl(op, t, 64);
@@ -187,12 +200,17 @@ __global__ void __launch_bounds__(256) rank_kernel(int NB, int n, int L, int nb_
     }
     if (mine) {
       const int dst = b0 + rank;
-      sorted_xyzphi[dst] = xyz[i];
-      sorted_xyzphi[(size_t)n + dst] = xyz[(size_t)n + i];
-      sorted_xyzphi[2 * (size_t)n + dst] = xyz[2 * (size_t)n + i];
-      sorted_xyzphi[3 * (size_t)n + dst] = ph;
-#pragma unroll
-      for (int c = 0; c < 6; ++c) sorted_cov[(size_t)c * n + dst] = cov[(size_t)c * n + i];
+      const size_t N = (size_t)n;
+      sorted_xyzphi[dst] = r0.x;
+      sorted_xyzphi[N + dst] = r0.y;
+      sorted_xyzphi[2 * N + dst] = r0.z;
+      sorted_xyzphi[3 * N + dst] = ph;
+      sorted_cov[dst] = r1.x;
+      sorted_cov[N + dst] = r1.y;
+      sorted_cov[2 * N + dst] = r1.z;
+      sorted_cov[3 * N + dst] = r1.w;
+      sorted_cov[4 * N + dst] = r2.x;
+      sorted_cov[5 * N + dst] = r2.y;
       sorted_orig[dst] = i - ev_base;
     }
   }
@@ -201,8 +219,9 @@ __global__ void __launch_bounds__(256) rank_kernel(int NB, int n, int L, int nb_
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct BinWs {
-  int32_t *gbin_of, *tmp_idx, *count, *cursor, *start, *bsum;
-  float *phi_of, *tmp_phi;
+  int32_t *gbin_of, *count, *cursor, *start, *bsum;
+  float* phi_of;
+  float4* rec;  // [n][3] hit records in bin slots
 };
 
 size_t bin_ws_layout(int E, int L, int n_phi, int n_z, int n, char* base, BinWs* w) {
@@ -215,17 +234,15 @@ size_t bin_ws_layout(int E, int L, int n_phi, int n_z, int n, char* base, BinWs*
     return p;
   };
   char* a = take(sizeof(int32_t) * (size_t)n);
-  char* b = take(sizeof(int32_t) * (size_t)n);
+  char* b = take(sizeof(float4) * 3 * (size_t)n);
   char* c = take(sizeof(float) * (size_t)n);
   char* d = take(sizeof(int32_t) * NB);
   char* e = take(sizeof(int32_t) * NB);
   char* f = take(sizeof(int32_t) * NB);
   char* g = take(sizeof(int32_t) * (nblk + 1));
-  char* h = take(sizeof(float) * (size_t)n);
   if (w) {
-    w->tmp_phi = (float*)h;
     w->gbin_of = (int32_t*)a;
-    w->tmp_idx = (int32_t*)b;
+    w->rec = (float4*)b;
     w->phi_of = (float*)c;
     w->count = (int32_t*)d;
     w->cursor = (int32_t*)e;
@@ -259,7 +276,7 @@ extern "C" int hit_bin(const kf_geometry* g, int32_t n_events, const int32_t* ev
   if (n_hits > 0 && (!layer || !xyz || !cov || !sorted_xyzphi || !sorted_cov || !sorted_orig))
     return KF_E_INVALID_ARG;
   const size_t need = hit_bin_workspace_bytes(n_events, L, n_phi, n_z, n_hits);
-  if (!ws || ws_bytes < need) return KF_E_WORKSPACE;
+  if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) return KF_E_WORKSPACE;
   BinWs w;
   bin_ws_layout(n_events, L, n_phi, n_z, n_hits, (char*)ws, &w);
   hipStream_t s = (hipStream_t)stream;
@@ -271,9 +288,6 @@ extern "C" int hit_bin(const kf_geometry* g, int32_t n_events, const int32_t* ev
                      NB, 0);
   hipLaunchKernelGGL(fill_i32, dim3(grid_for(NB, bs) > 4096 ? 4096 : grid_for(NB, bs)), dim3(bs), 0, s, w.cursor,
                      NB, 0);
-  if (n_hits > 0)
-    hipLaunchKernelGGL(fill_i32, dim3(grid_for(n_hits, bs) > 4096 ? 4096 : grid_for(n_hits, bs)), dim3(bs), 0, s,
-                       w.tmp_idx, (int64_t)n_hits, -1);
   if (out_bad) hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, out_bad, (int64_t)1, 0);
   if (n_hits > 0)
     hipLaunchKernelGGL(count_kernel, dim3(grid_for(n_hits, bs)), dim3(bs), 0, s, n_hits, n_events, event_offsets, L,
@@ -285,11 +299,10 @@ extern "C" int hit_bin(const kf_geometry* g, int32_t n_events, const int32_t* ev
   hipLaunchKernelGGL(offsets_kernel, dim3(grid_for((int64_t)EL * (nb + 1), bs)), dim3(bs), 0, s, w.start, w.count,
                      EL, nb, offsets);
   if (n_hits > 0) {
-    hipLaunchKernelGGL(place_kernel, dim3(grid_for(n_hits, bs)), dim3(bs), 0, s, n_hits, w.gbin_of, w.phi_of,
-                       w.start, w.cursor, w.tmp_idx, w.tmp_phi);
+    hipLaunchKernelGGL(place_kernel, dim3(grid_for(n_hits, bs)), dim3(bs), 0, s, n_hits, w.gbin_of, w.phi_of, xyz,
+                       cov, w.start, w.cursor, w.rec);
     hipLaunchKernelGGL(rank_kernel, dim3(grid_for(NB, bs / 64)), dim3(bs), 0, s, (int)NB, n_hits, L, nb,
-                       event_offsets, w.tmp_idx, w.tmp_phi, w.start, w.count, xyz, cov, sorted_xyzphi, sorted_cov,
-                       sorted_orig);
+                       event_offsets, w.rec, w.start, w.count, sorted_xyzphi, sorted_cov, sorted_orig);
   }
   return kf_check_launch();
 }
