@@ -91,6 +91,45 @@ def test_step_graph_replays_equal_eager(bt, hybrid):
     p.close()
 
 
+def test_gather_hits_matches_indexing(bt):
+    """kf_gather_hits against plain indexing of the input hits: layer l of
+    seed i holds hit event_offset + index, or zeros and the hole bit where the
+    index is -1, outside its event, or the seed's event is invalid."""
+    batch, kf, b = bt
+    w = b.w
+    L, F = w.geometry.n_layers, w.cuts.first_layer
+    n = b.eb.n_seeds
+    hoff = b.eb.hit_offsets.astype(np.int64)
+    E = len(hoff) - 1
+    sev = b.eb.seed_event.astype(np.int64).copy()
+    rng = np.random.default_rng(7)
+    built = np.full((L - F, b.eb.ld), -1, dtype=np.int32)
+    sizes = hoff[sev + 1] - hoff[sev]
+    pick = rng.random((L - F, n)) < 0.8
+    built[:, :n][pick] = (rng.random((L - F, n)) * sizes[None, :]).astype(np.int32)[pick]
+    built[0, :5] = sizes[:5].astype(np.int32)  # one past the event's last hit: a hole
+    sev[7] = E  # an invalid event: every layer a hole
+    dev = "cuda:0"
+    fh, hole = kf.kf_gather_hits(L, F, n, torch.from_numpy(built).to(dev), b.xyz, b.cov,
+                                 seed_event=torch.from_numpy(sev.astype(np.int32)).to(dev), event_offsets=b.hoff)
+    torch.cuda.synchronize()
+    fh, hole = host(fh), host(hole).view(np.uint32)
+    src = np.concatenate([b.eb.xyz, b.eb.cov], axis=0)  # [9][n_hits]
+    exp_hole = np.zeros(n, dtype=np.uint32)
+    for l in range(F, L):
+        h = built[l - F].astype(np.int64)
+        h = h[:n]
+        ok = (h >= 0) & (sev < E)
+        se = np.minimum(sev, E - 1)
+        ok &= h < hoff[se + 1] - hoff[se]
+        g = np.where(ok, hoff[se] + h, 0)
+        exp = np.where(ok[None, :], src[:, g], 0.0).astype(np.float32)
+        assert np.array_equal(fh[l, :, :n], exp), l
+        exp_hole |= np.where(ok, 0, 1 << l).astype(np.uint32)
+    assert np.array_equal(hole[:n], exp_hole)
+    assert hole[7] == sum(1 << l for l in range(F, L))
+
+
 def test_autotune_small_grid(bt):
     batch, kf, b = bt
     res = batch.autotune(b, lanes_set=(64, 256), bpcu_set=(1, 0), caps=(4, 6), refines=(4, 16), reps=2)
