@@ -191,7 +191,7 @@ typedef struct {
   int32_t lanes_per_block; /* 64, 128, 256 (0: the widest whose LDS fits) */
   int32_t persistent_blocks; /* blocks of the persistent grid (0: CUs x resident blocks per CU) */
   int32_t arith;       /* KF_ARITH_F32 or KF_ARITH_F64 */
-  int32_t phi_refine;  /* sub-bins per phi bin of the fine index the hit search uses, 1..64 (0: 32) */
+  int32_t phi_refine;  /* sub-bins per phi bin of the fine index the hit search uses, 1..64 (0: 64) */
   int32_t state;       /* 0 Cartesian; 1 hybrid (x, y, z, q/pT, phi, theta; section 3): seeds are
                           converted on entry, the charge follows the sign of q/pT, out_par/out_cov
                           are hybrid; the learned window still reads the Cartesian prediction */

@@ -979,7 +979,7 @@ size_t fine_bytes(int n_events, int n_layers, int n_phi, int n_z, int refine) {
   return (size_t)n_events * n_layers * n_z * ((size_t)n_phi * refine + 1) * 4;
 }
 
-int refine_of(const kf_build_params* bp) { return bp->phi_refine > 0 ? bp->phi_refine : 32; }
+int refine_of(const kf_build_params* bp) { return bp->phi_refine > 0 ? bp->phi_refine : 64; }
 
 // the launch shape of the last kf_build call of this host thread
 thread_local kf_build_launch_info g_last_launch = {};
