@@ -156,9 +156,9 @@ typedef struct {
   const int32_t* orig;    /* [n_hits] event-local original index of each sorted hit */
 } kf_hits;
 
-/* Workspace bytes for hit_bin (bin counts and cursors, and one 48-byte
-   record per hit in its bin's slot); the workspace must be 256-byte aligned
-   (device allocations are). */
+/* Workspace bytes for hit_bin (bin counts and starts, each hit's bin and
+   arrival index, and one 48-byte record per hit in its bin's slot); the
+   workspace must be 256-byte aligned (device allocations are). */
 size_t hit_bin_workspace_bytes(int32_t n_events, int32_t n_layers, int32_t n_phi, int32_t n_z, int32_t n_hits);
 
 /*

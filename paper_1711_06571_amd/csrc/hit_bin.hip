@@ -29,15 +29,17 @@ __device__ inline int event_of(const int32_t* __restrict__ eoff, int E, int i) {
   return lo;
 }
 
-// Bin of each hit.  phi and the bin indices are computed in FP64 with the
-// expression order of the definition, so the bin of a hit never depends on
-// contraction or reassociation.
+// Bin of each hit and its arrival index among the bin's hits (the value the
+// count's atomic returns; the rank pass fixes the order later).  phi and the
+// bin indices are computed in FP64 with the expression order of the
+// definition, so the bin of a hit never depends on contraction or
+// reassociation.
 __global__ void __launch_bounds__(256) count_kernel(int n, int E, const int32_t* __restrict__ eoff, int L,
                                                     int n_phi, int n_z, double z_half,
                                                     const int32_t* __restrict__ layer,
                                                     const float* __restrict__ xyz, int32_t* __restrict__ gbin_of,
-                                                    float* __restrict__ phi_of, int32_t* __restrict__ count,
-                                                    int32_t* __restrict__ bad) {
+                                                    float* __restrict__ phi_of, int32_t* __restrict__ arrival,
+                                                    int32_t* __restrict__ count, int32_t* __restrict__ bad) {
 #pragma clang fp contract(off)
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -60,7 +62,7 @@ __global__ void __launch_bounds__(256) count_kernel(int n, int E, const int32_t*
   const int gb = (e * L + l) * nb + iz * n_phi + ip;
   gbin_of[i] = gb;
   phi_of[i] = phf;
-  atomicAdd(&count[gb], 1);
+  arrival[i] = atomicAdd(&count[gb], 1);
 }
 
 // Phase 1: exclusive scan of 2*kScanBlock elements per block (Blelloch in LDS).
@@ -137,12 +139,13 @@ __global__ void offsets_kernel(const int32_t* __restrict__ start, const int32_t*
   offsets[k] = b < nb ? start[g + b] : start[g + nb - 1] + count[g + nb - 1];
 }
 
-// Each hit takes a slot of its bin (arrival order) and writes its whole
-// record there: (x, y, z, phi), (cov 0..3), (cov 4, cov 5, input index, 0).
+// Each hit takes the slot of its bin given by its arrival index and writes
+// its whole record there: (x, y, z, phi), (cov 0..3), (cov 4, cov 5, input
+// index, 0).
 __global__ void __launch_bounds__(256) place_kernel(int n, const int32_t* __restrict__ gbin_of,
-                                                    const float* __restrict__ phi_of, const float* __restrict__ xyz,
-                                                    const float* __restrict__ cov,
-                                                    const int32_t* __restrict__ start, int32_t* __restrict__ cursor,
+                                                    const float* __restrict__ phi_of,
+                                                    const int32_t* __restrict__ arrival, const float* __restrict__ xyz,
+                                                    const float* __restrict__ cov, const int32_t* __restrict__ start,
                                                     float4* __restrict__ rec) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -152,7 +155,7 @@ __global__ void __launch_bounds__(256) place_kernel(int n, const int32_t* __rest
   const float4 r0 = make_float4(xyz[i], xyz[N + i], xyz[2 * N + i], phi_of[i]);
   const float4 r1 = make_float4(cov[i], cov[N + i], cov[2 * N + i], cov[3 * N + i]);
   const float4 r2 = make_float4(cov[4 * N + i], cov[5 * N + i], __int_as_float(i), 0.f);
-  const int slot = start[gb] + atomicAdd(&cursor[gb], 1);
+  const int slot = start[gb] + arrival[i];
   float4* r = rec + (size_t)slot * 3;
   r[0] = r0;
   r[1] = r1;
@@ -219,7 +222,7 @@ __global__ void __launch_bounds__(256) rank_kernel(int NB, int n, int L, int nb_
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct BinWs {
-  int32_t *gbin_of, *count, *cursor, *start, *bsum;
+  int32_t *gbin_of, *arrival, *count, *start, *bsum;
   float* phi_of;
   float4* rec;  // [n][3] hit records in bin slots
 };
@@ -237,15 +240,15 @@ size_t bin_ws_layout(int E, int L, int n_phi, int n_z, int n, char* base, BinWs*
   char* b = take(sizeof(float4) * 3 * (size_t)n);
   char* c = take(sizeof(float) * (size_t)n);
   char* d = take(sizeof(int32_t) * NB);
-  char* e = take(sizeof(int32_t) * NB);
+  char* e = take(sizeof(int32_t) * (size_t)n);
   char* f = take(sizeof(int32_t) * NB);
   char* g = take(sizeof(int32_t) * (nblk + 1));
   if (w) {
     w->gbin_of = (int32_t*)a;
     w->rec = (float4*)b;
     w->phi_of = (float*)c;
+    w->arrival = (int32_t*)e;
     w->count = (int32_t*)d;
-    w->cursor = (int32_t*)e;
     w->start = (int32_t*)f;
     w->bsum = (int32_t*)g;
   }
@@ -286,12 +289,11 @@ extern "C" int hit_bin(const kf_geometry* g, int32_t n_events, const int32_t* ev
   // clear (kernels, not memset nodes, so the sequence can be captured in a graph)
   hipLaunchKernelGGL(fill_i32, dim3(grid_for(NB, bs) > 4096 ? 4096 : grid_for(NB, bs)), dim3(bs), 0, s, w.count,
                      NB, 0);
-  hipLaunchKernelGGL(fill_i32, dim3(grid_for(NB, bs) > 4096 ? 4096 : grid_for(NB, bs)), dim3(bs), 0, s, w.cursor,
-                     NB, 0);
   if (out_bad) hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, out_bad, (int64_t)1, 0);
   if (n_hits > 0)
     hipLaunchKernelGGL(count_kernel, dim3(grid_for(n_hits, bs)), dim3(bs), 0, s, n_hits, n_events, event_offsets, L,
-                       n_phi, n_z, (double)g->z_half, layer, xyz, w.gbin_of, w.phi_of, w.count, out_bad);
+                       n_phi, n_z, (double)g->z_half, layer, xyz, w.gbin_of, w.phi_of, w.arrival, w.count,
+                       out_bad);
   const int nblk = (int)((NB + 2 * kScanBlock - 1) / (2 * kScanBlock));
   hipLaunchKernelGGL(scan_blocks, dim3(nblk), dim3(kScanBlock), 0, s, w.count, w.start, w.bsum, (int)NB);
   hipLaunchKernelGGL(scan_sums, dim3(1), dim3(kScanBlock), 0, s, w.bsum, nblk);
@@ -299,8 +301,8 @@ extern "C" int hit_bin(const kf_geometry* g, int32_t n_events, const int32_t* ev
   hipLaunchKernelGGL(offsets_kernel, dim3(grid_for((int64_t)EL * (nb + 1), bs)), dim3(bs), 0, s, w.start, w.count,
                      EL, nb, offsets);
   if (n_hits > 0) {
-    hipLaunchKernelGGL(place_kernel, dim3(grid_for(n_hits, bs)), dim3(bs), 0, s, n_hits, w.gbin_of, w.phi_of, xyz,
-                       cov, w.start, w.cursor, w.rec);
+    hipLaunchKernelGGL(place_kernel, dim3(grid_for(n_hits, bs)), dim3(bs), 0, s, n_hits, w.gbin_of, w.phi_of,
+                       w.arrival, xyz, cov, w.start, w.rec);
     hipLaunchKernelGGL(rank_kernel, dim3(grid_for(NB, bs / 64)), dim3(bs), 0, s, (int)NB, n_hits, L, nb,
                        event_offsets, w.rec, w.start, w.count, sorted_xyzphi, sorted_cov, sorted_orig);
   }
