@@ -1,9 +1,10 @@
 """The benchmark's whole step (hit_bin -> kf_build -> kf_gather_hits ->
 kf_fit) at its full size (fit_scale: 200 events x 20 000 tracks, 17 layers),
 in the launch configuration the benchmark times (FP64 arithmetic, default
-launch shape, all events in one build launch).  The oracle builds seeds
-sampled from the first, a middle and the last event one by one, then fits
-the lists it built; the GPU step's lists and fits must agree."""
+launch shape, all events in one build launch).  The oracle builds 63
+seeds sampled from each of five events spread over the batch (the first,
+the quarters, the last) one by one, then fits the lists it built; the GPU
+step's lists and fits must agree."""
 import numpy as np
 import pytest
 
@@ -45,7 +46,8 @@ def test_step_scale_sampled_parity():
     torch.cuda.synchronize()
     gb = {k: host(v) for k, v in out.items()}
     gf = {k: host(v) for k, v in fout.items()}
-    for e in (0, w.n_events // 2, w.n_events - 1):
+    E = w.n_events
+    for e in (0, E // 4, E // 2, 3 * E // 4, E - 1):
         h0, h1 = int(eb.hit_offsets[e]), int(eb.hit_offsets[e + 1])
         s0, s1 = int(eb.seed_offsets[e]), int(eb.seed_offsets[e + 1])
         ne = s1 - s0
@@ -56,7 +58,7 @@ def test_step_scale_sampled_parity():
         Hs = np.zeros((3, 9, lde), dtype=np.float32)
         Hs[:, :, :ne] = eb.seed_hits[:, :, s0:s1]
         so = oracle.seed(g, Hs, ne)
-        lst = np.concatenate([np.arange(0, ne, 613)[:30], np.arange(ne - 3, ne)])
+        lst = np.concatenate([np.arange(0, ne, 331)[:60], np.arange(ne - 3, ne)])
         ob = oracle.build(g, cuts, le, xe, ce, so["par"], so["cov"], so["q"], ne, seed_list=lst)
         r = compare(gb, ob, lst.size, cols_g=s0 + lst, ctx=f"event {e}")
         # the fit of the lists the oracle built, where the GPU built the same
