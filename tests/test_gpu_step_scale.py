@@ -1,10 +1,10 @@
 """The benchmark's whole step (hit_bin -> kf_build -> kf_gather_hits ->
 kf_fit) at its full size (fit_scale: 200 events x 20 000 tracks, 17 layers),
 in the launch configuration the benchmark times (FP64 arithmetic, default
-launch shape, all events in one build launch).  The oracle builds 63
-seeds sampled from each of five events spread over the batch (the first,
-the quarters, the last) one by one, then fits the lists it built; the GPU
-step's lists and fits must agree."""
+launch shape, all events in one build launch), in the Cartesian state and in
+the hybrid state.  The oracle builds 63 seeds sampled from each of five
+events spread over the batch (the first, the quarters, the last) one by one,
+then fits the lists it built; the GPU step's lists and fits must agree."""
 import numpy as np
 import pytest
 
@@ -15,37 +15,53 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 from gpu_common import assert_fit_parity_converged, host, to_dev  # noqa: E402
-from test_gpu_build import compare, decidable  # noqa: E402
+from test_gpu_build import _hybrid_param_errors, compare, decidable  # noqa: E402
+from test_gpu_fit_hybrid import assert_hybrid_parity  # noqa: E402
 
 
-def test_step_scale_sampled_parity():
+@pytest.fixture(scope="module")
+def step():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1711_06571_amd import kftrack as kf
     w = presets.fit_scale()
     g, cuts = w.geometry, w.cuts
-    L, F = g.n_layers, cuts.first_layer
     eb = workloads.event_batch(w, range(w.n_events), seed_layers=3)
-    n = eb.n_seeds
-    assert n == 4_000_000
-    layer, xyz, cov = to_dev(eb.layer), to_dev(eb.xyz), to_dev(eb.cov)
-    hoff, sev = to_dev(eb.hit_offsets), to_dev(eb.seed_event)
-    binned = kf.hit_bin(g, cuts.n_phi_bins, cuts.n_z_bins, layer, xyz, cov, event_offsets=hoff)
-    seeds = kf.kf_seed(g, n, to_dev(eb.seed_hits))
+    assert eb.n_seeds == 4_000_000
+    d = dict(kf=kf, w=w, eb=eb, layer=to_dev(eb.layer), xyz=to_dev(eb.xyz), cov=to_dev(eb.cov),
+             hoff=to_dev(eb.hit_offsets), sev=to_dev(eb.seed_event))
+    d["binned"] = kf.hit_bin(g, cuts.n_phi_bins, cuts.n_z_bins, d["layer"], d["xyz"], d["cov"],
+                             event_offsets=d["hoff"])
+    d["seeds"] = kf.kf_seed(g, eb.n_seeds, to_dev(eb.seed_hits))
+    return d
+
+
+def run_step(d, state):
+    """The GPU step on every event: build, gather, final fit (FP64)."""
+    kf, w = d["kf"], d["w"]
+    g, cuts = w.geometry, w.cuts
+    L, F = g.n_layers, cuts.first_layer
+    n = d["eb"].n_seeds
+    seeds = d["seeds"]
     ex = kf.BuildExtra()
-    ex.seed_event = sev.data_ptr()
-    out = kf.kf_build(g, kf.build_params(cuts, arith=kf.ARITH_F64), binned, n, seeds["par"], seeds["cov"],
-                      seeds["q"], extra=ex)
+    ex.seed_event = d["sev"].data_ptr()
+    out = kf.kf_build(g, kf.build_params(cuts, arith=kf.ARITH_F64, state=state), d["binned"], n, seeds["par"],
+                      seeds["cov"], seeds["q"], extra=ex)
     ld = seeds["par"].shape[1]
     fit_hits = torch.zeros((L, 9, ld), dtype=torch.float32, device="cuda:0")
     hole = torch.zeros(ld, dtype=torch.int32, device="cuda:0")
-    kf.kf_gather_hits(L, F, n, out["hits"], xyz, cov, seed_event=sev, event_offsets=hoff, fit_hits=fit_hits,
-                      hole_mask=hole)
-    fout = kf.kf_fit(g, n, F, fit_hits, seeds["par"], seeds["cov"], seeds["q"], hole_mask=hole,
-                     arith=kf.ARITH_F64)
+    kf.kf_gather_hits(L, F, n, out["hits"], d["xyz"], d["cov"], seed_event=d["sev"], event_offsets=d["hoff"],
+                      fit_hits=fit_hits, hole_mask=hole)
+    fit = kf.kf_fit_hybrid if state == kf.STATE_HYBRID else kf.kf_fit
+    fout = fit(g, n, F, fit_hits, seeds["par"], seeds["cov"], seeds["q"], hole_mask=hole, arith=kf.ARITH_F64)
     torch.cuda.synchronize()
-    gb = {k: host(v) for k, v in out.items()}
-    gf = {k: host(v) for k, v in fout.items()}
+    return {k: host(v) for k, v in out.items()}, {k: host(v) for k, v in fout.items()}
+
+
+def sampled_events(d):
+    """(event, its hits, its oracle seeds, the sampled seed list) for five
+    events spread over the batch."""
+    w, eb = d["w"], d["eb"]
     E = w.n_events
     for e in (0, E // 4, E // 2, 3 * E // 4, E - 1):
         h0, h1 = int(eb.hit_offsets[e]), int(eb.hit_offsets[e + 1])
@@ -57,35 +73,84 @@ def test_step_scale_sampled_parity():
         lde = ((ne + 63) // 64) * 64
         Hs = np.zeros((3, 9, lde), dtype=np.float32)
         Hs[:, :, :ne] = eb.seed_hits[:, :, s0:s1]
-        so = oracle.seed(g, Hs, ne)
+        so = oracle.seed(w.geometry, Hs, ne)
         lst = np.concatenate([np.arange(0, ne, 331)[:60], np.arange(ne - 3, ne)])
+        yield e, s0, ne, xe, ce, le, so, lst
+
+
+def oracle_fit_inputs(d, ob, so, xe, ce, lst, same):
+    """Fit rows of the lists the oracle built for the seeds in `same`."""
+    g = d["w"].geometry
+    L, F = g.n_layers, d["w"].cuts.first_layer
+    m = lst.size
+    sel = lst[same]
+    k = sel.size
+    ldk = ((k + 63) // 64) * 64
+    Hf = np.zeros((L, 9, ldk), dtype=np.float32)
+    hm = np.zeros(ldk, dtype=np.uint32)
+    obh = ob["hits"][:, :m][:, same]
+    for j in range(k):
+        for l in range(F, L):
+            h = obh[l - F, j]
+            if h < 0:
+                hm[j] |= 1 << l
+            else:
+                Hf[l, 0:3, j] = xe[:, h]
+                Hf[l, 3:9, j] = ce[:, h]
+    sp = np.zeros((6, ldk), np.float32)
+    sc = np.zeros((21, ldk), np.float32)
+    q = np.ones(ldk, np.int8)
+    sp[:, :k] = so["par"][:, sel]
+    sc[:, :k] = so["cov"][:, sel]
+    q[:k] = so["q"][sel]
+    return sel, Hf, hm, sp, sc, q
+
+
+def test_step_scale_sampled_parity(step):
+    d = step
+    kf, w = d["kf"], d["w"]
+    g, cuts = w.geometry, w.cuts
+    F = cuts.first_layer
+    gb, gf = run_step(d, kf.STATE_CARTESIAN)
+    for e, s0, ne, xe, ce, le, so, lst in sampled_events(d):
         ob = oracle.build(g, cuts, le, xe, ce, so["par"], so["cov"], so["q"], ne, seed_list=lst)
         r = compare(gb, ob, lst.size, cols_g=s0 + lst, ctx=f"event {e}")
         # the fit of the lists the oracle built, where the GPU built the same
         m = lst.size
         same = decidable(ob)[:m] & np.all(gb["hits"][:, s0 + lst] == ob["hits"][:, :m], axis=0)
-        sel = lst[same]
+        sel, Hf, hm, sp, sc, q = oracle_fit_inputs(d, ob, so, xe, ce, lst, same)
         k = sel.size
-        ldk = ((k + 63) // 64) * 64
-        Hf = np.zeros((L, 9, ldk), dtype=np.float32)
-        hm = np.zeros(ldk, dtype=np.uint32)
-        obh = ob["hits"][:, :m][:, same]
-        for j in range(k):
-            for l in range(F, L):
-                h = obh[l - F, j]
-                if h < 0:
-                    hm[j] |= 1 << l
-                else:
-                    Hf[l, 0:3, j] = xe[:, h]
-                    Hf[l, 3:9, j] = ce[:, h]
-        sp = np.zeros((6, ldk), np.float32)
-        sc = np.zeros((21, ldk), np.float32)
-        q = np.ones(ldk, np.int8)
-        sp[:, :k] = so["par"][:, sel]
-        sc[:, :k] = so["cov"][:, sel]
-        q[:k] = so["q"][sel]
         of = oracle.fit(g, F, Hf, sp, sc, q, k, hole_mask=hm)
         gsub = {kk: v[..., s0 + sel] for kk, v in gf.items()}
         errs = assert_fit_parity_converged(gsub, of, k, f"event {e} fit")
         print(f"step at scale, event {e}: build {r}, fit on {k} identical lists {errs}")
+        assert k >= 0.8 * m
+
+
+def test_step_scale_sampled_parity_hybrid(step):
+    """The same in the hybrid state: build lists on every decidable seed,
+    then position, q/pT and angles of the build's converged candidates and of
+    the final hybrid fit of identical lists."""
+    d = step
+    kf, w = d["kf"], d["w"]
+    g, cuts = w.geometry, w.cuts
+    F = cuts.first_layer
+    gb, gf = run_step(d, kf.STATE_HYBRID)
+    for e, s0, ne, xe, ce, le, so, lst in sampled_events(d):
+        ob = oracle.build(g, cuts, le, xe, ce, so["par"], so["cov"], so["q"], ne, seed_list=lst, state=1)
+        r = compare(gb, ob, lst.size, cols_g=s0 + lst, ctx=f"hybrid event {e}", check_params=False)
+        m = lst.size
+        dec = decidable(ob)[:m]
+        same = dec & np.all(gb["hits"][:, s0 + lst] == ob["hits"][:, :m], axis=0) & \
+            (gb["nhits"][s0 + lst] == ob["nhits"][:m])
+        conv = np.where(same & (ob["chi2"][:m] <= 100 * np.maximum(2 * ob["nhits"][:m], 1)))[0]
+        ep, ek, ea = _hybrid_param_errors(gb, ob, s0 + lst, conv)
+        assert ep.max(initial=0) <= 1e-4 and ek.max(initial=0) <= 1e-4 and ea.max(initial=0) <= 1e-4, \
+            (e, ep.max(initial=0), ek.max(initial=0), ea.max(initial=0))
+        sel, Hf, hm, sp, sc, q = oracle_fit_inputs(d, ob, so, xe, ce, lst, same)
+        k = sel.size
+        of = oracle.fit_hybrid(g, F, Hf, sp, sc, q, k, hole_mask=hm)
+        gsub = {kk: v[..., s0 + sel] for kk, v in gf.items()}
+        errs = assert_hybrid_parity(gsub, of, k, f"hybrid event {e} fit")
+        print(f"hybrid step at scale, event {e}: build {r}, fit on {k} identical lists {errs}")
         assert k >= 0.8 * m
