@@ -9,7 +9,9 @@ from paper_1711_06571_amd import presets
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
+import oracle  # noqa: E402
 from gpu_common import host  # noqa: E402
+from test_gpu_build import compare  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -89,6 +91,36 @@ def test_step_graph_replays_equal_eager(bt, hybrid):
     ms = batch.run(p, reps=3)
     print(f"step graph ({'hybrid' if hybrid else 'Cartesian'}), 8 events, {n} seeds: {ms:.3f} ms per launch")
     p.close()
+
+
+def test_batched_build_matches_oracle(bt):
+    """The batched graph launch (FP64 arithmetic, largest event first) on
+    uneven events against the oracle: seeds sampled from the smallest, a
+    middle and the largest of the eight events; hit lists, nhits and status
+    on every decidable seed, chi2 and parameters on the converged ones."""
+    batch, kf, b = bt
+    w, eb = b.w, b.eb
+    p = batch.plan(b, arith=kf.ARITH_F64)
+    p.launch()
+    p.stream.synchronize()
+    gb = {k: host(v) for k, v in p.out.items()}
+    p.close()
+    counts = np.diff(eb.seed_offsets)
+    order = np.argsort(counts, kind="stable")
+    for e in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        h0, h1 = int(eb.hit_offsets[e]), int(eb.hit_offsets[e + 1])
+        s0, s1 = int(eb.seed_offsets[e]), int(eb.seed_offsets[e + 1])
+        ne = s1 - s0
+        lde = ((ne + 63) // 64) * 64
+        Hs = np.zeros((3, 9, lde), dtype=np.float32)
+        Hs[:, :, :ne] = eb.seed_hits[:, :, s0:s1]
+        so = oracle.seed(w.geometry, Hs, ne)
+        lst = np.unique(np.concatenate([np.linspace(0, ne - 1, 40).astype(np.int64), [ne - 1]]))
+        ob = oracle.build(w.geometry, w.cuts, np.ascontiguousarray(eb.layer[h0:h1]),
+                          np.ascontiguousarray(eb.xyz[:, h0:h1]), np.ascontiguousarray(eb.cov[:, h0:h1]),
+                          so["par"], so["cov"], so["q"], ne, seed_list=lst)
+        r = compare(gb, ob, lst.size, cols_g=s0 + lst, ctx=f"batched event {e} ({ne} tracks)")
+        print(f"batched build, event {e} ({ne} tracks, {h1 - h0} hits): {r}")
 
 
 def test_gather_hits_matches_indexing(bt):
