@@ -149,11 +149,17 @@ def autotune(b: Batch, lanes_set=(64, 128, 256), bpcu_set=(1, 2, 0), caps=(4, 6,
                     if log:
                         log(pt)
                     p.close()
-    ref = [q for q in res.points if q.cap == 6]
-    eff6 = ref[0].eff if ref else max(q.eff for q in res.points)
-    ok = [q for q in res.points if eff6 - q.eff <= eff_tol]
-    res.best = min(ok, key=lambda q: q.ms)
+    res.best = choose(res.points, eff_tol)
     return res
+
+
+def choose(points, eff_tol=0.001):
+    """The fastest point whose efficiency is within eff_tol of the cap-6
+    efficiency (the best efficiency seen if no cap-6 point was measured)."""
+    ref = [q for q in points if q.cap == 6]
+    eff6 = ref[0].eff if ref else max(q.eff for q in points)
+    ok = [q for q in points if eff6 - q.eff <= eff_tol]
+    return min(ok, key=lambda q: q.ms)
 
 
 def save(res: TuneResult, path, workload):
