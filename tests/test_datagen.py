@@ -1,5 +1,6 @@
 """Input generator: counter-based RNG known answers and event invariants."""
 import dataclasses
+import os
 
 import numpy as np
 
@@ -14,18 +15,30 @@ def _philox(ctr, key):
     return [int(v) for v in o]
 
 
+def _golden(name):
+    """Rows of hexadecimal words of a fixture under tests/golden (its header
+    cites the source)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    rows = []
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            rows.append([int(v, 16) for v in line.split()])
+    return rows
+
+
 def test_philox_known_answers():
-    # Known-answer vectors published with Random123 (Salmon et al., SC'11)
-    assert _philox([0, 0, 0, 0], [0, 0]) == [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]
-    f = 0xFFFFFFFF
-    assert _philox([f, f, f, f], [f, f]) == [0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD]
-    assert _philox([0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344], [0xA4093822, 0x299F31D0]) == \
-        [0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1]
+    rows = _golden("philox4x32_10_kat.txt")
+    assert len(rows) == 3
+    for r in rows:
+        assert _philox(r[0:4], r[4:6]) == r[6:10], r
 
 
 def test_splitmix64_known_answer():
-    # first output of SplitMix64 from state 0 (Steele, Lea and Flood, OOPSLA'14)
-    assert int(datagen.lib().kfg_splitmix64(0)) == 0xE220A8397B1DCDAF
+    rows = _golden("splitmix64_kat.txt")
+    assert len(rows) == 1
+    for state, out in rows:
+        assert int(datagen.lib().kfg_splitmix64(state)) == out
 
 
 def test_event_layout_and_truth():
