@@ -228,7 +228,7 @@ def cpu_baseline(w, eb, seconds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "libkftrack runs on one GPU; --gpus must be 1 (events would be split across GPUs, one process each)"}))
         sys.exit(2)
     if args.copy_bytes:
         copy_only(args.copy_bytes)
