@@ -54,3 +54,15 @@ def test_status_strings_on_host():
     lib.kf_status_string.restype = ctypes.c_char_p
     assert lib.kf_status_string(0) == b"ok"
     assert lib.kf_status_string(1) == b"invalid argument"
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the HIP library every entry point raises: there is no
+    fallback implementation of any step."""
+    from paper_1711_06571_amd import kftrack
+    monkeypatch.setattr(kftrack, "LIB_PATH", str(tmp_path / "absent" / "libkftrack.so"))
+    monkeypatch.setattr(kftrack, "_lib", None)
+    with pytest.raises(kftrack.KFError, match="no fallback"):
+        kftrack.lib()
+    with pytest.raises(kftrack.KFError):
+        kftrack.hit_bin_workspace_bytes(1, 17, 63, 16, 100)
