@@ -202,7 +202,8 @@ typedef struct {
   const int32_t* seed_event;  /* [n_seeds] event of each seed (NULL: all event 0) */
   const int32_t* seed_order;  /* [n_seeds] order in which seeds are taken (NULL: 0..n-1) */
   const int32_t* event_n_seeds; /* [n_events] seeds per event, needed for event_done_ticks */
-  int64_t* event_done_ticks;  /* [n_events] wall-clock tick when the event's last seed finished */
+  int64_t* event_done_ticks;  /* [n_events] wall-clock tick when the event's last seed finished (not
+                                 written for an event with no seeds) */
   int64_t* start_tick;        /* [1] earliest wall-clock tick seen by any wave of the launch */
   /* training-data dump: for every candidate whose hits so far are all true
      (or holes) and whose seed has a true hit on the layer, the 27 features

@@ -200,6 +200,61 @@ def test_build_batch_of_events(kf):
         print(f"event {e}", compare(g, o, lst.size, cols_g=s0 + lst, ctx=f"event {e}"))
 
 
+def test_build_batch_with_empty_events(kf):
+    """Four events in one launch: event 1 keeps its seeds but has no hits
+    (every layer a hole), event 2 has hits but no seeds.  Events 0 and 3
+    match the oracle on their sampled seeds, the seeds of event 1 find
+    nothing, event 2's hits are binned and its completion tick is never
+    written (it has no seed to finish)."""
+    w = presets.batch()
+    eb = workloads.event_batch(w, range(4))
+    ho, so_ = eb.hit_offsets.astype(np.int64), eb.seed_offsets.astype(np.int64)
+    keep_h = np.concatenate([np.arange(ho[0], ho[1]), np.arange(ho[2], ho[4])])
+    keep_s = np.concatenate([np.arange(so_[0], so_[2]), np.arange(so_[3], so_[4])])
+    nh = np.array([ho[1] - ho[0], 0, ho[3] - ho[2], ho[4] - ho[3]])
+    hoff = np.concatenate([[0], np.cumsum(nh)]).astype(np.int32)
+    ns = np.array([so_[1] - so_[0], so_[2] - so_[1], 0, so_[4] - so_[3]])
+    soff = np.concatenate([[0], np.cumsum(ns)])
+    n = int(ns.sum())
+    ld = ((n + 63) // 64) * 64
+    xyz, cov, layer = eb.xyz[:, keep_h], eb.cov[:, keep_h], eb.layer[keep_h]
+    sh = np.zeros((eb.seed_hits.shape[0], 9, ld), dtype=np.float32)
+    sh[:, :, :n] = eb.seed_hits[:, :, keep_s]
+    sev = eb.seed_event[keep_s].astype(np.int32)
+    b = kf.hit_bin(w.geometry, 63, 16, to_dev(layer), to_dev(xyz), to_dev(cov), event_offsets=to_dev(hoff))
+    sg = kf.kf_seed(w.geometry, n, to_dev(sh))
+    ex = kf.BuildExtra()
+    sevd = to_dev(sev)
+    ex.seed_event = sevd.data_ptr()
+    nps = to_dev(ns.astype(np.int32))
+    ticks = torch.zeros(4, dtype=torch.int64, device="cuda:0")
+    t0 = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    ex.event_n_seeds = nps.data_ptr()
+    ex.event_done_ticks = ticks.data_ptr()
+    ex.start_tick = t0.data_ptr()
+    out = kf.kf_build(w.geometry, kf.build_params(w.cuts, arith=kf.ARITH_F64), b, n, sg["par"], sg["cov"],
+                      sg["q"], extra=ex)
+    torch.cuda.synchronize()
+    g = {k: host(v) for k, v in out.items()}
+    offs = host(b.offsets).reshape(4, w.geometry.n_layers, -1)
+    assert np.all(offs[1] == hoff[1]) and offs[2, -1, -1] == hoff[3]
+    tk = host(ticks)
+    assert tk[0] > host(t0)[0] and tk[1] > host(t0)[0] and tk[3] > host(t0)[0] and tk[2] == 0
+    e1 = np.arange(soff[1], soff[2])
+    assert np.all(g["nhits"][e1] == 0) and np.all(g["hits"][:, e1] == -1)
+    for e in (0, 3):
+        s0, s1 = int(soff[e]), int(soff[e + 1])
+        h0, h1 = int(hoff[e]), int(hoff[e + 1])
+        m = s1 - s0
+        lst = np.arange(0, m, max(1, m // 25))
+        Hs = np.zeros((sh.shape[0], 9, ((m + 63) // 64) * 64), dtype=np.float32)
+        Hs[:, :, :m] = sh[:, :, s0:s1]
+        so = oracle.seed(w.geometry, Hs, m)
+        o = oracle.build(w.geometry, w.cuts, np.ascontiguousarray(layer[h0:h1]), np.ascontiguousarray(xyz[:, h0:h1]),
+                         np.ascontiguousarray(cov[:, h0:h1]), so["par"], so["cov"], so["q"], m, seed_list=lst)
+        print(f"event {e} beside empty events", compare(g, o, lst.size, cols_g=s0 + lst, ctx=f"event {e}"))
+
+
 @pytest.mark.parametrize("state", [0, 1])
 def test_build_edge_cases(kf, state):
     w = presets.build()
