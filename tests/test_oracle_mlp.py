@@ -80,3 +80,54 @@ def test_bf16_rounding():
     assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0 + 2.0 ** -6 and r[3] == 1.0 + 2.0 ** -7
     assert r[4] == -2.5
     assert np.isfinite(r[5]) or r[5] == np.inf
+
+
+def _adam_state():
+    master = {k: np.zeros(1) for k in mlp.TRAINABLE}
+    m = {k: np.zeros(1) for k in mlp.TRAINABLE}
+    v = {k: np.zeros(1) for k in mlp.TRAINABLE}
+    return master, m, v
+
+
+def test_adam_steps_by_hand():
+    """Adam (Kingma and Ba, Algorithm 1) worked by hand on scalars.
+
+    Step 1: the bias-corrected moments are g and g^2, so every weight moves
+    by lr * g / (|g| + eps) whatever beta1, beta2 are (lr * sign(g) when
+    |g| >> eps, lr / 2 when |g| = eps: eps sits outside the square root).
+    Step 2 after gradients g1, g2: the corrected moments are the weighted
+    means (beta1 g1 + g2) / (1 + beta1) and (beta2 g1^2 + g2^2) / (1 + beta2).
+    A constant gradient keeps moving by lr * g / (|g| + eps) at every step.
+    Dropping the bias correction, squaring inside the wrong moment or moving
+    eps under the root each fails one of these."""
+    lr, b1, b2, eps = 1e-2, 0.9, 0.999, 1e-8
+    g_vals = {"W1": 0.5, "b1": -2.0, "W2": 1e-8, "b2": 3.0, "W3": -1e-8, "b3": 0.25}
+    master, m, v = _adam_state()
+    grads = {k: np.array([g_vals[k]]) for k in mlp.TRAINABLE}
+    work = mlp.adam_step(master, grads, m, v, 1, lr=lr, beta1=b1, beta2=b2, eps=eps)
+    for k, g in g_vals.items():
+        expect = -lr * g / (abs(g) + eps)
+        assert abs(master[k][0] - expect) <= 1e-15, (k, master[k][0], expect)
+    # |g| = eps: half a step, not lr * g / sqrt(g^2 + eps)
+    assert abs(master["W2"][0] + lr / 2) < 1e-15
+    # the working copy: BF16 weight matrices, FP32-exact biases
+    assert work["W1"][0] == mlp.bf16(master["W1"])[0] and work["b1"][0] == master["b1"][0]
+
+    # step 2 with a second gradient of opposite sign: (g1, g2) = (1, -1)
+    master, m, v = _adam_state()
+    for t, g in ((1, 1.0), (2, -1.0)):
+        grads = {k: np.array([g]) for k in mlp.TRAINABLE}
+        mlp.adam_step(master, grads, m, v, t, lr=lr, beta1=b1, beta2=b2, eps=eps)
+    mhat = (b1 * 1.0 + (-1.0)) / (1 + b1)          # -0.0526...
+    vhat = (b2 * 1.0 + 1.0) / (1 + b2)             # 1
+    expect = -lr * 1.0 / (1.0 + eps) - lr * mhat / (np.sqrt(vhat) + eps)
+    for k in mlp.TRAINABLE:
+        assert abs(master[k][0] - expect) <= 1e-15, (k, master[k][0], expect)
+
+    # constant gradient for five steps: five equal moves
+    master, m, v = _adam_state()
+    for t in range(1, 6):
+        grads = {k: np.array([0.3]) for k in mlp.TRAINABLE}
+        mlp.adam_step(master, grads, m, v, t, lr=lr, beta1=b1, beta2=b2, eps=eps)
+    for k in mlp.TRAINABLE:
+        assert abs(master[k][0] - (-5 * lr * 0.3 / (0.3 + eps))) <= 1e-14
