@@ -23,6 +23,11 @@ TRK_NONFINITE = 4
 TRK_S_NOT_PD = 8
 TRK_CAP_TRUNC = 16
 
+# rows of the build's decision margins (smallest distance of a decision of
+# that kind from its threshold, per seed)
+MARGIN_CHI2, MARGIN_WINDOW, MARGIN_GEOMETRY, MARGIN_GATE, MARGIN_LEARNED = range(5)
+N_MARGIN = 5
+
 
 def build_lib() -> str:
     cmd = ["gcc", "-O2", "-std=c99", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-o", _LIB,
@@ -342,7 +347,7 @@ def build(g, cuts, layer, xyz, cov, seed_par, seed_cov, q, n_seeds, seed_list=No
     L = g.n_layers
     o = dict(hits=np.zeros((L - F, ld), np.int32), par=np.zeros((6, ld)), cov=np.zeros((21, ld)),
              chi2=np.zeros(ld), nhits=np.zeros(ld, np.int32), status=np.zeros(ld, np.int32),
-             margin=np.zeros((3, ld)))
+             margin=np.zeros((N_MARGIN, ld)))
     bp = BuildParams()
     bp.chi2_cut = cuts.chi2_cut
     bp.max_holes = cuts.max_holes
@@ -371,6 +376,35 @@ def build(g, cuts, layer, xyz, cov, seed_par, seed_cov, q, n_seeds, seed_list=No
         raise ValueError("orc_build: bad arguments")
     del blob
     return {k: (v[..., :nl]) for k, v in o.items()}
+
+
+# Parity rule of the build: a seed is decidable when every decision of its
+# search lies further from its threshold than the GPU's arithmetic can move
+# it.  The GPU's hit tests and hit chi2 run in FP32 (positions rounded to
+# ~1e-5 cm, chi2 ~3e-5 at the cut of 30), crossings and state in the mode's
+# arithmetic; the network's widths carry BF16 activations.  The tolerances
+# are about ten times those effects.  A gate decision compares a plain
+# half-width (3 sqrt(S) from the covariance, ~1e-7 cm rounding even in FP32)
+# with a constant: 1e-5 cm.
+MARGIN_TOL = {MARGIN_CHI2: 1e-3, MARGIN_WINDOW: 1e-4, MARGIN_GEOMETRY: 1e-3, MARGIN_GATE: 1e-5,
+              MARGIN_LEARNED: 1e-3}
+
+
+def decidable(margin):
+    """Per-seed mask: every margin row above its tolerance (MARGIN_TOL)."""
+    m = np.asarray(margin)
+    ok = np.ones(m.shape[1], dtype=bool)
+    for row, tol in MARGIN_TOL.items():
+        ok &= m[row] > tol
+    return ok
+
+
+def undecidable_by_row(margin):
+    """Fraction of seeds each margin row alone makes undecidable."""
+    m = np.asarray(margin)
+    names = {MARGIN_CHI2: "chi2", MARGIN_WINDOW: "window", MARGIN_GEOMETRY: "geometry", MARGIN_GATE: "gate",
+             MARGIN_LEARNED: "learned"}
+    return {names[r]: float(np.mean(m[r] <= t)) for r, t in MARGIN_TOL.items()}
 
 
 def mlp_forward(blob, x):

@@ -860,13 +860,22 @@ static double minf(double a, double b) { return a < b ? a : b; }
  * (they use the position and its covariance block), and the outputs are
  * hybrid.
  *
- * out_margin[3][ld] records, per seed, the smallest distance of any
- * decision from its threshold: [0] chi2 (absolute: |chi2 - cut| of in-window
- * hits, chi2 gaps at equal nhits for cap cuts, record replacements and the
- * final choice), [1] window (distance in cm from the window edge of the
- * test that decided: R*| |dphi| - dphi_w | or | |dz| - dz_w |; also learned
- * width vs floor and plain width vs gate),
- * [2] geometry (normalised crossing discriminant, | |z| - z_half |/z_half).
+ * out_margin[5][ld] records, per seed, the smallest distance of any
+ * decision from its threshold, one row per kind of decision:
+ *   [0] chi2 (absolute: |chi2 - cut| of in-window hits, chi2 gaps at equal
+ *       nhits for cap cuts, record replacements and the final choice);
+ *   [1] plain window edges (cm: R*| |dphi| - dphi_w | or | |dz| - dz_w | of
+ *       the coordinate whose test decided, where that coordinate's width is
+ *       the covariance window's);
+ *   [2] geometry (normalised crossing discriminant, | |z| - z_half |/z_half);
+ *   [3] gate of the learned window (cm: distance of the plain half-widths
+ *       from the gates that decide whether the network is consulted);
+ *   [4] learned widths (cm: window edges of a coordinate whose width came
+ *       from the network, and learned width vs floor).
+ * A window decision is "in" iff both coordinates pass: if both pass, each
+ * coordinate's distance goes to its own row; if one fails, that one's; if
+ * both fail, the larger of the two (flipping the decision needs both) goes to
+ * the learned row when either width is learned, else to the plain row.
  */
 int orc_build(const orc_geometry* g, const orc_build_params* bp, int n_hits, const int32_t* layer,
               const float* xyz, const float* cov, int n_seeds, int ld, const float* seed_par,
@@ -899,7 +908,7 @@ int orc_build(const orc_geometry* g, const orc_build_params* bp, int n_hits, con
 
   for (int li = 0; li < n_list; ++li) {
     int i = seed_list ? seed_list[li] : li;
-    double mc2 = INFINITY, mwin = INFINITY, mgeo = INFINITY;
+    double mc2 = INFINITY, mwin = INFINITY, mgeo = INFINITY, mgate = INFINITY, mlrn = INFINITY;
     int seed_status = 0;
     cand_t fin;
     int have_fin = 0;
@@ -946,13 +955,13 @@ int orc_build(const orc_geometry* g, const orc_build_params* bp, int n_hits, con
         double w_rphi = (double)bp->nsigma * sqrt(Suu), w_z = (double)bp->nsigma * sqrt(Sww);
         /* learned window: consulted where the covariance window is wide (its
            arc or z half-width above the gate); elsewhere the plain window */
-        int gated = 0;
+        int gated = 0, lrn_rphi = 0, lrn_z = 0; /* a width from the network */
         if (bp->window_mode == 1) {
           double dr = w_rphi - bp->mlp[MLP_OFF_GATE], dz = w_z - bp->mlp[MLP_OFF_GATE + 1];
           gated = dr > 0.0 || dz > 0.0;
           /* distance of the gate decision from flipping (cm) */
           double gm = gated ? fmax(dr > 0.0 ? dr : 0.0, dz > 0.0 ? dz : 0.0) : fmin(-dr, -dz);
-          mwin = minf(mwin, gm);
+          mgate = minf(mgate, gm);
         }
         if (gated) {
           /* features: the Cartesian prediction and covariance (a hybrid
@@ -974,10 +983,10 @@ int orc_build(const orc_geometry* g, const orc_build_params* bp, int n_hits, con
           double kap = bp->mlp[MLP_OFF_KAPPA];
           double fl[2] = {bp->mlp[MLP_OFF_FLOOR], bp->mlp[MLP_OFF_FLOOR + 1]};
           double lw[2] = {kap * wl[0], kap * wl[1]};
-          mwin = minf(mwin, fabs(lw[0] - fl[0]));
-          mwin = minf(mwin, fabs(lw[1] - fl[1]));
-          if (!(lw[0] < fl[0])) w_rphi = lw[0];
-          if (!(lw[1] < fl[1])) w_z = lw[1];
+          mlrn = minf(mlrn, fabs(lw[0] - fl[0]));
+          mlrn = minf(mlrn, fabs(lw[1] - fl[1]));
+          if (!(lw[0] < fl[0])) { w_rphi = lw[0]; lrn_rphi = 1; }
+          if (!(lw[1] < fl[1])) { w_z = lw[1]; lrn_z = 1; }
         }
         double dphi_w = w_rphi / R, dz_w = w_z;
         double php = atan2(Xp[1], Xp[0]), zp = Xp[2];
@@ -989,8 +998,14 @@ int orc_build(const orc_geometry* g, const orc_build_params* bp, int n_hits, con
           double aph = fabs(dph), az = fabs(dz);
           int pph = aph <= dphi_w, pz = az <= dz_w;
           double mph = R * fabs(aph - dphi_w), mz = fabs(az - dz_w);
-          double dm = (pph && pz) ? minf(mph, mz) : (!pph && !pz) ? (mph > mz ? mph : mz) : (!pph ? mph : mz);
-          mwin = minf(mwin, dm);
+          double* row_ph = lrn_rphi ? &mlrn : &mwin;
+          double* row_z = lrn_z ? &mlrn : &mwin;
+          if (pph && pz) { *row_ph = minf(*row_ph, mph); *row_z = minf(*row_z, mz); }
+          else if (!pph && !pz) {
+            double* row = (lrn_rphi || lrn_z) ? &mlrn : &mwin;
+            *row = minf(*row, mph > mz ? mph : mz);
+          } else if (!pph) *row_ph = minf(*row_ph, mph);
+          else *row_z = minf(*row_z, mz);
           if (!(pph && pz)) continue;
           double hit[9] = {hx, hy, hz};
           for (int cc = 0; cc < 6; ++cc) hit[3 + cc] = (double)cov[(size_t)cc * N + hi];
@@ -1062,6 +1077,8 @@ int orc_build(const orc_geometry* g, const orc_build_params* bp, int n_hits, con
       out_margin[li] = mc2;
       out_margin[(size_t)ld + li] = mwin;
       out_margin[2 * (size_t)ld + li] = mgeo;
+      out_margin[3 * (size_t)ld + li] = mgate;
+      out_margin[4 * (size_t)ld + li] = mlrn;
     }
   }
   free(act); free(nxt); free(ch); free(stopped); free(stop_status); free(lay_cnt); free(lay_off); free(lay_idx);

@@ -98,19 +98,29 @@ def seed_rel_sigma_p(seed_par, seed_cov, n):
 
 
 FAILED_FIT_CHI2_PER_NDOF = 100.0
+# A failed fit's parameters move with the rounding of every step: one ulp of
+# its FP32 inputs moves the oracle's own result by more than 1e-4 in 70 % of
+# them, up to the far side of the detector (tests/test_oracle_fit.py measures
+# it).  They are held to status and ndof exactly, to finite parameters, and
+# as a population: the median relative difference of position and momentum
+# stays within the parity tolerance (FP64 rounding differences are 2^-29 of
+# an FP32 ulp, so most failed fits still agree).
+FAILED_FIT_MEDIAN_BOUND = 1e-4
+# the failed fits seen at the workloads: 5.7 % (fit_small), 6.4 % (fit_scale)
+FAILED_FIT_MAX_FRACTION = 0.10
 
 
 def converged_mask(orc, n):
     """Oracle fits that converged to a track: chi2/ndof <= 100.  Above that
     the fit follows no track (the Cartesian-momentum filter swings through
     states far from any helix from a poorly measured seed) and its parameters
-    are set by the rounding of every step; those fits are compared on status
-    and hit count only."""
+    are set by the rounding of every step; those fits are compared on status,
+    ndof and a loose bound only."""
     ndof = np.maximum(orc["ndof"][:n], 1)
     return orc["chi2"][:n] / ndof <= FAILED_FIT_CHI2_PER_NDOF
 
 
-def assert_fit_parity_converged(gpu, orc, n, ctx=""):
+def assert_fit_parity_converged(gpu, orc, n, ctx="", max_failed=FAILED_FIT_MAX_FRACTION):
     st_g = gpu["status"][:n]
     st_o = orc["status"][:n]
     assert np.array_equal(st_g, st_o), f"{ctx} status mismatch at {np.where(st_g != st_o)[0][:10]}"
@@ -118,5 +128,16 @@ def assert_fit_parity_converged(gpu, orc, n, ctx=""):
     keep = converged_mask(orc, n)
     sub = lambda d: {k: v[..., :n][..., keep] for k, v in d.items()}
     errs = assert_fit_parity(sub(gpu), sub(orc), int(keep.sum()), ctx)
-    errs["failed_fit_fraction"] = float(1 - keep.mean())
+    failed = ~keep
+    errs["failed_fit_fraction"] = float(failed.mean()) if n else 0.0
+    assert errs["failed_fit_fraction"] <= max_failed, f"{ctx}: {errs['failed_fit_fraction']:.3f} failed fits"
+    if failed.any():
+        pg = gpu["par"][:, :n][:, failed].astype(np.float64)
+        po = orc["par"][:, :n][:, failed]
+        fin = np.all(np.isfinite(pg), axis=0)
+        assert fin.all(), f"{ctx}: non-finite failed fit"
+        e = np.maximum(rel_vec_err(pg[:3], po[:3]), rel_vec_err(pg[3:], po[3:]))
+        errs["failed_fit_median_rel"] = float(np.median(e))
+        errs["failed_fit_max_rel"] = float(e.max())
+        assert np.median(e) <= FAILED_FIT_MEDIAN_BOUND, f"{ctx}: failed fits median {np.median(e):.3g}"
     return errs

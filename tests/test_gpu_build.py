@@ -29,8 +29,18 @@ def kf():
 
 
 def decidable(o):
-    m = o["margin"]
-    return (m[0] > 1e-3) & (m[1] > 1e-4) & (m[2] > 1e-3)
+    return oracle.decidable(o["margin"])
+
+
+# Bounds on what the parity comparison excludes.  The fraction of undecidable
+# seeds grows with the number of decisions a seed makes (about 70 predicted
+# candidate-layers, 20-40 hits window-tested per candidate-layer): 8 % on 400
+# seeds of the full build event (chi2 row 4.3 %, window row 3.8 %), 2-17 %
+# over 63-seed samples of single events.  Seeds whose lists differ must be
+# undecidable and stay rare: none has been seen in any run.
+UNDECIDABLE_MAX = 0.15
+UNDECIDABLE_MAX_SMALL_SAMPLE = 0.25  # fewer than 100 seeds
+MISMATCH_MAX_FRACTION = 0.01
 
 
 def gpu_build_event(kf, w, ev, arith, cap=None, lanes=0, blocks=0, order=None, seeds=None, refine=0):
@@ -78,7 +88,15 @@ def compare(g, o, n_cols, cols_g=None, ctx="", check_params=True):
         em = rel_vec_err(pg[3:], po[3:])
         assert ep[conv].max(initial=0) <= 1e-4 and em[conv].max(initial=0) <= 1e-4, \
             f"{ctx}: params {ep[conv].max():.3g} {em[conv].max():.3g}"
-    return dict(undecidable=float(1 - dec.mean()), mismatched=int((~ok).sum()), n=int(n_cols))
+    rows = oracle.undecidable_by_row(o["margin"][:, :n_cols])
+    und = float(1 - dec.mean()) if n_cols else 0.0
+    mism = int((~ok).sum())
+    # the exclusions are bounded: few undecidable seeds, and fewer still
+    # whose lists differ
+    bound = UNDECIDABLE_MAX if n_cols >= 100 else UNDECIDABLE_MAX_SMALL_SAMPLE
+    assert und <= bound, f"{ctx}: {und:.3f} undecidable (by row {rows})"
+    assert mism <= max(1, int(MISMATCH_MAX_FRACTION * n_cols)), f"{ctx}: {mism} of {n_cols} seeds differ"
+    return dict(undecidable=und, by_row=rows, mismatched=mism, n=int(n_cols))
 
 
 def test_build_parity_small_event(kf):

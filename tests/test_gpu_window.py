@@ -13,6 +13,9 @@ torch = pytest.importorskip("torch")
 
 from gpu_common import host, to_dev  # noqa: E402
 
+# undecidable seeds of a learned build of a 500-track event (measured 0.02-0.08)
+UNDECIDABLE_MAX_LEARNED = 0.15
+
 
 @pytest.fixture(scope="module")
 def env():
@@ -102,14 +105,18 @@ def test_learned_build_matches_oracle(env, gate_q, state):
     so = oracle.seed(w.geometry, H, n)
     o = oracle.build(w.geometry, w.cuts, ev.layer, ev.xyz, ev.cov, so["par"], so["cov"], so["q"], n,
                      window_mode=1, mlp_blob=oracle_blob(kf, t, 1.5), state=state)
-    m = o["margin"]
-    # learned widths carry BF16 rounding of activations: window edges further
-    # than 1e-3 cm (a tenth of the arc resolution) decide
-    dec = (m[0] > 1e-3) & (m[1] > 1e-3) & (m[2] > 1e-3)
+    # learned widths carry BF16 rounding of activations: their window edges
+    # and floors decide beyond 1e-3 cm (a tenth of the arc resolution); gate
+    # decisions and plain-window edges at the plain tolerance (1e-4 cm)
+    dec = oracle.decidable(o["margin"])
     same = np.all(g["hits"][:, :n] == o["hits"], axis=0) & (g["nhits"][:n] == o["nhits"])
-    print(f"learned build (state {state}, gates {gr:.4f}, {gz:.4f}): undecidable {1 - dec.mean():.4f}, "
-          f"identical {same.mean():.4f}")
+    rows = oracle.undecidable_by_row(o["margin"])
+    print(f"learned build (state {state}, gates {gr:.4f}, {gz:.4f}): undecidable {1 - dec.mean():.4f} "
+          f"(by row {rows}), identical {same.mean():.4f}")
     assert same[dec].all(), np.where(dec & ~same)[0][:10]
+    # bounds: the excluded seeds stay few, and so do differing ones among them
+    assert 1 - dec.mean() <= UNDECIDABLE_MAX_LEARNED, rows
+    assert (~same).sum() <= max(2, int(0.01 * n))
 
 
 @pytest.mark.parametrize("arith,state", [("f32", 0), ("f64", 0), ("f32", 1), ("f64", 1)])

@@ -198,8 +198,10 @@ def test_build_efficiency_and_margins():
     assert eff.mean() > 0.6
     # decidable: chi2 gaps above 1e-3, window edges further than 1e-4 cm,
     # crossing and barrel-end tests further than 1e-3 relative
-    decidable = (o["margin"][0] > 1e-3) & (o["margin"][1] > 1e-4) & (o["margin"][2] > 1e-3)
+    decidable = oracle.decidable(o["margin"])
     assert decidable.mean() > 0.85
+    # the plain build makes no gate or learned-width decision
+    assert np.all(np.isinf(o["margin"][oracle.MARGIN_GATE])) and np.all(np.isinf(o["margin"][oracle.MARGIN_LEARNED]))
 
 
 def _window_network(seed, kappa, gates):

@@ -219,3 +219,48 @@ def test_failed_step_freezes_track():
     hm[2] = (1 << 4) | (1 << 7)
     o2 = oracle.fit(w.geometry, 3, H, sd["par"], sd["cov"], sd["q"], 64, hole_mask=hm)
     assert o2["ndof"][2] == 2 * (w.geometry.n_layers - 3 - 2)
+
+
+def _one_ulp(a, rng):
+    """Every element moved by one FP32 ulp, up or down at random."""
+    a = a.astype(np.float32)
+    up = rng.integers(0, 2, a.shape).astype(bool)
+    return np.where(up, np.nextafter(a, np.float32(np.inf)), np.nextafter(a, np.float32(-np.inf))).astype(np.float32)
+
+
+def test_failed_fits_move_with_one_ulp_of_their_inputs():
+    """Why the GPU parity tests compare fits with chi2/ndof > 100 on status,
+    ndof and as a population only: the oracle's own result for those fits moves
+    by more than the 1e-4 parameter tolerance when its FP32 inputs (hit
+    positions and seed state) move by one ulp, while converged fits stay put.
+    The two populations are measured on the fit workload (10 layers, 1 000
+    tracks) under four independent perturbations."""
+    w = presets.fit_small()
+    ev = datagen.generate(w.geometry, w.gen, 0, 1000)
+    n = ev.n_tracks
+    H = datagen.track_hits(ev)
+    so = oracle.seed(w.geometry, H, n)
+    F = 3
+    o = oracle.fit(w.geometry, F, H, so["par"], so["cov"], so["q"], n)
+    failed = o["chi2"][:n] / np.maximum(o["ndof"][:n], 1) > 100
+    rng = np.random.default_rng(7)
+    spread = np.zeros(n)
+    for _ in range(4):
+        H2 = H.copy()
+        H2[F:, 0:3] = _one_ulp(H[F:, 0:3], rng)
+        o2 = oracle.fit(w.geometry, F, H2, _one_ulp(so["par"], rng), so["cov"], so["q"], n)
+        po, p2 = o["par"][:, :n], o2["par"][:, :n]
+        ep = np.linalg.norm(p2[:3] - po[:3], axis=0) / np.linalg.norm(po[:3], axis=0)
+        em = np.linalg.norm(p2[3:] - po[3:], axis=0) / np.linalg.norm(po[3:], axis=0)
+        spread = np.maximum(spread, np.maximum(ep, em))
+    frac_failed = failed.mean()
+    moved_failed = np.mean(spread[failed] > 1e-4)
+    moved_conv = np.mean(spread[~failed] > 1e-4)
+    print(f"failed fits {frac_failed:.3f}: {moved_failed:.2f} move by > 1e-4 (max {spread[failed].max():.3g}); "
+          f"converged: {moved_conv:.4f} (median {np.median(spread[~failed]):.2g})")
+    # measured: 5.7 % failed fits, 70 % of them move by > 1e-4 (up to 0.4);
+    # 1.8 % of converged fits do, median 2e-6
+    assert 0.02 < frac_failed < 0.12
+    assert moved_failed > 0.5
+    assert moved_conv < 0.05
+    assert np.median(spread[~failed]) < 1e-5
