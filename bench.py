@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--events", type=int, default=None, help="override the number of events (testing)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=25.0)
     ap.add_argument("--arith", choices=["f32", "f64"], default="f64",
                     help="arithmetic of the fit and build kernels (storage is FP32)")
     ap.add_argument("--no-other-arith", action="store_true")
@@ -177,39 +177,54 @@ def batched(arith, autotune, log):
     return res
 
 
-def cpu_baseline(w, eb, seconds):
-    """FP64 oracle: brute-force build then fit, seed by seed, on event 0."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, eb, seconds, max_threads=16):
+    """FP64 oracle on the host cores: brute-force build (every hit of a layer
+    is window-tested, no binning), then the fit of the built lists, seed by
+    seed.  Single thread on event 0, then one thread per event (events 0..T-1)
+    on all usable cores (capped at the machine's CPU share of 16); the oracle's C
+    calls release the interpreter lock.  Seeding is outside the timed loops,
+    as on the GPU."""
+    import threading
     import oracle
     L = w.geometry.n_layers
     F = w.cuts.first_layer
-    h0, h1 = int(eb.hit_offsets[0]), int(eb.hit_offsets[1])
-    n0 = int(eb.seed_offsets[1])
-    xyz = np.ascontiguousarray(eb.xyz[:, h0:h1])
-    cov = np.ascontiguousarray(eb.cov[:, h0:h1])
-    layer = np.ascontiguousarray(eb.layer[h0:h1])
-    ld = ((n0 + 63) // 64) * 64
-    Hs = np.zeros((3, 9, ld), dtype=np.float32)
-    Hs[:, :, :n0] = eb.seed_hits[:, :, :n0]
-    so = oracle.seed(w.geometry, Hs, n0)
-    done = 0
-    chunk = 8
-    t0 = time.perf_counter()
-    k = 0
-    while time.perf_counter() - t0 < seconds:
-        lst = (np.arange(chunk) * 2503 + k * chunk * 7919) % n0
-        ob = oracle.build(w.geometry, w.cuts, layer, xyz, cov, so["par"], so["cov"], so["q"], n0, seed_list=lst)
-        # fit the built tracks from their seeds
+
+    def event_inputs(e):
+        h0, h1 = int(eb.hit_offsets[e]), int(eb.hit_offsets[e + 1])
+        s0, s1 = int(eb.seed_offsets[e]), int(eb.seed_offsets[e + 1])
+        ne = s1 - s0
+        xyz = np.ascontiguousarray(eb.xyz[:, h0:h1])
+        cov = np.ascontiguousarray(eb.cov[:, h0:h1])
+        layer = np.ascontiguousarray(eb.layer[h0:h1])
+        ld = ((ne + 63) // 64) * 64
+        Hs = np.zeros((3, 9, ld), dtype=np.float32)
+        Hs[:, :, :ne] = eb.seed_hits[:, :, s0:s1]
+        return xyz, cov, layer, ne, oracle.seed(w.geometry, Hs, ne)
+
+    def chunk(inp, k, chunk_n=8):
+        xyz, cov, layer, ne, so = inp
+        lst = (np.arange(chunk_n) * 2503 + k * chunk_n * 7919) % ne
+        ob = oracle.build(w.geometry, w.cuts, layer, xyz, cov, so["par"], so["cov"], so["q"], ne, seed_list=lst)
         m = lst.size
+        hb = ob["hits"][:, :m]
         Hf = np.zeros((L, 9, 64), dtype=np.float32)
         hm = np.zeros(64, dtype=np.uint32)
-        for j in range(m):
-            for l in range(F, L):
-                h = ob["hits"][l - F, j]
-                if h < 0:
-                    hm[j] |= 1 << l
-                else:
-                    Hf[l, 0:3, j] = xyz[:, h]
-                    Hf[l, 3:9, j] = cov[:, h]
+        for l in range(F, L):
+            h = hb[l - F]
+            have = h >= 0
+            Hf[l, 0:3, :m][:, have] = xyz[:, h[have]]
+            Hf[l, 3:9, :m][:, have] = cov[:, h[have]]
+            hm[:m] |= np.where(have, 0, 1 << l).astype(np.uint32)
         sp = np.zeros((6, 64), np.float32)
         sc = np.zeros((21, 64), np.float32)
         q = np.ones(64, np.int8)
@@ -217,12 +232,52 @@ def cpu_baseline(w, eb, seconds):
         sc[:, :m] = so["cov"][:, lst]
         q[:m] = so["q"][lst]
         oracle.fit(w.geometry, F, Hf, sp, sc, q, m, hole_mask=hm)
-        done += m
+        return m
+
+    # single core
+    inp0 = event_inputs(0)
+    t_single = 0.4 * seconds
+    done1, k, t0 = 0, 0, time.perf_counter()
+    while time.perf_counter() - t0 < t_single:
+        done1 += chunk(inp0, k)
         k += 1
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "tracks/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} seeds of fit_scale event 0 (20000 tracks): brute-force build over {L} layers "
-                      f"then fit, FP64 oracle, single thread, {dt:.1f} s"}
+    dt1 = time.perf_counter() - t0
+    # all cores: one event per thread
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    T = max(1, min(usable, max_threads, w.n_events))
+    inputs = [None] * T
+    done = [0] * T
+    ready = threading.Barrier(T + 1)
+    t_all = 0.6 * seconds
+    stop = [0.0]
+
+    def worker(t):
+        inputs[t] = event_inputs(t)
+        ready.wait()
+        kk = 0
+        while time.perf_counter() < stop[0]:
+            done[t] += chunk(inputs[t], kk)
+            kk += 1
+
+    th = [threading.Thread(target=worker, args=(t,)) for t in range(T)]
+    for x in th:
+        x.start()
+    stop[0] = float("inf")
+    ready.wait()
+    tA = time.perf_counter()
+    stop[0] = tA + t_all
+    for x in th:
+        x.join()
+    dtA = time.perf_counter() - tA
+    rate_all = sum(done) / dtA
+    return {"value": round(rate_all, 2), "unit": "tracks/s", "cores": T, "kind": "oracle",
+            "host_cores": os.cpu_count(), "usable_cores": usable, "cpu_model": _cpu_model(),
+            "single_core": {"value": round(done1 / dt1, 2), "seeds": done1, "seconds": round(dt1, 1)},
+            "sample": f"fit_scale events 0..{T - 1} (20000 tracks each), {sum(done)} seeds in {dtA:.1f} s on "
+                      f"{T} threads (one event per thread), seeds spread over each event; per seed a brute-force "
+                      f"FP64 oracle build over {L} layers (every hit of a layer window-tested; the GPU path "
+                      f"searches binned hits) then the FP64 oracle fit of the built list; single core: "
+                      f"{done1} seeds of event 0 in {dt1:.1f} s"}
 
 
 def main():
