@@ -48,6 +48,14 @@ class BuildParams(ctypes.Structure):
                 ("state", ctypes.c_int32)]
 
 
+class Detector(ctypes.Structure):
+    _fields_ = [("n_layers", ctypes.c_int32), ("kind", ctypes.c_int32 * 32), ("pos", ctypes.c_float * 32),
+                ("lo", ctypes.c_float * 32), ("hi", ctypes.c_float * 32), ("dmod", ctypes.c_float * 32),
+                ("bz", ctypes.c_float), ("x_over_x0", ctypes.c_float), ("mass", ctypes.c_float)]
+
+
+BARREL, DISK = 0, 1
+
 _lib = None
 
 
@@ -89,6 +97,19 @@ def lib():
                                 P, P, P, P, P, P, P, P]
         L.orc_mlp_forward.argtypes = [P, P, P]
         L.orc_mlp_blob_size.argtypes = []
+        DP = ctypes.POINTER(Detector)
+        L.orc_cyl_path.argtypes = [P, I, D, D, I, P, P]
+        L.orc_plane_path.argtypes = [P, D, I, P]
+        L.orc_jacobian_surf.argtypes = [P, I, D, D, I, P]
+        L.orc_jacobian_surf.restype = None
+        L.orc_ms_cov_surf.argtypes = [P, I, D, D, P]
+        L.orc_ms_cov_surf.restype = None
+        L.orc_step_surf.argtypes = [DP, I, D, I, I, P, I, P, P, P, P]
+        L.orc_update_disk.argtypes = [P, P, P, P, P, P]
+        L.orc_fit_det.argtypes = [DP, I, I, I] + [P] * 11
+        L.orc_fit_det64.argtypes = [DP, I, I, I] + [P] * 10
+        L.orc_hit_bin_det.argtypes = [DP, I, I, I, P, P, P, P, P]
+        L.orc_build_det.argtypes = [DP, ctypes.POINTER(BuildParams), I, P, P, P, I, I, P, P, P, I, P] + [P] * 8
         _lib = L
     return _lib
 
@@ -417,3 +438,160 @@ def mlp_forward(blob, x):
 
 def mlp_blob_size() -> int:
     return int(lib().orc_mlp_blob_size())
+
+
+# ------------------------------------------------------------ general detector
+
+def detector(d) -> Detector:
+    """From a presets.Detector."""
+    o = Detector()
+    o.n_layers = d.n_layers
+    for i in range(d.n_layers):
+        o.kind[i] = d.kind[i]
+        o.pos[i], o.lo[i], o.hi[i], o.dmod[i] = d.pos[i], d.lo[i], d.hi[i], d.dmod[i]
+    o.bz, o.x_over_x0, o.mass = d.bz, d.x_over_x0, d.mass
+    return o
+
+
+def cyl_path(X, q, R, bz, nearest=False):
+    """Path s to the crossing with r = R (first ahead, or the nearest either
+    way); None when the circles do not meet."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    s = ctypes.c_double(0)
+    dsc = ctypes.c_double(0)
+    rc = lib().orc_cyl_path(_p(X), int(q), float(R), float(bz), int(nearest), ctypes.byref(s), ctypes.byref(dsc))
+    return None if rc else s.value
+
+
+def plane_path(X, Z, nearest=False):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    s = ctypes.c_double(0)
+    rc = lib().orc_plane_path(_p(X), float(Z), int(nearest), ctypes.byref(s))
+    return None if rc else s.value
+
+
+def jacobian_surf(X, q, bz, s, kind):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    J = np.zeros(36)
+    lib().orc_jacobian_surf(_p(X), int(q), float(bz), float(s), int(kind), _p(J))
+    return J.reshape(6, 6)
+
+
+def ms_cov_surf(X, kind, x_over_x0, mass):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    Q = np.zeros(36)
+    lib().orc_ms_cov_surf(_p(X), int(kind), float(x_over_x0), float(mass), _p(Q))
+    return Q.reshape(6, 6)
+
+
+def step_surf(d, kind, value, X, q, P, nearest=False, material=True):
+    """One step to a surface (cylinder r = value or plane z = value): state,
+    transported covariance (+ scattering); None on failure."""
+    dd = detector(d)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    P = np.ascontiguousarray(P, dtype=np.float64).reshape(36)
+    Xo, Po = np.zeros(6), np.zeros(36)
+    rc = lib().orc_step_surf(ctypes.byref(dd), int(kind), float(value), int(nearest), int(material), _p(X), int(q),
+                             _p(P), _p(Xo), _p(Po), None)
+    return None if rc else (Xo, Po.reshape(6, 6))
+
+
+def update_disk(X, P, hit):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    P = np.ascontiguousarray(P, dtype=np.float64).reshape(36)
+    hit = np.ascontiguousarray(hit, dtype=np.float64)
+    Xo, Po, c2 = np.zeros(6), np.zeros(36), ctypes.c_double(0)
+    rc = lib().orc_update_disk(_p(X), _p(P), _p(hit), _p(Xo), _p(Po), ctypes.byref(c2))
+    return None if rc else (Xo, Po.reshape(6, 6), c2.value)
+
+
+def _fit_out(ld):
+    return dict(par=np.zeros((6, ld)), cov=np.zeros((21, ld)), chi2=np.zeros(ld), ndof=np.zeros(ld, np.int32),
+                status=np.zeros(ld, np.int32))
+
+
+def fit_det(d, first_layer, hits, visit, seed_par, seed_cov, q, n, hole_mask=None):
+    """Fit over a general detector: hits [L][9][ld] FP32, visit [ld] uint32
+    (bit l: the track crosses layer l), hole_mask (bit l: no hit there)."""
+    dd = detector(d)
+    hits = np.ascontiguousarray(hits, dtype=np.float32)
+    ld = hits.shape[2]
+    o = _fit_out(ld)
+    visit = np.ascontiguousarray(visit, dtype=np.uint32)
+    hm = None if hole_mask is None else np.ascontiguousarray(hole_mask, dtype=np.uint32)
+    sp = np.ascontiguousarray(seed_par, dtype=np.float32)
+    sc = np.ascontiguousarray(seed_cov, dtype=np.float32)
+    q = np.ascontiguousarray(q, dtype=np.int8)
+    rc = lib().orc_fit_det(ctypes.byref(dd), n, ld, first_layer, _p(hits), _p(visit), _p(hm), _p(sp), _p(sc), _p(q),
+                           _p(o["par"]), _p(o["cov"]), _p(o["chi2"]), _p(o["ndof"]), _p(o["status"]))
+    if rc:
+        raise ValueError("orc_fit_det: bad arguments")
+    return o
+
+
+def fit_det64(d, first_layer, hits, visit, seed_par, seed_cov, q, n):
+    dd = detector(d)
+    hits = np.ascontiguousarray(hits, dtype=np.float64)
+    ld = hits.shape[2]
+    o = _fit_out(ld)
+    visit = np.ascontiguousarray(visit, dtype=np.uint32)
+    sp = np.ascontiguousarray(seed_par, dtype=np.float64)
+    sc = np.ascontiguousarray(seed_cov, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.int8)
+    rc = lib().orc_fit_det64(ctypes.byref(dd), n, ld, first_layer, _p(hits), _p(visit), _p(sp), _p(sc), _p(q),
+                             _p(o["par"]), _p(o["cov"]), _p(o["chi2"]), _p(o["ndof"]), _p(o["status"]))
+    if rc:
+        raise ValueError("orc_fit_det64: bad arguments")
+    return o
+
+
+def hit_bin_det(d, n_phi, n_w, layer, xyz):
+    dd = detector(d)
+    layer = np.ascontiguousarray(layer, dtype=np.int32)
+    xyz = np.ascontiguousarray(xyz, dtype=np.float32)
+    n = layer.shape[0]
+    offsets = np.zeros((d.n_layers, n_phi * n_w + 1), np.int32)
+    order = np.zeros(max(n, 1), np.int32)
+    phi = np.zeros(max(n, 1), np.float32)
+    rc = lib().orc_hit_bin_det(ctypes.byref(dd), n_phi, n_w, n, _p(layer), _p(xyz), _p(offsets), _p(order), _p(phi))
+    if rc:
+        raise ValueError("orc_hit_bin_det: bad arguments")
+    return dict(offsets=offsets, order=order[:n], phi=phi[:n])
+
+
+def build_det(d, cuts, layer, xyz, cov, seed_par, seed_cov, q, n_seeds, seed_list=None, cap=None):
+    """Brute-force combinatorial build over a general detector (two-step
+    propagation, next layer per candidate).  Outputs indexed by position in
+    seed_list; hits [L - F][.] per layer, visit masks."""
+    dd = detector(d)
+    ld = seed_par.shape[1]
+    lst = None if seed_list is None else np.ascontiguousarray(seed_list, dtype=np.int32)
+    nl = n_seeds if lst is None else lst.shape[0]
+    F = cuts.first_layer
+    L = d.n_layers
+    o = dict(hits=np.zeros((L - F, ld), np.int32), visit=np.zeros(ld, np.uint32), par=np.zeros((6, ld)),
+             cov=np.zeros((21, ld)), chi2=np.zeros(ld), nhits=np.zeros(ld, np.int32), status=np.zeros(ld, np.int32),
+             margin=np.zeros((N_MARGIN, ld)))
+    bp = BuildParams()
+    bp.chi2_cut = cuts.chi2_cut
+    bp.max_holes = cuts.max_holes
+    bp.cand_cap = cuts.cand_cap if cap is None else cap
+    bp.nsigma = cuts.nsigma
+    bp.win_sig_rphi = cuts.win_sig_rphi
+    bp.win_sig_z = cuts.win_sig_z
+    bp.first_layer = F
+    bp.window_mode = 0
+    bp.state = 0
+    xyz = np.ascontiguousarray(xyz, dtype=np.float32)
+    cov = np.ascontiguousarray(cov, dtype=np.float32)
+    layer = np.ascontiguousarray(layer, dtype=np.int32)
+    sp = np.ascontiguousarray(seed_par, dtype=np.float32)
+    sc = np.ascontiguousarray(seed_cov, dtype=np.float32)
+    q = np.ascontiguousarray(q, dtype=np.int8)
+    rc = lib().orc_build_det(ctypes.byref(dd), ctypes.byref(bp), layer.shape[0], _p(layer), _p(xyz), _p(cov),
+                             n_seeds, ld, _p(sp), _p(sc), _p(q), nl, _p(lst), _p(o["hits"]), _p(o["visit"]),
+                             _p(o["par"]), _p(o["cov"]), _p(o["chi2"]), _p(o["nhits"]), _p(o["status"]),
+                             _p(o["margin"]))
+    if rc:
+        raise ValueError("orc_build_det: bad arguments")
+    return {k: (v[..., :nl]) for k, v in o.items()}

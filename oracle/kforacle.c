@@ -114,24 +114,19 @@ int orc_propagate(const double X[6], int q, double R, double bz, double Xo[6], d
   return 0;
 }
 
-/*
- * Jacobian of "state -> state at the crossing with the cylinder".
- * J = Js + w g^T, where Js = dX(s)/dX0 at fixed path s, w = dX/ds at the
- * crossing, and g = ds/dX0 = -(n . Js[x,y rows]) / (n . w[x,y]) keeps the
- * end point on the cylinder (n = radial unit vector at the crossing).
- */
-void orc_jacobian(const double X[6], int q, double bz, double s, double J[36]) {
+/* Js = dX(s)/dX0 at fixed transverse path s, and w = dX/ds at the end point
+ * (the end state is returned in Xo). */
+static void jacobian_fixed_path(const double X[6], int q, double bz, double s, double Js[36], double w[6],
+                                double Xo[6]) {
   double px = X[3], py = X[4], pz = X[5];
   double pt2 = px * px + py * py, pt = sqrt(pt2);
   double h = -(double)q * KAPPA * bz / pt;
   double a = h * s, ca = cos(a), sa = sin(a);
   double c = pt * h; /* = -q KAPPA bz, independent of pT */
-  double Xo[6];
   orc_state_at(X, q, bz, s, Xo);
   double px1 = Xo[3], py1 = Xo[4];
   double da_dpx = -a * px / pt2, da_dpy = -a * py / pt2;
-  double Js[36];
-  memset(Js, 0, sizeof(Js));
+  memset(Js, 0, sizeof(double) * 36);
   Js[0 * 6 + 0] = 1.0; Js[1 * 6 + 1] = 1.0; Js[2 * 6 + 2] = 1.0;
   Js[0 * 6 + 3] = (sa + px1 * da_dpx) / c;
   Js[0 * 6 + 4] = (-(1.0 - ca) + px1 * da_dpy) / c;
@@ -145,7 +140,18 @@ void orc_jacobian(const double X[6], int q, double bz, double s, double J[36]) {
   Js[4 * 6 + 3] = sa + px1 * da_dpx;
   Js[4 * 6 + 4] = ca + px1 * da_dpy;
   Js[5 * 6 + 5] = 1.0;
-  double w[6] = {px1 / pt, py1 / pt, pz / pt, -h * py1, h * px1, 0.0};
+  w[0] = px1 / pt; w[1] = py1 / pt; w[2] = pz / pt; w[3] = -h * py1; w[4] = h * px1; w[5] = 0.0;
+}
+
+/*
+ * Jacobian of "state -> state at the crossing with the cylinder".
+ * J = Js + w g^T, where Js = dX(s)/dX0 at fixed path s, w = dX/ds at the
+ * crossing, and g = ds/dX0 = -(n . Js[x,y rows]) / (n . w[x,y]) keeps the
+ * end point on the cylinder (n = radial unit vector at the crossing).
+ */
+void orc_jacobian(const double X[6], int q, double bz, double s, double J[36]) {
+  double Js[36], w[6], Xo[6];
+  jacobian_fixed_path(X, q, bz, s, Js, w, Xo);
   double r = sqrt(Xo[0] * Xo[0] + Xo[1] * Xo[1]);
   double nx = Xo[0] / r, ny = Xo[1] / r;
   double den = nx * w[0] + ny * w[1];
@@ -1082,5 +1088,582 @@ int orc_build(const orc_geometry* g, const orc_build_params* bp, int n_hits, con
     }
   }
   free(act); free(nxt); free(ch); free(stopped); free(stop_status); free(lay_cnt); free(lay_off); free(lay_idx);
+  return 0;
+}
+
+/* ===================================================================
+ * General detector (section 4.1): barrel cylinders and endcap disks (the
+ * "cylinder with lids"), whose modules may sit off the layer's average
+ * surface.  Track building propagates in two steps: to the layer's average
+ * surface (average radius of a barrel layer, average z of a disk), then from
+ * there to the surface of each candidate hit; the update is made at the
+ * hit.  A barrel hit is measured on the plane tangent to the cylinder
+ * through the hit (section 4.1), a disk hit in the disk's plane (x, y).
+ * =================================================================== */
+
+static int det_kind_ok(const orc_detector* d, int l) { return d->kind[l] == ORC_BARREL || d->kind[l] == ORC_DISK; }
+
+/*
+ * Crossing of the helix with the cylinder r = R.  nearest = 0: the first
+ * crossing along the motion (s > 0, as orc_propagate); nearest = 1: the
+ * crossing reached by the shortest path forwards or backwards (s of either
+ * sign), the second step from a layer's average surface to a hit's.
+ * Returns ORC_TRK_NO_CROSSING if the circles do not meet; *disc as
+ * orc_propagate.
+ */
+int orc_cyl_path(const double X[6], int q, double R, double bz, int nearest, double* s_out, double* disc) {
+  double px = X[3], py = X[4];
+  double pt = sqrt(px * px + py * py);
+  if (disc) *disc = INFINITY;
+  if (!(pt > 0.0) || bz == 0.0) return ORC_TRK_NO_CROSSING;
+  double h = -(double)q * KAPPA * bz / pt;
+  double cx = X[0] - py / (pt * h), cy = X[1] + px / (pt * h);
+  double rho = 1.0 / fabs(h);
+  double d = sqrt(cx * cx + cy * cy);
+  if (!(d > 0.0) || d > R + rho || d < fabs(R - rho)) return ORC_TRK_NO_CROSSING;
+  double a = (R * R - rho * rho + d * d) / (2.0 * d);
+  double b2 = R * R - a * a;
+  if (b2 < 0.0) b2 = 0.0;
+  if (disc) *disc = b2 / (R * R);
+  double b = sqrt(b2);
+  double best = INFINITY;
+  for (int sgn = -1; sgn <= 1; sgn += 2) {
+    double Px = (a / d) * cx + sgn * (b / d) * (-cy);
+    double Py = (a / d) * cy + sgn * (b / d) * cx;
+    double ux = X[0] - cx, uy = X[1] - cy;
+    double vx = Px - cx, vy = Py - cy;
+    double alpha = atan2(ux * vy - uy * vx, ux * vx + uy * vy); /* (-pi, pi] */
+    if (!nearest) {
+      if (h > 0.0 && alpha <= 0.0) alpha += TWO_PI;
+      if (h < 0.0 && alpha >= 0.0) alpha -= TWO_PI;
+    }
+    double s = alpha / h;
+    if (nearest ? fabs(s) < fabs(best) : s < best) best = s;
+  }
+  *s_out = best;
+  return 0;
+}
+
+/*
+ * Crossing with the plane z = Z: z(s) = z + pz s / pT gives s = (Z - z) pT / pz.
+ * nearest = 0 requires s > 0 (the plane lies ahead); nearest = 1 takes s of
+ * either sign.  A track parallel to the plane (pz = 0) has no crossing.
+ */
+int orc_plane_path(const double X[6], double Z, int nearest, double* s_out) {
+  double pt = sqrt(X[3] * X[3] + X[4] * X[4]);
+  if (!(pt > 0.0) || X[5] == 0.0) return ORC_TRK_NO_CROSSING;
+  double s = (Z - X[2]) * pt / X[5];
+  if (!nearest && !(s > 0.0)) return ORC_TRK_NO_CROSSING;
+  if (!isfinite(s)) return ORC_TRK_NO_CROSSING;
+  *s_out = s;
+  return 0;
+}
+
+/* Unit normal of a surface at point x: radial for a cylinder, zhat for a plane. */
+static void surface_normal(int kind, const double x[3], double n[3]) {
+  if (kind == ORC_DISK) { n[0] = 0.0; n[1] = 0.0; n[2] = 1.0; return; }
+  double r = sqrt(x[0] * x[0] + x[1] * x[1]);
+  n[0] = x[0] / r; n[1] = x[1] / r; n[2] = 0.0;
+}
+
+/*
+ * Jacobian of "state -> state on the surface" (cylinder: kind = barrel,
+ * plane: kind = disk) after the path s: J = Js + w g^T with
+ * g = ds/dX0 = -(n . Js[position rows]) / (n . w[position]), n the surface
+ * normal at the end point.  The end point stays on the surface, so every
+ * transported covariance has the null vector (n, 0, 0, 0).
+ */
+void orc_jacobian_surf(const double X[6], int q, double bz, double s, int kind, double J[36]) {
+  double Js[36], w[6], Xo[6], n[3];
+  jacobian_fixed_path(X, q, bz, s, Js, w, Xo);
+  surface_normal(kind, Xo, n);
+  double den = n[0] * w[0] + n[1] * w[1] + n[2] * w[2];
+  double g[6];
+  for (int j = 0; j < 6; ++j) g[j] = -(n[0] * Js[0 * 6 + j] + n[1] * Js[1 * 6 + j] + n[2] * Js[2 * 6 + j]) / den;
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) J[i * 6 + j] = Js[i * 6 + j] + w[i] * g[j];
+}
+
+/* Highland noise of a thin layer crossed at X: as orc_ms_cov with the
+ * incidence measured from the normal of the surface (radial or zhat). */
+void orc_ms_cov_surf(const double X[6], int kind, double x_over_x0, double mass, double Q[36]) {
+  memset(Q, 0, sizeof(double) * 36);
+  if (!(x_over_x0 > 0.0)) return;
+  double p2 = X[3] * X[3] + X[4] * X[4] + X[5] * X[5];
+  double p = sqrt(p2);
+  double n[3];
+  surface_normal(kind, X, n);
+  double cospsi = fabs((n[0] * X[3] + n[1] * X[4] + n[2] * X[5]) / p);
+  double xe = x_over_x0 / cospsi;
+  double beta = p / sqrt(p2 + mass * mass);
+  double th0 = 0.0136 / (beta * p) * sqrt(xe) * (1.0 + 0.038 * log(xe / (beta * beta)));
+  double t2 = th0 * th0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) Q[(3 + i) * 6 + 3 + j] = t2 * ((i == j ? p2 : 0.0) - X[3 + i] * X[3 + j]);
+}
+
+/*
+ * One propagation step to a surface (kind, value = radius or z): the helix
+ * to the crossing (first along the motion, or nearest when `nearest`), the
+ * covariance transported with the surface Jacobian, and, when `material`,
+ * the scattering noise of a thin layer at the end point.
+ */
+int orc_step_surf(const orc_detector* d, int kind, double value, int nearest, int material, const double X[6],
+                  int q, const double P[36], double Xo[6], double Po[36], double* disc) {
+  double s;
+  int rc = kind == ORC_DISK ? orc_plane_path(X, value, nearest, &s)
+                            : orc_cyl_path(X, q, value, (double)d->bz, nearest, &s, disc);
+  if (rc) return rc;
+  orc_state_at(X, q, (double)d->bz, s, Xo);
+  double J[36], JT[36], T[36];
+  orc_jacobian_surf(X, q, (double)d->bz, s, kind, J);
+  transpose(J, JT, 6, 6);
+  matmul(J, P, T, 6, 6, 6);
+  matmul(T, JT, Po, 6, 6, 6);
+  if (material) {
+    double Q[36];
+    orc_ms_cov_surf(Xo, kind, (double)d->x_over_x0, (double)d->mass, Q);
+    for (int i = 0; i < 36; ++i) Po[i] += Q[i];
+  }
+  return 0;
+}
+
+/*
+ * Kalman update with a disk hit, measured in the disk's plane: H picks
+ * (x, y), residual (m_x - x, m_y - y), V2 the (x, y) block of the hit's
+ * covariance; otherwise as orc_update.
+ */
+int orc_update_disk(const double X[6], const double P[36], const double hit[9], double Xo[6], double Po[36],
+                    double* chi2) {
+  double H[12] = {1, 0, 0, 0, 0, 0, 0, 1, 0, 0, 0, 0};
+  double V2[4] = {hit[3], hit[4], hit[4], hit[6]};
+  double res[2] = {hit[0] - X[0], hit[1] - X[1]};
+  double HT[12], PHT[12], S[4];
+  transpose(H, HT, 2, 6);
+  matmul(P, HT, PHT, 6, 6, 2);
+  matmul(H, PHT, S, 2, 6, 2);
+  for (int i = 0; i < 4; ++i) S[i] += V2[i];
+  double det = S[0] * S[3] - S[1] * S[2];
+  if (!(S[0] > 0.0) || !(det > 0.0)) return ORC_TRK_S_NOT_PD;
+  double Si[4] = {S[3] / det, -S[1] / det, -S[2] / det, S[0] / det};
+  double K[12], HP[12], KHP[36];
+  matmul(PHT, Si, K, 6, 2, 2);
+  for (int i = 0; i < 6; ++i) Xo[i] = X[i] + K[i * 2 + 0] * res[0] + K[i * 2 + 1] * res[1];
+  matmul(H, P, HP, 2, 6, 6);
+  matmul(K, HP, KHP, 6, 2, 6);
+  for (int i = 0; i < 36; ++i) Po[i] = P[i] - KHP[i];
+  double Sir[2] = {Si[0] * res[0] + Si[1] * res[1], Si[2] * res[0] + Si[3] * res[1]};
+  *chi2 = res[0] * Sir[0] + res[1] * Sir[1];
+  return 0;
+}
+
+/* the surface a hit lies on: its radius (barrel) or its z (disk) */
+static double hit_surface(int kind, const double hit[9]) {
+  return kind == ORC_DISK ? hit[2] : sqrt(hit[0] * hit[0] + hit[1] * hit[1]);
+}
+
+/* update with a hit of a layer of the given kind, at the predicted state */
+static int update_kind(int kind, const double X[6], const double P[36], const double hit[9], double Xo[6],
+                       double Po[36], double* chi2) {
+  return kind == ORC_DISK ? orc_update_disk(X, P, hit, Xo, Po, chi2) : orc_update(X, P, hit, Xo, Po, chi2);
+}
+
+/* coordinate along a layer's extent: z on a barrel layer, r on a disk */
+static double extent_coord(int kind, const double x[3]) {
+  return kind == ORC_DISK ? sqrt(x[0] * x[0] + x[1] * x[1]) : x[2];
+}
+
+/*
+ * Fit over a general detector (section 2: the Kalman filter over a fixed hit
+ * list).  For each layer l >= first_layer (in index order) whose bit is set
+ * in visit_mask[i]: with a hit (bit clear in hole_mask[i]) the state goes in
+ * one step to the hit's own surface (its radius on a barrel layer, its z on a
+ * disk; first crossing along the motion), takes the layer's scattering there
+ * and is updated with the hit; on a hole it goes to the layer's average
+ * surface and takes the scattering there.  The extents are not checked: the
+ * list says which layers the track crossed.  Outputs as orc_fit.
+ */
+static void fit_one_det(const orc_detector* d, int first_layer, const double* hitrows, uint32_t visit,
+                        uint32_t holes, const double Xs[6], const double Ps[36], int q, double Xout[6],
+                        double Pout[36], double* chi2_out, int* ndof_out, int* status_out) {
+  double X[6], P[36];
+  memcpy(X, Xs, sizeof(X));
+  memcpy(P, Ps, sizeof(P));
+  double chi2 = 0.0;
+  int ndof = 0, st = 0;
+  if (!all_finite(X, 6) || !all_finite(P, 36)) st = ORC_TRK_NONFINITE;
+  for (int l = first_layer; l < d->n_layers && !st; ++l) {
+    if (!((visit >> l) & 1u)) continue;
+    const double* h = hitrows + (size_t)l * 9;
+    const int kind = d->kind[l];
+    int use = !((holes >> l) & 1u);
+    if (use && !all_finite(h, 9)) { st = ORC_TRK_NONFINITE; break; }
+    double Xp[6], Pp[36];
+    int rc = orc_step_surf(d, kind, use ? hit_surface(kind, h) : (double)d->pos[l], 0, 1, X, q, P, Xp, Pp, NULL);
+    if (rc) { st = rc; break; }
+    if (!use) {
+      if (!all_finite(Xp, 6) || !all_finite(Pp, 36)) { st = ORC_TRK_NONFINITE; break; }
+      memcpy(X, Xp, sizeof(X)); memcpy(P, Pp, sizeof(P));
+      continue;
+    }
+    double Xu[6], Pu[36], c2;
+    rc = update_kind(kind, Xp, Pp, h, Xu, Pu, &c2);
+    if (rc) { st = rc; break; }
+    if (!all_finite(Xu, 6) || !all_finite(Pu, 36) || !isfinite(c2)) { st = ORC_TRK_NONFINITE; break; }
+    memcpy(X, Xu, sizeof(X)); memcpy(P, Pu, sizeof(P));
+    chi2 += c2;
+    ndof += 2;
+  }
+  memcpy(Xout, X, sizeof(X));
+  memcpy(Pout, P, sizeof(P));
+  *chi2_out = chi2;
+  *ndof_out = ndof;
+  *status_out = st;
+}
+
+static int det_ok(const orc_detector* d) {
+  if (d->n_layers < 1 || d->n_layers > 32) return 0;
+  for (int l = 0; l < d->n_layers; ++l)
+    if (!det_kind_ok(d, l) || !(d->hi[l] > d->lo[l])) return 0;
+  return 1;
+}
+
+int orc_fit_det(const orc_detector* d, int n, int ld, int first_layer, const float* hits, const uint32_t* visit_mask,
+                const uint32_t* hole_mask, const float* seed_par, const float* seed_cov, const int8_t* q,
+                double* out_par, double* out_cov, double* out_chi2, int32_t* out_ndof, int32_t* out_status) {
+  if (n < 0 || ld < n || !det_ok(d) || first_layer < 0 || !visit_mask) return 1;
+  double rows[9 * 32];
+  for (int i = 0; i < n; ++i) {
+    for (int l = 0; l < d->n_layers; ++l) load_hit(hits, ld, l, i, rows + l * 9);
+    double Xs[6], u[21], Ps[36], X[6], P[36], c2;
+    int ndof, st;
+    for (int c = 0; c < 6; ++c) Xs[c] = (double)seed_par[(size_t)c * ld + i];
+    for (int c = 0; c < 21; ++c) u[c] = (double)seed_cov[(size_t)c * ld + i];
+    sym_from_upper(u, Ps);
+    fit_one_det(d, first_layer, rows, visit_mask[i], hole_mask ? hole_mask[i] : 0u, Xs, Ps, q[i], X, P, &c2, &ndof,
+                &st);
+    store_fit(ld, i, X, P, c2, ndof, st, out_par, out_cov, out_chi2, out_ndof, out_status);
+  }
+  return 0;
+}
+
+/* FP64 inputs throughout (used by the exactness pins). */
+int orc_fit_det64(const orc_detector* d, int n, int ld, int first_layer, const double* hits,
+                  const uint32_t* visit_mask, const double* seed_par, const double* seed_cov, const int8_t* q,
+                  double* out_par, double* out_cov, double* out_chi2, int32_t* out_ndof, int32_t* out_status) {
+  if (n < 0 || ld < n || !det_ok(d) || first_layer < 0 || !visit_mask) return 1;
+  double rows[9 * 32];
+  for (int i = 0; i < n; ++i) {
+    for (int l = 0; l < d->n_layers; ++l)
+      for (int c = 0; c < 9; ++c) rows[l * 9 + c] = hits[((size_t)l * 9 + c) * (size_t)ld + (size_t)i];
+    double Xs[6], u[21], Ps[36], X[6], P[36], c2;
+    int ndof, st;
+    for (int c = 0; c < 6; ++c) Xs[c] = seed_par[(size_t)c * ld + i];
+    for (int c = 0; c < 21; ++c) u[c] = seed_cov[(size_t)c * ld + i];
+    sym_from_upper(u, Ps);
+    fit_one_det(d, first_layer, rows, visit_mask[i], 0u, Xs, Ps, q[i], X, P, &c2, &ndof, &st);
+    store_fit(ld, i, X, P, c2, ndof, st, out_par, out_cov, out_chi2, out_ndof, out_status);
+  }
+  return 0;
+}
+
+/*
+ * Binning over a general detector: per layer n_w x n_phi bins, bin =
+ * iw * n_phi + iphi, with phi as orc_hit_bin and the extent coordinate w = z
+ * (barrel) or w = r = sqrt(x^2 + y^2) (disk), both in FP64 from the FP32
+ * inputs: iw = clamp(floor((w - lo) * n_w / (hi - lo)), 0, n_w - 1).  Order
+ * and offsets as orc_hit_bin.
+ */
+int orc_hit_bin_det(const orc_detector* d, int n_phi, int n_w, int n_hits, const int32_t* layer, const float* xyz,
+                    int32_t* offsets, int32_t* order, float* phi_sorted) {
+  if (n_phi < 1 || n_w < 1 || n_hits < 0 || !det_ok(d)) return 1;
+  int nb = n_phi * n_w, L = d->n_layers;
+  bin_key* k = (bin_key*)malloc(sizeof(bin_key) * (size_t)(n_hits > 0 ? n_hits : 1));
+  for (int i = 0; i < n_hits; ++i) {
+    double x = (double)xyz[i], y = (double)xyz[(size_t)n_hits + i], z = (double)xyz[2 * (size_t)n_hits + i];
+    int l = layer[i];
+    double ph = atan2(y, x);
+    if (ph < 0.0) ph += TWO_PI;
+    float phf = (float)ph;
+    int ip = (int)floor((double)phf * (double)n_phi / TWO_PI);
+    if (ip > n_phi - 1) ip = n_phi - 1;
+    if (ip < 0) ip = 0;
+    int iw = 0;
+    if (l >= 0 && l < L) {
+      double w = d->kind[l] == ORC_DISK ? sqrt(x * x + y * y) : z;
+      double lo = (double)d->lo[l], hi = (double)d->hi[l];
+      iw = (int)floor((w - lo) * (double)n_w / (hi - lo));
+      if (iw < 0) iw = 0;
+      if (iw > n_w - 1) iw = n_w - 1;
+    }
+    k[i].layer = layer[i];
+    k[i].bin = iw * n_phi + ip;
+    k[i].phi = phf;
+    k[i].idx = i;
+  }
+  qsort(k, (size_t)n_hits, sizeof(bin_key), bin_key_cmp);
+  for (int i = 0; i < n_hits; ++i) { order[i] = k[i].idx; phi_sorted[i] = k[i].phi; }
+  int pos = 0;
+  for (int l = 0; l < L; ++l)
+    for (int b = 0; b <= nb; ++b) {
+      while (pos < n_hits && (k[pos].layer < l || (k[pos].layer == l && k[pos].bin < b))) ++pos;
+      offsets[l * (nb + 1) + b] = pos;
+    }
+  free(k);
+  return 0;
+}
+
+typedef struct {
+  double X[6], P[36];
+  int nhits, holes, status, layer; /* layer: the last layer the candidate visited */
+  double chi2;
+  int32_t hits[32];                /* per layer: original hit index, -1 none */
+  uint32_t visit;                  /* layers visited (hit or hole) */
+} dcand_t;
+
+typedef struct {
+  int nhits, parent, hit, holes, layer;
+  double chi2;
+  double X[6], P[36];
+} dchild_t;
+
+static int dchild_cmp(const void* pa, const void* pb) {
+  const dchild_t* a = (const dchild_t*)pa;
+  const dchild_t* b = (const dchild_t*)pb;
+  if (a->nhits != b->nhits) return a->nhits > b->nhits ? -1 : 1;
+  if (a->chi2 != b->chi2) return a->chi2 < b->chi2 ? -1 : 1;
+  if (a->parent != b->parent) return a->parent < b->parent ? -1 : 1;
+  long ha = a->hit < 0 ? 0x7fffffffL : a->hit, hb = b->hit < 0 ? 0x7fffffffL : b->hit;
+  return ha < hb ? -1 : (ha > hb ? 1 : 0);
+}
+
+/*
+ * The next layer of a candidate on layer `cur` (section 4.1's cylinder with
+ * lids): the first layer after `cur`, in index order, whose average surface
+ * the helix crosses ahead of it with the crossing inside the layer's extent
+ * (barrel: z in [lo, hi]; disk: r in [lo, hi]) and, on a disk, within less
+ * than half a turn and while still moving outwards (x px + y py > 0; a
+ * barrel crossing from inside always is).  On success the
+ * state and covariance on that surface (propagated without material) are
+ * returned; -1 when the candidate leaves the detector.  Every crossing
+ * test is recorded in *mgeo (crossing discriminant, side of a plane), every
+ * extent test in *mwin (distance in cm of the extent coordinate from the
+ * nearer edge: a position decision like a window edge).
+ */
+static int next_layer(const orc_detector* d, int cur, const double X[6], int q, const double P[36], double Xa[6],
+                      double Pa[36], double* mgeo, double* mwin) {
+  for (int j = cur + 1; j < d->n_layers; ++j) {
+    double disc = INFINITY;
+    int rc = orc_step_surf(d, d->kind[j], (double)d->pos[j], 0, 0, X, q, P, Xa, Pa, &disc);
+    if (isfinite(disc)) *mgeo = minf(*mgeo, disc);
+    if (d->kind[j] == ORC_DISK && X[5] != 0.0) /* which side of the plane the track is on */
+      *mgeo = minf(*mgeo, fabs((double)d->pos[j] - X[2]) / fabs((double)d->pos[j]));
+    if (rc) continue;
+    if (d->kind[j] == ORC_DISK) {
+      /* met on the way out, within less than half a turn (a looper that comes
+         back is not followed) */
+      double pt0 = sqrt(X[3] * X[3] + X[4] * X[4]);
+      double turn = fabs(KAPPA * (double)d->bz / pt0 * ((double)d->pos[j] - X[2]) * pt0 / X[5]);
+      double pr = Xa[0] * Xa[3] + Xa[1] * Xa[4];
+      double ptr = sqrt(Xa[0] * Xa[0] + Xa[1] * Xa[1]) * sqrt(Xa[3] * Xa[3] + Xa[4] * Xa[4]);
+      *mgeo = minf(*mgeo, minf(fabs(pr) / ptr, fabs(PI - turn) / PI));
+      if (!(pr > 0.0) || !(turn < PI)) continue;
+    }
+    double w = extent_coord(d->kind[j], Xa), lo = (double)d->lo[j], hi = (double)d->hi[j];
+    *mwin = minf(*mwin, minf(fabs(w - lo), fabs(hi - w)));
+    if (w >= lo && w <= hi) return j;
+  }
+  return -1;
+}
+
+/*
+ * Combinatorial build over a general detector (sections 2, 4.1, 4.3), with
+ * the rules of orc_build (window, chi2 cut, children, ranking, cap,
+ * best-finished record) and these differences:
+ *   - each candidate moves to its own next layer (next_layer): a track that
+ *     leaves the barrel through its end continues on the disks; a candidate
+ *     with no next layer has left the detector and finishes (status 0);
+ *   - two-step propagation: step 1 to the layer's average surface (no
+ *     material), where the window is formed; step 2, for every hit in the
+ *     window, from there to the hit's own surface (nearest crossing),
+ *     scattering of the layer at the hit, then the update (tangent plane at
+ *     the hit's radius on a barrel layer, the disk's plane on a disk) and its
+ *     chi2; a hole child takes the layer's scattering at the average surface;
+ *   - window: barrel (phi, z), disk (phi, r), each half-width nsigma *
+ *     sqrt(S) of the predicted covariance with the nominal resolution
+ *     (win_sig_rphi along the arc, win_sig_z along z or r), widened by the
+ *     module offset dmod times the track's slope (|dz/dr| and |dphi/dr| on a
+ *     barrel layer, |dr/dz| and |dphi/dz| on a disk) so hits of displaced
+ *     modules stay inside; a hit is in the window iff |wrap(phi_h - phi_p)|
+ *     <= dphi and |w_h - w_p| <= dw (w = z or r).
+ * Outputs: out_hits[L - F][ld] per layer (original index, -1 for a hole or a
+ * layer not visited), out_visit[ld] the layers the chosen candidate visited,
+ * the rest as orc_build; out_margin rows as orc_build, the extent tests
+ * counted with the window edges (cm) and the side of a disk's plane with the
+ * geometry (gate and learned rows stay infinite).  Cartesian state, plain
+ * window.
+ */
+int orc_build_det(const orc_detector* d, const orc_build_params* bp, int n_hits, const int32_t* layer,
+                  const float* xyz, const float* cov, int n_seeds, int ld, const float* seed_par,
+                  const float* seed_cov, const int8_t* q, int n_list, const int32_t* seed_list, int32_t* out_hits,
+                  uint32_t* out_visit, double* out_par, double* out_cov, double* out_chi2, int32_t* out_nhits,
+                  int32_t* out_status, double* out_margin) {
+  const int L = d->n_layers, F = bp->first_layer;
+  if (!det_ok(d) || n_seeds < 0 || ld < n_seeds || F < 1 || F >= L || bp->cand_cap < 1 || n_list < 0 ||
+      n_list > ld || bp->window_mode != 0 || bp->state != 0)
+    return 1;
+  int* lay_cnt = (int*)calloc((size_t)L, sizeof(int));
+  int* lay_off = (int*)calloc((size_t)L + 1, sizeof(int));
+  int* lay_idx = (int*)malloc(sizeof(int) * (size_t)(n_hits > 0 ? n_hits : 1));
+  for (int i = 0; i < n_hits; ++i) if (layer[i] >= 0 && layer[i] < L) lay_cnt[layer[i]]++;
+  for (int l = 0; l < L; ++l) lay_off[l + 1] = lay_off[l] + lay_cnt[l];
+  for (int l = 0; l < L; ++l) lay_cnt[l] = 0;
+  for (int i = 0; i < n_hits; ++i)
+    if (layer[i] >= 0 && layer[i] < L) lay_idx[lay_off[layer[i]] + lay_cnt[layer[i]]++] = i;
+
+  const int cap = bp->cand_cap;
+  dcand_t* act = (dcand_t*)malloc(sizeof(dcand_t) * (size_t)cap);
+  dcand_t* nxt = (dcand_t*)malloc(sizeof(dcand_t) * (size_t)cap);
+  int* stopped = (int*)malloc(sizeof(int) * (size_t)cap);
+  size_t ch_cap = 64;
+  dchild_t* ch = (dchild_t*)malloc(sizeof(dchild_t) * ch_cap);
+  const size_t N = (size_t)n_hits;
+  const double ns = (double)bp->nsigma, sr = (double)bp->win_sig_rphi, sw = (double)bp->win_sig_z;
+
+  for (int li = 0; li < n_list; ++li) {
+    int i = seed_list ? seed_list[li] : li;
+    double mc2 = INFINITY, mwin = INFINITY, mgeo = INFINITY;
+    int seed_status = 0, have_fin = 0, qi = q[i], n_act = 1;
+    dcand_t fin;
+    memset(&act[0], 0, sizeof(dcand_t));
+    double u[21];
+    for (int c = 0; c < 6; ++c) act[0].X[c] = (double)seed_par[(size_t)c * ld + i];
+    for (int c = 0; c < 21; ++c) u[c] = (double)seed_cov[(size_t)c * ld + i];
+    sym_from_upper(u, act[0].P);
+    for (int l = 0; l < 32; ++l) act[0].hits[l] = -1;
+    act[0].layer = F - 1;
+    if (!all_finite(act[0].X, 6) || !all_finite(act[0].P, 36)) {
+      act[0].status = ORC_TRK_NONFINITE;
+      n_act = 0;
+      fin = act[0];
+      have_fin = 1;
+    }
+    while (n_act > 0) {
+      size_t nch = 0;
+      int n_stop = 0;
+      for (int a = 0; a < n_act; ++a) {
+        dcand_t* c = &act[a];
+        double Xa[6], Pa[36];
+        const int l = next_layer(d, c->layer, c->X, qi, c->P, Xa, Pa, &mgeo, &mwin);
+        if (l < 0) { stopped[n_stop++] = a; continue; }
+        const int kind = d->kind[l];
+        const double dm = (double)d->dmod[l];
+        /* window on the average surface */
+        double ra = sqrt(Xa[0] * Xa[0] + Xa[1] * Xa[1]);
+        double tx = -Xa[1] / ra, ty = Xa[0] / ra, nx = Xa[0] / ra, ny = Xa[1] / ra;
+        double Stt = tx * tx * Pa[0] + 2.0 * tx * ty * Pa[1] + ty * ty * Pa[7] + sr * sr;
+        double Sww, slope_w, slope_phi;
+        double pr = nx * Xa[3] + ny * Xa[4], pphi = tx * Xa[3] + ty * Xa[4]; /* radial, azimuthal momentum */
+        if (kind == ORC_DISK) {
+          Sww = nx * nx * Pa[0] + 2.0 * nx * ny * Pa[1] + ny * ny * Pa[7] + sw * sw;
+          slope_w = pr / Xa[5];           /* dr/dz */
+          slope_phi = pphi / (ra * Xa[5]); /* dphi/dz */
+        } else {
+          Sww = Pa[14] + sw * sw;
+          slope_w = Xa[5] / pr;           /* dz/dr */
+          slope_phi = pphi / (ra * pr);   /* dphi/dr */
+        }
+        double dphi_w = ns * sqrt(Stt) / ra, dw_w = ns * sqrt(Sww);
+        if (dm > 0.0) { dphi_w += dm * fabs(slope_phi); dw_w += dm * fabs(slope_w); }
+        double php = atan2(Xa[1], Xa[0]), wp = kind == ORC_DISK ? ra : Xa[2];
+        int n_own = 0;
+        for (int k = lay_off[l]; k < lay_off[l + 1]; ++k) {
+          int hi = lay_idx[k];
+          double hit[9] = {(double)xyz[hi], (double)xyz[N + hi], (double)xyz[2 * N + hi]};
+          for (int cc = 0; cc < 6; ++cc) hit[3 + cc] = (double)cov[(size_t)cc * N + hi];
+          double dph = wrap_pi(atan2(hit[1], hit[0]) - php);
+          double dw = (kind == ORC_DISK ? sqrt(hit[0] * hit[0] + hit[1] * hit[1]) : hit[2]) - wp;
+          double aph = fabs(dph), aw = fabs(dw);
+          int pph = aph <= dphi_w, pw = aw <= dw_w;
+          double mph = ra * fabs(aph - dphi_w), mw = fabs(aw - dw_w);
+          double dmrg = (pph && pw) ? minf(mph, mw) : (!pph && !pw) ? (mph > mw ? mph : mw) : (!pph ? mph : mw);
+          mwin = minf(mwin, dmrg);
+          if (!(pph && pw)) continue;
+          /* step 2: to the hit's surface, scattering there, update */
+          double Xh[6], Ph[36], Xu[6], Pu[36], c2, disc = INFINITY;
+          int rc = orc_step_surf(d, kind, hit_surface(kind, hit), 1, 1, Xa, qi, Pa, Xh, Ph, &disc);
+          if (isfinite(disc)) mgeo = minf(mgeo, disc);
+          if (rc) continue;
+          if (update_kind(kind, Xh, Ph, hit, Xu, Pu, &c2)) continue;
+          mc2 = minf(mc2, fabs(c2 - (double)bp->chi2_cut));
+          if (!(c2 < (double)bp->chi2_cut)) continue;
+          if (nch == ch_cap) { ch_cap *= 2; ch = (dchild_t*)realloc(ch, sizeof(dchild_t) * ch_cap); }
+          dchild_t* e = &ch[nch++];
+          e->nhits = c->nhits + 1; e->parent = a; e->hit = hi; e->holes = c->holes; e->layer = l;
+          e->chi2 = c->chi2 + c2;
+          memcpy(e->X, Xu, sizeof(Xu)); memcpy(e->P, Pu, sizeof(Pu));
+          ++n_own;
+        }
+        if (c->holes < bp->max_holes) {
+          /* hole: the layer's scattering at the average surface */
+          double Q[36];
+          if (nch == ch_cap) { ch_cap *= 2; ch = (dchild_t*)realloc(ch, sizeof(dchild_t) * ch_cap); }
+          dchild_t* e = &ch[nch++];
+          e->nhits = c->nhits; e->parent = a; e->hit = -1; e->holes = c->holes + 1; e->layer = l;
+          e->chi2 = c->chi2;
+          orc_ms_cov_surf(Xa, kind, (double)d->x_over_x0, (double)d->mass, Q);
+          memcpy(e->X, Xa, sizeof(Xa));
+          for (int m = 0; m < 36; ++m) e->P[m] = Pa[m] + Q[m];
+          ++n_own;
+        }
+        if (n_own == 0) stopped[n_stop++] = a;
+      }
+      for (int s = 0; s < n_stop; ++s) {
+        dcand_t* c = &act[stopped[s]];
+        if (!have_fin) { fin = *c; have_fin = 1; continue; }
+        if (c->nhits == fin.nhits) mc2 = minf(mc2, fabs(c->chi2 - fin.chi2));
+        if (better(c->nhits, c->chi2, fin.nhits, fin.chi2)) fin = *c;
+      }
+      qsort(ch, nch, sizeof(dchild_t), dchild_cmp);
+      size_t keep = nch < (size_t)cap ? nch : (size_t)cap;
+      if (nch > (size_t)cap) {
+        seed_status |= ORC_TRK_CAP_TRUNC;
+        if (ch[cap - 1].nhits == ch[cap].nhits) mc2 = minf(mc2, fabs(ch[cap].chi2 - ch[cap - 1].chi2));
+      }
+      for (size_t k = 0; k < keep; ++k) {
+        dcand_t* e = &nxt[k];
+        const dcand_t* p = &act[ch[k].parent];
+        memcpy(e->hits, p->hits, sizeof(e->hits));
+        e->hits[ch[k].layer] = ch[k].hit;
+        e->visit = p->visit | (1u << ch[k].layer);
+        e->layer = ch[k].layer;
+        memcpy(e->X, ch[k].X, sizeof(e->X)); memcpy(e->P, ch[k].P, sizeof(e->P));
+        e->nhits = ch[k].nhits; e->holes = ch[k].holes; e->chi2 = ch[k].chi2; e->status = 0;
+      }
+      dcand_t* t = act; act = nxt; nxt = t;
+      n_act = (int)keep;
+    }
+    /* every candidate has finished: the result is the record */
+    const dcand_t* best = have_fin ? &fin : NULL;
+    double ub[21];
+    for (int l = F; l < L; ++l) out_hits[(size_t)(l - F) * ld + li] = best ? best->hits[l] : -1;
+    if (best) {
+      upper_from_sym(best->P, ub);
+      for (int c = 0; c < 6; ++c) out_par[(size_t)c * ld + li] = best->X[c];
+      for (int c = 0; c < 21; ++c) out_cov[(size_t)c * ld + li] = ub[c];
+    }
+    out_visit[li] = best ? best->visit : 0u;
+    out_chi2[li] = best ? best->chi2 : 0.0;
+    out_nhits[li] = best ? best->nhits : 0;
+    out_status[li] = (best ? best->status : 0) | seed_status;
+    if (out_margin) {
+      out_margin[li] = mc2;
+      out_margin[(size_t)ld + li] = mwin;
+      out_margin[2 * (size_t)ld + li] = mgeo;
+      out_margin[3 * (size_t)ld + li] = INFINITY;
+      out_margin[4 * (size_t)ld + li] = INFINITY;
+    }
+  }
+  free(act); free(nxt); free(ch); free(stopped); free(lay_cnt); free(lay_off); free(lay_idx);
   return 0;
 }

@@ -62,6 +62,24 @@ typedef struct {
   int32_t state;      /* 0 Cartesian; 1 hybrid (x, y, z, q/pT, phi, theta) */
 } orc_build_params;
 
+/* General detector (section 4.1): barrel cylinders and endcap disks, listed
+ * in the order a track from the origin meets them (barrel layers outwards,
+ * then the disks of each side outwards).  Modules may sit off a layer's
+ * average surface by up to dmod (barrel: radius, disk: z). */
+#define ORC_BARREL 0
+#define ORC_DISK 1
+typedef struct {
+  int32_t n_layers;
+  int32_t kind[32]; /* ORC_BARREL or ORC_DISK */
+  float pos[32];    /* average radius (barrel) or z of the average plane (disk), cm */
+  float lo[32];     /* active extent: z range (barrel) or r range (disk), cm */
+  float hi[32];
+  float dmod[32];   /* largest module offset from the average surface, cm */
+  float bz;
+  float x_over_x0;
+  float mass;
+} orc_detector;
+
 /* --- primitives (exposed for the pins) --- */
 int orc_propagate(const double X[6], int q, double R, double bz, double Xo[6], double* s_out, double* disc);
 void orc_state_at(const double X[6], int q, double bz, double s, double Xo[6]);
@@ -104,6 +122,29 @@ int orc_build(const orc_geometry* g, const orc_build_params* bp, int n_hits, con
               int32_t* out_hits, double* out_par, double* out_cov, double* out_chi2, int32_t* out_nhits,
               int32_t* out_status, double* out_margin);
 int orc_mlp_forward(const double* mlp, const double x[27], double w[2]);
+
+/* --- general detector --- */
+int orc_cyl_path(const double X[6], int q, double R, double bz, int nearest, double* s_out, double* disc);
+int orc_plane_path(const double X[6], double Z, int nearest, double* s_out);
+void orc_jacobian_surf(const double X[6], int q, double bz, double s, int kind, double J[36]);
+void orc_ms_cov_surf(const double X[6], int kind, double x_over_x0, double mass, double Q[36]);
+int orc_step_surf(const orc_detector* d, int kind, double value, int nearest, int material, const double X[6],
+                  int q, const double P[36], double Xo[6], double Po[36], double* disc);
+int orc_update_disk(const double X[6], const double P[36], const double hit[9], double Xo[6], double Po[36],
+                    double* chi2);
+int orc_fit_det(const orc_detector* d, int n, int ld, int first_layer, const float* hits, const uint32_t* visit_mask,
+                const uint32_t* hole_mask, const float* seed_par, const float* seed_cov, const int8_t* q,
+                double* out_par, double* out_cov, double* out_chi2, int32_t* out_ndof, int32_t* out_status);
+int orc_fit_det64(const orc_detector* d, int n, int ld, int first_layer, const double* hits,
+                  const uint32_t* visit_mask, const double* seed_par, const double* seed_cov, const int8_t* q,
+                  double* out_par, double* out_cov, double* out_chi2, int32_t* out_ndof, int32_t* out_status);
+int orc_hit_bin_det(const orc_detector* d, int n_phi, int n_w, int n_hits, const int32_t* layer, const float* xyz,
+                    int32_t* offsets, int32_t* order, float* phi_sorted);
+int orc_build_det(const orc_detector* d, const orc_build_params* bp, int n_hits, const int32_t* layer,
+                  const float* xyz, const float* cov, int n_seeds, int ld, const float* seed_par,
+                  const float* seed_cov, const int8_t* q, int n_list, const int32_t* seed_list, int32_t* out_hits,
+                  uint32_t* out_visit, double* out_par, double* out_cov, double* out_chi2, int32_t* out_nhits,
+                  int32_t* out_status, double* out_margin);
 int orc_mlp_blob_size(void);
 
 #ifdef __cplusplus

@@ -31,6 +31,19 @@ class _Cfg(ctypes.Structure):
     ]
 
 
+class _DetCfg(ctypes.Structure):
+    _fields_ = [
+        ("n_layers", ctypes.c_int32), ("smear", ctypes.c_int32), ("kind", ctypes.c_int32 * 32),
+        ("pos", ctypes.c_double * 32), ("lo", ctypes.c_double * 32), ("hi", ctypes.c_double * 32),
+        ("dmod", ctypes.c_double * 32), ("n_mod", ctypes.c_int32), ("n_seed_layers", ctypes.c_int32),
+        ("bz", ctypes.c_double), ("x_over_x0", ctypes.c_double), ("mass", ctypes.c_double),
+        ("sig_rphi", ctypes.c_double), ("sig_w", ctypes.c_double), ("pt_min", ctypes.c_double),
+        ("pt_max", ctypes.c_double), ("eta_max", ctypes.c_double), ("vtx_sxy", ctypes.c_double),
+        ("vtx_sz", ctypes.c_double), ("noise_lo", ctypes.c_double), ("noise_hi", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
 def build_lib() -> str:
     cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
@@ -57,6 +70,9 @@ def lib():
         L.kfg_philox4x32_10.restype = None
         L.kfg_splitmix64.argtypes = [ctypes.c_uint64]
         L.kfg_splitmix64.restype = ctypes.c_uint64
+        L.kfg_det_event.argtypes = [ctypes.POINTER(_DetCfg), ctypes.c_uint64, ctypes.c_int32] + [P] * 10 + [
+            ctypes.c_int64, P]
+        L.kfg_det_event.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -147,3 +163,70 @@ def track_hits(ev: Event, ld: int | None = None, dtype=np.float32) -> np.ndarray
         out[l, 0:3, :n] = ev.xyz[:, idx]
         out[l, 3:9, :n] = ev.cov[:, idx]
     return out
+
+
+# ------------------------------------------------------------ general detector
+
+def _det_cfg(det, gen: GenSettings, x_over_x0=None) -> _DetCfg:
+    c = _DetCfg()
+    c.n_layers = det.n_layers
+    c.smear = 1 if gen.smear else 0
+    for i in range(det.n_layers):
+        c.kind[i] = det.kind[i]
+        c.pos[i], c.lo[i], c.hi[i], c.dmod[i] = det.pos[i], det.lo[i], det.hi[i], det.dmod[i]
+    c.n_mod = det.n_mod
+    c.n_seed_layers = det.n_seed_layers
+    c.bz, c.mass = det.bz, det.mass
+    c.x_over_x0 = det.x_over_x0 if x_over_x0 is None else x_over_x0
+    c.sig_rphi, c.sig_w = gen.sig_rphi, gen.sig_z
+    c.pt_min, c.pt_max, c.eta_max = gen.pt_min, gen.pt_max, gen.eta_max
+    c.vtx_sxy, c.vtx_sz = gen.vtx_sxy, gen.vtx_sz
+    c.noise_lo, c.noise_hi = gen.noise_lo, gen.noise_hi
+    c.seed = gen.seed & 0xFFFFFFFFFFFFFFFF
+    return c
+
+
+def generate_det(det, gen: GenSettings, event: int, n_tracks: int, truth: bool = False, x_over_x0=None) -> Event:
+    """One event over a general detector (barrel cylinders and disks).  A
+    track's hit index on a layer it does not cross is -1 (trk_hits); truth is
+    NaN there."""
+    L = lib()
+    cfg = _det_cfg(det, gen, x_over_x0)
+    nl = det.n_layers
+    cap = int(nl * n_tracks * (1.0 + max(gen.noise_hi, gen.noise_lo)) + nl + 16)
+    hx, hy, hz = np.zeros(cap), np.zeros(cap), np.zeros(cap)
+    hcov = np.zeros((6, cap))
+    hl = np.zeros(cap, dtype=np.int32)
+    ht = np.zeros(cap, dtype=np.int32)
+    th = np.zeros((nl, n_tracks), dtype=np.int32)
+    q = np.zeros(n_tracks, dtype=np.int8)
+    tr = np.zeros((nl, 6, n_tracks)) if truth else None
+    vt = np.zeros((6, n_tracks)) if truth else None
+    nh = ctypes.c_int64(0)
+    rc = L.kfg_det_event(ctypes.byref(cfg), event, n_tracks, hx.ctypes.data, hy.ctypes.data, hz.ctypes.data,
+                         hcov.ctypes.data, hl.ctypes.data, ht.ctypes.data, th.ctypes.data, q.ctypes.data,
+                         tr.ctypes.data if tr is not None else None, vt.ctypes.data if vt is not None else None,
+                         cap, ctypes.byref(nh))
+    if rc:
+        raise RuntimeError(f"kfg_det_event failed with code {rc}")
+    n = int(nh.value)
+    return Event(np.stack([hx[:n], hy[:n], hz[:n]]), np.ascontiguousarray(hcov[:, :n]), hl[:n].copy(), ht[:n].copy(),
+                 th, q, tr, vt)
+
+
+def det_track_rows(ev: Event, ld: int | None = None, dtype=np.float32):
+    """Per-track hit rows [L][9][ld] over a general detector (zeros where the
+    track does not cross a layer) and the visit masks [ld] (bit l: the track
+    has a hit on layer l)."""
+    L, n = ev.trk_hits.shape
+    ld = padded(n) if ld is None else ld
+    out = np.zeros((L, 9, ld), dtype=dtype)
+    visit = np.zeros(ld, dtype=np.uint32)
+    for l in range(L):
+        idx = ev.trk_hits[l]
+        have = idx >= 0
+        cols = np.where(have)[0]
+        out[l, 0:3, cols] = ev.xyz[:, idx[have]].T
+        out[l, 3:9, cols] = ev.cov[:, idx[have]].T
+        visit[:n] |= np.where(have, np.uint32(1 << l), np.uint32(0)).astype(np.uint32)
+    return out, visit

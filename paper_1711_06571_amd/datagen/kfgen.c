@@ -372,3 +372,305 @@ int kfg_event(const kfg_config* cfg, uint64_t event, int32_t n_tracks,
   free(perm); free(inv); free(tmp); free(itmp);
   return 0;
 }
+
+/* ===================================================================
+ * General detector (section 4.1's "cylinder with lids"): barrel cylinders
+ * and endcap disks, listed in the order a track from the origin meets them
+ * (barrel layers outwards, then the disks of each side outwards).  Each
+ * layer is divided into n_mod phi sectors (modules); module k sits at the
+ * layer's average surface + dmod (k even) or - dmod (k odd): radius on a
+ * barrel layer, z on a disk.  A track crosses, in index order, every layer
+ * whose average surface it reaches ahead of it inside the layer's extent
+ * (barrel: z in [lo, hi]; disk: r in [lo, hi], reached within half a turn
+ * while still moving outwards); its hit lies on the module at the phi of
+ * that crossing.  Barrel hits are smeared
+ * along the arc and in z, disk hits along the arc and in r.
+ * =================================================================== */
+
+#define KFG_BARREL 0
+#define KFG_DISK 1
+
+typedef struct {
+  int32_t n_layers;
+  int32_t smear;
+  int32_t kind[32];
+  double pos[32];  /* average radius (barrel) or z of the average plane (disk) */
+  double lo[32];   /* extent: z range (barrel), r range (disk) */
+  double hi[32];
+  double dmod[32]; /* module offset from the average surface */
+  int32_t n_mod;   /* modules (phi sectors) per layer */
+  int32_t n_seed_layers; /* a track must cross layers 0 .. n_seed_layers - 1 */
+  double bz, x_over_x0, mass;
+  double sig_rphi; /* along the arc, cm */
+  double sig_w;    /* along z (barrel) or r (disk), cm */
+  double pt_min, pt_max, eta_max, vtx_sxy, vtx_sz;
+  double noise_lo, noise_hi; /* noise hits per layer: U[lo,hi] times the layer's true hits */
+  uint64_t seed;
+} kfg_det_config;
+
+/* Helix to the plane z = Z ahead of the particle; 1 if it lies behind or
+ * the motion is parallel to it. */
+static int move_to_z(particle* pa, int q, double bz, double Z) {
+  double pt = hypot(pa->px, pa->py);
+  if (pa->pz == 0.0) return 1;
+  double s = (Z - pa->z) * pt / pa->pz;
+  if (!(s > 0.0)) return 1;
+  double omega = -(double)q * KFG_KAPPA * bz / pt;
+  double cx = pa->x - pa->py / (pt * omega);
+  double cy = pa->y + pa->px / (pt * omega);
+  double a = omega * s;
+  double th0 = atan2(pa->y - cy, pa->x - cx);
+  double rho = 1.0 / fabs(omega);
+  double ca = cos(a), sa = sin(a);
+  double npx = pa->px * ca - pa->py * sa;
+  double npy = pa->py * ca + pa->px * sa;
+  pa->x = cx + rho * cos(th0 + a);
+  pa->y = cy + rho * sin(th0 + a);
+  pa->z = Z;
+  pa->px = npx;
+  pa->py = npy;
+  return 0;
+}
+
+/* Highland width with the incidence measured from the layer's normal. */
+static double highland_theta0_kind(const particle* pa, int kind, double x0, double mass) {
+  double p2 = pa->px * pa->px + pa->py * pa->py + pa->pz * pa->pz;
+  double p = sqrt(p2);
+  double cospsi;
+  if (kind == KFG_DISK) cospsi = fabs(pa->pz / p);
+  else cospsi = fabs((pa->x * pa->px + pa->y * pa->py) / (hypot(pa->x, pa->y) * p));
+  double xe = x0 / cospsi;
+  double beta = p / sqrt(p2 + mass * mass);
+  return 0.0136 / (beta * p) * sqrt(xe) * (1.0 + 0.038 * log(xe / (beta * beta)));
+}
+
+static double module_surface(const kfg_det_config* cfg, int l, double phi) {
+  double ph = phi < 0.0 ? phi + KFG_TWO_PI : phi;
+  int k = (int)floor(ph * (double)cfg->n_mod / KFG_TWO_PI);
+  if (k >= cfg->n_mod) k = cfg->n_mod - 1;
+  if (k < 0) k = 0;
+  return cfg->pos[l] + ((k & 1) ? -cfg->dmod[l] : cfg->dmod[l]);
+}
+
+/* covariance of a disk hit: sig_rphi along the arc, sig_r along r, exact z */
+static void disk_hit_cov(double phi, double srphi, double sr, double cov[6]) {
+  double tx = -sin(phi), ty = cos(phi), rx = cos(phi), ry = sin(phi);
+  double a = srphi * srphi, b = sr * sr;
+  cov[0] = a * tx * tx + b * rx * rx;
+  cov[1] = a * tx * ty + b * rx * ry;
+  cov[2] = 0.0;
+  cov[3] = a * ty * ty + b * ry * ry;
+  cov[4] = 0.0;
+  cov[5] = 0.0;
+}
+
+/* One track through the detector: returns 1 if it misses a seed layer.
+ * hit[l][9] and crossed[l] per layer, truth[l][6] after the kick. */
+static int det_track(const kfg_det_config* cfg, const kfg_key* key, int32_t t, uint32_t att, int* q_out,
+                     particle* start, double hit[][9], int crossed[], double truthl[][6]) {
+  const int L = cfg->n_layers;
+  double u[2], v[2], g[2], g2[2];
+  uniform2(key, (uint32_t)t, P_KIN, att, 0, u);
+  uniform2(key, (uint32_t)t, P_KIN, att, 1, v);
+  normal2(key, (uint32_t)t, P_KIN, att, 2, g);
+  normal2(key, (uint32_t)t, P_KIN, att, 3, g2);
+  int q = u[0] < 0.5 ? 1 : -1;
+  double pt = cfg->pt_min + u[1] * (cfg->pt_max - cfg->pt_min);
+  double phi0 = KFG_TWO_PI * v[0];
+  double eta = -cfg->eta_max + 2.0 * cfg->eta_max * v[1];
+  particle pa;
+  pa.x = cfg->vtx_sxy * g[0];
+  pa.y = cfg->vtx_sxy * g[1];
+  pa.z = cfg->vtx_sz * g2[0];
+  pa.px = pt * cos(phi0);
+  pa.py = pt * sin(phi0);
+  pa.pz = pt * sinh(eta);
+  *start = pa;
+  *q_out = q;
+  for (int l = 0; l < L; ++l) {
+    crossed[l] = 0;
+    const int kind = cfg->kind[l];
+    particle av = pa, pm = pa;
+    /* the layer is crossed where the average surface is: inside the extent
+       and, on a disk, within half a turn while still moving outwards (a
+       looper coming back is not followed) */
+    int miss = kind == KFG_DISK ? move_to_z(&av, q, cfg->bz, cfg->pos[l])
+                                : move_to_radius(&av, q, cfg->bz, cfg->pos[l]);
+    if (!miss) {
+      double w = kind == KFG_DISK ? hypot(av.x, av.y) : av.z;
+      miss = !(w >= cfg->lo[l] && w <= cfg->hi[l]);
+      if (kind == KFG_DISK) {
+        double turn = fabs(KFG_KAPPA * cfg->bz * (av.z - pa.z) / pa.pz);
+        if (!(av.x * av.px + av.y * av.py > 0.0) || !(turn < 3.14159265358979323846)) miss = 1;
+      }
+    }
+    /* the hit: on the module at the phi of that crossing */
+    if (!miss) {
+      double surf = module_surface(cfg, l, atan2(av.y, av.x));
+      miss = kind == KFG_DISK ? move_to_z(&pm, q, cfg->bz, surf) : move_to_radius(&pm, q, cfg->bz, surf);
+    }
+    if (miss) {
+      if (l < cfg->n_seed_layers) return 1;
+      continue;
+    }
+    pa = pm;
+    double gs[2], gm[2];
+    normal2(key, (uint32_t)t, P_LAYER + (uint32_t)l, att, 0, gs);
+    normal2(key, (uint32_t)t, P_LAYER + (uint32_t)l, att, 1, gm);
+    double phit = atan2(pa.y, pa.x), r = hypot(pa.x, pa.y);
+    double cv[6];
+    if (kind == KFG_DISK) {
+      double rh = cfg->smear ? r + cfg->sig_w * gs[1] : r;
+      double phih = cfg->smear ? phit + cfg->sig_rphi * gs[0] / r : phit;
+      hit[l][0] = cfg->smear ? rh * cos(phih) : pa.x;
+      hit[l][1] = cfg->smear ? rh * sin(phih) : pa.y;
+      hit[l][2] = pa.z;
+      disk_hit_cov(phih, cfg->sig_rphi, cfg->sig_w, cv);
+    } else {
+      double phih = cfg->smear ? phit + cfg->sig_rphi * gs[0] / r : phit;
+      hit[l][0] = cfg->smear ? r * cos(phih) : pa.x;
+      hit[l][1] = cfg->smear ? r * sin(phih) : pa.y;
+      hit[l][2] = cfg->smear ? pa.z + cfg->sig_w * gs[1] : pa.z;
+      hit_cov(phih, cfg->sig_rphi, cfg->sig_w, cv);
+    }
+    for (int c = 0; c < 6; ++c) hit[l][3 + c] = cv[c];
+    crossed[l] = 1;
+    if (cfg->x_over_x0 > 0) {
+      double th0 = highland_theta0_kind(&pa, kind, cfg->x_over_x0, cfg->mass);
+      scatter(&pa, th0 * gm[0], th0 * gm[1]);
+    }
+    truthl[l][0] = pa.x; truthl[l][1] = pa.y; truthl[l][2] = pa.z;
+    truthl[l][3] = pa.px; truthl[l][4] = pa.py; truthl[l][5] = pa.pz;
+  }
+  return 0;
+}
+
+/*
+ * Generate one event over a general detector.  Hits are grouped by layer and
+ * shuffled within each layer; a hit's position is its original index.
+ * Arrays are sized by the caller for n_hits_cap hits; *n_hits receives the
+ * count.  trk_hits [L][n_tracks] (-1 where the track does not cross the
+ * layer), truth [L][6][n_tracks] (NaN where not crossed) or NULL, vtx
+ * [6][n_tracks] or NULL.  Returns 2 if the capacity is too small, 3 if a
+ * track could not be generated.
+ */
+int kfg_det_event(const kfg_det_config* cfg, uint64_t event, int32_t n_tracks, double* hx, double* hy, double* hz,
+                  double* hcov, int32_t* hlayer, int32_t* htrack, int32_t* trk_hits, int8_t* trk_q, double* truth,
+                  double* vtx, int64_t n_hits_cap, int64_t* n_hits) {
+  const int L = cfg->n_layers;
+  if (L < 1 || L > 32 || n_tracks < 0 || cfg->n_mod < 1 || cfg->n_seed_layers > L) return 1;
+  kfg_key key = make_key(cfg->seed, event);
+  double* th = (double*)malloc(sizeof(double) * 9 * (size_t)L * (size_t)(n_tracks > 0 ? n_tracks : 1));
+  int* cr = (int*)malloc(sizeof(int) * (size_t)L * (size_t)(n_tracks > 0 ? n_tracks : 1));
+  if (!th || !cr) { free(th); free(cr); return 4; }
+  int failed = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+:failed)
+  for (int32_t t = 0; t < n_tracks; ++t) {
+    double hit[32][9], tr[32][6];
+    int crossed[32], q = 1, ok = 0;
+    particle st;
+    for (uint32_t att = 0; att < 1000 && !ok; ++att) ok = !det_track(cfg, &key, t, att, &q, &st, hit, crossed, tr);
+    if (!ok) { failed += 1; continue; }
+    trk_q[t] = (int8_t)q;
+    for (int l = 0; l < L; ++l) {
+      cr[(size_t)l * n_tracks + t] = crossed[l];
+      for (int c = 0; c < 9; ++c) th[((size_t)l * n_tracks + t) * 9 + c] = hit[l][c];
+      if (truth)
+        for (int c = 0; c < 6; ++c) truth[((int64_t)l * 6 + c) * n_tracks + t] = crossed[l] ? tr[l][c] : NAN;
+    }
+    if (vtx) {
+      double s6[6] = {st.x, st.y, st.z, st.px, st.py, st.pz};
+      for (int c = 0; c < 6; ++c) vtx[(int64_t)c * n_tracks + t] = s6[c];
+    }
+  }
+  if (failed) { free(th); free(cr); return 3; }
+  int64_t ntrue[32], counts[32], base[33];
+  base[0] = 0;
+  for (int l = 0; l < L; ++l) {
+    ntrue[l] = 0;
+    for (int32_t t = 0; t < n_tracks; ++t) ntrue[l] += cr[(size_t)l * n_tracks + t];
+    double fr = cfg->noise_lo;
+    if (cfg->noise_hi > cfg->noise_lo) {
+      double uu[2];
+      uniform2(&key, 0, P_NFRAC + (uint32_t)l, 0, 0, uu);
+      fr = cfg->noise_lo + uu[0] * (cfg->noise_hi - cfg->noise_lo);
+    }
+    counts[l] = ntrue[l] + (int64_t)llround(fr * (double)ntrue[l]);
+    base[l + 1] = base[l] + counts[l];
+  }
+  *n_hits = base[L];
+  if (base[L] > n_hits_cap) { free(th); free(cr); return 2; }
+  /* true hits in track order, then noise, per layer */
+  for (int l = 0; l < L; ++l) {
+    int64_t slot = base[l];
+    for (int32_t t = 0; t < n_tracks; ++t) {
+      trk_hits[(int64_t)l * n_tracks + t] = -1;
+      if (!cr[(size_t)l * n_tracks + t]) continue;
+      const double* h = th + ((size_t)l * n_tracks + t) * 9;
+      hx[slot] = h[0]; hy[slot] = h[1]; hz[slot] = h[2];
+      for (int c = 0; c < 6; ++c) hcov[(int64_t)c * n_hits_cap + slot] = h[3 + c];
+      hlayer[slot] = l;
+      htrack[slot] = t;
+      trk_hits[(int64_t)l * n_tracks + t] = (int32_t)(slot - base[l]); /* pre-shuffle position */
+      ++slot;
+    }
+    for (int64_t j = 0; j < counts[l] - ntrue[l]; ++j, ++slot) {
+      double uu[2];
+      uniform2(&key, (uint32_t)j, P_NOISE + (uint32_t)l, (uint32_t)(j >> 32), 0, uu);
+      double phi = KFG_TWO_PI * uu[0];
+      double w = cfg->lo[l] + (cfg->hi[l] - cfg->lo[l]) * uu[1];
+      double surf = module_surface(cfg, l, phi);
+      double cv[6];
+      if (cfg->kind[l] == KFG_DISK) {
+        hx[slot] = w * cos(phi); hy[slot] = w * sin(phi); hz[slot] = surf;
+        disk_hit_cov(phi, cfg->sig_rphi, cfg->sig_w, cv);
+      } else {
+        hx[slot] = surf * cos(phi); hy[slot] = surf * sin(phi); hz[slot] = w;
+        hit_cov(phi, cfg->sig_rphi, cfg->sig_w, cv);
+      }
+      for (int c = 0; c < 6; ++c) hcov[(int64_t)c * n_hits_cap + slot] = cv[c];
+      hlayer[slot] = l;
+      htrack[slot] = -1;
+    }
+  }
+  free(th);
+  free(cr);
+  /* keyed shuffle within each layer (as kfg_event); perm maps new -> old */
+  int64_t maxc = 1;
+  for (int l = 0; l < L; ++l) if (counts[l] > maxc) maxc = counts[l];
+  int64_t* perm = (int64_t*)malloc(sizeof(int64_t) * (size_t)maxc);
+  int64_t* inv = (int64_t*)malloc(sizeof(int64_t) * (size_t)maxc);
+  double* tmp = (double*)malloc(sizeof(double) * (size_t)maxc);
+  int32_t* itmp = (int32_t*)malloc(sizeof(int32_t) * (size_t)maxc);
+  if (!perm || !inv || !tmp || !itmp) { free(perm); free(inv); free(tmp); free(itmp); return 4; }
+  for (int l = 0; l < L; ++l) {
+    int64_t n = counts[l], b = base[l];
+    for (int64_t i = 0; i < n; ++i) perm[i] = i;
+    for (int64_t i = n - 1; i > 0; --i) {
+      double uu[2];
+      uniform2(&key, (uint32_t)i, P_SHUFFLE + (uint32_t)l, (uint32_t)(i >> 32), 0, uu);
+      int64_t j = (int64_t)floor(uu[0] * (double)(i + 1));
+      if (j > i) j = i;
+      int64_t sw = perm[i]; perm[i] = perm[j]; perm[j] = sw;
+    }
+    for (int64_t i = 0; i < n; ++i) inv[perm[i]] = i;
+    double* darr[3] = {hx, hy, hz};
+    for (int a = 0; a < 3; ++a) {
+      for (int64_t i = 0; i < n; ++i) tmp[i] = darr[a][b + perm[i]];
+      memcpy(darr[a] + b, tmp, sizeof(double) * (size_t)n);
+    }
+    for (int c = 0; c < 6; ++c) {
+      double* col = hcov + (int64_t)c * n_hits_cap + b;
+      for (int64_t i = 0; i < n; ++i) tmp[i] = col[perm[i]];
+      memcpy(col, tmp, sizeof(double) * (size_t)n);
+    }
+    for (int64_t i = 0; i < n; ++i) itmp[i] = htrack[b + perm[i]];
+    memcpy(htrack + b, itmp, sizeof(int32_t) * (size_t)n);
+    for (int32_t t = 0; t < n_tracks; ++t) {
+      int32_t* th_l = trk_hits + (int64_t)l * n_tracks + t;
+      if (*th_l >= 0) *th_l = (int32_t)(b + inv[*th_l]);
+    }
+  }
+  free(perm); free(inv); free(tmp); free(itmp);
+  return 0;
+}

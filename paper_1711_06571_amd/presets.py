@@ -124,4 +124,92 @@ def learned() -> Workload:
                     barrel(17), GenSettings(seed=SEED_BASE + 5, noise_lo=0.2, noise_hi=0.2), 1, 20000)
 
 
+BARREL, DISK = 0, 1
+
+
+@dataclass
+class Detector:
+    """General detector (section 4.1): barrel cylinders and endcap disks in
+    the order a track from the origin meets them (barrel layers outwards,
+    then the disks of each side outwards).  pos: average radius (barrel) or z
+    of the average plane (disk); lo, hi: active extent in z (barrel) or r
+    (disk); dmod: module offset from the average surface (modules of even
+    phi sector at +dmod, odd at -dmod; n_mod sectors)."""
+    kind: list
+    pos: list
+    lo: list
+    hi: list
+    dmod: list
+    bz: float = f32(3.8)
+    x_over_x0: float = f32(0.02)
+    mass: float = f32(0.13957)
+    beam_sigma: float = f32(0.01)
+    n_mod: int = 24
+    n_seed_layers: int = 3
+
+    def __post_init__(self):
+        for k in ("pos", "lo", "hi", "dmod"):
+            setattr(self, k, [f32(v) for v in getattr(self, k)])
+        self.kind = [int(v) for v in self.kind]
+        self.bz, self.x_over_x0, self.mass = f32(self.bz), f32(self.x_over_x0), f32(self.mass)
+        self.beam_sigma = f32(self.beam_sigma)
+
+    @property
+    def n_layers(self) -> int:
+        return len(self.kind)
+
+    def seed_geometry(self) -> Geometry:
+        """The barrel of the seed layers (exact cylinders), for the seed
+        convention."""
+        ns = self.n_seed_layers
+        assert all(k == BARREL for k in self.kind[:ns]) and all(d == 0 for d in self.dmod[:ns])
+        zh = max(max(abs(v) for v in self.lo[:ns]), max(abs(v) for v in self.hi[:ns]))
+        return Geometry(n_layers=ns, r=list(self.pos[:ns]), z_half=zh, bz=self.bz, x_over_x0=self.x_over_x0,
+                        mass=self.mass, beam_sigma=self.beam_sigma)
+
+    def replace(self, **kw) -> "Detector":
+        return dataclasses.replace(self, **kw)
+
+
+def cylinder_with_lids(dmod_barrel=0.5, dmod_disk=1.0, **kw) -> Detector:
+    """Ten barrel layers at r = 4, 8, .., 40 cm (the three seed layers over
+    |z| <= 100 cm, the others over |z| <= 50 cm, their modules 0.5 cm off the
+    average radius) closed by seven disks on each side at |z| = 55 .. 112 cm
+    covering 14 <= r <= 42 cm (modules 1 cm off the average z)."""
+    zd = [55.0, 62.0, 70.0, 79.0, 89.0, 100.0, 112.0]
+    kind = [BARREL] * 10 + [DISK] * 14
+    pos = [4.0 * (i + 1) for i in range(10)] + zd + [-z for z in zd]
+    lo = [-100.0] * 3 + [-50.0] * 7 + [14.0] * 14
+    hi = [100.0] * 3 + [50.0] * 7 + [42.0] * 14
+    dmod = [0.0] * 3 + [dmod_barrel] * 7 + [dmod_disk] * 14
+    return Detector(kind, pos, lo, hi, dmod, **kw)
+
+
+@dataclass
+class DetWorkload:
+    name: str
+    detector: Detector
+    gen: GenSettings
+    n_events: int
+    n_tracks: int
+    cuts: BuildCuts = field(default_factory=BuildCuts)
+
+
+def lids() -> DetWorkload:
+    """Building and fitting in the cylinder with lids with displaced modules
+    (two-step propagation): 20 000 tracks with |eta| <= 2 + 20 % noise per
+    layer, 63 phi x 16 (z or r) bins per layer."""
+    return DetWorkload("lids: 1 event x 20000 tracks |eta|<=2 + 20% noise/layer, 10 barrel layers + 2x7 disks, "
+                       "modules off the average surface, 63x16 bins, cap 6, chi2<30, 1 hole",
+                       cylinder_with_lids(), GenSettings(seed=SEED_BASE + 6, eta_max=2.0, noise_lo=0.2, noise_hi=0.2),
+                       1, 20000)
+
+
+def lids_fit() -> DetWorkload:
+    """Fit at scale in the cylinder with lids: 50 events x 20 000 tracks."""
+    return DetWorkload("lids_fit: 50 events x 20000 tracks |eta|<=2, 10 barrel layers + 2x7 disks, displaced modules",
+                       cylinder_with_lids(), GenSettings(seed=SEED_BASE + 7, eta_max=2.0), 50, 20000)
+
+
 ALL = {"fit_small": fit_small, "fit_scale": fit_scale, "build": build, "batch": batch, "learned": learned}
+DETECTOR_WORKLOADS = {"lids": lids, "lids_fit": lids_fit}

@@ -123,6 +123,53 @@ def test_batched_build_matches_oracle(bt):
         print(f"batched build, event {e} ({ne} tracks, {h1 - h0} hits): {r}")
 
 
+
+def test_batched_64_events_graph_matches_oracle():
+    """The batched configuration the benchmark times: all 64 uneven events
+    (log-uniform 500..50 000 tracks) binned and built by one replay of the
+    captured graph in FP64 arithmetic.  Seeds sampled from seven events (the
+    smallest, the largest and five between) are built by the oracle one by
+    one; hit lists, nhits and status must agree on every decidable seed."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1711_06571_amd import batch, kftrack as kf
+    b = batch.load(presets.batch())
+    w, eb = b.w, b.eb
+    assert w.n_events == 64 and len(eb.seed_offsets) == 65
+    p = batch.plan(b, arith=kf.ARITH_F64)
+    p.launch()
+    p.stream.synchronize()
+    gb = {k: host(v) for k, v in p.out.items()}
+    p.close()
+    counts = np.diff(eb.seed_offsets)
+    order = np.argsort(counts, kind="stable")
+    picks = sorted({int(order[int(round(q * (len(order) - 1)))]) for q in (0, 1 / 6, 2 / 6, 3 / 6, 4 / 6, 5 / 6, 1)})
+    tot = dict(n=0, undecidable=0.0, mismatched=0)
+    for e in picks:
+        h0, h1 = int(eb.hit_offsets[e]), int(eb.hit_offsets[e + 1])
+        s0, s1 = int(eb.seed_offsets[e]), int(eb.seed_offsets[e + 1])
+        ne = s1 - s0
+        lde = ((ne + 63) // 64) * 64
+        Hs = np.zeros((3, 9, lde), dtype=np.float32)
+        Hs[:, :, :ne] = eb.seed_hits[:, :, s0:s1]
+        so = oracle.seed(w.geometry, Hs, ne)
+        lst = np.unique(np.linspace(0, ne - 1, 30).astype(np.int64))
+        ob = oracle.build(w.geometry, w.cuts, np.ascontiguousarray(eb.layer[h0:h1]),
+                          np.ascontiguousarray(eb.xyz[:, h0:h1]), np.ascontiguousarray(eb.cov[:, h0:h1]),
+                          so["par"], so["cov"], so["q"], ne, seed_list=lst)
+        r = compare(gb, ob, lst.size, cols_g=s0 + lst, ctx=f"64-event graph, event {e} ({ne} tracks)")
+        print(f"64-event graph, event {e} ({ne} tracks, {h1 - h0} hits): {r}", flush=True)
+        tot["n"] += r["n"]
+        tot["undecidable"] += r["undecidable"] * r["n"]
+        tot["mismatched"] += r["mismatched"]
+    und = tot["undecidable"] / tot["n"]
+    print(f"64-event graph: {tot['n']} sampled seeds of {len(picks)} events, undecidable {und:.3f}, "
+          f"differing {tot['mismatched']}")
+    assert len(picks) >= 5
+    from test_gpu_build import MISMATCH_MAX_FRACTION, UNDECIDABLE_MAX
+    assert und <= UNDECIDABLE_MAX
+    assert tot["mismatched"] <= max(1, int(MISMATCH_MAX_FRACTION * tot["n"]))
+
 def test_gather_hits_matches_indexing(bt):
     """kf_gather_hits against plain indexing of the input hits: layer l of
     seed i holds hit event_offset + index, or zeros and the hole bit where the

@@ -78,7 +78,10 @@ def test_fit_fp32_arithmetic_agreement(kf):
     print(f"fp32 arithmetic: agreement {agree.mean():.4f} overall, {agree[well].mean():.4f} on "
           f"{well.mean():.3f} well-conditioned seeds")
     assert agree[well].mean() >= 0.999
-    assert agree.mean() > 0.8
+    # FP32 arithmetic meets the tolerances on well-conditioned seeds only; over
+    # all tracks it agrees on 0.8895 (measured), FP64 arithmetic is the parity
+    # mode
+    assert agree.mean() >= 0.87
 
 
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 777])

@@ -119,6 +119,34 @@ def test_learned_build_matches_oracle(env, gate_q, state):
     assert (~same).sum() <= max(2, int(0.01 * n))
 
 
+def test_learned_build_full_event_matches_oracle(env):
+    """The learned configuration the benchmark times, at its size: the gated
+    network (trained on the gated rows) on a 20 000-track test event plus
+    20 % noise, FP64 arithmetic, against the oracle with the same network on
+    seeds sampled over the event."""
+    kf, window, w = env["kf"], env["window"], env["w"]
+    if "tg" not in env:
+        env["tg"] = window.train_gated(w, env["rows"], epochs=3)
+    t = env["tg"]
+    kappa = 1.0
+    kf.mlp_set_header(t.block, kappa=kappa)
+    e = 2
+    test = window.load_events(w, [e])
+    n = test.eb.n_seeds
+    assert n == w.n_tracks
+    out, _ = window.build(w, test, window_mode=1, block=t.block, arith=kf.ARITH_F64)
+    torch.cuda.synchronize()
+    g = {k: host(v) for k, v in out.items()}
+    ev = datagen.generate(w.geometry, w.gen, e, w.n_tracks)
+    H = datagen.track_hits(ev)
+    so = oracle.seed(w.geometry, H, n)
+    lst = np.concatenate([np.arange(0, n, 97)[:200], np.arange(n - 40, n)])
+    o = oracle.build(w.geometry, w.cuts, ev.layer, ev.xyz, ev.cov, so["par"], so["cov"], so["q"], n, seed_list=lst,
+                     window_mode=1, mlp_blob=oracle_blob(kf, t, kappa))
+    from test_gpu_build import compare
+    r = compare(g, o, lst.size, cols_g=lst, ctx="learned full event f64")
+    print("learned build, full event, f64:", r)
+
 @pytest.mark.parametrize("arith,state", [("f32", 0), ("f64", 0), ("f32", 1), ("f64", 1)])
 def test_closed_gates_build_equals_plain(env, arith, state):
     """Gates above every plain window: the learned kernel never runs the
@@ -161,5 +189,6 @@ def test_learned_vs_plain(env, arith):
     print(f"{arith}: gates {t.gates}, kappa {kap} (val trace {trace}); test eff plain {ep:.4f} learned {el:.4f}; "
           f"hits tested per cand-layer plain {cp[1] / cp[0]:.2f} learned {cl[1] / cl[0]:.2f}; "
           f"build ms plain {tp:.3f} learned {tl:.3f}")
-    assert ep - el <= 0.002  # calibrated on validation events to 0.1 %; test events disjoint
+    assert ep - el <= 0.001  # calibrated on a validation event to 0.1 %; the test event is disjoint
     assert cl[1] <= cp[1]
+    assert tl < tp  # the learned window pays in the Cartesian state
