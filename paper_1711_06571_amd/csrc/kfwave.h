@@ -1,0 +1,239 @@
+// Wave-level building blocks of the combinatorial track builders (sections
+// 4.3: fixed candidate slots per seed, ranked children): lane shuffles,
+// reductions over a seed's slots, the 64-bit rank key of a child, a lane's
+// list of its best accepted hits in LDS, wave prefix sums, and the per-call
+// preparation kernels shared by the builders (queue reset, fine phi index of
+// the binned hits, packed hit copy) with the layout of their workspace.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kfhost.h"
+
+namespace {
+
+constexpr uint64_t kInfKey = ~0ull;
+constexpr uint32_t kHoleIdx = 0xFFFFFFu;
+constexpr int kMaxOrig = (1 << 24) - 2;
+
+template <typename T> __device__ inline T shfl(T v, int src) { return __shfl(v, src, 64); }
+__device__ inline uint64_t shfl_u64(uint64_t v, int src) {
+  uint32_t lo = __shfl((uint32_t)v, src, 64), hi = __shfl((uint32_t)(v >> 32), src, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline double shfl_d(double v, int src) {
+  uint64_t b = __double_as_longlong(v);
+  return __longlong_as_double((long long)shfl_u64(b, src));
+}
+__device__ inline float shfl_t(float v, int src) { return __shfl(v, src, 64); }
+// value of lane j (j uniform across the wave)
+__device__ inline float readlane_t(float v, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+__device__ inline double readlane_t(double v, int j) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, j);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), j);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ inline double shfl_t(double v, int src) { return shfl_d(v, src); }
+
+// Reductions over the S lanes base .. base+S-1 of one seed (S <= 8, any
+// value).  The minimum doubles a rotation: after the steps 1, 2, 4 a lane
+// has seen the slots slot .. slot+7 (mod S), which covers the group.  Lanes
+// that hold no seed (used = false) only ever read themselves.
+__device__ inline int rot_lane(int base, int slot, int d, int S, bool used) {
+  const int t = slot + d;
+  return used ? base + (t >= S ? t - S : t) : base + slot;
+}
+__device__ inline uint64_t group_min(uint64_t k, int base, int slot, int S, bool used) {
+  for (int d = 1; d < S; d <<= 1) {
+    const uint64_t o = shfl_u64(k, rot_lane(base, slot, d, S, used));
+    k = o < k ? o : k;
+  }
+  return k;
+}
+__device__ inline int group_sum(int v, int base, int slot, int S, bool used) {
+  int acc = v;
+  for (int d = 1; d < S; ++d) {
+    const int o = __shfl(v, rot_lane(base, slot, d, S, used), 64);
+    acc += used ? o : 0;
+  }
+  return acc;
+}
+
+__device__ inline uint32_t chi2_bits(float c) {
+  c = c > 0.f ? c : 0.f;  // chi2 >= 0; clears a negative rounding residue and -0
+  return __float_as_uint(c);
+}
+
+// rank key: nhits desc, chi2 asc, parent slot asc, hit index asc (hole last)
+__device__ inline uint64_t make_key(int nhits, float chi2, int slot, uint32_t orig24) {
+  return ((uint64_t)(31 - nhits) << 59) | ((uint64_t)chi2_bits(chi2) << 27) | ((uint64_t)slot << 24) | orig24;
+}
+
+__device__ inline float wrap_2pi(float p) {
+  const float tp = 6.283185307179586f;
+  if (p < 0.f) p += tp;
+  if (p >= tp) p -= tp;
+  return p;
+}
+
+// Fine phi index of a z row: key(phi) = the sub-bin of a stored phi, with
+// n_phi * refine sub-bins over [0, 2 pi).  The stored phi of a row is
+// non-decreasing along the sorted order (hits are sorted by bin, then phi,
+// and rounding to FP32 keeps the order of the FP64 phi that set the bin), so
+// key is non-decreasing too and fine[j] = first position with key >= j
+// brackets every hit whose stored phi lies in an interval.
+__host__ __device__ inline int fine_key(float phi, float inv, int nf) {
+  const float t = floorf(phi * inv);
+  const int k = t > 0.f ? (int)t : 0;  // also maps NaN to 0
+  return k < nf - 1 ? k : nf - 1;
+}
+__host__ __device__ inline float fine_inv(int nf) { return (float)nf / 6.283185307179586f; }
+
+// A lane's accepted hits, best first (chi2 ascending, hit index ascending),
+// at most cap of them.  The entries live in LDS, [cap][64] per wave, so that
+// the list costs no registers; this lane's column starts at c2 / pos / orig.
+// chi2 is kept in FP32 (the hit search computes it in FP32, see coop_scan).
+struct TopList {
+  float* c2;
+  int32_t* pos;
+  uint32_t* orig;
+  int n;    // entries held (<= cap)
+  int tot;  // accepted hits seen
+  int scanned, tested;  // work counters of the hits this lane examined
+};
+
+__device__ inline bool top_before(float c2, uint32_t orig, float oc2, uint32_t oorig) {
+  return c2 < oc2 || (c2 == oc2 && orig < oorig);
+}
+
+// Insertion into a lane's list: a full list admits only a hit that ranks
+// before its last entry (which drops out); the entries that rank after the
+// new hit shift down one slot.
+__device__ inline void lds_insert(TopList& tl, int cap, int& held, float c2, int pos, uint32_t orig) {
+  int j = held;
+  if (j == cap) {
+    if (!top_before(c2, orig, tl.c2[(cap - 1) * 64], tl.orig[(cap - 1) * 64])) return;
+    j = cap - 1;
+  } else {
+    held += 1;
+  }
+  while (j > 0) {
+    const float pc = tl.c2[(j - 1) * 64];
+    const uint32_t po = tl.orig[(j - 1) * 64];
+    if (!top_before(c2, orig, pc, po)) break;
+    tl.c2[j * 64] = pc;
+    tl.pos[j * 64] = tl.pos[(j - 1) * 64];
+    tl.orig[j * 64] = po;
+    --j;
+  }
+  tl.c2[j * 64] = c2;
+  tl.pos[j * 64] = pos;
+  tl.orig[j * 64] = orig;
+}
+
+__device__ inline void top_get(const TopList& tl, int k, float& c2, int& pos, uint32_t& orig) {
+  c2 = tl.c2[k * 64];
+  pos = tl.pos[k * 64];
+  orig = tl.orig[k * 64];
+}
+
+// Wave-wide inclusive prefix sum; returns the exclusive prefix, total via ref.
+__device__ inline int wave_excl_scan(int v, int lane, int& total) {
+  int x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(x, d, 64);
+    if (lane >= d) x += t;
+  }
+  total = __shfl(x, 63, 64);
+  return x - v;
+}
+
+__device__ inline int wave_max(int v) {
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    const int o = __shfl_xor(v, m, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Per-wave LDS of the cooperative hit search: each candidate's count of
+// accepted hits, and per round the candidate whose pairs start at each lane.
+struct AccBuf {
+  int32_t* tot;
+  int32_t* start;
+};
+
+__device__ inline uint32_t pack_hist(int parent, uint32_t orig24) {
+  return ((uint32_t)parent << 24) | (orig24 == kHoleIdx ? 0xFFFFFFu : orig24);
+}
+
+__global__ void build_clear(int32_t* queue, int32_t* event_done, int n_events, int64_t* start_tick) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *queue = 0;
+  if (i == 0 && start_tick) *start_tick = INT64_MAX;
+  for (int e = i; e < n_events; e += gridDim.x * blockDim.x) event_done[e] = 0;
+}
+
+// Fine phi index: one wave per (event, layer, z row).  Entry j of the row is
+// the first sorted position whose key is >= j (the row's end if none).
+__global__ void __launch_bounds__(256) fine_kernel(int n_rows, int n_phi, int n_z, int nf,
+                                                   const int32_t* __restrict__ offsets,
+                                                   const float* __restrict__ phi, int32_t* __restrict__ fine) {
+  const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n_rows) return;
+  const int nb = n_phi * n_z;
+  const int el = row / n_z, iz = row % n_z;
+  const int32_t* off = offsets + (size_t)el * (nb + 1);
+  const int rs = off[iz * n_phi], re = off[(iz + 1) * n_phi];
+  int32_t* f = fine + (size_t)row * (nf + 1);
+  const float inv = fine_inv(nf);
+  for (int p = rs + lane; p < re; p += 64) {
+    const int k = fine_key(phi[p], inv, nf);
+    const int kp = p > rs ? fine_key(phi[p - 1], inv, nf) : -1;
+    for (int j = kp + 1; j <= k; ++j) f[j] = p;
+  }
+  const int kl = re > rs ? fine_key(phi[re - 1], inv, nf) : -1;
+  for (int j = kl + 1 + lane; j <= nf; j += 64) f[j] = re;
+}
+
+// Packed hits for the hit search: one thread per sorted position.
+__global__ void __launch_bounds__(256) pack_kernel(int n_hits, const float* __restrict__ x, const float* __restrict__ y,
+                                                   const float* __restrict__ z, const float* __restrict__ phi,
+                                                   const float* __restrict__ cov, const int32_t* __restrict__ orig,
+                                                   float4* __restrict__ pack) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_hits) return;
+  const size_t n = (size_t)n_hits;
+  float4* o = pack + (size_t)p * 3;
+  o[0] = make_float4(phi[p], x[p], y[p], z[p]);
+  o[1] = make_float4(cov[p], cov[n + p], cov[2 * n + p], cov[3 * n + p]);
+  o[2] = make_float4(cov[4 * n + p], cov[5 * n + p], __int_as_float(orig[p]), 0.f);
+}
+
+size_t pack_bytes(int n_hits) { return (((size_t)n_hits * 48) + 255) & ~(size_t)255; }
+
+size_t fine_bytes(int n_events, int n_layers, int n_phi, int n_z, int refine) {
+  return (size_t)n_events * n_layers * n_z * ((size_t)n_phi * refine + 1) * 4;
+}
+
+// Workspace: queue head and per-event counters | fine phi index | packed
+// hits (48 bytes each) | history tables of the resident waves (16 per CU of the current device: four per
+// SIMD, more than the build kernels' register use allows; a grid that would
+// hold more waves is clamped).
+size_t ws_head_bytes(int n_events) { return 256 + (((size_t)n_events * 4 + 255) & ~(size_t)255); }
+int hist_waves_of_device() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                               hipSuccess || cus < 1)
+    cus = 256;
+  return cus * 16;
+}
+
+
+}  // namespace
