@@ -32,6 +32,12 @@ FLOP_WINDOW = 25        # window half-widths from the predicted covariance
 FLOP_WINDOW_TEST = 8    # exact phi/z test of one scanned hit
 FLOP_CHI2 = 47          # innovation + chi2 of one in-window hit
 FLOP_UPDATE = 202       # innovation + Kalman gain and state/covariance update
+# the general detector's build (two-step propagation): step 1 per candidate
+# step is FLOP_PREDICT + FLOP_WINDOW; per in-window hit, step 2 (helix step
+# 40, measured rows of the surface Jacobian 60, S = M P M^T + V 170) and chi2
+FLOP_STEP2_CHI2 = 310
+# a chosen hit: step 2 with the full transport and scattering, then the update
+FLOP_STEP2_UPDATE = FLOP_PREDICT + FLOP_UPDATE
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X vector peaks (published)
 PEAK_HBM_GBS = 8000.0
 
@@ -49,6 +55,7 @@ def parse():
     ap.add_argument("--no-other-arith", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain window comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-events measurement")
+    ap.add_argument("--no-lids", action="store_true", help="skip the general-detector (endcap disks) measurement")
     ap.add_argument("--autotune", action="store_true", help="sweep the batched build's launch parameters")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes 5 times (counter calibration)")
@@ -174,6 +181,116 @@ def batched(arith, autotune, log):
         res["tuned"] = dict(tr.best.__dict__)
         res["tune_points"] = len(tr.points)
     log(f"batch: {ms:.3f} ms per launch")
+    return res
+
+
+def lids(arith, log, n_events=16, fit_events=50):
+    """The general detector (section 4.1: the barrel closed by endcap disks,
+    modules off the average surfaces): 16 events x 20 000 tracks (|eta| <= 2,
+    20 % noise per layer) through hit_bin_det -> kf_build_det (two-step
+    propagation, one persistent launch) -> kf_gather_hits -> kf_fit_det, and
+    the fit alone over 50 events x 20 000 tracks (lids_fit)."""
+    import torch
+    from paper_1711_06571_amd import kftrack as kf
+    from paper_1711_06571_amd import presets, workloads
+    dev = "cuda:0"
+    w = presets.lids()
+    d = w.detector
+    cuts = w.cuts
+    L, F = d.n_layers, cuts.first_layer
+    t0 = time.perf_counter()
+    eb = workloads.det_event_batch(w, range(n_events))
+    n = eb.n_seeds
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    layer, xyz, cov, hoff, sev = T(eb.layer), T(eb.xyz), T(eb.cov), T(eb.hit_offsets), T(eb.seed_event)
+    seeds = kf.kf_seed(d.seed_geometry(), n, T(eb.track_rows[:3]))
+    binned = kf.BinnedHits(n_events, L, cuts.n_phi_bins, cuts.n_z_bins, xyz.shape[1], dev)
+    ws_bin = torch.empty(kf.hit_bin_workspace_bytes(n_events, L, cuts.n_phi_bins, cuts.n_z_bins, xyz.shape[1]),
+                         dtype=torch.uint8, device=dev)
+    bp = kf.build_params(cuts, arith=arith)
+    ws_build = torch.empty(kf.kf_build_workspace_bytes(bp, binned, n), dtype=torch.uint8, device=dev)
+    ld = seeds["par"].shape[1]
+    fit_hits = torch.zeros((L, 9, ld), dtype=torch.float32, device=dev)
+    hole = torch.zeros(ld, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    state = {}
+
+    def step(evs=None, counters=None):
+        rec = (lambda i: evs[i].record(stream)) if evs is not None else (lambda i: None)
+        ex = kf.BuildExtra()
+        ex.seed_event = sev.data_ptr()
+        if counters is not None:
+            ex.counters = counters.data_ptr()
+        rec(0)
+        kf.hit_bin_det(d, cuts.n_phi_bins, cuts.n_z_bins, layer, xyz, cov, event_offsets=hoff, out=binned, ws=ws_bin)
+        rec(1)
+        state["b"] = kf.kf_build_det(d, bp, binned, n, seeds["par"], seeds["cov"], seeds["q"], extra=ex,
+                                     out=state.get("b"), ws=ws_build)
+        rec(2)
+        kf.kf_gather_hits(L, F, n, state["b"]["hits"], xyz, cov, seed_event=sev, event_offsets=hoff,
+                          fit_hits=fit_hits, hole_mask=hole)
+        rec(3)
+        state["f"] = kf.kf_fit_det(d, n, F, fit_hits, state["b"]["visit"], seeds["par"], seeds["cov"], seeds["q"],
+                                   hole_mask=hole, out=state.get("f"), arith=arith)
+        rec(4)
+
+    step()
+    reps = 5
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(reps)]
+    torch.cuda.synchronize()
+    tw = time.perf_counter()
+    for k in range(reps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - tw) * 1e3 / reps
+    st = np.array([[evs[k][i].elapsed_time(evs[k][i + 1]) for i in range(4)] for k in range(reps)]).mean(axis=0)
+    cnt = torch.zeros(4, dtype=torch.int64, device=dev)
+    step(counters=cnt)
+    torch.cuda.synchronize()
+    n_pred, n_scan, n_chi2, n_upd = [int(v) for v in cnt.cpu().numpy()]
+    build_flop = (n_pred * (FLOP_PREDICT + FLOP_WINDOW) + n_scan * FLOP_WINDOW_TEST + n_chi2 * FLOP_STEP2_CHI2 +
+                  n_upd * FLOP_STEP2_UPDATE)
+    hits = state["b"]["hits"].cpu().numpy()[:, :n]
+    true = eb.true_hits[F:, :n]
+    found = ((hits == true) & (true >= 0)).sum(axis=0)
+    eff = float(np.mean(found >= 0.75 * (true >= 0).sum(axis=0)))
+    fst = state["f"]["status"].cpu().numpy()[:n]
+    names = ["hit_bin_det", "kf_build_det", "kf_gather_hits", "kf_fit_det"]
+    res = {"workload": f"{w.name}; {n_events} events in one launch, {n} seeds, {eb.xyz.shape[1]} hits",
+           "ms_per_step": round(ms, 4), "tracks_per_s": round(n / (ms * 1e-3), 1),
+           "stages_ms": {k: round(float(v), 4) for k, v in zip(names, st)},
+           "efficiency_75pct": round(eff, 4), "fit_status_ok": round(float(np.mean(fst == 0)), 4),
+           "tracks_reaching_disks": round(float(np.mean(eb.visit[:n] >= (1 << 10))), 4),
+           "work": {"steps": n_pred, "hits_scanned": n_scan, "step2_chi2": n_chi2, "updates": n_upd,
+                    "build_gflop": round(build_flop / 1e9, 3),
+                    "build_tflops": round(build_flop / (float(st[1]) * 1e-3) / 1e12, 3)}}
+    del binned, ws_bin, ws_build, fit_hits, state, seeds, layer, xyz, cov
+    # the fit alone at scale over the tracks' own hit lists
+    wf = presets.lids_fit()
+    fb = workloads.det_event_batch(wf, range(fit_events))
+    nf = fb.n_seeds
+    Hd = T(fb.track_rows)
+    vis = T(fb.visit.view(np.int32))
+    sf = kf.kf_seed(d.seed_geometry(), nf, T(fb.track_rows[:3]))
+    out = kf.kf_fit_det(d, nf, F, Hd, vis, sf["par"], sf["cov"], sf["q"], arith=arith)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        kf.kf_fit_det(d, nf, F, Hd, vis, sf["par"], sf["cov"], sf["q"], out=out, arith=arith)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fms = e0.elapsed_time(e1) / reps
+    nd = out["ndof"].cpu().numpy()[:nf]
+    vb = np.array([bin(int(v)).count("1") for v in fb.visit[:nf]])
+    fit_flop = int(np.sum(vb - np.array([bin(int(v) & 7).count("1") for v in fb.visit[:nf]]))) * FLOP_PREDICT + \
+        int(nd.sum() // 2) * FLOP_UPDATE
+    res["fit_at_scale"] = {"workload": f"{wf.name}: {nf} tracks", "kf_fit_det_ms": round(fms, 4),
+                           "tracks_per_s": round(nf / (fms * 1e-3), 1),
+                           "tflops": round(fit_flop / (fms * 1e-3) / 1e12, 3),
+                           "fit_status_ok": round(float(np.mean(out["status"].cpu().numpy()[:nf] == 0)), 4)}
+    res["total_seconds"] = round(time.perf_counter() - t0, 1)
+    log(f"lids: step {ms:.3f} ms ({res['stages_ms']}), fit at scale {fms:.3f} ms")
     return res
 
 
@@ -432,6 +549,8 @@ def main():
         res["learned_vs_plain"] = learned_vs_plain([kf.ARITH_F32, kf.ARITH_F64], log)
     if not args.no_batch:
         res["batched"] = batched(arith, args.autotune, log)
+    if not args.no_lids:
+        res["lids"] = lids(arith, log)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, eb, args.cpu_seconds)
     print(json.dumps(res), flush=True)

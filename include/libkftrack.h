@@ -371,6 +371,115 @@ int kf_batch_plan_destroy(kf_batch_plan* plan);
 /* frequency of the device wall clock read by the build's completion ticks */
 int kf_wall_clock_khz(int32_t* khz);
 
+/*
+ * General detector (section 4.1: the barrel of concentric cylinders closed
+ * by endcap disks, "a cylinder with lids", and modules that sit off a
+ * layer's average surface).  Layers are listed in the order a track from
+ * the origin meets them: barrel layers outwards, then the disks of each
+ * side outwards.  Layer l is a cylinder of average radius pos[l] active over
+ * lo[l] <= z <= hi[l] (kind KF_LAYER_BARREL), or a plane z = pos[l] active
+ * over lo[l] <= r <= hi[l] (kind KF_LAYER_DISK).  Its modules may sit up to
+ * dmod[l] cm off that average surface (in radius on a barrel layer, in z on a
+ * disk): a hit lies on its module's surface, which the hit itself gives
+ * (barrel: its radius sqrt(x^2 + y^2); disk: its z).  x_over_x0 is the
+ * material of every layer at normal incidence.
+ */
+#define KF_LAYER_BARREL 0
+#define KF_LAYER_DISK 1
+typedef struct {
+  int32_t n_layers; /* 1..32 */
+  int32_t kind[32]; /* KF_LAYER_BARREL or KF_LAYER_DISK */
+  float pos[32];    /* average radius (barrel, > 0) or z of the average plane (disk), cm */
+  float lo[32];     /* active extent: z range (barrel) or r range (disk), cm; lo < hi */
+  float hi[32];
+  float dmod[32];   /* largest module offset from the average surface, cm (>= 0) */
+  float bz;         /* field, tesla (non-zero) */
+  float x_over_x0;
+  float mass;
+} kf_detector;
+
+/*
+ * hit_bin_det — hit_bin over a general detector: per event and layer n_w x
+ * n_phi bins, bin = iw * n_phi + iphi, phi as hit_bin, and the row
+ * coordinate w = z on a barrel layer or w = r = sqrt(x^2 + y^2) (FP64 from
+ * the FP32 inputs) on a disk, iw = clamp(floor((w - lo) * n_w / (hi - lo)),
+ * 0, n_w - 1).  The output descriptor (kf_hits) has n_z = n_w.  Arguments,
+ * workspace (hit_bin_workspace_bytes with n_z = n_w) and errors as hit_bin;
+ * a hit with a non-finite coordinate is rejected like one on a bad layer.
+ */
+int hit_bin_det(const kf_detector* d, int32_t n_events, const int32_t* event_offsets, int32_t n_phi, int32_t n_w,
+                int32_t n_hits, const int32_t* layer, const float* xyz, const float* cov, int32_t* offsets,
+                float* sorted_xyzphi, float* sorted_cov, int32_t* sorted_orig, int32_t* out_bad, void* ws,
+                size_t ws_bytes, void* stream);
+
+/*
+ * kf_fit_det — the Kalman-filter fit (section 2) over a general detector,
+ * one lane per track.  For every layer l >= first_layer (in index order)
+ * with bit l set in visit_mask[i] (the layers the track crossed): with a hit
+ * (bit l clear in hole_mask[i], which may be NULL) the state moves along the
+ * helix in one step to the hit's own surface (barrel: the cylinder of the
+ * hit's radius; disk: the plane of the hit's z; the first crossing along the
+ * motion), the covariance follows with the surface Jacobian, the layer's
+ * Highland scattering is added there (incidence from the surface normal),
+ * and the state is updated with the hit (barrel: on the plane tangent to the
+ * cylinder at the predicted point, coordinates along the arc and z; disk:
+ * in the disk's plane, coordinates x and y).  On a hole the step goes to the
+ * layer's average surface and takes its scattering.  Extents are not
+ * checked: the visit mask says which layers the track crossed.
+ *   hits [n_layers][9][ld] FP32 (rows of layers not visited are not read),
+ *   visit_mask [ld], hole_mask [ld] or NULL; seeds, outputs, statuses
+ *   (KF_TRK_NO_CROSSING: no crossing with a surface) and arith as kf_fit.
+ */
+int kf_fit_det(const kf_detector* d, int32_t n, int32_t ld, int32_t first_layer, const float* hits,
+               const uint32_t* visit_mask, const uint32_t* hole_mask, const float* seed_par, const float* seed_cov,
+               const int8_t* q, float* out_par, float* out_cov, float* out_chi2, int32_t* out_ndof,
+               int32_t* out_status, int32_t arith, void* stream);
+
+/*
+ * kf_build_det — combinatorial building (sections 2, 4.1, 4.3) over a
+ * general detector with two-step propagation.  The rules of kf_build (chi2
+ * cut, one hole child while holes < max_holes, ranking of the children,
+ * cand_cap, best-finished record) with these differences:
+ *   - each candidate moves to its own next layer: the first layer after its
+ *     current one (index order) whose average surface the helix meets ahead
+ *     within the layer's extent, on a disk also moving outwards
+ *     (x px + y py > 0) within less than half a turn; a track leaving the
+ *     barrel through its end continues on the disks; a candidate with no
+ *     next layer has left the detector and finishes (status 0);
+ *   - step 1 goes to that layer's average surface (no material), where the
+ *     window is formed: (phi, w) with w = z (barrel) or r (disk), half-widths
+ *     nsigma * sqrt(S) with the nominal resolution (win_sig_rphi along the
+ *     arc, win_sig_z along w), widened by dmod times the track's slope
+ *     (|dw/dr| and |dphi/dr| on a barrel layer, |dr/dz| and |dphi/dz| on a
+ *     disk); a hit is in the window iff |wrap(phi_h - phi_p)| <= dphi and
+ *     |w_h - w_p| <= dw;
+ *   - step 2, for every hit in the window: from the average surface to the
+ *     hit's own surface (the nearest crossing, forwards or backwards), the
+ *     layer's scattering there, then the update and its chi2 (tangent plane
+ *     on a barrel layer, the disk's plane on a disk); a hole child takes the
+ *     layer's scattering on the average surface;
+ *   - every candidate ends in the best-finished record, which is the result.
+ * Plain window and Cartesian state only (window_mode and state must be 0,
+ * else KF_E_UNSUPPORTED).  hits: from hit_bin_det (n_z = n_w rows).  extra:
+ * seed_event, seed_order and counters are honoured; the training dump and
+ * the completion ticks are not available (KF_E_UNSUPPORTED if set).
+ * Workspace: kf_build_workspace_bytes(bp, hits, n_seeds).
+ *   out_hits [n_layers - first_layer][ld]: event-local original hit index
+ *     per layer, -1 for a hole or a layer not visited
+ *   out_visit [ld]: bit l set for every layer the chosen candidate visited
+ *     (with a hit or a hole)
+ *   out_par, out_cov, out_chi2, out_nhits, out_status [ld] as kf_build
+ * Results do not depend on lanes_per_block, persistent_blocks or the order
+ * of the seeds.
+ */
+int kf_build_det(const kf_detector* d, const kf_build_params* bp, const kf_hits* hits, int32_t n_seeds, int32_t ld,
+                 const float* seed_par, const float* seed_cov, const int8_t* q, int32_t* out_hits,
+                 uint32_t* out_visit, float* out_par, float* out_cov, float* out_chi2, int32_t* out_nhits,
+                 int32_t* out_status, const kf_build_extra* extra, void* ws, size_t ws_bytes, void* stream);
+/* Launch shape chosen by the last kf_build_det call of the calling host thread
+ * (as kf_build_last_launch). */
+int kf_build_det_last_launch(kf_build_launch_info* info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -683,7 +683,10 @@ int orc_fit64(const orc_geometry* g, int n, int ld, int first_layer, const doubl
  *   iz   = clamp(floor((z + z_half) * n_z / (2 z_half)), 0, n_z - 1) (FP64).
  * Hits are ordered by (layer, bin, phi_f32, original index).
  * offsets[l*(nb+1) + b] is the position of the first hit of bin b of layer
- * l in that order (nb = n_phi*n_z; entry nb closes the layer).
+ * l in that order (nb = n_phi*n_z; entry nb closes the layer).  A hit on a
+ * layer outside [0, L) or with a non-finite coordinate has no place in the
+ * binned structure: it sorts after every layer (reading: such a hit is
+ * rejected, not binned).
  */
 typedef struct { int32_t layer, bin; float phi; int32_t idx; } bin_key;
 
@@ -704,6 +707,10 @@ int orc_hit_bin(const orc_geometry* g, int n_phi, int n_z, int n_hits, const int
   double zh = (double)g->z_half;
   for (int i = 0; i < n_hits; ++i) {
     double x = (double)xyz[i], y = (double)xyz[(size_t)n_hits + i], z = (double)xyz[2 * (size_t)n_hits + i];
+    if (layer[i] < 0 || layer[i] >= L || !isfinite(x) || !isfinite(y) || !isfinite(z)) {
+      k[i].layer = INT32_MAX; k[i].bin = 0; k[i].phi = 0.0f; k[i].idx = i;
+      continue;
+    }
     double ph = atan2(y, x);
     if (ph < 0.0) ph += TWO_PI;
     float phf = (float)ph;
@@ -1382,6 +1389,10 @@ int orc_hit_bin_det(const orc_detector* d, int n_phi, int n_w, int n_hits, const
   for (int i = 0; i < n_hits; ++i) {
     double x = (double)xyz[i], y = (double)xyz[(size_t)n_hits + i], z = (double)xyz[2 * (size_t)n_hits + i];
     int l = layer[i];
+    if (l < 0 || l >= L || !isfinite(x) || !isfinite(y) || !isfinite(z)) { /* rejected, as orc_hit_bin */
+      k[i].layer = INT32_MAX; k[i].bin = 0; k[i].phi = 0.0f; k[i].idx = i;
+      continue;
+    }
     double ph = atan2(y, x);
     if (ph < 0.0) ph += TWO_PI;
     float phf = (float)ph;

@@ -29,13 +29,21 @@ __device__ inline int event_of(const int32_t* __restrict__ eoff, int E, int i) {
   return lo;
 }
 
+// The row coordinate of each layer: w = z on a barrel layer, w = r =
+// sqrt(x^2 + y^2) on an endcap disk, binned over [lo, hi] in n_z rows.
+struct RowGeom {
+  int32_t disk[32];
+  double lo[32], hi[32];
+};
+
 // Bin of each hit and its arrival index among the bin's hits (the value the
 // count's atomic returns; the rank pass fixes the order later).  phi and the
 // bin indices are computed in FP64 with the expression order of the
 // definition, so the bin of a hit never depends on contraction or
-// reassociation.
+// reassociation.  A hit on a layer outside [0, L) or with a non-finite
+// coordinate has no bin: it is counted in `bad` and left out.
 __global__ void __launch_bounds__(256) count_kernel(int n, int E, const int32_t* __restrict__ eoff, int L,
-                                                    int n_phi, int n_z, double z_half,
+                                                    int n_phi, int n_z, RowGeom rg,
                                                     const int32_t* __restrict__ layer,
                                                     const float* __restrict__ xyz, int32_t* __restrict__ gbin_of,
                                                     float* __restrict__ phi_of, int32_t* __restrict__ arrival,
@@ -44,20 +52,22 @@ __global__ void __launch_bounds__(256) count_kernel(int n, int E, const int32_t*
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int l = layer[i];
-  if (l < 0 || l >= L) {
+  const double x = (double)xyz[i], y = (double)xyz[(size_t)n + i], z = (double)xyz[2 * (size_t)n + i];
+  if (l < 0 || l >= L || !__builtin_isfinite(x) || !__builtin_isfinite(y) || !__builtin_isfinite(z)) {
     gbin_of[i] = -1;
     if (bad) atomicAdd(bad, 1);
     return;
   }
   const int e = eoff ? event_of(eoff, E, i) : 0;
-  const double x = (double)xyz[i], y = (double)xyz[(size_t)n + i], z = (double)xyz[2 * (size_t)n + i];
   double ph = atan2(y, x);
   if (ph < 0.0) ph += kTwoPi;
   const float phf = (float)ph;
   int ip = (int)floor((double)phf * (double)n_phi / kTwoPi);
   ip = ip > n_phi - 1 ? n_phi - 1 : (ip < 0 ? 0 : ip);
-  int iz = (int)floor((z + z_half) * (double)n_z / (2.0 * z_half));
-  iz = iz < 0 ? 0 : (iz > n_z - 1 ? n_z - 1 : iz);
+  const double w = rg.disk[l] ? sqrt(x * x + y * y) : z;
+  const double lo = rg.lo[l], hi = rg.hi[l];
+  const double fz = floor((w - lo) * (double)n_z / (hi - lo));
+  const int iz = fz < 0.0 ? 0 : (fz > (double)(n_z - 1) ? n_z - 1 : (int)fz);
   const int nb = n_phi * n_z;
   const int gb = (e * L + l) * nb + iz * n_phi + ip;
   gbin_of[i] = gb;
@@ -265,14 +275,14 @@ extern "C" size_t hit_bin_workspace_bytes(int32_t n_events, int32_t n_layers, in
   return bin_ws_layout(n_events, n_layers, n_phi, n_z, n_hits, nullptr, nullptr);
 }
 
-extern "C" int hit_bin(const kf_geometry* g, int32_t n_events, const int32_t* event_offsets, int32_t n_phi,
-                       int32_t n_z, int32_t n_hits, const int32_t* layer, const float* xyz, const float* cov,
-                       int32_t* offsets, float* sorted_xyzphi, float* sorted_cov, int32_t* sorted_orig,
-                       int32_t* out_bad, void* ws, size_t ws_bytes, void* stream) {
-  if (kf_check_geometry(g)) return KF_E_INVALID_ARG;
+namespace {
+
+int run_hit_bin(int L, const RowGeom& rg, int32_t n_events, const int32_t* event_offsets, int32_t n_phi,
+                int32_t n_z, int32_t n_hits, const int32_t* layer, const float* xyz, const float* cov,
+                int32_t* offsets, float* sorted_xyzphi, float* sorted_cov, int32_t* sorted_orig, int32_t* out_bad,
+                void* ws, size_t ws_bytes, void* stream) {
   if (n_events < 1 || n_phi < 1 || n_z < 1 || n_hits < 0) return KF_E_INVALID_ARG;
   if (n_events > 1 && !event_offsets) return KF_E_INVALID_ARG;
-  const int L = g->n_layers;
   const int64_t NB = (int64_t)n_events * L * n_phi * n_z;
   if (NB >= (1ll << 31) - 1) return KF_E_UNSUPPORTED;
   if (!offsets) return KF_E_INVALID_ARG;
@@ -292,8 +302,7 @@ extern "C" int hit_bin(const kf_geometry* g, int32_t n_events, const int32_t* ev
   if (out_bad) hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, out_bad, (int64_t)1, 0);
   if (n_hits > 0)
     hipLaunchKernelGGL(count_kernel, dim3(grid_for(n_hits, bs)), dim3(bs), 0, s, n_hits, n_events, event_offsets, L,
-                       n_phi, n_z, (double)g->z_half, layer, xyz, w.gbin_of, w.phi_of, w.arrival, w.count,
-                       out_bad);
+                       n_phi, n_z, rg, layer, xyz, w.gbin_of, w.phi_of, w.arrival, w.count, out_bad);
   const int nblk = (int)((NB + 2 * kScanBlock - 1) / (2 * kScanBlock));
   hipLaunchKernelGGL(scan_blocks, dim3(nblk), dim3(kScanBlock), 0, s, w.count, w.start, w.bsum, (int)NB);
   hipLaunchKernelGGL(scan_sums, dim3(1), dim3(kScanBlock), 0, s, w.bsum, nblk);
@@ -307,4 +316,37 @@ extern "C" int hit_bin(const kf_geometry* g, int32_t n_events, const int32_t* ev
                        event_offsets, w.rec, w.start, w.count, sorted_xyzphi, sorted_cov, sorted_orig);
   }
   return kf_check_launch();
+}
+
+}  // namespace
+
+extern "C" int hit_bin(const kf_geometry* g, int32_t n_events, const int32_t* event_offsets, int32_t n_phi,
+                       int32_t n_z, int32_t n_hits, const int32_t* layer, const float* xyz, const float* cov,
+                       int32_t* offsets, float* sorted_xyzphi, float* sorted_cov, int32_t* sorted_orig,
+                       int32_t* out_bad, void* ws, size_t ws_bytes, void* stream) {
+  if (kf_check_geometry(g)) return KF_E_INVALID_ARG;
+  // every layer binned in z over [-z_half, z_half]
+  RowGeom rg = {};
+  for (int l = 0; l < g->n_layers; ++l) {
+    rg.disk[l] = 0;
+    rg.lo[l] = -(double)g->z_half;
+    rg.hi[l] = (double)g->z_half;
+  }
+  return run_hit_bin(g->n_layers, rg, n_events, event_offsets, n_phi, n_z, n_hits, layer, xyz, cov, offsets,
+                     sorted_xyzphi, sorted_cov, sorted_orig, out_bad, ws, ws_bytes, stream);
+}
+
+extern "C" int hit_bin_det(const kf_detector* d, int32_t n_events, const int32_t* event_offsets, int32_t n_phi,
+                           int32_t n_w, int32_t n_hits, const int32_t* layer, const float* xyz, const float* cov,
+                           int32_t* offsets, float* sorted_xyzphi, float* sorted_cov, int32_t* sorted_orig,
+                           int32_t* out_bad, void* ws, size_t ws_bytes, void* stream) {
+  if (kf_check_detector(d)) return KF_E_INVALID_ARG;
+  RowGeom rg = {};
+  for (int l = 0; l < d->n_layers; ++l) {
+    rg.disk[l] = d->kind[l] == KF_LAYER_DISK ? 1 : 0;
+    rg.lo[l] = (double)d->lo[l];
+    rg.hi[l] = (double)d->hi[l];
+  }
+  return run_hit_bin(d->n_layers, rg, n_events, event_offsets, n_phi, n_w, n_hits, layer, xyz, cov, offsets,
+                     sorted_xyzphi, sorted_cov, sorted_orig, out_bad, ws, ws_bytes, stream);
 }

@@ -73,7 +73,9 @@ KFD inline bool k_finite(double v) { return __builtin_isfinite(v); }
 // tau covers one full turn (alpha in (-pi, pi)); both roots are formed in
 // the cancellation-free pair q/A, -c/q with q = -(a + sign(a) sqrt(disc)).
 // The first crossing along the motion is the root whose turn, taken with the
-// sign of h and in (0, 2 pi) in magnitude, is smallest.
+// sign of h and in (0, 2 pi) in magnitude, is smallest.  NEAREST: the
+// crossing reached by the smallest turn forwards or backwards (|alpha| < pi,
+// the root of smallest |tau|); s then has either sign.
 template <typename T> struct Step {
   T s;      // transverse path
   T alpha;  // turning angle
@@ -82,7 +84,7 @@ template <typename T> struct Step {
   T h, pt, ipt;  // ipt = 1 / pt
 };
 
-template <typename T>
+template <typename T, bool NEAREST = false>
 KFD inline int propagate(const T X[6], int q, T R, T bz, T Xo[6], Step<T>& st) {
   const T px = X[3], py = X[4], pz = X[5];
   const T pt2 = px * px + py * py;
@@ -109,13 +111,19 @@ KFD inline int propagate(const T X[6], int q, T R, T bz, T Xo[6], Step<T>& st) {
   // first along the motion: the smallest positive oriented root if any,
   // otherwise the most negative one (a turn beyond pi)
   T t;
-  if (t1 > T(0) && t2 > T(0)) t = t1 < t2 ? t1 : t2;
-  else if (t1 > T(0)) t = t1;
-  else if (t2 > T(0)) t = t2;
-  else t = t1 < t2 ? t1 : t2;
+  if constexpr (NEAREST) {
+    t = (fabs(t2) < fabs(t1) || !(t1 == t1)) ? t2 : t1;
+  } else {
+    if (t1 > T(0) && t2 > T(0)) t = t1 < t2 ? t1 : t2;
+    else if (t1 > T(0)) t = t1;
+    else if (t2 > T(0)) t = t2;
+    else t = t1 < t2 ? t1 : t2;
+  }
   if (!(t == t)) return KF_NO_CROSSING;  // both roots undefined (degenerate circle)
   T half = k_atan(t);
-  if (!(half > T(0))) half += T(3.14159265358979323846);
+  if constexpr (!NEAREST) {
+    if (!(half > T(0))) half += T(3.14159265358979323846);
+  }
   half *= sg;
   const T alpha = T(2) * half;
   // sin(alpha) and 1 - cos(alpha) from tau = tan(alpha / 2) = sg * t (tan has
@@ -133,7 +141,7 @@ KFD inline int propagate(const T X[6], int q, T R, T bz, T Xo[6], Step<T>& st) {
   const T ca = T(1) - omc;
   const T ih = k_rcp(h);
   const T s = alpha * ih;
-  if (!(s > T(0))) return KF_NO_CROSSING;
+  if (!NEAREST && !(s > T(0))) return KF_NO_CROSSING;
   const T Ah = sa * ih, Bh = omc * ih;
   Xo[0] = X[0] + tx * Ah - ty * Bh;
   Xo[1] = X[1] + ty * Ah + tx * Bh;

@@ -9,3 +9,4 @@ int kf_check_launch();
 // Records a HIP error code from a runtime call; returns KF_OK or KF_E_HIP.
 int kf_check(hipError_t e);
 int kf_check_geometry(const kf_geometry* g);
+int kf_check_detector(const kf_detector* d);

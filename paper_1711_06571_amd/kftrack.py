@@ -52,6 +52,16 @@ class BuildParams(ctypes.Structure):
                 ("arith", ctypes.c_int32), ("phi_refine", ctypes.c_int32), ("state", ctypes.c_int32)]
 
 
+class Detector(ctypes.Structure):
+    _fields_ = [("n_layers", ctypes.c_int32), ("kind", ctypes.c_int32 * 32), ("pos", ctypes.c_float * 32),
+                ("lo", ctypes.c_float * 32), ("hi", ctypes.c_float * 32), ("dmod", ctypes.c_float * 32),
+                ("bz", ctypes.c_float), ("x_over_x0", ctypes.c_float), ("mass", ctypes.c_float)]
+
+
+LAYER_BARREL = 0
+LAYER_DISK = 1
+
+
 class LaunchInfo(ctypes.Structure):
     _fields_ = [("lanes_per_block", ctypes.c_int32), ("blocks", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
                 ("resident_blocks_per_cu", ctypes.c_int32), ("max_lds_per_block", ctypes.c_int32)]
@@ -117,6 +127,11 @@ def lib():
         L.kf_build_workspace_bytes.argtypes = [ctypes.POINTER(BuildParams), ctypes.POINTER(Hits), I]
         L.kf_build.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(BuildParams), ctypes.POINTER(Hits), I,
                                I, P, P, P, P, P, P, P, P, P, ctypes.POINTER(BuildExtra), P, ctypes.c_size_t, P]
+        L.hit_bin_det.argtypes = [ctypes.POINTER(Detector)] + list(L.hit_bin.argtypes[1:])
+        L.kf_fit_det.argtypes = [ctypes.POINTER(Detector), I, I, I, P, P, P, P, P, P, P, P, P, P, P, I, P]
+        L.kf_build_det.argtypes = [ctypes.POINTER(Detector), ctypes.POINTER(BuildParams), ctypes.POINTER(Hits), I,
+                                   I, P, P, P, P, P, P, P, P, P, P, ctypes.POINTER(BuildExtra), P, ctypes.c_size_t,
+                                   P]
         _lib = L
     return _lib
 
@@ -307,6 +322,90 @@ def kf_build(g, bp, binned: BinnedHits, n_seeds, seed_par, seed_cov, q, extra=No
                           _ptr(out["chi2"]), _ptr(out["nhits"]), _ptr(out["status"]), ctypes.byref(ex), _ptr(ws),
                           ctypes.c_size_t(need), _stream(stream)))
     return out
+
+
+# ------------------------------------------------------- general detector
+
+def detector(d) -> Detector:
+    """From a presets.Detector (barrel cylinders and endcap disks)."""
+    o = Detector()
+    o.n_layers = d.n_layers
+    for i in range(d.n_layers):
+        o.kind[i] = d.kind[i]
+        o.pos[i], o.lo[i], o.hi[i], o.dmod[i] = d.pos[i], d.lo[i], d.hi[i], d.dmod[i]
+    o.bz, o.x_over_x0, o.mass = d.bz, d.x_over_x0, d.mass
+    return o
+
+
+def hit_bin_det(d, n_phi, n_w, layer, xyz, cov, event_offsets=None, out=None, ws=None, stream=None):
+    """hit_bin over a general detector: rows in z on barrel layers, in r on
+    disks (the descriptor's n_z is n_w)."""
+    n = layer.shape[0]
+    E = 1 if event_offsets is None else event_offsets.shape[0] - 1
+    dev = layer.device
+    if out is None:
+        out = BinnedHits(E, d.n_layers, n_phi, n_w, n, dev)
+    need = hit_bin_workspace_bytes(E, d.n_layers, n_phi, n_w, n)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    dd = detector(d)
+    _check(lib().hit_bin_det(ctypes.byref(dd), E, _ptr(event_offsets), n_phi, n_w, n, _ptr(layer), _ptr(xyz),
+                             _ptr(cov), _ptr(out.offsets), _ptr(out.xyzphi), _ptr(out.cov), _ptr(out.orig),
+                             _ptr(out.bad), _ptr(ws), ctypes.c_size_t(need), _stream(stream)))
+    return out
+
+
+def kf_fit_det(d, n, first_layer, hits, visit, seed_par, seed_cov, q, hole_mask=None, out=None, arith=ARITH_F32,
+               stream=None):
+    """Fit over a general detector: hits [L][9][ld], visit [ld] (int32 view
+    of the uint32 masks: bit l, the track crossed layer l)."""
+    ld = hits.shape[2]
+    dev = hits.device
+    if out is None:
+        out = dict(par=torch.empty((6, ld), dtype=torch.float32, device=dev),
+                   cov=torch.empty((21, ld), dtype=torch.float32, device=dev),
+                   chi2=torch.empty(ld, dtype=torch.float32, device=dev),
+                   ndof=torch.empty(ld, dtype=torch.int32, device=dev),
+                   status=torch.empty(ld, dtype=torch.int32, device=dev))
+    dd = detector(d)
+    _check(lib().kf_fit_det(ctypes.byref(dd), n, ld, first_layer, _ptr(hits), _ptr(visit), _ptr(hole_mask),
+                            _ptr(seed_par), _ptr(seed_cov), _ptr(q), _ptr(out["par"]), _ptr(out["cov"]),
+                            _ptr(out["chi2"]), _ptr(out["ndof"]), _ptr(out["status"]), arith, _stream(stream)))
+    return out
+
+
+def kf_build_det(d, bp, binned: BinnedHits, n_seeds, seed_par, seed_cov, q, extra=None, out=None, ws=None,
+                 stream=None):
+    """Two-step build over a general detector; outputs as kf_build plus
+    visit [ld] (int32 view of the uint32 masks of visited layers)."""
+    ld = seed_par.shape[1]
+    dev = seed_par.device
+    F = bp.first_layer
+    if out is None:
+        out = dict(hits=torch.empty((d.n_layers - F, ld), dtype=torch.int32, device=dev),
+                   visit=torch.empty(ld, dtype=torch.int32, device=dev),
+                   par=torch.empty((6, ld), dtype=torch.float32, device=dev),
+                   cov=torch.empty((21, ld), dtype=torch.float32, device=dev),
+                   chi2=torch.empty(ld, dtype=torch.float32, device=dev),
+                   nhits=torch.empty(ld, dtype=torch.int32, device=dev),
+                   status=torch.empty(ld, dtype=torch.int32, device=dev))
+    need = kf_build_workspace_bytes(bp, binned, n_seeds)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    dd = detector(d)
+    hd = binned.descriptor()
+    ex = extra if extra is not None else BuildExtra()
+    _check(lib().kf_build_det(ctypes.byref(dd), ctypes.byref(bp), ctypes.byref(hd), n_seeds, ld, _ptr(seed_par),
+                              _ptr(seed_cov), _ptr(q), _ptr(out["hits"]), _ptr(out["visit"]), _ptr(out["par"]),
+                              _ptr(out["cov"]), _ptr(out["chi2"]), _ptr(out["nhits"]), _ptr(out["status"]),
+                              ctypes.byref(ex), _ptr(ws), ctypes.c_size_t(need), _stream(stream)))
+    return out
+
+
+def kf_build_det_last_launch() -> dict:
+    info = LaunchInfo()
+    _check(lib().kf_build_det_last_launch(ctypes.byref(info)))
+    return {k: int(getattr(info, k)) for k, _ in LaunchInfo._fields_}
 
 
 def kf_build_last_launch() -> dict:

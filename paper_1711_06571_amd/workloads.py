@@ -105,3 +105,51 @@ def event_batch(w: Workload, events, n_tracks=None, seed_layers=None) -> EventBa
         sev[sl] = k
         del ev
     return EventBatch(xyz, cov, layer, hoff.astype(np.int32), H, TH, sev, soff.astype(np.int32), n_seeds, ld, trk)
+
+
+@dataclass
+class DetEventBatch:
+    """Several events of a general detector concatenated for hit_bin_det /
+    kf_build_det, with the per-track rows the fit takes."""
+    xyz: np.ndarray          # [3][n_hits] float32
+    cov: np.ndarray          # [6][n_hits] float32
+    layer: np.ndarray        # [n_hits] int32
+    hit_offsets: np.ndarray  # [E+1] int32
+    track_rows: np.ndarray   # [L][9][ld] float32 each track's hits (zeros where it crosses no module)
+    visit: np.ndarray        # [ld] uint32 layers each track has a hit on
+    true_hits: np.ndarray    # [L][ld] int32 event-local original index of each track's hit (-1 none)
+    seed_event: np.ndarray   # [n_seeds] int32
+    seed_offsets: np.ndarray  # [E+1] int32
+    n_seeds: int
+    ld: int
+
+
+def det_event_batch(w, events, n_tracks=None) -> DetEventBatch:
+    """Generate events of a general-detector workload into concatenated FP32
+    arrays (one event at a time)."""
+    events = list(events)
+    T = w.n_tracks if n_tracks is None else n_tracks
+    L = w.detector.n_layers
+    evs = [datagen.generate_det(w.detector, w.gen, e, T) for e in events]
+    hoff = np.concatenate([[0], np.cumsum([ev.n_hits for ev in evs])]).astype(np.int64)
+    soff = np.concatenate([[0], np.cumsum([ev.n_tracks for ev in evs])]).astype(np.int64)
+    if hoff[-1] >= 2 ** 31:
+        raise ValueError("too many hits for int32 offsets")
+    n_seeds = int(soff[-1])
+    ld = datagen.padded(n_seeds)
+    xyz = np.concatenate([ev.xyz for ev in evs], axis=1).astype(np.float32)
+    cov = np.concatenate([ev.cov for ev in evs], axis=1).astype(np.float32)
+    layer = np.concatenate([ev.layer for ev in evs]).astype(np.int32)
+    rows = np.zeros((L, 9, ld), dtype=np.float32)
+    visit = np.zeros(ld, dtype=np.uint32)
+    TH = np.full((L, ld), -1, dtype=np.int32)
+    sev = np.zeros(n_seeds, dtype=np.int32)
+    for k, ev in enumerate(evs):
+        sl = slice(soff[k], soff[k + 1])
+        r, v = datagen.det_track_rows(ev)
+        rows[:, :, sl] = r[:, :, :ev.n_tracks]
+        visit[sl] = v[:ev.n_tracks]
+        TH[:, sl] = ev.trk_hits
+        sev[sl] = k
+    return DetEventBatch(np.ascontiguousarray(xyz), np.ascontiguousarray(cov), layer, hoff.astype(np.int32), rows,
+                         visit, TH, sev, soff.astype(np.int32), n_seeds, ld)

@@ -19,7 +19,7 @@ def _declared_functions():
 
 
 def _defines():
-    return {k: int(v) for k, v in re.findall(r"#define\s+(KF_[A-Z_]+)\s+(\d+)", open(HEADER).read())}
+    return {k: int(v) for k, v in re.findall(r"#define\s+(KF_[A-Z0-9_]+)\s+(\d+)", open(HEADER).read())}
 
 
 def test_header_declares_the_boundary():
@@ -45,6 +45,8 @@ def test_binding_constants_match_header():
     assert kftrack.KF_E_UNSUPPORTED == d["KF_E_UNSUPPORTED"]
     for k in ["NO_CROSSING", "OUT_OF_Z", "NONFINITE", "S_NOT_PD", "CAP_TRUNC"]:
         assert getattr(kftrack, "TRK_" + k) == d["KF_TRK_" + k]
+    assert kftrack.LAYER_BARREL == d["KF_LAYER_BARREL"] and kftrack.LAYER_DISK == d["KF_LAYER_DISK"]
+    assert kftrack.ARITH_F32 == d["KF_ARITH_F32"] and kftrack.ARITH_F64 == d["KF_ARITH_F64"]
 
 
 def test_status_strings_on_host():

@@ -1,0 +1,299 @@
+"""GPU path over the general detector (section 4.1: barrel cylinders closed
+by endcap disks, modules off the average surface) against the oracle:
+binning bit-exact, the fit within the parity tolerances, and the two-step
+build's hit lists, visit masks, nhits and status identical on every
+decidable seed (the rule of the barrel build: chi2 gaps above 1e-3, window
+and extent edges further than 1e-4 cm, crossings further than 1e-3
+relative)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_06571_amd import datagen, presets
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from gpu_common import FAILED_FIT_CHI2_PER_NDOF, failed_fit_bound, host, rel_vec_err, to_dev  # noqa: E402
+
+# undecidable seeds measured on the lids workload: the oracle's own pin
+# (test_det_build_efficiency_and_margins) bounds them by 15 %
+DET_UNDECIDABLE_MAX = 0.18
+
+
+@pytest.fixture(scope="module")
+def kf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1711_06571_amd import kftrack
+    return kftrack
+
+
+def _event(w, n, event=0):
+    return datagen.generate_det(w.detector, w.gen, event, n)
+
+
+def _seeds_gpu(kf, d, H, n):
+    return kf.kf_seed(d.seed_geometry(), n, to_dev(np.ascontiguousarray(H[:3])))
+
+
+def _bin(kf, w, ev):
+    return kf.hit_bin_det(w.detector, w.cuts.n_phi_bins, w.cuts.n_z_bins, to_dev(ev.layer),
+                          to_dev(ev.xyz.astype(np.float32)), to_dev(ev.cov.astype(np.float32)))
+
+
+def gpu_build(kf, w, ev, arith, lanes=0, blocks=0, order=None, cap=None):
+    d = w.detector
+    b = _bin(kf, w, ev)
+    H, visit = datagen.det_track_rows(ev)
+    n = ev.n_tracks
+    sg = _seeds_gpu(kf, d, H, n)
+    bp = kf.build_params(w.cuts, arith=arith, lanes_per_block=lanes, persistent_blocks=blocks, cap=cap)
+    ex = kf.BuildExtra()
+    keep = []
+    if order is not None:
+        od = to_dev(order.astype(np.int32))
+        keep.append(od)
+        ex.seed_order = od.data_ptr()
+    cnt = torch.zeros(4, dtype=torch.int64, device="cuda:0")
+    ex.counters = cnt.data_ptr()
+    out = kf.kf_build_det(d, bp, b, n, sg["par"], sg["cov"], sg["q"], extra=ex)
+    torch.cuda.synchronize()
+    g = {k: host(v) for k, v in out.items()}
+    g["visit"] = g["visit"].view(np.uint32)
+    g["counters"] = host(cnt)
+    return g, sg
+
+
+def compare_det(g, o, n_cols, cols_g, ctx, und_max=DET_UNDECIDABLE_MAX):
+    dec = oracle.decidable(o["margin"])[:n_cols]
+    same = (np.all(g["hits"][:, cols_g] == o["hits"][:, :n_cols], axis=0) & (g["visit"][cols_g] == o["visit"][:n_cols])
+            & (g["nhits"][cols_g] == o["nhits"][:n_cols]) & (g["status"][cols_g] == o["status"][:n_cols]))
+    bad = np.where(dec & ~same)[0]
+    assert bad.size == 0, f"{ctx}: {bad.size} decidable seeds differ, first {bad[:10]}"
+    c2g = g["chi2"][cols_g].astype(np.float64)
+    c2o = o["chi2"][:n_cols]
+    sel = dec & same
+    e = np.abs(c2g - c2o) / np.maximum(1.0, c2o)
+    assert e[sel].max(initial=0) <= 1e-3, f"{ctx}: chi2 {e[sel].max():.3g}"
+    conv = sel & (c2o <= FAILED_FIT_CHI2_PER_NDOF * np.maximum(2 * o["nhits"][:n_cols], 1))
+    pg = g["par"][:, cols_g].astype(np.float64)
+    po = o["par"][:, :n_cols]
+    ep, em = rel_vec_err(pg[:3], po[:3]), rel_vec_err(pg[3:], po[3:])
+    assert ep[conv].max(initial=0) <= 1e-4 and em[conv].max(initial=0) <= 1e-4, \
+        f"{ctx}: params {ep[conv].max():.3g} {em[conv].max():.3g}"
+    und = float(1 - dec.mean())
+    mism = int((~same).sum())
+    rows = oracle.undecidable_by_row(o["margin"][:, :n_cols])
+    assert und <= und_max, f"{ctx}: {und:.3f} undecidable (by row {rows})"
+    assert mism <= max(1, int(0.01 * n_cols)), f"{ctx}: {mism} of {n_cols} seeds differ"
+    return dict(undecidable=und, by_row=rows, mismatched=mism, n=int(n_cols))
+
+
+def test_hit_bin_det_matches_oracle(kf):
+    w = presets.lids()
+    d = w.detector
+    ev = _event(w, w.n_tracks)
+    b = _bin(kf, w, ev)
+    torch.cuda.synchronize()
+    assert int(host(b.bad)[0]) == 0
+    xyz = ev.xyz.astype(np.float32)
+    o = oracle.hit_bin_det(d, 63, 16, ev.layer, xyz)
+    assert np.array_equal(host(b.offsets)[0], o["offsets"])
+    assert np.array_equal(host(b.orig), o["order"])
+    xp = host(b.xyzphi)
+    assert np.array_equal(xp[3], o["phi"])
+    assert np.array_equal(xp[:3], xyz[:, o["order"]])
+    assert np.array_equal(host(b.cov), ev.cov.astype(np.float32)[:, o["order"]])
+
+
+@pytest.mark.parametrize("det", [False, True])
+def test_hit_bin_rejects_non_finite_hits(kf, det):
+    """A hit with a NaN or infinite coordinate is counted as bad and left
+    out, like one on a bad layer; every other hit is binned exactly as the
+    oracle bins it."""
+    w = presets.lids() if det else presets.build()
+    ev = _event(w, 300) if det else datagen.generate(w.geometry, w.gen, 0, 300)
+    xyz = ev.xyz.astype(np.float32)
+    cov = ev.cov.astype(np.float32)
+    n = ev.n_hits
+    bad_xyz = np.array([[np.nan, 1.0, 2.0, 3.0], [1.0, np.inf, 2.0, 3.0], [0.0, 0.0, -np.inf, 1.0]], dtype=np.float32)
+    lay = np.concatenate([ev.layer, np.array([4, 4, 4, -1], dtype=np.int32)])
+    X = np.concatenate([xyz, bad_xyz], axis=1)
+    C = np.concatenate([cov, np.ones((6, 4), np.float32)], axis=1)
+    if det:
+        b = kf.hit_bin_det(w.detector, 63, 16, to_dev(lay), to_dev(X), to_dev(C))
+        o = oracle.hit_bin_det(w.detector, 63, 16, lay, X)
+    else:
+        b = kf.hit_bin(w.geometry, 63, 16, to_dev(lay), to_dev(X), to_dev(C))
+        o = oracle.hit_bin(w.geometry, 63, 16, lay, X)
+    torch.cuda.synchronize()
+    assert int(host(b.bad)[0]) == 4
+    assert np.array_equal(host(b.offsets)[0], o["offsets"])
+    assert np.array_equal(host(b.orig)[:n], o["order"][:n])
+    assert np.array_equal(host(b.xyzphi)[:3, :n], X[:, o["order"][:n]])
+
+
+def test_fit_det_parity(kf):
+    """The lids fit workload's tracks (barrel layers with displaced modules,
+    then disks), FP64 arithmetic.  The seeds: GPU and oracle agree within one
+    FP32 rounding step.  The fit from identical seeds: status and ndof
+    identical, parameters within 1e-4 and chi2 within 1e-3 on every
+    converged fit (measured 6e-7).  From the GPU's own seeds the same holds
+    for every seed whose momentum is measured (relative uncertainty below
+    0.1); a seed that is not (a nearly straight track: |p| = 7.5e4 GeV with a
+    69 % uncertainty) can move by more under its one-ulp difference."""
+    w = presets.lids_fit()
+    d = w.detector
+    ev = _event(w, w.n_tracks, event=1)
+    n = ev.n_tracks
+    H, visit = datagen.det_track_rows(ev)
+    so = oracle.seed(d.seed_geometry(), H[:3], n)
+    sg = {k: host(v) for k, v in _seeds_gpu(kf, d, H, n).items()}
+    assert np.array_equal(so["q"][:n], sg["q"][:n]) and np.array_equal(so["status"][:n], sg["status"][:n])
+    dp = np.abs(sg["par"][:, :n].astype(np.float64) - so["par"][:, :n])
+    assert np.all(dp <= 2.5e-7 * np.abs(so["par"][:, :n]) + 1e-30)
+    o = oracle.fit_det(d, 3, H, visit, so["par"], so["cov"], so["q"], n)
+    ndof = np.maximum(o["ndof"][:n], 1)
+    conv = (o["status"][:n] == 0) & (o["chi2"][:n] <= FAILED_FIT_CHI2_PER_NDOF * ndof)
+    failed = float(1 - conv.mean())
+    assert failed <= failed_fit_bound(n)
+    Hd, vd = to_dev(H), to_dev(visit.view(np.int32))
+    res = {}
+    for name, seeds in (("oracle seeds", so), ("gpu seeds", sg)):
+        g = kf.kf_fit_det(d, n, 3, Hd, vd, to_dev(seeds["par"]), to_dev(seeds["cov"]), to_dev(seeds["q"]),
+                          arith=kf.ARITH_F64)
+        torch.cuda.synchronize()
+        g = {k: host(v) for k, v in g.items()}
+        assert np.array_equal(g["status"][:n], o["status"][:n]) and np.array_equal(g["ndof"][:n], o["ndof"][:n])
+        pg = g["par"][:, :n].astype(np.float64)
+        po = o["par"][:, :n]
+        e = np.maximum(rel_vec_err(pg[:3], po[:3]), rel_vec_err(pg[3:], po[3:]))
+        e2 = np.abs(g["chi2"][:n] - o["chi2"][:n]) / np.maximum(1.0, o["chi2"][:n])
+        res[name] = (e, e2, g)
+    e, e2, g = res["oracle seeds"]
+    assert e[conv].max() <= 1e-4 and e2[conv].max() <= 1e-3, (e[conv].max(), e2[conv].max())
+    from gpu_common import seed_rel_sigma_p
+    well = conv & (seed_rel_sigma_p(so["par"], so["cov"], n) < 0.1)
+    eg, e2g, _ = res["gpu seeds"]
+    assert eg[well].max() <= 1e-4 and e2g[well].max() <= 1e-3
+    agree = float(np.mean(eg[conv] <= 1e-4))
+    assert agree >= 0.999
+    # the covariance diagonal of statistically consistent fits
+    wc = conv & (o["chi2"][:n] <= 5 * ndof)
+    for c in (0, 6, 11, 15, 18, 20):
+        ec = np.abs(g["cov"][c, :n][wc] - o["cov"][c, :n][wc]) / np.abs(o["cov"][c, :n][wc])
+        assert np.median(ec) < 1e-5, (c, np.median(ec))
+    print(f"fit_det f64: {n} tracks, failed fits {failed:.4f}; oracle seeds: max {e[conv].max():.3g}; gpu seeds: "
+          f"max on measured seeds {eg[well].max():.3g}, agreement {agree:.5f}; tracks on disks "
+          f"{np.mean(visit[:n] >= (1 << 10)):.3f}")
+
+
+def test_fit_det_zero_noise_returns_generating_helix(kf):
+    """No smearing and no material: the GPU fit (FP64) over barrel layers,
+    displaced modules and disks returns the generating track at its last hit,
+    as the oracle's pin does."""
+    w = presets.lids()
+    d = w.detector.replace(x_over_x0=0.0)
+    gen = dataclasses.replace(w.gen, smear=False, vtx_sxy=0.0)
+    ev = datagen.generate_det(d, gen, 0, 400, truth=True, x_over_x0=0.0)
+    n = ev.n_tracks
+    H, visit = datagen.det_track_rows(ev)
+    sg = kf.kf_seed(d.seed_geometry().replace(x_over_x0=0.0), n, to_dev(np.ascontiguousarray(H[:3])), beam_sigma=0.0)
+    g = kf.kf_fit_det(d, n, 3, to_dev(H), to_dev(visit.view(np.int32)), sg["par"], sg["cov"], sg["q"],
+                      arith=kf.ARITH_F64)
+    torch.cuda.synchronize()
+    par = host(g["par"])[:, :n].astype(np.float64)
+    assert np.all(host(g["status"])[:n] == 0)
+    last = np.array([int(v).bit_length() - 1 for v in visit[:n]])
+    truth = ev.truth[last, :, np.arange(n)].T
+    e = rel_vec_err(par[:3], truth[:3])
+    em = rel_vec_err(par[3:], truth[3:])
+    assert np.median(e) < 1e-6 and np.median(em) < 1e-5, (np.median(e), np.median(em))
+
+
+def test_build_det_parity_small_event(kf):
+    w = presets.lids()
+    d = w.detector
+    ev = _event(w, 500, event=3)
+    n = ev.n_tracks
+    g, sg = gpu_build(kf, w, ev, kf.ARITH_F64)
+    H, _ = datagen.det_track_rows(ev)
+    so = oracle.seed(d.seed_geometry(), H[:3], n)
+    o = oracle.build_det(d, w.cuts, ev.layer, ev.xyz, ev.cov, so["par"], so["cov"], so["q"], n)
+    r = compare_det(g, o, n, np.arange(n), "lids small f64", und_max=0.25)
+    print("build_det small f64", r)
+
+
+def test_build_det_parity_full_event_sampled(kf):
+    """The lids build workload at its size (20 000 tracks, |eta| <= 2, 20 %
+    noise per layer), FP64 arithmetic, in the launch configuration the
+    benchmark uses; the oracle builds 240 sampled seeds."""
+    w = presets.lids()
+    d = w.detector
+    ev = _event(w, w.n_tracks)
+    n = ev.n_tracks
+    g, sg = gpu_build(kf, w, ev, kf.ARITH_F64)
+    H, _ = datagen.det_track_rows(ev)
+    so = oracle.seed(d.seed_geometry(), H[:3], n)
+    lst = np.concatenate([np.arange(0, n, 97)[:200], np.arange(n - 40, n)])
+    o = oracle.build_det(d, w.cuts, ev.layer, ev.xyz, ev.cov, so["par"], so["cov"], so["q"], n, seed_list=lst)
+    r = compare_det(g, o, lst.size, lst, "lids full f64")
+    F = w.cuts.first_layer
+    true = ev.trk_hits[F:, :n]
+    found = ((g["hits"][:, :n] == true) & (true >= 0)).sum(axis=0)
+    eff = float(np.mean(found >= 0.75 * (true >= 0).sum(axis=0)))
+    c = g["counters"]
+    print(f"build_det full f64: {r}; efficiency {eff:.4f}; steps {c[0]}, hits scanned {c[1]}, chi2 {c[2]}, "
+          f"updates {c[3]}")
+    assert eff > 0.7
+
+
+def test_build_det_launch_shape_and_order_invariance(kf):
+    w = presets.lids()
+    ev = _event(w, 2000, event=5)
+    n = ev.n_tracks
+    g1, _ = gpu_build(kf, w, ev, kf.ARITH_F64)
+    g2, _ = gpu_build(kf, w, ev, kf.ARITH_F64, lanes=64, blocks=7, order=np.arange(n)[::-1].copy())
+    for k in ("hits", "visit", "nhits", "status", "chi2", "par", "cov"):
+        a, b = g1[k], g2[k]
+        assert np.array_equal(a[..., :n], b[..., :n]), k
+
+
+def test_build_det_fp32_arithmetic_agreement(kf):
+    w = presets.lids()
+    d = w.detector
+    ev = _event(w, 600, event=7)
+    n = ev.n_tracks
+    g, _ = gpu_build(kf, w, ev, kf.ARITH_F32)
+    H, _ = datagen.det_track_rows(ev)
+    so = oracle.seed(d.seed_geometry(), H[:3], n)
+    o = oracle.build_det(d, w.cuts, ev.layer, ev.xyz, ev.cov, so["par"], so["cov"], so["q"], n)
+    dec = oracle.decidable(o["margin"])[:n]
+    same = np.all(g["hits"][:, :n] == o["hits"][:, :n], axis=0) & (g["nhits"][:n] == o["nhits"][:n])
+    print(f"build_det fp32: identical lists {same.mean():.4f} overall, {same[dec].mean():.4f} decidable")
+    assert same.mean() >= 0.95
+
+
+def test_build_det_edge_cases(kf):
+    w = presets.lids()
+    d = w.detector
+    ev = _event(w, 50)
+    b = _bin(kf, w, ev)
+    H, _ = datagen.det_track_rows(ev)
+    sg = _seeds_gpu(kf, d, H, ev.n_tracks)
+    # zero seeds: nothing to do
+    bp = kf.build_params(w.cuts, arith=kf.ARITH_F64)
+    kf.kf_build_det(d, bp, b, 0, sg["par"], sg["cov"], sg["q"])
+    # the learned window and the hybrid state are not available here
+    for kw in (dict(window_mode=1, mlp_block=torch.zeros(16, device="cuda:0")), dict(state=1)):
+        bp = kf.build_params(w.cuts, arith=kf.ARITH_F64, **kw)
+        with pytest.raises(kf.KFError, match="status 4"):
+            kf.kf_build_det(d, bp, b, ev.n_tracks, sg["par"], sg["cov"], sg["q"])
+    # a malformed detector
+    bad = d.replace(lo=list(d.hi), hi=list(d.lo))
+    with pytest.raises(kf.KFError, match="status 1"):
+        kf.kf_fit_det(bad, 4, 3, to_dev(H), to_dev(np.zeros(H.shape[2], np.int32)), sg["par"], sg["cov"], sg["q"])
+    torch.cuda.synchronize()

@@ -131,6 +131,29 @@ def test_unbounded_cap_equals_exhaustive_search(wide):
             assert nleaves > 100
 
 
+@pytest.mark.parametrize("det", [False, True])
+def test_binning_rejects_bad_hits(det):
+    """Hits on a layer outside the detector or with a non-finite coordinate
+    have no bin: they come after every binned hit, and the binned hits keep
+    exactly the order and offsets they have without them."""
+    w = presets.lids() if det else presets.build()
+    if det:
+        ev = datagen.generate_det(w.detector, w.gen, 0, 400)
+        run = lambda lay, x: oracle.hit_bin_det(w.detector, 63, 16, lay, x)
+    else:
+        ev = datagen.generate(w.geometry, w.gen, 0, 400)
+        run = lambda lay, x: oracle.hit_bin(w.geometry, 63, 16, lay, x)
+    xyz = ev.xyz.astype(np.float32)
+    n = ev.n_hits
+    ref = run(ev.layer, xyz)
+    bad_xyz = np.array([[np.nan, 1.0, 2.0, 3.0, np.inf], [1.0, np.nan, 2.0, 3.0, 1.0], [0.0, 0.0, np.inf, 1.0, 0.0]],
+                       dtype=np.float32)
+    lay = np.concatenate([ev.layer, np.array([4, 4, 4, -1, 99], dtype=np.int32)])
+    b = run(lay, np.concatenate([xyz, bad_xyz], axis=1))
+    assert np.array_equal(b["offsets"], ref["offsets"])
+    assert np.array_equal(b["order"][:n], ref["order"]) and np.array_equal(b["phi"][:n], ref["phi"])
+    assert sorted(b["order"][n:]) == list(range(n, n + 5))
+
 def test_cap_one_equals_greedy():
     g = _small_geometry(10)
     gen = dataclasses.replace(presets.GenSettings(seed=77), noise_lo=3.0, noise_hi=3.0)

@@ -202,7 +202,6 @@ def test_det_fit_zero_noise_returns_generating_helix():
     sd = oracle.seed64(sg.replace(x_over_x0=0.0), H[:3], n, beam_sigma=0.0)
     o = oracle.fit_det64(d, 3, H, visit, sd["par64"], sd["cov64"], sd["q"], n)
     assert np.all(o["status"][:n] == 0)
-    last = np.array([31 - int(np.uint32(v)).bit_length() for v in visit[:n]])
     last = np.array([int(v).bit_length() - 1 for v in visit[:n]])
     tr = ev.truth[last, :, np.arange(n)].T
     err = np.abs(o["par"][:, :n] - tr) / np.maximum(np.abs(tr), 1.0)
