@@ -181,11 +181,16 @@ def test_fit_det_parity(kf):
     assert eg[well].max() <= 1e-4 and e2g[well].max() <= 1e-3
     agree = float(np.mean(eg[conv] <= 1e-4))
     assert agree >= 0.999
-    # the covariance diagonal of statistically consistent fits
+    # the covariance diagonal of statistically consistent fits, against the
+    # scale of its block (a fit ending on a disk has the z direction as null
+    # vector, so P_zz alone is ~0 there; on a barrel layer the radial one)
     wc = conv & (o["chi2"][:n] <= 5 * ndof)
-    for c in (0, 6, 11, 15, 18, 20):
-        ec = np.abs(g["cov"][c, :n][wc] - o["cov"][c, :n][wc]) / np.abs(o["cov"][c, :n][wc])
-        assert np.median(ec) < 1e-5, (c, np.median(ec))
+    blocks = {c: (0, 6, 11) for c in (0, 6, 11)}
+    blocks.update({c: (15, 18, 20) for c in (15, 18, 20)})
+    for c, blk in blocks.items():
+        scale = sum(np.abs(o["cov"][j, :n][wc]) for j in blk)
+        ec = np.abs(g["cov"][c, :n][wc] - o["cov"][c, :n][wc]) / scale
+        assert ec.max() < 1e-3 and np.median(ec) < 1e-6, (c, ec.max(), np.median(ec))
     print(f"fit_det f64: {n} tracks, failed fits {failed:.4f}; oracle seeds: max {e[conv].max():.3g}; gpu seeds: "
           f"max on measured seeds {eg[well].max():.3g}, agreement {agree:.5f}; tracks on disks "
           f"{np.mean(visit[:n] >= (1 << 10)):.3f}")
