@@ -264,6 +264,25 @@ int kf_build(const kf_geometry* g, const kf_build_params* bp, const kf_hits* hit
              float* out_cov, float* out_chi2, int32_t* out_nhits, int32_t* out_status,
              const kf_build_extra* extra, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * kf_build_noalloc — kf_build for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same build, arguments, outputs and errors as kf_build
+ * without the workspace, which lives in a static device array of the library
+ * holding kf_build_noalloc_max_bytes() = 64 MiB on every GPU the library
+ * runs on, until the process ends (enough for one event of 20 000 tracks
+ * plus 20 % noise on 17 layers, about 39 MB).  A call whose
+ * kf_build_workspace_bytes exceeds it returns KF_E_WORKSPACE (message in
+ * kf_last_error) without launching anything.  The call allocates nothing.
+ * Every call on one GPU uses the same array: calls that overlap on one GPU
+ * (two streams, two host threads) race and must be serialised by the caller.
+ */
+int kf_build_noalloc(const kf_geometry* g, const kf_build_params* bp, const kf_hits* hits, int32_t n_seeds, int32_t ld,
+                     const float* seed_par, const float* seed_cov, const int8_t* q, int32_t* out_hits,
+                     float* out_par, float* out_cov, float* out_chi2, int32_t* out_nhits, int32_t* out_status,
+                     const kf_build_extra* extra, void* stream);
+size_t kf_build_noalloc_max_bytes(void);
+
 /* Launch shape chosen by the last kf_build call of the calling host thread
  * (zeros before the first): lanes per block, blocks of the persistent grid,
  * dynamic LDS bytes per block, blocks per CU the occupancy calculator allows,

@@ -16,6 +16,11 @@ int kf_check(hipError_t e) {
 
 int kf_check_launch() { return kf_check(hipGetLastError()); }
 
+int kf_fail(int status, const char* msg) {
+  snprintf(g_last_error, sizeof(g_last_error), "%s", msg);
+  return status;
+}
+
 extern "C" const char* kf_status_string(int status) {
   switch (status) {
     case KF_OK: return "ok";

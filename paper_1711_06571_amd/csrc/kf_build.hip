@@ -22,6 +22,9 @@
 //      hit list is recovered at the end by walking it backwards.
 // Candidates with no child compete for a per-seed best-finished record (LDS).
 #include <stdint.h>
+#include <stdio.h>
+
+#include <mutex>
 
 #include "kfdev.h"
 #include "kfhost.h"
@@ -924,4 +927,65 @@ extern "C" int kf_build(const kf_geometry* g, const kf_build_params* bp, const k
                                      : launch<float, false, true>(A, lanes, bp->persistent_blocks, hist_waves, s))
              : (bp->window_mode == 1 ? launch<float, true, false>(A, lanes, bp->persistent_blocks, hist_waves, s)
                                      : launch<float, false, false>(A, lanes, bp->persistent_blocks, hist_waves, s));
+}
+
+// ------------------------------------------------- allocation-free variant
+//
+// kf_build_noalloc runs kf_build with its workspace in `scratch`, a static
+// device array of this library: every GPU the library runs on holds its own
+// copy (kScratchBytes) until the process ends.  In host code the array's
+// name stands for a host-side shadow, not a device address: the device
+// address is looked up once per device (hipGetSymbolAddress, with that
+// device current) and only that pointer is handed to kernels.  What the
+// build needs zeroed (queue head, per-event counters) is cleared by a kernel
+// of every call; the fine index and the packed hits are rebuilt by every
+// call; so the contents left by the previous call do not matter.  Calls that
+// overlap on one GPU share the array and race.
+
+static constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// device address of this device's copy of `scratch`
+int scratch_of_current_device(void** out) {
+  int dev = 0;
+  if (kf_check(hipGetDevice(&dev))) return KF_E_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return kf_fail(KF_E_UNSUPPORTED, "kf_build_noalloc: device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (kf_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)))) return KF_E_HIP;
+    if (!p) return kf_fail(KF_E_HIP, "kf_build_noalloc: no device address for the scratch array");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return KF_OK;
+}
+
+}  // namespace
+
+extern "C" size_t kf_build_noalloc_max_bytes(void) { return kScratchBytes; }
+
+extern "C" int kf_build_noalloc(const kf_geometry* g, const kf_build_params* bp, const kf_hits* hits,
+                                int32_t n_seeds, int32_t ld, const float* seed_par, const float* seed_cov,
+                                const int8_t* q, int32_t* out_hits, float* out_par, float* out_cov, float* out_chi2,
+                                int32_t* out_nhits, int32_t* out_status, const kf_build_extra* extra, void* stream) {
+  if (kf_check_geometry(g) || !bp || !hits) return KF_E_INVALID_ARG;
+  const size_t need = kf_build_workspace_bytes(bp, hits, n_seeds);
+  if (need == 0) return KF_E_INVALID_ARG;
+  if (need > kScratchBytes) {
+    char msg[160];
+    snprintf(msg, sizeof(msg), "kf_build_noalloc: this call needs %zu workspace bytes, the static scratch holds %zu",
+             need, kScratchBytes);
+    return kf_fail(KF_E_WORKSPACE, msg);
+  }
+  void* ws = nullptr;
+  if (int rc = scratch_of_current_device(&ws)) return rc;
+  return kf_build(g, bp, hits, n_seeds, ld, seed_par, seed_cov, q, out_hits, out_par, out_cov, out_chi2, out_nhits,
+                  out_status, extra, ws, kScratchBytes, stream);
 }

@@ -127,6 +127,9 @@ def lib():
         L.kf_build_workspace_bytes.argtypes = [ctypes.POINTER(BuildParams), ctypes.POINTER(Hits), I]
         L.kf_build.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(BuildParams), ctypes.POINTER(Hits), I,
                                I, P, P, P, P, P, P, P, P, P, ctypes.POINTER(BuildExtra), P, ctypes.c_size_t, P]
+        L.kf_build_noalloc.argtypes = list(L.kf_build.argtypes[:15]) + [P]
+        L.kf_build_noalloc_max_bytes.restype = ctypes.c_size_t
+        L.kf_build_noalloc_max_bytes.argtypes = []
         L.hit_bin_det.argtypes = [ctypes.POINTER(Detector)] + list(L.hit_bin.argtypes[1:])
         L.kf_fit_det.argtypes = [ctypes.POINTER(Detector), I, I, I, P, P, P, P, P, P, P, P, P, P, P, I, P]
         L.kf_build_det.argtypes = [ctypes.POINTER(Detector), ctypes.POINTER(BuildParams), ctypes.POINTER(Hits), I,
@@ -406,6 +409,33 @@ def kf_build_det_last_launch() -> dict:
     info = LaunchInfo()
     _check(lib().kf_build_det_last_launch(ctypes.byref(info)))
     return {k: int(getattr(info, k)) for k, _ in LaunchInfo._fields_}
+
+
+def kf_build_noalloc(g, bp, binned: BinnedHits, n_seeds, seed_par, seed_cov, q, extra=None, out=None, stream=None):
+    """kf_build with the library's static workspace (no workspace argument;
+    the call allocates no device memory when `out` is given)."""
+    ld = seed_par.shape[1]
+    dev = seed_par.device
+    F = bp.first_layer
+    if out is None:
+        out = dict(hits=torch.empty((g.n_layers - F, ld), dtype=torch.int32, device=dev),
+                   par=torch.empty((6, ld), dtype=torch.float32, device=dev),
+                   cov=torch.empty((21, ld), dtype=torch.float32, device=dev),
+                   chi2=torch.empty(ld, dtype=torch.float32, device=dev),
+                   nhits=torch.empty(ld, dtype=torch.int32, device=dev),
+                   status=torch.empty(ld, dtype=torch.int32, device=dev))
+    gg = geometry(g)
+    hd = binned.descriptor()
+    ex = extra if extra is not None else BuildExtra()
+    _check(lib().kf_build_noalloc(ctypes.byref(gg), ctypes.byref(bp), ctypes.byref(hd), n_seeds, ld, _ptr(seed_par),
+                                  _ptr(seed_cov), _ptr(q), _ptr(out["hits"]), _ptr(out["par"]), _ptr(out["cov"]),
+                                  _ptr(out["chi2"]), _ptr(out["nhits"]), _ptr(out["status"]), ctypes.byref(ex),
+                                  _stream(stream)))
+    return out
+
+
+def kf_build_noalloc_max_bytes() -> int:
+    return int(lib().kf_build_noalloc_max_bytes())
 
 
 def kf_build_last_launch() -> dict:
