@@ -39,6 +39,9 @@ FLOP_STEP2_CHI2 = 310
 # a chosen hit: step 2 with the full transport and scattering, then the update
 FLOP_STEP2_UPDATE = FLOP_PREDICT + FLOP_UPDATE
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X vector peaks (published)
+# algorithmic bytes of one fitted track (14 layers): hit rows 14 x 36 B, seed
+# (27 FP32 + charge) 109 B, outputs (27 FP32, chi2, ndof, status) 120 B
+FIT_BYTES_PER_TRACK = 14 * 36 + 109 + 120
 PEAK_HBM_GBS = 8000.0
 
 
@@ -96,60 +99,83 @@ def copy_only(nbytes):
     print(json.dumps({"copy_bytes": n * 4, "reps": 5}), flush=True)
 
 
+TRAIN_ROWS = 2_000_000
+
+
 def learned_vs_plain(ariths, log):
     """Learned search window against the plain one on the learned workload
-    (the build workload's generator, other events): rows dumped by the plain
-    build of event 0, gates at a quantile of their plain widths, GPU training
-    on the gated rows, kappa calibrated on event 1 to keep the plain
-    efficiency within 0.1 %, comparison on events 2..33, in each arithmetic
-    and in both states (the network reads the Cartesian prediction; in the
-    hybrid state it is trained on rows of the hybrid-state build, whose plain
-    windows are narrower)."""
+    (the build workload's generator, other events): 2 M rows dumped by the
+    plain build of train events 0..2, gates at a quantile of their plain
+    widths, GPU training on the gated rows (and, beside it, an ungated
+    network trained on all rows), kappa calibrated on event 3 to keep the
+    plain efficiency within 0.1 %, comparison on events 4..35, in each
+    arithmetic and in both states (the network reads the Cartesian
+    prediction; in the hybrid state it is trained on rows of the hybrid-state
+    build, whose plain windows are narrower)."""
     import torch
     from paper_1711_06571_amd import kftrack as kf
     from paper_1711_06571_amd import presets, window
     w = presets.learned()
     t0 = time.perf_counter()
-    tr = window.load_events(w, [0])
-    rows = window.dump_rows(w, tr)
+    tr = window.load_events(w, [0, 1, 2])
+    rows = window.dump_rows(w, tr)[:TRAIN_ROWS]
     t = window.train_gated(w, rows, epochs=4)
-    rows_h = window.dump_rows(w, tr, state=kf.STATE_HYBRID)
+    tu = window.train_gated(w, rows, quantile=0.0, epochs=4)
+    rows_h = window.dump_rows(w, tr, state=kf.STATE_HYBRID)[:TRAIN_ROWS]
     t_h = window.train_gated(w, rows_h, epochs=4)
-    val = window.load_events(w, [1])
+    del tr
+    val = window.load_events(w, [3])
     # 32 events (640 k seeds, ~30 seed groups per wave): with only a few groups
     # per wave the build time is the slowest group's, not the throughput
-    test = window.load_events(w, list(range(2, 34)))
+    test = window.load_events(w, list(range(4, 36)))
     n = test.eb.n_seeds
     res = {"workload": f"{w.name}: 32 test events x {n // 32} tracks + noise", "train_rows": int(rows.shape[0]),
+           "train_events": [0, 1, 2], "validation_event": 3,
            "gate_quantile": window.GATE_QUANTILE, "gates_cm": [round(v, 5) for v in t.gates],
            "rows_gated": int(t.rows_used), "train_seconds": round(t.seconds, 3), "loss_initial": round(t.loss0, 5),
            "loss_final": round(t.losses[-1], 5),
+           "ungated_network": {"rows": int(tu.rows_used), "loss_initial": round(tu.loss0, 5),
+                               "loss_final": round(tu.losses[-1], 5)},
            "hybrid_state_network": {"train_rows": int(rows_h.shape[0]), "gates_cm": [round(v, 5) for v in t_h.gates],
                                     "rows_gated": int(t_h.rows_used), "loss_initial": round(t_h.loss0, 5),
                                     "loss_final": round(t_h.losses[-1], 5)}}
-    for arith, state in [(a, kf.STATE_CARTESIAN) for a in ariths] + [(a, kf.STATE_HYBRID) for a in ariths]:
-        name = ("f64" if arith == kf.ARITH_F64 else "f32") + ("_hybrid" if state == kf.STATE_HYBRID else "")
-        net = t_h if state == kf.STATE_HYBRID else t
-        out_p, _ = window.build(w, val, arith=arith, state=state)
-        eff_val = window.efficiency(w, val, out_p)
+
+    def compare(net, arith, state, outp, ep, tp, cp):
+        out_v, _ = window.build(w, val, arith=arith, state=state)
+        eff_val = window.efficiency(w, val, out_v)
         kap, trace = window.calibrate(w, net, val, eff_val, target=0.001, arith=arith, state=state)
         kf.mlp_set_header(net.block, kappa=kap)
-        outp, cp = window.build(w, test, counters=True, arith=arith, state=state)
         outl, cl = window.build(w, test, window_mode=1, block=net.block, counters=True, arith=arith, state=state)
         torch.cuda.synchronize()
-        ep, el = window.efficiency(w, test, outp), window.efficiency(w, test, outl)
-        tp = window.time_build(w, test, 0, arith=arith, state=state)
+        el = window.efficiency(w, test, outl)
         tl = window.time_build(w, test, 1, net.block, arith=arith, state=state)
-        cp, cl = cp.cpu().numpy(), cl.cpu().numpy()
-        log(f"learned {name}: kappa {kap}, eff plain {ep:.4f} learned {el:.4f}, ms {tp:.3f} vs {tl:.3f}")
-        res[name] = {
-            "kappa": kap, "calibration": trace,
-            "plain": {"build_ms": round(tp, 4), "seeds_per_s": round(n / (tp * 1e-3), 1), "efficiency": round(ep, 4),
-                      "hits_tested_per_cand_layer": round(float(cp[1]) / max(float(cp[0]), 1), 3)},
-            "learned": {"build_ms": round(tl, 4), "seeds_per_s": round(n / (tl * 1e-3), 1),
-                        "efficiency": round(el, 4),
-                        "hits_tested_per_cand_layer": round(float(cl[1]) / max(float(cl[0]), 1), 3)},
-            "speedup": round(tp / tl, 3), "efficiency_loss": round(ep - el, 4)}
+        lost, lost_frac = window.lost_hits(w, test, outp, outl)
+        cl = cl.cpu().numpy()
+        return {"kappa": kap, "calibration": trace,
+                "learned": {"build_ms": round(tl, 4), "seeds_per_s": round(n / (tl * 1e-3), 1),
+                            "efficiency": round(el, 4),
+                            "hits_tested_per_cand_layer": round(float(cl[1]) / max(float(cl[0]), 1), 3),
+                            "lost_hits": lost, "lost_hit_fraction": round(lost_frac, 6)},
+                "speedup": round(tp / tl, 3), "efficiency_loss": round(ep - el, 4)}
+
+    for arith, state in [(a, kf.STATE_CARTESIAN) for a in ariths] + [(a, kf.STATE_HYBRID) for a in ariths]:
+        name = ("f64" if arith == kf.ARITH_F64 else "f32") + ("_hybrid" if state == kf.STATE_HYBRID else "")
+        outp, cp = window.build(w, test, counters=True, arith=arith, state=state)
+        torch.cuda.synchronize()
+        ep = window.efficiency(w, test, outp)
+        tp = window.time_build(w, test, 0, arith=arith, state=state)
+        cp = cp.cpu().numpy()
+        r = compare(t_h if state == kf.STATE_HYBRID else t, arith, state, outp, ep, tp, cp)
+        r["plain"] = {"build_ms": round(tp, 4), "seeds_per_s": round(n / (tp * 1e-3), 1), "efficiency": round(ep, 4),
+                      "hits_tested_per_cand_layer": round(float(cp[1]) / max(float(cp[0]), 1), 3)}
+        if state == kf.STATE_CARTESIAN:
+            # the same comparison with the ungated network (consulted for every candidate)
+            u = compare(tu, arith, state, outp, ep, tp, cp)
+            r["ungated"] = {"kappa": u["kappa"], **u["learned"], "speedup": u["speedup"],
+                            "efficiency_loss": u["efficiency_loss"]}
+        log(f"learned {name}: kappa {r['kappa']}, eff plain {ep:.4f} learned {r['learned']['efficiency']:.4f}, "
+            f"ms {tp:.3f} vs {r['learned']['build_ms']:.3f}, lost hits {r['learned']['lost_hit_fraction']:.5f}")
+        res[name] = r
     res["total_seconds"] = round(time.perf_counter() - t0, 1)
     return res
 
@@ -160,28 +186,65 @@ def batched(arith, autotune, log):
     (binning of every event + the build)."""
     import numpy as np
     from paper_1711_06571_amd import batch, presets
+    from paper_1711_06571_amd import kftrack as kf
     w = presets.batch()
     b = batch.load(w)
+    if autotune:
+        # sweep in the benchmark's arithmetic; the choice goes into the cache
+        # (kftrack.TUNE_CACHE layout) written beside the other outputs
+        tr = batch.autotune(b, log=lambda q: log(f"tune {q}"), arith=arith)
+        os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+        batch.save_cache(tr, arith, os.path.join(ROOT, "gpurun_out", "autotune.json"), w.name)
+        batch.save(tr, os.path.join(ROOT, "gpurun_out", "autotune_points.json"), w.name)
+    # the default launch shape, then the autotuner's cached choice
     p = batch.plan(b, arith=arith)
+    ms_default = batch.run(p, reps=5)
+    p.close()
+    cached = kf.tuned_launch(arith)
+    p = batch.plan(b, arith=arith, tuned=True)
     ms = batch.run(p, reps=5)
     lat = batch.latencies_ms(b)
     eff = batch.efficiency(b, p.out)
     p.close()
     # the whole step (binning, build, gather, final fit) as one graph
-    pf = batch.plan(b, arith=arith, fit=True)
+    pf = batch.plan(b, arith=arith, fit=True, tuned=True)
     ms_fit = batch.run(pf, reps=5)
     pf.close()
     res = {"workload": f"{w.name}: {w.n_events} events, {b.eb.n_seeds} seeds", "ms_per_launch": round(ms, 4),
            "events_per_s": round(w.n_events / (ms * 1e-3), 2), "seeds_per_s": round(b.eb.n_seeds / (ms * 1e-3), 1),
            "latency_ms_p50": round(float(np.percentile(lat, 50)), 4),
            "latency_ms_p99": round(float(np.percentile(lat, 99)), 4), "efficiency": round(eff, 4),
-           "ms_per_launch_with_fit": round(ms_fit, 4)}
-    if autotune:
-        tr = batch.autotune(b, log=lambda q: log(f"tune {q}"))
-        res["tuned"] = dict(tr.best.__dict__)
-        res["tune_points"] = len(tr.points)
+           "ms_per_launch_with_fit": round(ms_fit, 4), "ms_per_launch_default_shape": round(ms_default, 4),
+           "launch": "autotuned (cached choice)" if cached else "default (no cached choice)",
+           "tuned": cached}
     log(f"batch: {ms:.3f} ms per launch")
     return res
+
+
+def fit_latency(arith, reps=50):
+    """Latency of one kf_fit call on the small fit workload (1 event, 1 000
+    tracks, 10 layers, fit over layers 4..10): median of HIP-event times
+    around single calls on an idle stream."""
+    import torch
+    from paper_1711_06571_amd import datagen, kftrack as kf, presets
+    w = presets.fit_small()
+    ev = datagen.generate(w.geometry, w.gen, 0, w.n_tracks)
+    n = ev.n_tracks
+    H = torch.from_numpy(datagen.track_hits(ev)).to("cuda:0")
+    s = kf.kf_seed(w.geometry, n, H)
+    out = kf.kf_fit(w.geometry, n, 3, H, s["par"], s["cov"], s["q"], arith=arith)
+    torch.cuda.synchronize()
+    ts = []
+    st = torch.cuda.current_stream()
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        kf.kf_fit(w.geometry, n, 3, H, s["par"], s["cov"], s["q"], out=out, arith=arith)
+        b.record(st)
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b) * 1e3)
+    return {"workload": w.name, "tracks": n, "us_median": round(float(np.median(ts)), 2),
+            "us_min": round(float(np.min(ts)), 2)}
 
 
 def lids(arith, log, n_events=16, fit_events=50):
@@ -328,11 +391,16 @@ def cpu_baseline(w, eb, seconds, max_threads=16):
         Hs[:, :, :ne] = eb.seed_hits[:, :, s0:s1]
         return xyz, cov, layer, ne, oracle.seed(w.geometry, Hs, ne)
 
-    def chunk(inp, k, chunk_n=8):
+    kept = []
+
+    def chunk(inp, k, chunk_n=8, keep=False):
         xyz, cov, layer, ne, so = inp
         lst = (np.arange(chunk_n) * 2503 + k * chunk_n * 7919) % ne
         ob = oracle.build(w.geometry, w.cuts, layer, xyz, cov, so["par"], so["cov"], so["q"], ne, seed_list=lst)
         m = lst.size
+        if keep:
+            kept.append((lst, ob["hits"][:, :m].copy(), ob["nhits"][:m].copy(), ob["status"][:m].copy(),
+                         ob["margin"][:, :m].copy()))
         hb = ob["hits"][:, :m]
         Hf = np.zeros((L, 9, 64), dtype=np.float32)
         hm = np.zeros(64, dtype=np.uint32)
@@ -356,7 +424,7 @@ def cpu_baseline(w, eb, seconds, max_threads=16):
     t_single = 0.4 * seconds
     done1, k, t0 = 0, 0, time.perf_counter()
     while time.perf_counter() - t0 < t_single:
-        done1 += chunk(inp0, k)
+        done1 += chunk(inp0, k, keep=True)
         k += 1
     dt1 = time.perf_counter() - t0
     # all cores: one event per thread
@@ -387,7 +455,7 @@ def cpu_baseline(w, eb, seconds, max_threads=16):
         x.join()
     dtA = time.perf_counter() - tA
     rate_all = sum(done) / dtA
-    return {"value": round(rate_all, 2), "unit": "tracks/s", "cores": T, "kind": "oracle",
+    return kept, {"value": round(rate_all, 2), "unit": "tracks/s", "cores": T, "kind": "oracle",
             "host_cores": os.cpu_count(), "usable_cores": usable, "cpu_model": _cpu_model(),
             "single_core": {"value": round(done1 / dt1, 2), "seeds": done1, "seconds": round(dt1, 1)},
             "sample": f"fit_scale events 0..{T - 1} (20000 tracks each), {sum(done)} seeds in {dtA:.1f} s on "
@@ -509,6 +577,7 @@ def main():
                 "traffic": None, "kernel": dom, "avg_ms": stage_ms[dom]}
     # physics: fraction of seeds whose built list holds >= 75 % of their true hits
     hits = bout["hits"].cpu().numpy()[:, :n]
+    nhits_g = bout["nhits"].cpu().numpy()[:n]
     eff = float(np.mean((hits == eb.true_hits[F:, :n]).mean(axis=0) >= 0.75))
     res = {
         "metric": METRIC, "value": round(value, 1), "unit": "tracks/s", "n_gpus": 1, "steps": args.steps,
@@ -522,6 +591,8 @@ def main():
         "work": {"build_cand_layers": n_pred, "build_hits_tested": n_scan, "build_chi2": n_chi2,
                  "build_updates": n_upd, "build_gflop": round(build_flop / 1e9, 3),
                  "fit_gflop": round(fit_flop / 1e9, 3),
+                 "fit_algorithmic_gb": round(n * FIT_BYTES_PER_TRACK / 1e9, 3),
+                 "fit_gbs": round(n * FIT_BYTES_PER_TRACK / (stage_ms["kf_fit"] * 1e-3) / 1e9, 1),
                  "build_tflops": round(build_flop / (stage_ms["kf_build"] * 1e-3) / 1e12, 3),
                  "fit_tflops": round(fit_flop / (stage_ms["kf_fit"] * 1e-3) / 1e12, 3)},
         "efficiency_75pct": round(eff, 4),
@@ -545,6 +616,7 @@ def main():
                            "efficiency_75pct": round(heff, 4),
                            "fit_status_ok": round(float(np.mean(fout["status"].cpu().numpy()[:n] == 0)), 4)}
     log = lambda m: print(m, file=sys.stderr, flush=True)
+    res["fit_small_latency"] = fit_latency(arith)
     if not args.no_learned:
         res["learned_vs_plain"] = learned_vs_plain([kf.ARITH_F32, kf.ARITH_F64], log)
     if not args.no_batch:
@@ -552,7 +624,23 @@ def main():
     if not args.no_lids:
         res["lids"] = lids(arith, log)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(w, eb, args.cpu_seconds)
+        kept, res["cpu_baseline"] = cpu_baseline(w, eb, args.cpu_seconds)
+        # the oracle's builds of the single-core sample against the timed
+        # step's lists (event 0 is seeds 0..19 999): identical on every
+        # decidable seed, and how many are decidable
+        import oracle
+        lst = np.concatenate([k_[0] for k_ in kept]) if kept else np.zeros(0, np.int64)
+        if lst.size:
+            oh = np.concatenate([k_[1] for k_ in kept], axis=1)
+            on = np.concatenate([k_[2] for k_ in kept])
+            om = np.concatenate([k_[4] for k_ in kept], axis=1)
+            dec = oracle.decidable(om)
+            same = np.all(hits[:, lst] == oh, axis=0) & (nhits_g[lst] == on)
+            res["parity_sample"] = {"seeds": int(lst.size), "decidable": round(float(dec.mean()), 4),
+                                    "identical_on_decidable": round(float(same[dec].mean()), 4),
+                                    "identical_overall": round(float(same.mean()), 4),
+                                    "what": "oracle build of the CPU baseline's single-core seeds vs the timed "
+                                            "FP64 step's hit lists and nhits (event 0)"}
     print(json.dumps(res), flush=True)
 
 

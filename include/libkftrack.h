@@ -58,6 +58,8 @@ extern "C" {
 #define KF_TRK_NONFINITE 4   /* a non-finite input or intermediate */
 #define KF_TRK_S_NOT_PD 8    /* the 2x2 innovation covariance is not positive definite */
 #define KF_TRK_CAP_TRUNC 16  /* build: children were dropped by the candidate cap */
+#define KF_TRK_EVENT_TOO_LARGE 32 /* build: the seed's event holds more than 2^24 - 1 binned hits (hit
+                                     indices are event-local and 24 bits wide); the seed is not built */
 
 /* arithmetic of the fit and build kernels (storage is always FP32) */
 #define KF_ARITH_F32 0 /* FP32 arithmetic */
@@ -206,10 +208,12 @@ typedef struct {
                                  written for an event with no seeds) */
   int64_t* start_tick;        /* [1] earliest wall-clock tick seen by any wave of the launch */
   /* training-data dump: for every candidate whose hits so far are all true
-     (or holes) and whose seed has a true hit on the layer, the 27 features
-     (predicted state and covariance, Cartesian in either state: what the
-     learned window reads) and the 2 labels (|arc| and |dz| to the
-     true hit) as 29 floats per row */
+     (or holes) and whose seed has a true hit on the layer, one row of 32
+     words: the 27 features (predicted state and covariance, Cartesian in
+     either state: what the learned window reads), the 2 labels (|arc| and
+     |dz| to the true hit), the plain arc and z half-widths of the
+     candidate's window, and the int32 (seed << 8) | (layer << 3) | slot
+     (seed indices below 2^24 identify the seed) */
   const int32_t* true_hits;   /* [n_layers][ld] true original hit index per seed and layer */
   const float* true_xyz;      /* [n_layers][3][ld] position of that true hit */
   float* dump;                /* [dump_capacity][32] */

@@ -66,16 +66,18 @@ def extra_for(b: Batch, timestamps=True) -> kf.BuildExtra:
 
 
 def plan(b: Batch, cap=None, lanes=0, blocks=0, arith=kf.ARITH_F32, window_mode=0, mlp_block=None, refine=0,
-         fit=False, state=kf.STATE_CARTESIAN):
+         fit=False, state=kf.STATE_CARTESIAN, tuned=False):
     """The batch's graph: binning and build, and with fit=True also the
     gather and the final fit of the built lists (in the same arithmetic and
-    state)."""
+    state).  tuned=True takes the launch parameters left at 0 from the
+    autotuner's cached choice."""
     cuts = b.w.cuts
     bp = kf.build_params(cuts, cap=cap, lanes_per_block=lanes, persistent_blocks=blocks, arith=arith,
-                         window_mode=window_mode, mlp_block=mlp_block, phi_refine=refine, state=state)
+                         window_mode=window_mode, mlp_block=mlp_block, phi_refine=refine, state=state, tuned=tuned)
+    keep = (b.sev, b.order, b.n_per_event, b.ticks, b.t0) + ((mlp_block,) if mlp_block is not None else ())
     return kf.BatchPlan(b.w.geometry, bp, b.layer, b.xyz, b.cov, b.hoff, cuts.n_phi_bins, cuts.n_z_bins,
                         b.eb.n_seeds, b.seeds["par"], b.seeds["cov"], b.seeds["q"], extra=extra_for(b),
-                        fit_arith=arith if fit else None)
+                        fit_arith=arith if fit else None, keep=keep)
 
 
 def run(p: kf.BatchPlan, reps=5) -> float:
@@ -127,7 +129,7 @@ class TuneResult:
 
 
 def autotune(b: Batch, lanes_set=(64, 128, 256), bpcu_set=(1, 2, 0), caps=(4, 6, 8), refines=(8, 32, 64), reps=3,
-             eff_tol=0.001, log=None) -> TuneResult:
+             eff_tol=0.001, log=None, arith=kf.ARITH_F32) -> TuneResult:
     """Sweep launch shape x candidate cap x granularity of the fine phi index
     (the hit-search structure: sub-bins per phi bin).  Launch shape and
     granularity never change the results; the cap does, so the chosen point
@@ -139,7 +141,7 @@ def autotune(b: Batch, lanes_set=(64, 128, 256), bpcu_set=(1, 2, 0), caps=(4, 6,
         for refine in refines:
             for lanes in lanes_set:
                 for bpcu in bpcu_set:
-                    p = plan(b, cap=cap, lanes=lanes, blocks=bpcu * cus, refine=refine)
+                    p = plan(b, cap=cap, lanes=lanes, blocks=bpcu * cus, refine=refine, arith=arith)
                     ms = run(p, reps=reps)
                     lat = latencies_ms(b)
                     eff = efficiency(b, p.out)
@@ -165,5 +167,24 @@ def choose(points, eff_tol=0.001):
 def save(res: TuneResult, path, workload):
     data = {"gpu": res.gpu, "workload": workload, "best": res.best.__dict__,
             "points": [q.__dict__ for q in res.points]}
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1)
+
+
+def save_cache(res: TuneResult, arith, path, workload):
+    """Merge the chosen launch parameters into the cache kftrack reads
+    (kftrack.TUNE_CACHE layout): kf_build -> arithmetic -> lanes_per_block,
+    blocks_per_cu, phi_refine, plus the measurement they came from.  The cap
+    is a parameter of the method, not of the launch, and is not cached."""
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        data = {}
+    b = res.best
+    data.setdefault("kf_build", {})["f64" if arith == kf.ARITH_F64 else "f32"] = {
+        "lanes_per_block": b.lanes, "blocks_per_cu": b.blocks_per_cu, "phi_refine": b.refine,
+        "ms": round(b.ms, 4), "cap_of_the_measurement": b.cap, "efficiency": round(b.eff, 4),
+        "gpu": res.gpu, "workload": workload, "points": len(res.points)}
     with open(path, "w") as f:
         json.dump(data, f, indent=1)

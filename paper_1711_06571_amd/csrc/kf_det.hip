@@ -129,6 +129,7 @@ struct DetBuildArgs {
   float nsigma, win_sig_rphi, win_sig_w;
   int first_layer;
   int n_events, n_phi, n_w;
+  const int32_t* offsets;  // [events][layers][n_phi * n_w + 1]
   const float4* hpack;  // packed hits: (phi, x, y, z), (cov 0..3), (cov 4, cov 5, orig bits, 0)
   int refine;
   const int32_t* fine;  // [events][layers][n_w][n_phi * refine + 1]
@@ -493,9 +494,13 @@ __global__ void __launch_bounds__(256, KF_BUILD_DET_WAVES) build_det_kernel(DetB
     int n_active = seed_ok ? 1 : 0;
     int seed_status = 0;
     if (lane_used && slot == 0) finm[sidx * 5 + 0] = 0;
-    if (seed_ok && !(all_finite(X, 6) && all_finite(P, 21))) {
+    const int bad = !seed_ok ? 0
+                    : event_too_large(A.offsets, ev, L, A.n_phi * A.n_w) ? KF_EVENT_TOO_LARGE
+                    : !(all_finite(X, 6) && all_finite(P, 21))          ? KF_NONFINITE
+                                                                        : 0;
+    if (bad) {
       if (slot == 0) {
-        finm[sidx * 5 + 0] = 1; finm[sidx * 5 + 1] = 0; finm[sidx * 5 + 2] = KF_NONFINITE;
+        finm[sidx * 5 + 0] = 1; finm[sidx * 5 + 1] = 0; finm[sidx * 5 + 2] = bad;
         finm[sidx * 5 + 3] = -1; finm[sidx * 5 + 4] = 0;
         for (int k = 0; k < 6; ++k) fin[sidx * 27 + k] = (float)X[k];
         for (int k = 0; k < 21; ++k) fin[sidx * 27 + 6 + k] = (float)P[k];
@@ -843,7 +848,7 @@ extern "C" int kf_build_det(const kf_detector* d, const kf_build_params* bp, con
   A.chi2_cut = bp->chi2_cut; A.max_holes = bp->max_holes; A.cap = bp->cand_cap;
   A.nsigma = bp->nsigma; A.win_sig_rphi = bp->win_sig_rphi; A.win_sig_w = bp->win_sig_z;
   A.first_layer = bp->first_layer;
-  A.n_events = hits->n_events; A.n_phi = hits->n_phi; A.n_w = hits->n_z;
+  A.n_events = hits->n_events; A.n_phi = hits->n_phi; A.n_w = hits->n_z; A.offsets = hits->offsets;
   A.refine = refine;
   // workspace: the layout of kf_build's (queue head and event counters, fine
   // index, packed hits, history tables)

@@ -31,6 +31,7 @@ constexpr int KF_OUT_OF_Z = 2;
 constexpr int KF_NONFINITE = 4;
 constexpr int KF_S_NOT_PD = 8;
 constexpr int KF_CAP_TRUNC = 16;
+constexpr int KF_EVENT_TOO_LARGE = 32;
 
 // GeV / (T cm): pT = KAPPA * B * rho
 template <typename T> KFD constexpr T kappa() { return T(0.299792458e-2); }

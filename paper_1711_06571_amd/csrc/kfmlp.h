@@ -50,7 +50,8 @@
 #define KFMLP_P_W3 (KFMLP_P_B2 + 64)
 #define KFMLP_P_B3 (KFMLP_P_W3 + 2 * 64)
 #define KFMLP_NPARAM (KFMLP_P_B3 + 2)
-// one row of training data: 27 features, 2 labels, then seed, layer, slot
+// one row of training data: 27 features, 2 labels, the plain arc and z
+// half-widths of the candidate's window, then (seed << 8) | (layer << 3) | slot
 #define KFMLP_DUMP_ROW 32
 // LDS row pitch of the activation buffer (bf16 elements; 64 + 8 padding)
 #define KFMLP_PITCH 72

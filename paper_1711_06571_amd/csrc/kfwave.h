@@ -16,6 +16,13 @@ constexpr uint64_t kInfKey = ~0ull;
 constexpr uint32_t kHoleIdx = 0xFFFFFFu;
 constexpr int kMaxOrig = (1 << 24) - 2;
 
+// Event-local hit indices are 24 bits wide (0xFFFFFF marks a hole): an event
+// with more than kMaxOrig + 1 binned hits cannot be built.
+__device__ inline bool event_too_large(const int32_t* offsets, int ev, int n_layers, int nb) {
+  const int32_t* eo = offsets + (size_t)ev * n_layers * (nb + 1);
+  return eo[(size_t)(n_layers - 1) * (nb + 1) + nb] - eo[0] > kMaxOrig + 1;
+}
+
 template <typename T> __device__ inline T shfl(T v, int src) { return __shfl(v, src, 64); }
 __device__ inline uint64_t shfl_u64(uint64_t v, int src) {
   uint32_t lo = __shfl((uint32_t)v, src, 64), hi = __shfl((uint32_t)(v >> 32), src, 64);
@@ -150,6 +157,16 @@ __device__ inline int wave_excl_scan(int v, int lane, int& total) {
   }
   total = __shfl(x, 63, 64);
   return x - v;
+}
+
+// Wave-wide inclusive prefix maximum.
+__device__ inline int wave_incl_max(int v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(v, d, 64);
+    if (lane >= d) v = t > v ? t : v;
+  }
+  return v;
 }
 
 __device__ inline int wave_max(int v) {

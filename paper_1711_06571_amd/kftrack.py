@@ -30,6 +30,7 @@ TRK_OUT_OF_Z = 2
 TRK_NONFINITE = 4
 TRK_S_NOT_PD = 8
 TRK_CAP_TRUNC = 16
+TRK_EVENT_TOO_LARGE = 32
 
 
 class Geometry(ctypes.Structure):
@@ -277,8 +278,38 @@ STATE_CARTESIAN = 0
 STATE_HYBRID = 1
 
 
+# Launch parameters chosen by the autotuner (batch.autotune) per arithmetic,
+# read once; a missing file means the library's defaults.
+TUNE_CACHE = os.path.join(_HERE, "autotune.json")
+_tune = None
+
+
+def tuned_launch(arith):
+    """The cached launch choice for kf_build in this arithmetic: dict with
+    lanes_per_block, blocks_per_cu (0: as many as fit), phi_refine; or None."""
+    global _tune
+    if _tune is None:
+        try:
+            import json
+            with open(TUNE_CACHE) as f:
+                _tune = json.load(f)
+        except (OSError, ValueError):
+            _tune = {}
+    return _tune.get("kf_build", {}).get("f64" if arith == ARITH_F64 else "f32")
+
+
 def build_params(cuts, window_mode=0, mlp_block=None, lanes_per_block=0, persistent_blocks=0, cap=None,
-                 arith=ARITH_F32, phi_refine=0, state=STATE_CARTESIAN):
+                 arith=ARITH_F32, phi_refine=0, state=STATE_CARTESIAN, tuned=False):
+    """kf_build_params from the cuts.  tuned=True fills the launch parameters
+    left at 0 (lanes per block, persistent blocks, fine-index granularity)
+    from the autotuner's cached choice for the arithmetic, if there is one."""
+    if tuned and lanes_per_block == 0 and persistent_blocks == 0 and phi_refine == 0:
+        t = tuned_launch(arith)
+        if t:
+            lanes_per_block = int(t["lanes_per_block"])
+            cus = torch.cuda.get_device_properties(0).multi_processor_count
+            persistent_blocks = int(t["blocks_per_cu"]) * cus
+            phi_refine = int(t["phi_refine"])
     bp = BuildParams()
     bp.chi2_cut = cuts.chi2_cut
     bp.max_holes = cuts.max_holes
@@ -584,11 +615,14 @@ def kf_mlp_adam(block, master, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999
 class BatchPlan:
     """hit_bin + kf_build of a batch of events captured as one HIP graph;
     with fit_arith set, also kf_gather_hits + kf_fit of the built lists (the
-    whole step), fit outputs in self.fit.  Holds references to every buffer
-    the graph uses."""
+    whole step), fit outputs in self.fit.  The graph bakes in raw device
+    pointers: the plan holds references to the buffers it allocates and to
+    the inputs it is given, and `keep` must list the tensors behind the raw
+    pointers of `extra` (seed_event, seed_order, counters, ticks, ...) and of
+    bp.mlp (the network block), so none is freed while the plan lives."""
 
     def __init__(self, g, bp, layer, xyz, cov, event_offsets, n_phi, n_z, n_seeds, seed_par, seed_cov, q,
-                 extra=None, stream=None, fit_arith=None):
+                 extra=None, stream=None, fit_arith=None, keep=()):
         dev = layer.device
         n_hits = layer.shape[0]
         E = event_offsets.shape[0] - 1
@@ -605,7 +639,7 @@ class BatchPlan:
                         chi2=torch.empty(ld, dtype=torch.float32, device=dev),
                         nhits=torch.empty(ld, dtype=torch.int32, device=dev),
                         status=torch.empty(ld, dtype=torch.int32, device=dev))
-        self._keep = (layer, xyz, cov, event_offsets, seed_par, seed_cov, q)
+        self._keep = (layer, xyz, cov, event_offsets, seed_par, seed_cov, q) + tuple(keep)
         self.stream = stream if stream is not None else torch.cuda.Stream()
         self.g = geometry(g)
         self.bp = bp

@@ -84,6 +84,20 @@ def efficiency(w, e: EventOnGPU, out) -> float:
     return float(np.mean((hits == e.eb.true_hits[F:, :n]).mean(axis=0) >= 0.75))
 
 
+def lost_hits(w, e: EventOnGPU, out_plain, out_learned):
+    """True hits on the plain build's best candidates that the learned
+    build's best candidates miss: (count, fraction of the plain build's true
+    hits)."""
+    F = w.cuts.first_layer
+    n = e.eb.n_seeds
+    t = e.eb.true_hits[F:, :n]
+    hp = out_plain["hits"].cpu().numpy()[:, :n]
+    hl = out_learned["hits"].cpu().numpy()[:, :n]
+    found_p = (hp == t) & (t >= 0)
+    lost = int(np.sum(found_p & (hl != t)))
+    return lost, lost / max(int(found_p.sum()), 1)
+
+
 def dump_rows(w, e: EventOnGPU, capacity=3_000_000, state=kf.STATE_CARTESIAN) -> np.ndarray:
     """Training rows from the plain FP32 build in the given state (the
     features are the Cartesian prediction in either state)."""
@@ -111,27 +125,25 @@ def dump_rows(w, e: EventOnGPU, capacity=3_000_000, state=kf.STATE_CARTESIAN) ->
     torch.cuda.synchronize()
     k = min(int(cnt.item()), capacity)
     rows = dump[:k].cpu().numpy()
-    # a deterministic order (the dump order depends on scheduling)
-    key = rows[:, 29].view(np.int32).astype(np.int64) * 4096 + rows[:, 30].view(np.int32) * 16 + \
-        rows[:, 31].view(np.int32)
-    return rows[np.argsort(key, kind="stable")]
+    # a deterministic order (the dump order depends on scheduling): by the
+    # row's (seed, layer, slot) word
+    return rows[np.argsort(rows[:, 31].view(np.uint32), kind="stable")]
+
+
+def row_ids(rows):
+    """(seed, layer, slot) of dumped rows."""
+    v = rows[:, 31].view(np.uint32)
+    return (v >> 8).astype(np.int64), ((v >> 3) & 31).astype(np.int64), (v & 7).astype(np.int64)
 
 
 def plain_widths(w, rows):
-    """Plain half-widths (arc at the layer radius, z; cm) of dumped rows, from
-    their predicted state and covariance: nsigma * sqrt(H P H^T + diag(
-    win_sig^2)) as the builder forms them (covariance entries in upper-
-    triangle order: 0 = xx, 1 = xy, 6 = yy, 11 = zz)."""
-    c = w.cuts
-    X = rows[:, :6].astype(np.float64)
-    P = rows[:, 6:27].astype(np.float64)
-    rr = np.hypot(X[:, 0], X[:, 1])
-    tx, ty = -X[:, 1] / rr, X[:, 0] / rr
-    suu = tx * tx * P[:, 0] + 2 * tx * ty * P[:, 1] + ty * ty * P[:, 6] + float(c.win_sig_rphi) ** 2
-    sww = P[:, 11] + float(c.win_sig_z) ** 2
-    # FP32 rows of a nearly singular covariance can round the projection
-    # below zero: those count as the narrowest window
-    return float(c.nsigma) * np.sqrt(np.maximum(suu, 0.0)), float(c.nsigma) * np.sqrt(np.maximum(sww, 0.0))
+    """Plain half-widths (arc at the layer radius, z; cm) of dumped rows, as
+    the builder formed them (it writes them into each row).  A nearly
+    singular FP32 covariance can round H P H^T below zero, which gives the
+    builder an undefined width, i.e. a window that admits no hit: those count
+    as the narrowest window."""
+    wr, wz = rows[:, 29].astype(np.float64), rows[:, 30].astype(np.float64)
+    return np.where(np.isfinite(wr), wr, 0.0), np.where(np.isfinite(wz), wz, 0.0)
 
 
 def gates(w, rows, quantile):

@@ -43,7 +43,7 @@ def test_binding_constants_match_header():
     assert kftrack.KF_OK == d["KF_OK"] and kftrack.KF_E_INVALID_ARG == d["KF_E_INVALID_ARG"]
     assert kftrack.KF_E_WORKSPACE == d["KF_E_WORKSPACE"] and kftrack.KF_E_HIP == d["KF_E_HIP"]
     assert kftrack.KF_E_UNSUPPORTED == d["KF_E_UNSUPPORTED"]
-    for k in ["NO_CROSSING", "OUT_OF_Z", "NONFINITE", "S_NOT_PD", "CAP_TRUNC"]:
+    for k in ["NO_CROSSING", "OUT_OF_Z", "NONFINITE", "S_NOT_PD", "CAP_TRUNC", "EVENT_TOO_LARGE"]:
         assert getattr(kftrack, "TRK_" + k) == d["KF_TRK_" + k]
     assert kftrack.LAYER_BARREL == d["KF_LAYER_BARREL"] and kftrack.LAYER_DISK == d["KF_LAYER_DISK"]
     assert kftrack.ARITH_F32 == d["KF_ARITH_F32"] and kftrack.ARITH_F64 == d["KF_ARITH_F64"]

@@ -377,3 +377,50 @@ def test_hybrid_state_build_efficiency(kf):
     eh = ((gh["hits"][:, :n] == true).sum(axis=0) / true.shape[0] >= 0.75).mean()
     print(f"build efficiency, {n} seeds: Cartesian {ec:.4f}, hybrid {eh:.4f}")
     assert eh >= ec
+
+
+def test_build_event_too_large(kf):
+    """Event-local hit indices are 24 bits wide: a seed whose event holds
+    2^24 binned hits is not built (status KF_TRK_EVENT_TOO_LARGE, no hits),
+    while the seeds of a normal event in the same launch are built exactly as
+    on their own."""
+    w = presets.build()
+    g = w.geometry
+    ev = datagen.generate(g, w.gen, 3, 300)
+    n0 = ev.n_tracks
+    big = 1 << 24
+    rng = np.random.default_rng(5)
+    ph = rng.uniform(0, 2 * np.pi, big)
+    R = g.r[5]
+    xyz1 = np.stack([R * np.cos(ph), R * np.sin(ph), rng.uniform(-100, 100, big)]).astype(np.float32)
+    del ph
+    cov1 = np.zeros((6, big), np.float32)
+    cov1[0] = cov1[3] = 1e-4
+    cov1[5] = 1e-2
+    xyz = np.concatenate([ev.xyz.astype(np.float32), xyz1], axis=1)
+    cov = np.concatenate([ev.cov.astype(np.float32), cov1], axis=1)
+    layer = np.concatenate([ev.layer, np.full(big, 5, np.int32)])
+    hoff = np.array([0, ev.n_hits, ev.n_hits + big], np.int32)
+    del xyz1, cov1
+    b = kf.hit_bin(g, 63, 16, to_dev(layer), to_dev(xyz), to_dev(cov), event_offsets=to_dev(hoff))
+    H = datagen.track_hits(ev)
+    s = kf.kf_seed(g, n0, to_dev(H))
+    ld = datagen.padded(n0 + 1)
+    sp = torch.zeros((6, ld), device="cuda:0")
+    sc = torch.zeros((21, ld), device="cuda:0")
+    q = torch.ones(ld, dtype=torch.int8, device="cuda:0")
+    sp[:, :n0], sc[:, :n0], q[:n0] = s["par"][:, :n0], s["cov"][:, :n0], s["q"][:n0]
+    sp[:, n0], sc[:, n0], q[n0] = s["par"][:, 0], s["cov"][:, 0], s["q"][0]
+    sev = torch.zeros(n0 + 1, dtype=torch.int32, device="cuda:0")
+    sev[n0] = 1
+    ex = kf.BuildExtra()
+    ex.seed_event = sev.data_ptr()
+    bp = kf.build_params(w.cuts, arith=kf.ARITH_F64)
+    out = kf.kf_build(g, bp, b, n0 + 1, sp, sc, q, extra=ex)
+    torch.cuda.synchronize()
+    o = {k: host(v) for k, v in out.items()}
+    del b
+    assert o["status"][n0] == kf.TRK_EVENT_TOO_LARGE and o["nhits"][n0] == 0 and np.all(o["hits"][:, n0] == -1)
+    ref, _ = gpu_build_event(kf, w, ev, kf.ARITH_F64, seeds=s)
+    for k in ("hits", "nhits", "status", "chi2", "par"):
+        assert np.array_equal(o[k][..., :n0], ref[k][..., :n0]), k

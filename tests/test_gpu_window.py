@@ -57,6 +57,29 @@ def test_training_reduces_loss(env):
     assert np.all(r[:, 27] >= 0) and np.all(r[:, 28] >= 0)
 
 
+def test_dump_rows_carry_the_plain_widths(env):
+    """The plain half-widths the builder writes into each row are
+    nsigma * sqrt(H P H^T + sigma^2) of the row's own prediction (arc along
+    the tangent at the predicted point, z)."""
+    w, r = env["w"], env["rows"]
+    c = w.cuts
+    X, P = r[:, :6].astype(np.float64), r[:, 6:27].astype(np.float64)
+    rr = np.hypot(X[:, 0], X[:, 1])
+    tx, ty = -X[:, 1] / rr, X[:, 0] / rr
+    suu = tx * tx * P[:, 0] + 2 * tx * ty * P[:, 1] + ty * ty * P[:, 6] + float(c.win_sig_rphi) ** 2
+    sww = P[:, 11] + float(c.win_sig_z) ** 2
+    # a nearly singular FP32 covariance can round the projection below zero:
+    # the builder's width is then undefined (a window admitting no hit); rare
+    fin = np.isfinite(r[:, 29]) & np.isfinite(r[:, 30])
+    assert fin.mean() > 0.999, fin.mean()
+    er = np.abs(r[fin, 29] - c.nsigma * np.sqrt(np.maximum(suu[fin], 0))) / (c.nsigma * c.win_sig_rphi)
+    wz = c.nsigma * np.sqrt(sww[fin])
+    ez = np.abs(r[fin, 30] - wz) / wz
+    # the widths agree to the FP32 rounding of the rows
+    assert np.median(er) < 1e-5 and np.percentile(er, 99.9) < 1e-2, (np.median(er), er.max())
+    assert ez.max() < 1e-5, ez.max()
+
+
 def test_hybrid_dump_rows_are_cartesian(env):
     """Rows dumped by the hybrid-state build carry the Cartesian prediction:
     on the first searched layer (predicted straight from the seed, where the
@@ -68,11 +91,14 @@ def test_hybrid_dump_rows_are_cartesian(env):
     F = w.cuts.first_layer
 
     def first(r):
-        lay, slot = r[:, 30].view(np.int32), r[:, 31].view(np.int32)
+        seed, lay, slot = window.row_ids(r)
         sel = (lay == F) & (slot == 0)
-        return r[sel][np.argsort(r[sel, 29].view(np.int32), kind="stable")]
+        return r[sel][np.argsort(seed[sel], kind="stable")]
     a, b = first(rc), first(rh)
-    assert a.shape[0] > 1000 and np.array_equal(a[:, 29:], b[:, 29:])
+    assert a.shape[0] > 1000 and np.array_equal(a[:, 31].view(np.uint32), b[:, 31].view(np.uint32))
+    # the plain widths, from the position block of either state's prediction
+    ew = np.abs(a[:, 29:31] - b[:, 29:31]) / np.abs(a[:, 29:31])
+    assert np.median(ew) < 1e-4 and np.percentile(ew, 99) < 1e-2, (np.median(ew), np.percentile(ew, 99))
     st = np.sqrt(np.abs(a[:, [6, 12, 17, 21, 24, 26]]))  # sigma of each parameter
     dx = np.abs(a[:, :6] - b[:, :6]) / np.maximum(st, 1e-30)
     ds = np.abs(a[:, 6:27] - b[:, 6:27]) / np.maximum(np.abs(a[:, 6:27]), 1e-30)

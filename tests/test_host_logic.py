@@ -48,25 +48,25 @@ def test_kf_build_workspace_bytes(kf):
     assert lib.kf_build_workspace_bytes(ctypes.byref(bp), ctypes.byref(hd), 100) == 0
 
 
-def test_plain_widths_and_gates():
+def test_gates_from_the_dumped_plain_widths():
+    """The gates are quantiles of the plain half-widths the builder writes
+    into each dumped row (columns 29 and 30); quantile 0 consults the network
+    everywhere."""
     from paper_1711_06571_amd import window
     w = presets.learned()
-    c = w.cuts
     rng = np.random.default_rng(3)
     n = 1000
     rows = np.zeros((n, 32), dtype=np.float32)
-    phi = rng.uniform(0, 2 * np.pi, n)
-    r = rng.uniform(4, 60, n)
-    rows[:, 0], rows[:, 1], rows[:, 2] = r * np.cos(phi), r * np.sin(phi), rng.uniform(-50, 50, n)
-    # an isotropic transverse position covariance s2 I and a z variance v
-    s2, v = rng.uniform(1e-6, 1e-2, n), rng.uniform(1e-4, 1.0, n)
-    rows[:, 6], rows[:, 12], rows[:, 17] = s2, s2, v  # P_xx, P_yy, P_zz in the row layout
+    rows[:, 29] = rng.uniform(0.01, 0.5, n)
+    rows[:, 30] = rng.uniform(0.3, 3.0, n)
+    rows[:, 31] = ((np.arange(n, dtype=np.uint32) << 8) | (5 << 3) | 2).view(np.float32)
     wr, wz = window.plain_widths(w, rows)
-    assert np.allclose(wr, c.nsigma * np.sqrt(s2 + c.win_sig_rphi ** 2), rtol=1e-5)
-    assert np.allclose(wz, c.nsigma * np.sqrt(v + c.win_sig_z ** 2), rtol=1e-5)
+    assert np.array_equal(wr, rows[:, 29].astype(np.float64)) and np.array_equal(wz, rows[:, 30].astype(np.float64))
     assert window.gates(w, rows, 0.0) == (0.0, 0.0)
     gr, gz = window.gates(w, rows, 0.9)
     assert np.mean(wr > gr) == pytest.approx(0.1, abs=0.01) and np.mean(wz > gz) == pytest.approx(0.1, abs=0.01)
+    seed, layer, slot = window.row_ids(rows)
+    assert np.array_equal(seed, np.arange(n)) and np.all(layer == 5) and np.all(slot == 2)
 
 
 def test_autotune_choice():
@@ -76,3 +76,27 @@ def test_autotune_choice():
     assert choose(pts, 0.001) is pts[1]  # cap 4 loses 0.46 % > 0.1 %
     assert choose(pts, 0.01) is pts[2]
     assert choose(pts[2:], 0.001) is pts[3]  # no cap-6 point: the best efficiency is the reference
+
+
+def test_autotune_cache_round_trip(tmp_path, monkeypatch):
+    """The autotuner's choice is written to the cache per arithmetic (merged
+    with what is there) and read back by the binding; the cap stays out of
+    the launch parameters."""
+    from paper_1711_06571_amd import kftrack as kf
+    from paper_1711_06571_amd.batch import TunePoint, TuneResult, save_cache
+    path = str(tmp_path / "autotune.json")
+    r64 = TuneResult(points=[TunePoint(256, 2, 6, 64, 24.1, 0.803, 21.0, 22.0)], gpu="gfx950")
+    r64.best = r64.points[0]
+    r32 = TuneResult(points=[TunePoint(128, 0, 6, 32, 19.0, 0.803, 15.0, 16.0)], gpu="gfx950")
+    r32.best = r32.points[0]
+    save_cache(r64, kf.ARITH_F64, path, "batch")
+    save_cache(r32, kf.ARITH_F32, path, "batch")
+    monkeypatch.setattr(kf, "TUNE_CACHE", path)
+    monkeypatch.setattr(kf, "_tune", None)
+    t64, t32 = kf.tuned_launch(kf.ARITH_F64), kf.tuned_launch(kf.ARITH_F32)
+    assert (t64["lanes_per_block"], t64["blocks_per_cu"], t64["phi_refine"]) == (256, 2, 64)
+    assert (t32["lanes_per_block"], t32["blocks_per_cu"], t32["phi_refine"]) == (128, 0, 32)
+    assert "cap" not in t64
+    monkeypatch.setattr(kf, "TUNE_CACHE", str(tmp_path / "missing.json"))
+    monkeypatch.setattr(kf, "_tune", None)
+    assert kf.tuned_launch(kf.ARITH_F64) is None
