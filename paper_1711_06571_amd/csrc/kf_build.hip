@@ -108,25 +108,14 @@ struct BuildArgs {
 // chosen hit runs in the arithmetic of the mode.
 // pairs per lane per round of the hit search (at most; FP64 builds take one)
 constexpr int NP = 2;
-// hit search from LDS tiles of the hits the wave's candidates need (1), or
-// straight from the packed hits in global memory (0)
-#ifndef KF_HIT_TILE
-#define KF_HIT_TILE 0
-#endif
-// hits per tile piece (a multiple of 64): TILE in plain builds (a region of
-// its own), TILE_LEARNED in learned builds, where the tile shares the
-// network's activation buffer with the hit lists (the network runs first)
-constexpr int TILE = 128;
-constexpr int TILE_LEARNED = 64;
 
-template <typename T, int TILE_N>
+
+template <typename T>
 __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, const T Xp[6], const T Pp[21],
-                                 T dphi_w, T dz_w, TopList& tl, const AccBuf& ab, float4* tile, int lane) {
-#if !KF_HIT_TILE
+                                 T dphi_w, T dz_w, TopList& tl, const AccBuf& ab, int lane) {
   // FP32 builds take NP pairs per lane and round, FP64 builds (short of
   // registers) one
   constexpr int NPT = sizeof(T) == 4 ? NP : 1;
-#endif
   const int nz = A.n_z, nf = A.n_phi * A.refine;
   const float inv = fine_inv(nf);
   const float tp = 6.283185307179586f;
@@ -202,163 +191,6 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
       }
     }
   };
-#if KF_HIT_TILE
-  // Per range r the candidates' intervals of sorted positions are merged
-  // across the wave (sorted by start, overlapping or touching ones joined),
-  // so every hit some candidate needs is fetched once: in pieces of TILE_N hits,
-  // 64 per instruction straight into LDS (three 16-byte planes), and the
-  // (candidate, hit) pairs read their hits from there.  Tile index of
-  // position p in a candidate's interval: p + delta of the candidate's run.
-  for (int r = 0; r < Rmax; ++r) {
-    float a, b;
-    int q0, q1;
-    range_of(r, a, b, q0, q1);
-    const int cnt = q1 > q0 ? q1 - q0 : 0;
-    int key = cnt > 0 ? q0 : 0x7fffffff, kend = cnt > 0 ? q1 : 0x7fffffff, who = lane;
-#pragma unroll
-    for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        const int pk = __shfl_xor(key, j, 64), pe = __shfl_xor(kend, j, 64), pw = __shfl_xor(who, j, 64);
-        const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
-        const bool less = pk < key || (pk == key && pw < who);
-        if (keep_min == less) {
-          key = pk;
-          kend = pe;
-          who = pw;
-        }
-      }
-    }
-    const bool vs = key != 0x7fffffff;
-    const int pm = wave_incl_max(vs ? kend : -1, lane);
-    const int pm_prev = __shfl_up(pm, 1, 64);
-    const bool is_start = vs && (lane == 0 || key > pm_prev);
-    const int rs_q0 = wave_incl_max(is_start ? key : -1, lane);
-    const bool next_breaks = __shfl_down((int)(is_start || !vs), 1, 64) != 0;
-    const bool is_end = vs && (lane == 63 || next_breaks);
-    int M = 0;
-    const int toff = wave_excl_scan(is_end ? pm - rs_q0 : 0, lane, M);
-    const int delta = toff - rs_q0;
-    const int my_delta = __builtin_amdgcn_ds_permute(who << 2, delta);
-    const unsigned long long starts = __ballot(is_start);
-    for (int pl = 0; pl < M; pl += TILE_N) {
-      const int pe = M < pl + TILE_N ? M : pl + TILE_N;
-      // stage tile indices [pl, pe): index t belongs to the last run that
-      // starts at or before it
-      for (int t0 = pl; t0 < pe; t0 += 64) {
-        ab.start[lane] = 0x7fffffff;
-        __builtin_amdgcn_wave_barrier();
-        if (is_start && toff > t0 && toff < t0 + 64) ab.start[toff - t0] = delta;
-        const unsigned long long le = starts & __ballot(toff <= t0);
-        const int dcarry = __shfl(delta, 63 - (int)__builtin_clzll(le), 64);
-        __builtin_amdgcn_wave_barrier();
-        const int mk = ab.start[lane];
-        const unsigned long long mm = __ballot(mk != 0x7fffffff) & ((2ull << lane) - 1ull);
-        const int dm = __shfl(mk, mm ? 63 - (int)__builtin_clzll(mm) : 0, 64);
-        const int d = mm ? dm : dcarry;
-        const int t = t0 + lane;
-        if (t < pe) {
-          const float4* src = A.hpack + (size_t)(t - d) * 3;
-#pragma unroll
-          for (int k = 0; k < 3; ++k)
-            __builtin_amdgcn_global_load_lds((const void*)(src + k),
-                                             (__attribute__((address_space(3))) void*)(tile + k * TILE_N + (t0 - pl)),
-                                             16, 0, 0);
-        }
-      }
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      __builtin_amdgcn_wave_barrier();
-      // this piece's pairs: each candidate's tile interval cut to [pl, pe)
-      const int cs = q0 + my_delta, ce = q1 + my_delta;
-      const int s0 = cs > pl ? cs : pl, e0 = ce < pe ? ce : pe;
-      const int cntp = (cnt > 0 && e0 > s0) ? e0 - s0 : 0;
-      int total = 0;
-      const int off = wave_excl_scan(cntp, lane, total);
-      const int pb = s0 - off;  // tile index of this candidate's pair k: pb + k
-      int carry = 0;
-      for (int base = 0; base < total; base += 64) {
-        ab.start[lane] = -1;
-        if (cntp > 0 && off >= base && off - base < 64) ab.start[off - base] = lane;
-        __builtin_amdgcn_wave_barrier();
-        const int st = ab.start[lane];
-        const unsigned long long sm = __ballot(st >= 0) & ((2ull << lane) - 1ull);
-        const int hb = sm ? 63 - (int)__builtin_clzll(sm) : 0;
-        const int sc = __shfl(st, hb, 64);
-        const int c = sm ? sc : carry;
-        const int my_lo = sm ? hb : 0;
-        carry = __builtin_amdgcn_readlane(c, 63);
-        const int k = base + lane;
-        const bool valid = k < total;
-        const int tix = __shfl(pb, c, 64) + k;
-        const int p = tix - __shfl(my_delta, c, 64);  // sorted position of the hit
-        const float ca = __shfl(a, c, 64), cb = __shfl(b, c, 64);
-        const float cx = __shfl(fx, c, 64), cy = __shfl(fy, c, 64), cz = __shfl(fz, c, 64);
-        const float cdz = __shfl(fdz, c, 64), cdphi = __shfl(fdphi, c, 64), ctan = __shfl(ftan, c, 64);
-        const float cirr = __shfl(firr, c, 64), csuu = __shfl(suu, c, 64), csuw = __shfl(suw, c, 64);
-        const float csww = __shfl(sww, c, 64), cthr = __shfl(thr_c2, c, 64);
-        const uint32_t cthro = (uint32_t)__shfl((int)thr_o, c, 64);
-        const int ti = valid ? tix - pl : 0;
-        const float4 u0 = tile[ti], u1 = tile[TILE_N + ti], u2 = tile[2 * TILE_N + ti];
-        bool keep = false;
-        float c2 = 0.f;
-        uint32_t orig = 0;
-        if (valid && u0.x >= ca && u0.x <= cb) {
-          tl.scanned += 1;
-          const float hx = u0.y, hy = u0.z, hz = u0.w;
-          const float cr = cx * hy - cy * hx, dt = cx * hx + cy * hy;
-          const bool in_phi = ctan < 0.f ? fabsf(atan2f(cr, dt)) <= cdphi : (dt > 0.f && fabsf(cr) <= ctan * dt);
-          if (fabsf(hz - cz) <= cdz && in_phi) {
-            tl.tested += 1;
-            const float ctx = -cy * cirr, cty = cx * cirr;
-            const float r0 = ctx * (hx - cx) + cty * (hy - cy), r1 = hz - cz;
-            const float s00 = csuu + ctx * ctx * u1.x + 2.f * ctx * cty * u1.y + cty * cty * u1.w;
-            const float s01 = csuw + ctx * u1.z + cty * u2.x;
-            const float s11 = csww + u2.y;
-            const float det = s00 * s11 - s01 * s01;
-            if (s00 > 0.f && det > 0.f) {
-              c2 = (s11 * r0 * r0 - 2.f * s01 * r0 * r1 + s00 * r1 * r1) / det;
-              if (c2 < cut) {
-                atomicAdd(&ab.tot[c], 1);
-                orig = __float_as_uint(u2.z);
-                keep = top_before(c2, orig, cthr, cthro);
-              }
-            }
-          }
-        }
-        unsigned long long m = __ballot(keep);
-        if (m) {
-          const int s0r = off - base > 0 ? off - base : 0;
-          const int e0r = off + cntp - base < 64 ? off + cntp - base : 64;
-          do {
-            int j = 64;
-            if (s0r < e0r) {
-              const unsigned long long mmk = m >> s0r;
-              if (mmk) {
-                j = s0r + (int)__builtin_ctzll(mmk);
-                if (j >= e0r) j = 64;
-              }
-            }
-            const int js = j & 63;
-            const float jc2 = __shfl(c2, js, 64);
-            const int jp = __shfl(p, js, 64);
-            const uint32_t jo = (uint32_t)__shfl((int)orig, js, 64);
-            if (j < 64) lds_insert(tl, A.cap, held, jc2, jp, jo);
-            const bool first = ((m >> lane) & 1ull) && ((m >> my_lo) & ((1ull << (lane - my_lo)) - 1ull)) == 0;
-            m &= ~__ballot(first);
-          } while (m);
-          if (held == A.cap) {
-            thr_c2 = tl.c2[(A.cap - 1) * 64];
-            thr_o = tl.orig[(A.cap - 1) * 64];
-          }
-        }
-      }
-      // every read of this piece has returned before the next piece's loads
-      // overwrite the tile
-      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-      __builtin_amdgcn_wave_barrier();
-    }
-  }
-#else
 
   float an = 1.f, bn = 0.f;
   int p0n = 0, p1n = 0;
@@ -515,7 +347,6 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
       }
     }
   }
-#endif
   tl.n = held;
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
@@ -529,13 +360,10 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
 //   toplist  [cap][64] f32 chi2, then [cap][64] i32 positions, [cap][64] u32 indices
 //   accept   [64] i32 accepted hits per candidate, [64 NP] i32 run starts
 //            (the cooperative hit search)
-//   tile     [3][TILE] float4 hits staged for the hit search (plain builds;
-//            learned builds stage [3][TILE_LEARNED] after the hit lists in
-//            the network's buffer)
 //   mlp      activation buffer of the learned window (the network runs before
 //            the hit search, so the toplists of a learned build live in it)
 struct LdsPlan {
-  size_t stash, rec, recf, acc, tile, tl, tl_stride, mlp, total;
+  size_t stash, rec, recf, acc, tl, tl_stride, mlp, total;
 };
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 __host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsize, bool learned) {
@@ -548,11 +376,9 @@ __host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsi
   (void)tsize;
   const size_t tl_wave = (size_t)cap * 64 * 12;
   p.acc = align16(p.recf + (size_t)nwaves * seeds * 5 * 4);
-  p.tile = align16(p.acc + (size_t)nwaves * (64 + 64 * NP) * 4);
-  p.tl = align16(p.tile + ((KF_HIT_TILE && !learned) ? (size_t)nwaves * 3 * TILE * 16 : 0));
+  p.tl = align16(p.acc + (size_t)nwaves * (64 + 64 * NP) * 4);
   if (learned) {
-    const size_t need = tl_wave + (KF_HIT_TILE ? (size_t)3 * TILE_LEARNED * 16 : 0);
-    const size_t per = need > KFMLP_LDS_BYTES ? need : (size_t)KFMLP_LDS_BYTES;
+    const size_t per = tl_wave > KFMLP_LDS_BYTES ? tl_wave : (size_t)KFMLP_LDS_BYTES;
     p.mlp = p.tl;
     p.total = p.mlp + (size_t)nwaves * per;
     p.tl_stride = per;
@@ -605,8 +431,6 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
   AccBuf ab;
   ab.tot = (int32_t*)(base + lp.acc) + (size_t)wave * (64 + 64 * NP);
   ab.start = ab.tot + 64;
-  // learned builds: the tile follows the hit lists in the network's buffer
-  float4* tile = LEARNED ? (float4*)(wave_tl + (size_t)S * 64 * 12) : (float4*)(base + lp.tile) + (size_t)wave * 3 * TILE;
   (void)mlp_buf;
   const int sidx = lane / S, slot = lane - (lane / S) * S, sbase = sidx * S;
   const bool lane_used = sidx < SEEDS;
@@ -782,7 +606,7 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
         }
       }
       const T dphi_w = pok ? w_rphi / R : T(0), dz_w = pok ? w_z : T(0);
-      coop_scan<T, LEARNED ? TILE_LEARNED : TILE>(A, ev, l, pok, Xp, Pp, dphi_w, dz_w, tl, ab, tile, lane);
+      coop_scan<T>(A, ev, l, pok, Xp, Pp, dphi_w, dz_w, tl, ab, lane);
       cnt_pred += live ? 1u : 0u;
       cnt_scan += (unsigned)tl.scanned;
       cnt_chi2 += (unsigned)tl.tested;

@@ -159,16 +159,6 @@ __device__ inline int wave_excl_scan(int v, int lane, int& total) {
   return x - v;
 }
 
-// Wave-wide inclusive prefix maximum.
-__device__ inline int wave_incl_max(int v, int lane) {
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int t = __shfl_up(v, d, 64);
-    if (lane >= d) v = t > v ? t : v;
-  }
-  return v;
-}
-
 __device__ inline int wave_max(int v) {
 #pragma unroll
   for (int m = 1; m < 64; m <<= 1) {
