@@ -221,6 +221,38 @@ def batched(arith, autotune, log):
     return res
 
 
+def practical_peaks():
+    """What the device sustains on the two roofline axes: a plain 1 GiB
+    device copy (bytes read + written per second) and FMA chains in FP64 and
+    FP32 (packed FP32 disabled, as in the library's kernels)."""
+    import torch
+    from paper_1711_06571_amd import kftrack as kf
+    st = torch.cuda.current_stream()
+    n = (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(5):
+        dst.copy_(src)
+    b.record(st)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * n * 4 * 5 / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    res = {"hbm_copy_gbs": round(copy_gbs, 1)}
+    blocks, iters = 8192, 4096
+    for name, ar, dt in (("f64", kf.ARITH_F64, torch.float64), ("f32", kf.ARITH_F32, torch.float32)):
+        out = torch.empty(blocks * 256, dtype=dt, device="cuda:0")
+        kf.kf_peak_fma(ar, blocks, iters, out)
+        a.record(st)
+        kf.kf_peak_fma(ar, blocks, iters, out)
+        b.record(st)
+        torch.cuda.synchronize()
+        res[f"fma_{name}_tflops"] = round(blocks * 256.0 * iters * 8 * 2 / (a.elapsed_time(b) * 1e-3) / 1e12, 2)
+    return res
+
+
 def fit_latency(arith, reps=50):
     """Latency of one kf_fit call on the small fit workload (1 event, 1 000
     tracks, 10 layers, fit over layers 4..10): median of HIP-event times
@@ -617,6 +649,7 @@ def main():
                            "fit_status_ok": round(float(np.mean(fout["status"].cpu().numpy()[:n] == 0)), 4)}
     log = lambda m: print(m, file=sys.stderr, flush=True)
     res["fit_small_latency"] = fit_latency(arith)
+    res["practical_peaks"] = practical_peaks()
     if not args.no_learned:
         res["learned_vs_plain"] = learned_vs_plain([kf.ARITH_F32, kf.ARITH_F64], log)
     if not args.no_batch:

@@ -394,6 +394,13 @@ int kf_batch_plan_destroy(kf_batch_plan* plan);
 /* frequency of the device wall clock read by the build's completion ticks */
 int kf_wall_clock_khz(int32_t* khz);
 
+/* Practical vector peak (measurement support, not the method): `blocks`
+ * blocks of 256 lanes each run `iters` rounds of 8 independent fused
+ * multiply-adds in the arithmetic `arith` (2 flops each) and write one value
+ * per lane to out [blocks * 256] (float or double).  The caller times the
+ * launch. */
+int kf_peak_fma(int32_t arith, int32_t blocks, int32_t iters, void* out, void* stream);
+
 /*
  * General detector (section 4.1: the barrel of concentric cylinders closed
  * by endcap disks, "a cylinder with lids", and modules that sit off a

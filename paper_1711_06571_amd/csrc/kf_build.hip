@@ -96,7 +96,8 @@ struct BuildArgs {
 // lane shuffles.  Every hit whose stored phi lies in the candidate's interval
 // gets the exact window test (z first, then the angle about the axis);
 // in-window hits get their chi2; accepted hits (chi2 < cut) are counted for
-// their candidate and, if they can enter its list of the best cap (a full
+// their candidate (a ballot over its run of lanes: a candidate's pairs occupy
+// consecutive lanes) and, if they can enter its list of the best cap (a full
 // list admits only hits that rank before its last entry), handed to the
 // candidate's lane, which inserts them.  The order of insertion does not
 // change a list (the ranking is total), so the result equals a serial scan.
@@ -108,8 +109,6 @@ struct BuildArgs {
 // chosen hit runs in the arithmetic of the mode.
 // pairs per lane per round of the hit search (at most; FP64 builds take one)
 constexpr int NP = 2;
-
-
 template <typename T>
 __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, const T Xp[6], const T Pp[21],
                                  T dphi_w, T dz_w, TopList& tl, const AccBuf& ab, int lane) {
@@ -151,7 +150,8 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
       else if (hi >= tp) { a0 = lo; b0v = tp; a1 = 0.f; b1v = hi - tp; }
       else { a0 = lo; b0v = hi; }
     }
-    ftan = !(dphi_w < T(1.5707963267948966)) ? -1.f : (float)k_tan(dphi_w);
+    // (the angle test runs in FP32: so does the tangent of its bound)
+    ftan = !(dphi_w < T(1.5707963267948966)) ? -1.f : tanf((float)dphi_w);
     const T rr = k_sqrt(Xp[0] * Xp[0] + Xp[1] * Xp[1]);
     const T irr = k_rcp(rr);
     const T tx = -Xp[1] * irr, ty = Xp[0] * irr;
@@ -166,7 +166,7 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
   const int nint = a1 <= b1v ? 2 : 1;
   const int R = pok ? (iz1 - iz0 + 1) * nint : 0;
   const int Rmax = wave_max(R);
-  ab.tot[lane] = 0;
+  int n_acc = 0;  // accepted hits of this lane's candidate
   int held = 0;  // entries in the list
   // the candidate's admission threshold: its last entry once its list is
   // full (before, +inf admits every accepted hit)
@@ -274,12 +274,13 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
       for (int h = 0; h < NPT; ++h)
         asm volatile("" ::"v"(ph[h]), "v"(hx[h]), "v"(hy[h]), "v"(hz[h]), "v"(V[h][0]), "v"(V[h][1]), "v"(V[h][2]),
                      "v"(V[h][3]), "v"(V[h][4]), "v"(V[h][5]), "v"(forig[h]));
-      bool keep[NPT];
+      bool keep[NPT], acc[NPT];
       float c2[NPT];
       uint32_t orig[NPT];
 #pragma unroll
       for (int h = 0; h < NPT; ++h) {
         keep[h] = false;
+        acc[h] = false;
         c2[h] = 0.f;
         orig[h] = 0;
         if (valid[h] && ph[h] >= ca[h] && ph[h] <= cb[h]) {
@@ -299,7 +300,7 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
             if (s00 > 0.f && det > 0.f) {
               c2[h] = (s11 * r0 * r0 - 2.f * s01 * r0 * r1 + s00 * r1 * r1) / det;
               if (c2[h] < cut) {
-                atomicAdd(&ab.tot[c[h]], 1);
+                acc[h] = true;
                 orig[h] = forig[h];
                 keep[h] = top_before(c2[h], orig[h], cthr[h], cthro[h]);
               }
@@ -313,12 +314,15 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
       // number the most hits any one candidate has in the half
 #pragma unroll
       for (int h = 0; h < NPT; ++h) {
+        // this lane's run as a candidate in the half: lanes [s0, e0)
+        const int bh = base + 64 * h;
+        const int s0 = off - bh > 0 ? off - bh : 0;
+        const int e0 = off + cnt - bh < 64 ? off + cnt - bh : 64;
+        // accepted hits of each candidate: the accepted lanes of its run
+        const unsigned long long am = __ballot(acc[h]);
+        if (s0 < e0) n_acc += __builtin_popcountll((am >> s0) & (e0 - s0 == 64 ? ~0ull : ((1ull << (e0 - s0)) - 1ull)));
         unsigned long long m = __ballot(keep[h]);
         if (m) {
-          // this lane's run as a candidate in the half
-          const int bh = base + 64 * h;
-          const int s0 = off - bh > 0 ? off - bh : 0;
-          const int e0 = off + cnt - bh < 64 ? off + cnt - bh : 64;
           do {
             int j = 64;
             if (s0 < e0) {
@@ -350,7 +354,7 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
   tl.n = held;
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
-  tl.tot = ab.tot[lane];
+  tl.tot = n_acc;
 }
 
 // LDS of one block (byte offsets), per wave:
@@ -358,8 +362,7 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
 //   record   [SEEDS][27] f32   best finished candidate of each seed
 //   recfield [SEEDS][5] i32    valid, nhits, status, last layer, slot
 //   toplist  [cap][64] f32 chi2, then [cap][64] i32 positions, [cap][64] u32 indices
-//   accept   [64] i32 accepted hits per candidate, [64 NP] i32 run starts
-//            (the cooperative hit search)
+//   starts   [64 NP] i32 run starts of the cooperative hit search
 //   mlp      activation buffer of the learned window (the network runs before
 //            the hit search, so the toplists of a learned build live in it)
 struct LdsPlan {
@@ -376,7 +379,7 @@ __host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsi
   (void)tsize;
   const size_t tl_wave = (size_t)cap * 64 * 12;
   p.acc = align16(p.recf + (size_t)nwaves * seeds * 5 * 4);
-  p.tl = align16(p.acc + (size_t)nwaves * (64 + 64 * NP) * 4);
+  p.tl = align16(p.acc + (size_t)nwaves * 64 * NP * 4);
   if (learned) {
     const size_t per = tl_wave > KFMLP_LDS_BYTES ? tl_wave : (size_t)KFMLP_LDS_BYTES;
     p.mlp = p.tl;
@@ -429,8 +432,7 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
   int32_t* tl_pos = (int32_t*)(wave_tl + (size_t)S * 64 * 4) + lane;
   uint32_t* tl_orig = (uint32_t*)(wave_tl + (size_t)S * 64 * 8) + lane;
   AccBuf ab;
-  ab.tot = (int32_t*)(base + lp.acc) + (size_t)wave * (64 + 64 * NP);
-  ab.start = ab.tot + 64;
+  ab.start = (int32_t*)(base + lp.acc) + (size_t)wave * 64 * NP;
   (void)mlp_buf;
   const int sidx = lane / S, slot = lane - (lane / S) * S, sbase = sidx * S;
   const bool lane_used = sidx < SEEDS;

@@ -158,7 +158,7 @@ __device__ inline uint32_t det_hist(int parent, int layer, uint32_t orig24) {
 //                           (step 1), read by the lanes that test its hits
 //   record   [SEEDS][27] f32, recfield [SEEDS][5] i32 (valid, nhits, status,
 //                           last step, slot)
-//   accept   [128] i32      accepted hits per candidate, run starts
+//   starts   [64] i32       run starts of the cooperative hit search
 //   toplist  [cap][64] f32 chi2, i32 positions, u32 indices
 struct DetLds {
   size_t stash, cand, rec, recf, acc, tl, total;
@@ -172,7 +172,7 @@ __host__ __device__ inline DetLds det_lds(int nwaves, int cap) {
   p.rec = al16(p.cand + (size_t)nwaves * 27 * 64 * 4);
   p.recf = al16(p.rec + (size_t)nwaves * seeds * 27 * 4);
   p.acc = al16(p.recf + (size_t)nwaves * seeds * 5 * 4);
-  p.tl = al16(p.acc + (size_t)nwaves * 128 * 4);
+  p.tl = al16(p.acc + (size_t)nwaves * 64 * 4);
   p.total = al16(p.tl + (size_t)nwaves * cap * 64 * 12);
   return p;
 }
@@ -319,13 +319,13 @@ __device__ inline void coop_scan_det(const DetBuildArgs& A, int ev, int lj, int 
       else if (phi_ >= tp) { a0 = plo; b0v = tp; a1 = 0.f; b1v = phi_ - tp; }
       else { a0 = plo; b0v = phi_; }
     }
-    ftan = !(dphi_w < T(1.5707963267948966)) ? -1.f : (float)k_tan(dphi_w);
+    ftan = !(dphi_w < T(1.5707963267948966)) ? -1.f : tanf((float)dphi_w);
   }
   const int32_t* frow = A.fine + ((size_t)ev * A.d.n_layers + (pok ? lj : 0)) * nw * (nf + 1);
   const int nint = a1 <= b1v ? 2 : 1;
   const int R = pok ? (iw1 - iw0 + 1) * nint : 0;
   const int Rmax = wave_max(R);
-  ab.tot[lane] = 0;
+  int n_acc = 0;  // accepted hits of this lane's candidate
   int held = 0;
   float thr_c2 = __builtin_inff();
   uint32_t thr_o = 0xFFFFFFFFu;
@@ -382,7 +382,7 @@ __device__ inline void coop_scan_det(const DetBuildArgs& A, int ev, int lj, int 
       const int p_first = __builtin_amdgcn_readfirstlane(__shfl(p, 0, 64));
       const float4* hp = A.hpack + (size_t)(valid ? p : p_first) * 3;
       const float4 u0 = hp[0], u1 = hp[1], u2 = hp[2];
-      bool keep = false;
+      bool keep = false, acc = false;
       float c2 = 0.f;
       uint32_t orig = 0;
       if (valid && u0.x >= ca && u0.x <= cb) {
@@ -402,16 +402,20 @@ __device__ inline void coop_scan_det(const DetBuildArgs& A, int ev, int lj, int 
           const bool ok = ckind == KIND_DISK ? pair_chi2<true>(Xc, Pc, cq, bz, hx, hy, hz, V, c2)
                                              : pair_chi2<false>(Xc, Pc, cq, bz, hx, hy, hz, V, c2);
           if (ok && c2 < cut) {
-            atomicAdd(&ab.tot[c], 1);
+            acc = true;
             orig = __float_as_uint(u2.z);
             keep = top_before(c2, orig, cthr, cthro);
           }
         }
       }
+      // this lane's run as a candidate in the round: lanes [s0, e0); its
+      // accepted hits are the accepted lanes of the run
+      const int s0 = off - base > 0 ? off - base : 0;
+      const int e0 = off + cnt - base < 64 ? off + cnt - base : 64;
+      const unsigned long long am = __ballot(acc);
+      if (s0 < e0) n_acc += __builtin_popcountll((am >> s0) & (e0 - s0 == 64 ? ~0ull : ((1ull << (e0 - s0)) - 1ull)));
       unsigned long long m = __ballot(keep);
       if (m) {
-        const int s0 = off - base > 0 ? off - base : 0;
-        const int e0 = off + cnt - base < 64 ? off + cnt - base : 64;
         do {
           int j = 64;
           if (s0 < e0) {
@@ -439,7 +443,7 @@ __device__ inline void coop_scan_det(const DetBuildArgs& A, int ev, int lj, int 
   tl.n = held;
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
-  tl.tot = ab.tot[lane];
+  tl.tot = n_acc;
 }
 
 #ifndef KF_BUILD_DET_WAVES
@@ -467,8 +471,7 @@ __global__ void __launch_bounds__(256, KF_BUILD_DET_WAVES) build_det_kernel(DetB
   int32_t* tl_pos = (int32_t*)(wave_tl + (size_t)S * 64 * 4) + lane;
   uint32_t* tl_orig = (uint32_t*)(wave_tl + (size_t)S * 64 * 8) + lane;
   AccBuf ab;
-  ab.tot = (int32_t*)(base + lp.acc) + (size_t)wave * 128;
-  ab.start = ab.tot + 64;
+  ab.start = (int32_t*)(base + lp.acc) + (size_t)wave * 64;
   const int sidx = lane / S, slot = lane - (lane / S) * S, sbase = sidx * S;
   const bool lane_used = sidx < SEEDS;
   const T bz = (T)A.d.bz, x0 = (T)A.d.x_over_x0, mass = (T)A.d.mass;

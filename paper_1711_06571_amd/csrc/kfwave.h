@@ -168,10 +168,9 @@ __device__ inline int wave_max(int v) {
   return v;
 }
 
-// Per-wave LDS of the cooperative hit search: each candidate's count of
-// accepted hits, and per round the candidate whose pairs start at each lane.
+// Per-wave LDS of the cooperative hit search: per round, the candidate
+// whose pairs start at each lane.
 struct AccBuf {
-  int32_t* tot;
   int32_t* start;
 };
 

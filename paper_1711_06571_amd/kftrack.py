@@ -131,6 +131,7 @@ def lib():
         L.kf_build_noalloc.argtypes = list(L.kf_build.argtypes[:15]) + [P]
         L.kf_build_noalloc_max_bytes.restype = ctypes.c_size_t
         L.kf_build_noalloc_max_bytes.argtypes = []
+        L.kf_peak_fma.argtypes = [I, I, I, P, P]
         L.hit_bin_det.argtypes = [ctypes.POINTER(Detector)] + list(L.hit_bin.argtypes[1:])
         L.kf_fit_det.argtypes = [ctypes.POINTER(Detector), I, I, I, P, P, P, P, P, P, P, P, P, P, P, I, P]
         L.kf_build_det.argtypes = [ctypes.POINTER(Detector), ctypes.POINTER(BuildParams), ctypes.POINTER(Hits), I,
@@ -467,6 +468,11 @@ def kf_build_noalloc(g, bp, binned: BinnedHits, n_seeds, seed_par, seed_cov, q, 
 
 def kf_build_noalloc_max_bytes() -> int:
     return int(lib().kf_build_noalloc_max_bytes())
+
+
+def kf_peak_fma(arith, blocks, iters, out, stream=None):
+    """Launch the FMA-chain kernel (8 chains x iters x 2 flops per lane)."""
+    _check(lib().kf_peak_fma(arith, blocks, iters, _ptr(out), _stream(stream)))
 
 
 def kf_build_last_launch() -> dict:
