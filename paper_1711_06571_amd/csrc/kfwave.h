@@ -148,24 +148,50 @@ __device__ inline void top_get(const TopList& tl, int k, float& c2, int& pos, ui
 }
 
 // Wave-wide inclusive prefix sum; returns the exclusive prefix, total via ref.
+// Wave-wide scans and reductions with DPP row operations (a lane reads a
+// neighbour's register through the VALU's data-parallel primitives, a few
+// cycles, where a shuffle goes through the LDS crossbar): shifts by 1, 2, 4,
+// 8 inside each row of 16 lanes, then lane 15 of a row into the next row and
+// lane 31 into rows 2 and 3.  A lane whose source lies outside its row keeps
+// the identity (`old`).
+template <int CTRL, int ROWS>
+__device__ inline int dpp_or(int old, int x) {
+  return __builtin_amdgcn_update_dpp(old, x, CTRL, ROWS, 0xf, false);
+}
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+
+// Wave-wide inclusive prefix sum; returns the exclusive prefix, total via ref.
 __device__ inline int wave_excl_scan(int v, int lane, int& total) {
+  (void)lane;
   int x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int t = __shfl_up(x, d, 64);
-    if (lane >= d) x += t;
-  }
-  total = __shfl(x, 63, 64);
+  x += dpp_or<kRowShr1, 0xf>(0, x);
+  x += dpp_or<kRowShr2, 0xf>(0, x);
+  x += dpp_or<kRowShr4, 0xf>(0, x);
+  x += dpp_or<kRowShr8, 0xf>(0, x);
+  x += dpp_or<kRowBcast15, 0xa>(0, x);
+  x += dpp_or<kRowBcast31, 0xc>(0, x);
+  total = __builtin_amdgcn_readlane(x, 63);
   return x - v;
 }
 
+// Wave-wide maximum (the running maximum's last lane, read by every lane).
 __device__ inline int wave_max(int v) {
-#pragma unroll
-  for (int m = 1; m < 64; m <<= 1) {
-    const int o = __shfl_xor(v, m, 64);
-    v = o > v ? o : v;
-  }
-  return v;
+  constexpr int lo = -2147483647 - 1;
+  int x = v;
+  int t = dpp_or<kRowShr1, 0xf>(lo, x);
+  x = t > x ? t : x;
+  t = dpp_or<kRowShr2, 0xf>(lo, x);
+  x = t > x ? t : x;
+  t = dpp_or<kRowShr4, 0xf>(lo, x);
+  x = t > x ? t : x;
+  t = dpp_or<kRowShr8, 0xf>(lo, x);
+  x = t > x ? t : x;
+  t = dpp_or<kRowBcast15, 0xa>(lo, x);
+  x = t > x ? t : x;
+  t = dpp_or<kRowBcast31, 0xc>(lo, x);
+  x = t > x ? t : x;
+  return __builtin_amdgcn_readlane(x, 63);
 }
 
 // Per-wave LDS of the cooperative hit search: per round, the candidate

@@ -15,7 +15,12 @@ __global__ void __launch_bounds__(256) fma_kernel(int iters, T* __restrict__ out
   const T m = (T)0.9999999, c = (T)1e-9;
   for (int it = 0; it < iters; ++it) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) a[k] = __builtin_fma(a[k], m, c);
+    for (int k = 0; k < 8; ++k) {
+      if constexpr (sizeof(T) == 4)
+        a[k] = __builtin_fmaf(a[k], m, c);
+      else
+        a[k] = __builtin_fma(a[k], m, c);
+    }
   }
   T s = 0;
 #pragma unroll
