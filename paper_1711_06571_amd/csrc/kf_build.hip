@@ -215,6 +215,7 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
       if (cnt > 0 && off >= base && off - base < 64 * NPT) ab.start[off - base] = lane;
       __builtin_amdgcn_wave_barrier();
       int c[NPT], my_lo[NPT], p[NPT];
+      unsigned long long sma[NPT];  // the half's marks
       bool valid[NPT];
       float ca[NPT], cb[NPT], cx[NPT], cy[NPT], cz[NPT], cdz[NPT], cdphi[NPT], ctan[NPT], cirr[NPT], csuu[NPT], csuw[NPT],
           csww[NPT], cthr[NPT];
@@ -222,7 +223,8 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
 #pragma unroll
       for (int h = 0; h < NPT; ++h) {
         const int st = ab.start[h * 64 + lane];
-        const unsigned long long sm = __ballot(st >= 0) & ((2ull << lane) - 1ull);
+        sma[h] = __ballot(st >= 0);
+        const unsigned long long sm = sma[h] & ((2ull << lane) - 1ull);
         const int hb = sm ? 63 - (int)__builtin_clzll(sm) : 0;
         const int sc = __shfl(st, hb, 64);
         c[h] = sm ? sc : carry;
@@ -308,10 +310,7 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
           }
         }
       }
-      // the admissible hits of each half go to their candidates' lanes: in
-      // each step every candidate takes the first pending hit of its own run
-      // of lanes (a candidate's pairs occupy consecutive lanes), so the steps
-      // number the most hits any one candidate has in the half
+      // the admissible hits of each half enter their candidates' lists
 #pragma unroll
       for (int h = 0; h < NPT; ++h) {
         // this lane's run as a candidate in the half: lanes [s0, e0)
@@ -320,33 +319,14 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
         const int e0 = off + cnt - bh < 64 ? off + cnt - bh : 64;
         // accepted hits of each candidate: the accepted lanes of its run
         const unsigned long long am = __ballot(acc[h]);
-        if (s0 < e0) n_acc += __builtin_popcountll((am >> s0) & (e0 - s0 == 64 ? ~0ull : ((1ull << (e0 - s0)) - 1ull)));
-        unsigned long long m = __ballot(keep[h]);
+        if (s0 < e0) n_acc += __builtin_popcountll(am & run_mask(s0, e0));
+        const unsigned long long m = __ballot(keep[h]);
         if (m) {
-          do {
-            int j = 64;
-            if (s0 < e0) {
-              const unsigned long long mm = m >> s0;
-              if (mm) {
-                j = s0 + (int)__builtin_ctzll(mm);
-                if (j >= e0) j = 64;
-              }
-            }
-            const int js = j & 63;
-            const float jc2 = __shfl(c2[h], js, 64);
-            const int jp = __shfl(p[h], js, 64);
-            const uint32_t jo = (uint32_t)__shfl((int)orig[h], js, 64);
-            if (j < 64) {
-              lds_insert(tl, A.cap, held, jc2, jp, jo);
-            }
-            const bool first =
-                ((m >> lane) & 1ull) && ((m >> my_lo[h]) & ((1ull << (lane - my_lo[h])) - 1ull)) == 0;
-            m &= ~__ballot(first);
-          } while (m);
-          if (held == A.cap) {
-            thr_c2 = tl.c2[(A.cap - 1) * 64];
-            thr_o = tl.orig[(A.cap - 1) * 64];
-          }
+          // the run of this lane's pair: from its candidate's mark to the next
+          const unsigned long long above = sma[h] & ~((2ull << lane) - 1ull);
+          const int rhi = above ? (int)__builtin_ctzll(above) : 64;
+          round_insert(tl, A.cap, lane, m, keep[h], c2[h], p[h], orig[h], c[h], my_lo[h], rhi, s0, e0, held, thr_c2,
+                       thr_o, ab.pub_c2, ab.pub_o);
         }
       }
     }
@@ -363,10 +343,11 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
 //   recfield [SEEDS][5] i32    valid, nhits, status, last layer, slot
 //   toplist  [cap][64] f32 chi2, then [cap][64] i32 positions, [cap][64] u32 indices
 //   starts   [64 NP] i32 run starts of the cooperative hit search
+//   publish  [64] f32 chi2, [64] u32 indices of a round's admissible hits
 //   mlp      activation buffer of the learned window (the network runs before
 //            the hit search, so the toplists of a learned build live in it)
 struct LdsPlan {
-  size_t stash, rec, recf, acc, tl, tl_stride, mlp, total;
+  size_t stash, rec, recf, acc, pub, tl, tl_stride, mlp, total;
 };
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 __host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsize, bool learned) {
@@ -379,7 +360,8 @@ __host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsi
   (void)tsize;
   const size_t tl_wave = (size_t)cap * 64 * 12;
   p.acc = align16(p.recf + (size_t)nwaves * seeds * 5 * 4);
-  p.tl = align16(p.acc + (size_t)nwaves * 64 * NP * 4);
+  p.pub = align16(p.acc + (size_t)nwaves * 64 * NP * 4);
+  p.tl = align16(p.pub + (size_t)nwaves * 64 * 8);
   if (learned) {
     const size_t per = tl_wave > KFMLP_LDS_BYTES ? tl_wave : (size_t)KFMLP_LDS_BYTES;
     p.mlp = p.tl;
@@ -433,6 +415,8 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
   uint32_t* tl_orig = (uint32_t*)(wave_tl + (size_t)S * 64 * 8) + lane;
   AccBuf ab;
   ab.start = (int32_t*)(base + lp.acc) + (size_t)wave * 64 * NP;
+  ab.pub_c2 = (float*)(base + lp.pub) + (size_t)wave * 128;
+  ab.pub_o = (uint32_t*)ab.pub_c2 + 64;
   (void)mlp_buf;
   const int sidx = lane / S, slot = lane - (lane / S) * S, sbase = sidx * S;
   const bool lane_used = sidx < SEEDS;

@@ -159,9 +159,10 @@ __device__ inline uint32_t det_hist(int parent, int layer, uint32_t orig24) {
 //   record   [SEEDS][27] f32, recfield [SEEDS][5] i32 (valid, nhits, status,
 //                           last step, slot)
 //   starts   [64] i32       run starts of the cooperative hit search
+//   publish  [64] f32 chi2, [64] u32 indices of a round's admissible hits
 //   toplist  [cap][64] f32 chi2, i32 positions, u32 indices
 struct DetLds {
-  size_t stash, cand, rec, recf, acc, tl, total;
+  size_t stash, cand, rec, recf, acc, pub, tl, total;
 };
 __host__ __device__ inline size_t al16(size_t v) { return (v + 15) & ~(size_t)15; }
 __host__ __device__ inline DetLds det_lds(int nwaves, int cap) {
@@ -172,7 +173,8 @@ __host__ __device__ inline DetLds det_lds(int nwaves, int cap) {
   p.rec = al16(p.cand + (size_t)nwaves * 27 * 64 * 4);
   p.recf = al16(p.rec + (size_t)nwaves * seeds * 27 * 4);
   p.acc = al16(p.recf + (size_t)nwaves * seeds * 5 * 4);
-  p.tl = al16(p.acc + (size_t)nwaves * 64 * 4);
+  p.pub = al16(p.acc + (size_t)nwaves * 64 * 4);
+  p.tl = al16(p.pub + (size_t)nwaves * 64 * 8);
   p.total = al16(p.tl + (size_t)nwaves * cap * 64 * 12);
   return p;
 }
@@ -364,7 +366,8 @@ __device__ inline void coop_scan_det(const DetBuildArgs& A, int ev, int lj, int 
       if (cnt > 0 && off >= base && off - base < 64) ab.start[off - base] = lane;
       __builtin_amdgcn_wave_barrier();
       const int stv = ab.start[lane];
-      const unsigned long long sm = __ballot(stv >= 0) & ((2ull << lane) - 1ull);
+      const unsigned long long sma = __ballot(stv >= 0);
+      const unsigned long long sm = sma & ((2ull << lane) - 1ull);
       const int hb = sm ? 63 - (int)__builtin_clzll(sm) : 0;
       const int sc = __shfl(stv, hb, 64);
       const int c = sm ? sc : carry;
@@ -413,30 +416,14 @@ __device__ inline void coop_scan_det(const DetBuildArgs& A, int ev, int lj, int 
       const int s0 = off - base > 0 ? off - base : 0;
       const int e0 = off + cnt - base < 64 ? off + cnt - base : 64;
       const unsigned long long am = __ballot(acc);
-      if (s0 < e0) n_acc += __builtin_popcountll((am >> s0) & (e0 - s0 == 64 ? ~0ull : ((1ull << (e0 - s0)) - 1ull)));
-      unsigned long long m = __ballot(keep);
+      if (s0 < e0) n_acc += __builtin_popcountll(am & run_mask(s0, e0));
+      const unsigned long long m = __ballot(keep);
       if (m) {
-        do {
-          int j = 64;
-          if (s0 < e0) {
-            const unsigned long long mm = m >> s0;
-            if (mm) {
-              j = s0 + (int)__builtin_ctzll(mm);
-              if (j >= e0) j = 64;
-            }
-          }
-          const int js = j & 63;
-          const float jc2 = __shfl(c2, js, 64);
-          const int jp = __shfl(p, js, 64);
-          const uint32_t jo = (uint32_t)__shfl((int)orig, js, 64);
-          if (j < 64) lds_insert(tl, A.cap, held, jc2, jp, jo);
-          const bool first = ((m >> lane) & 1ull) && ((m >> my_lo) & ((1ull << (lane - my_lo)) - 1ull)) == 0;
-          m &= ~__ballot(first);
-        } while (m);
-        if (held == A.cap) {
-          thr_c2 = tl.c2[(A.cap - 1) * 64];
-          thr_o = tl.orig[(A.cap - 1) * 64];
-        }
+        // the run of this lane's pair: from its candidate's mark to the next
+        const unsigned long long above = sma & ~((2ull << lane) - 1ull);
+        const int rhi = above ? (int)__builtin_ctzll(above) : 64;
+        round_insert(tl, A.cap, lane, m, keep, c2, p, orig, c, my_lo, rhi, s0, e0, held, thr_c2, thr_o, ab.pub_c2,
+                     ab.pub_o);
       }
     }
   }
@@ -472,6 +459,8 @@ __global__ void __launch_bounds__(256, KF_BUILD_DET_WAVES) build_det_kernel(DetB
   uint32_t* tl_orig = (uint32_t*)(wave_tl + (size_t)S * 64 * 8) + lane;
   AccBuf ab;
   ab.start = (int32_t*)(base + lp.acc) + (size_t)wave * 64;
+  ab.pub_c2 = (float*)(base + lp.pub) + (size_t)wave * 128;
+  ab.pub_o = (uint32_t*)ab.pub_c2 + 64;
   const int sidx = lane / S, slot = lane - (lane / S) * S, sbase = sidx * S;
   const bool lane_used = sidx < SEEDS;
   const T bz = (T)A.d.bz, x0 = (T)A.d.x_over_x0, mass = (T)A.d.mass;

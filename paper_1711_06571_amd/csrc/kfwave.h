@@ -141,6 +141,117 @@ __device__ inline void lds_insert(TopList& tl, int cap, int& held, float c2, int
   tl.orig[j * 64] = orig;
 }
 
+// Lanes lo .. hi-1 of a wave as a mask (0 <= lo <= 63, hi <= 64).
+__device__ inline unsigned long long run_mask(int lo, int hi) {
+  const unsigned long long up = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
+  return up & ~((1ull << lo) - 1ull);
+}
+
+// One round's admissible hits into their candidates' lists, all at once.
+//
+// In a round of the cooperative hit search every lane holds one
+// (candidate, hit) pair, and the pairs of a candidate occupy a run of
+// consecutive lanes.  The new list of a candidate is the best cap of its
+// held entries and its admissible hits of the round.  Its admissible hits
+// are ranked in parallel: a hit's place is the number of held entries that
+// rank before it (the list is sorted) plus the number of the round's other
+// admissible hits of the candidate that rank before it (read from a
+// per-wave buffer the lanes publish to); a held entry moves down by the
+// number of new hits whose place among the held entries is at or before
+// its own (one ballot per list position).  Places at or past cap drop out.
+// The ranking is a total order, so the lists equal those of inserting the
+// hits one at a time.
+//
+//   keep, c2, pos, orig   this lane's pair (keep: admissible) and its hit
+//   c, rlo, rhi           the pair's candidate lane and its run [rlo, rhi)
+//   s0, e0                this lane's own run as a candidate (empty if s0 >= e0)
+//   m                     ballot of keep (nonzero)
+//   held, thr_c2, thr_o   this lane's list: entries and admission threshold
+//   pub_c2, pub_o         the wave's publish buffer, 64 entries each
+__device__ inline void round_insert(TopList& tl, int cap, int lane, unsigned long long m, bool keep, float c2,
+                                    int pos, uint32_t orig, int c, int rlo, int rhi, int s0, int e0, int& held,
+                                    float& thr_c2, uint32_t& thr_o, float* pub_c2, uint32_t* pub_o) {
+  float* wc2 = tl.c2 - lane;
+  int32_t* wpos = tl.pos - lane;
+  uint32_t* wor = tl.orig - lane;
+  if (keep) {
+    pub_c2[lane] = c2;
+    pub_o[lane] = orig;
+  }
+  asm volatile("" ::: "memory");
+  // place among the candidate's held entries
+  const int hc = __shfl(held, c, 64);
+  int rl = 0;
+  if (keep) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k < hc) rl += top_before(wc2[k * 64 + c], wor[k * 64 + c], c2, orig) ? 1 : 0;
+  }
+  // place among the round's admissible hits of the same candidate
+  int rank = rl;
+  unsigned long long M = keep ? (m & run_mask(rlo, rhi) & ~(1ull << lane)) : 0ull;
+  while (__any(M != 0ull)) {
+    int j[4];
+    bool v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      v[u] = M != 0ull;
+      j[u] = v[u] ? (int)__builtin_ctzll(M) : lane;
+      M &= M - 1ull;
+    }
+    float sc[4];
+    uint32_t so[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      sc[u] = pub_c2[j[u]];
+      so[u] = pub_o[j[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) rank += (v[u] && top_before(sc[u], so[u], c2, orig)) ? 1 : 0;
+  }
+  // held entries of this lane's list move down past the new hits before them
+  const unsigned long long own = s0 < e0 ? run_mask(s0, e0) : 0ull;
+  const int na = __builtin_popcountll(m & own);
+  int sh[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sh[k] = k < cap ? __builtin_popcountll(__ballot(keep && rl <= k) & own) : 0;
+  if (na > 0) {
+    float ec[8];
+    int32_t ep[8];
+    uint32_t eo[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (k < held && sh[k] > 0 && k + sh[k] < cap) {
+        ec[k] = tl.c2[k * 64];
+        ep[k] = tl.pos[k * 64];
+        eo[k] = tl.orig[k * 64];
+      }
+    }
+#pragma unroll
+    for (int k = 7; k >= 0; --k) {
+      if (k < held && sh[k] > 0 && k + sh[k] < cap) {
+        tl.c2[(k + sh[k]) * 64] = ec[k];
+        tl.pos[(k + sh[k]) * 64] = ep[k];
+        tl.orig[(k + sh[k]) * 64] = eo[k];
+      }
+    }
+  }
+  asm volatile("" ::: "memory");
+  if (keep && rank < cap) {
+    wc2[rank * 64 + c] = c2;
+    wpos[rank * 64 + c] = pos;
+    wor[rank * 64 + c] = orig;
+  }
+  asm volatile("" ::: "memory");
+  if (na > 0) {
+    held = held + na < cap ? held + na : cap;
+    if (held == cap) {
+      thr_c2 = tl.c2[(cap - 1) * 64];
+      thr_o = tl.orig[(cap - 1) * 64];
+    }
+  }
+}
+
 __device__ inline void top_get(const TopList& tl, int k, float& c2, int& pos, uint32_t& orig) {
   c2 = tl.c2[k * 64];
   pos = tl.pos[k * 64];
@@ -198,6 +309,8 @@ __device__ inline int wave_max(int v) {
 // whose pairs start at each lane.
 struct AccBuf {
   int32_t* start;
+  float* pub_c2;     // [64] the round's admissible hits (round_insert)
+  uint32_t* pub_o;   // [64]
 };
 
 __device__ inline uint32_t pack_hist(int parent, uint32_t orig24) {
