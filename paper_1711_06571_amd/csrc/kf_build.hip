@@ -98,9 +98,9 @@ struct BuildArgs {
 // in-window hits get their chi2; accepted hits (chi2 < cut) are counted for
 // their candidate (a ballot over its run of lanes: a candidate's pairs occupy
 // consecutive lanes) and, if they can enter its list of the best cap (a full
-// list admits only hits that rank before its last entry), handed to the
-// candidate's lane, which inserts them.  The order of insertion does not
-// change a list (the ranking is total), so the result equals a serial scan.
+// list admits only hits that rank before its last entry), placed in it by
+// their ranks, all of the round's at once (round_insert).  The ranking is
+// total, so the result equals a serial scan.
 //
 // The tests and chi2 run in FP32 in both arithmetic modes, from the
 // prediction rounded to FP32: their rounding (chi2 ~ 3e-5 at the cut,

@@ -285,7 +285,7 @@ __device__ inline bool pair_chi2(const float Xa[6], const float Pa[21], int q, f
 // barrel builder's cooperative search (ranges of sorted positions from the
 // fine phi index per (layer, w row) and phi interval, pairs of all candidates
 // handed out 64 at a time, the pair's candidate from run-start marks,
-// insertion into the candidate's list by its own lane), one pair per lane and
+// the round's admissible hits placed in the lists by rank), one pair per lane and
 // round, with the window test in (phi, w) and the chi2 after step 2.
 template <typename T>
 __device__ inline void coop_scan_det(const DetBuildArgs& A, int ev, int lj, int kind, bool pok, int q, const T Xa[6],

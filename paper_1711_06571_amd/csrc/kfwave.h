@@ -116,31 +116,6 @@ __device__ inline bool top_before(float c2, uint32_t orig, float oc2, uint32_t o
   return c2 < oc2 || (c2 == oc2 && orig < oorig);
 }
 
-// Insertion into a lane's list: a full list admits only a hit that ranks
-// before its last entry (which drops out); the entries that rank after the
-// new hit shift down one slot.
-__device__ inline void lds_insert(TopList& tl, int cap, int& held, float c2, int pos, uint32_t orig) {
-  int j = held;
-  if (j == cap) {
-    if (!top_before(c2, orig, tl.c2[(cap - 1) * 64], tl.orig[(cap - 1) * 64])) return;
-    j = cap - 1;
-  } else {
-    held += 1;
-  }
-  while (j > 0) {
-    const float pc = tl.c2[(j - 1) * 64];
-    const uint32_t po = tl.orig[(j - 1) * 64];
-    if (!top_before(c2, orig, pc, po)) break;
-    tl.c2[j * 64] = pc;
-    tl.pos[j * 64] = tl.pos[(j - 1) * 64];
-    tl.orig[j * 64] = po;
-    --j;
-  }
-  tl.c2[j * 64] = c2;
-  tl.pos[j * 64] = pos;
-  tl.orig[j * 64] = orig;
-}
-
 // Lanes lo .. hi-1 of a wave as a mask (0 <= lo <= 63, hi <= 64).
 __device__ inline unsigned long long run_mask(int lo, int hi) {
   const unsigned long long up = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
