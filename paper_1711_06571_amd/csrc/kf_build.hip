@@ -89,11 +89,11 @@ struct BuildArgs {
 // interval (two where the window wraps at 2 pi), one range of sorted hit
 // positions bracketed by the fine phi index.  Range r of every candidate is
 // taken in turn; the (candidate, hit) pairs of all candidates' ranges r are
-// numbered through a wave prefix sum and handed out 64 at a time, one pair
-// per lane, so a candidate with a wide window no longer holds up the wave
-// while the others wait.  A lane finds the pair's candidate by a binary
-// search of the prefix sums and reads what that candidate's tests share by
-// lane shuffles.  Every hit whose stored phi lies in the candidate's interval
+// numbered through a wave prefix sum and handed out 64 NP at a time, NP
+// pairs per lane, so a candidate with a wide window no longer holds up the
+// wave while the others wait.  A lane finds the pair's candidate from the
+// marks the candidates set where their pairs start and reads what that
+// candidate's tests share by lane shuffles.  Every hit whose stored phi lies in the candidate's interval
 // gets the exact window test (z first, then the angle about the axis);
 // in-window hits get their chi2; accepted hits (chi2 < cut) are counted for
 // their candidate (a ballot over its run of lanes: a candidate's pairs occupy
@@ -107,14 +107,14 @@ struct BuildArgs {
 // positions ~ 1e-5 cm) stays far below the chi2 gaps (1e-3) and window-edge
 // distances (1e-4 cm) that separate decisions; the Kalman update of a
 // chosen hit runs in the arithmetic of the mode.
-// pairs per lane per round of the hit search (at most; FP64 builds take one)
+// pairs per lane per round of the hit search
 constexpr int NP = 2;
 template <typename T>
 __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, const T Xp[6], const T Pp[21],
                                  T dphi_w, T dz_w, TopList& tl, const AccBuf& ab, int lane) {
-  // FP32 builds take NP pairs per lane and round, FP64 builds (short of
-  // registers) one
-  constexpr int NPT = sizeof(T) == 4 ? NP : 1;
+  // NP pairs per lane and round in both arithmetics (FP64 builds spill a
+  // little more for it and still gain)
+  constexpr int NPT = NP;
   const int nz = A.n_z, nf = A.n_phi * A.refine;
   const float inv = fine_inv(nf);
   const float tp = 6.283185307179586f;
