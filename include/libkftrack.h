@@ -159,21 +159,28 @@ typedef struct {
 } kf_hits;
 
 /* Workspace bytes for hit_bin (bin counts and starts, each hit's bin and
-   arrival index, and one 48-byte record per hit in its bin's slot); the
-   workspace must be 256-byte aligned (device allocations are). */
+   arrival index, one 48-byte record per hit in its bin's slot, and a path
+   flag); the workspace must be 256-byte aligned (device allocations are). */
 size_t hit_bin_workspace_bytes(int32_t n_events, int32_t n_layers, int32_t n_phi, int32_t n_z, int32_t n_hits);
 
 /*
  * hit_bin — counting sort of the hits of n_events events into the binned
- * layout above.  Events are concatenated: event e owns input hits
- * [event_offsets[e], event_offsets[e+1]) (event_offsets may be NULL when
- * n_events == 1); a hit's original index is its position minus the event's
- * first position.
- *   layer [n_hits] int32 (hits with a layer outside [0, n_layers) are
- *   rejected with KF_E_INVALID_ARG by a device-side check reported via
- *   out_bad (int32 count, may be NULL)), xyz [3][n_hits], cov [6][n_hits]
+ * layout above (section 3.1).  Events are concatenated: event e owns input
+ * hits [event_offsets[e], event_offsets[e+1]) (event_offsets may be NULL
+ * when n_events == 1); a hit's original index is its position minus the
+ * event's first position.
+ *   layer [n_hits] int32, xyz [3][n_hits], cov [6][n_hits]
  *   outputs: offsets [E][L][nb+1], sorted x,y,z,phi [4][n_hits] (x block,
  *   then y, z, phi), sorted cov [6][n_hits], orig [n_hits]
+ * A hit on a layer outside [0, n_layers) or with a non-finite coordinate is
+ * left out of every bin and counted in *out_bad (int32, may be NULL); the
+ * sorted arrays then hold n_hits - bad hits and their tail is unspecified.
+ * Any input order is accepted.  When every event's hits come grouped by
+ * layer in ascending order, all valid, and n_phi * n_z <= 4096, one block
+ * per (event, layer) sorts the call; otherwise the general kernels do, with
+ * the same result.  Diagnostic: after the call, the int32 at byte offset
+ * hit_bin_workspace_bytes(...) - 256 of ws is 0 when the grouped path sorted
+ * the call and 1 otherwise.
  */
 int hit_bin(const kf_geometry* g, int32_t n_events, const int32_t* event_offsets, int32_t n_phi, int32_t n_z,
             int32_t n_hits, const int32_t* layer, const float* xyz, const float* cov, int32_t* offsets,

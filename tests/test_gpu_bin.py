@@ -19,9 +19,9 @@ def kf():
     return kftrack
 
 
-def _check_event(w, b_gpu, e, ev_xyz, ev_cov, ev_layer, base):
+def _check_event(w, b_gpu, e, ev_xyz, ev_cov, ev_layer, base, n_phi=63, n_z=16):
     """Compare event e of a binned batch with the oracle's binning of that event."""
-    o = oracle.hit_bin(w.geometry, 63, 16, ev_layer, ev_xyz)
+    o = oracle.hit_bin(w.geometry, n_phi, n_z, ev_layer, ev_xyz)
     off_g = host(b_gpu.offsets)[e] - base
     assert np.array_equal(off_g, o["offsets"])
     n = ev_layer.shape[0]
@@ -77,3 +77,103 @@ def test_hit_bin_edge_cases(kf):
     o = oracle.hit_bin(g, 63, 16, layer, xyz)
     assert np.array_equal(host(b.offsets)[0], o["offsets"])
     assert np.array_equal(host(b.orig)[:5], o["order"][:5])
+
+
+# ---- the two sorting paths -------------------------------------------------
+# Input grouped by layer (all valid) is sorted by one block per (event,
+# layer); any other input by the general kernels.  The workspace's last 256
+# bytes hold the path flag (0: grouped path).
+
+def _bin(kf, g, n_phi, n_z, layer, xyz, cov, eoff=None):
+    E = 1 if eoff is None else len(eoff) - 1
+    need = kf.hit_bin_workspace_bytes(E, g.n_layers, n_phi, n_z, layer.shape[0])
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda:0")
+    b = kf.hit_bin(g, n_phi, n_z, to_dev(layer), to_dev(np.ascontiguousarray(xyz)), to_dev(np.ascontiguousarray(cov)),
+                   event_offsets=None if eoff is None else to_dev(np.asarray(eoff, np.int32)), ws=ws)
+    torch.cuda.synchronize()
+    flag = int(ws[need - 256:need - 252].view(torch.int32).cpu()[0])
+    return b, flag
+
+
+def _event(seed=0):
+    w = presets.build()
+    ev = datagen.generate(w.geometry, w.gen, seed, w.n_tracks)
+    return w, ev.layer.astype(np.int32), ev.xyz.astype(np.float32), ev.cov.astype(np.float32)
+
+
+def test_grouped_input_takes_the_block_path(kf):
+    w, layer, xyz, cov = _event()
+    assert np.all(np.diff(layer) >= 0)
+    b, flag = _bin(kf, w.geometry, 63, 16, layer, xyz, cov)
+    assert flag == 0
+    assert int(host(b.bad)[0]) == 0
+    _check_event(w, b, 0, xyz, cov, layer, 0)
+
+
+def test_shuffled_input_takes_the_general_path(kf):
+    """The same hits in a random order: general kernels, oracle order (the
+    original index is the shuffled position)."""
+    w, layer, xyz, cov = _event()
+    perm = np.random.default_rng(5).permutation(layer.shape[0])
+    layer, xyz, cov = layer[perm], np.ascontiguousarray(xyz[:, perm]), np.ascontiguousarray(cov[:, perm])
+    b, flag = _bin(kf, w.geometry, 63, 16, layer, xyz, cov)
+    assert flag == 1
+    _check_event(w, b, 0, xyz, cov, layer, 0)
+
+
+def test_layers_in_descending_order_take_the_general_path(kf):
+    w, layer, xyz, cov = _event()
+    order = np.argsort(-layer, kind="stable")
+    layer, xyz, cov = layer[order], np.ascontiguousarray(xyz[:, order]), np.ascontiguousarray(cov[:, order])
+    b, flag = _bin(kf, w.geometry, 63, 16, layer, xyz, cov)
+    assert flag == 1
+    _check_event(w, b, 0, xyz, cov, layer, 0)
+
+
+def test_bin_above_the_tile_takes_the_general_path(kf):
+    """One bin per layer (more than 2048 hits each): the grouped path gives way."""
+    w, layer, xyz, cov = _event()
+    assert np.bincount(layer).min() > 2048
+    b, flag = _bin(kf, w.geometry, 1, 1, layer, xyz, cov)
+    assert flag == 1
+    _check_event(w, b, 0, xyz, cov, layer, 0, n_phi=1, n_z=1)
+
+
+def test_many_bins_take_the_general_path(kf):
+    w, layer, xyz, cov = _event()
+    b, flag = _bin(kf, w.geometry, 128, 64, layer, xyz, cov)
+    assert flag == 1
+    _check_event(w, b, 0, xyz, cov, layer, 0, n_phi=128, n_z=64)
+
+
+def test_block_path_with_empty_layers_and_events(kf):
+    """Grouped events where some layers (and one whole event) hold no hits;
+    small bins (a tile of 2048 positions spans many bins), coarse bins (a
+    tile ends inside a layer's range)."""
+    w, layer, xyz, cov = _event()
+    keep = (layer != 3) & (layer != 9)
+    l2, x2, c2 = layer[keep], np.ascontiguousarray(xyz[:, keep]), np.ascontiguousarray(cov[:, keep])
+    n1 = l2.shape[0]
+    lay = np.concatenate([l2, l2[:0], layer])
+    X = np.concatenate([x2, x2[:, :0], xyz], axis=1)
+    C = np.concatenate([c2, c2[:, :0], cov], axis=1)
+    eoff = [0, n1, n1, lay.shape[0]]
+    for n_phi, n_z in ((63, 16), (8, 2)):
+        b, flag = _bin(kf, w.geometry, n_phi, n_z, lay, X, C, eoff=eoff)
+        assert flag == 0
+        for e in (0, 1, 2):
+            sl = slice(eoff[e], eoff[e + 1])
+            _check_event(w, b, e, np.ascontiguousarray(X[:, sl]), np.ascontiguousarray(C[:, sl]),
+                         np.ascontiguousarray(lay[sl]), eoff[e], n_phi=n_phi, n_z=n_z)
+
+
+def test_batch_of_events_takes_the_block_path(kf):
+    w = presets.batch()
+    eb = workloads.event_batch(w, range(6))
+    b, flag = _bin(kf, w.geometry, 63, 16, eb.layer, eb.xyz, eb.cov, eoff=eb.hit_offsets)
+    assert flag == 0
+    eoff = eb.hit_offsets
+    for e in range(6):
+        sl = slice(eoff[e], eoff[e + 1])
+        _check_event(w, b, e, np.ascontiguousarray(eb.xyz[:, sl]), np.ascontiguousarray(eb.cov[:, sl]),
+                     np.ascontiguousarray(eb.layer[sl]), int(eoff[e]))
