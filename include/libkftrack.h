@@ -176,11 +176,14 @@ size_t hit_bin_workspace_bytes(int32_t n_events, int32_t n_layers, int32_t n_phi
  * left out of every bin and counted in *out_bad (int32, may be NULL); the
  * sorted arrays then hold n_hits - bad hits and their tail is unspecified.
  * Any input order is accepted.  When every event's hits come grouped by
- * layer in ascending order, all valid, and n_phi * n_z <= 4096, one block
- * per (event, layer) sorts the call; otherwise the general kernels do, with
- * the same result.  Diagnostic: after the call, the int32 at byte offset
- * hit_bin_workspace_bytes(...) - 256 of ws is 0 when the grouped path sorted
- * the call and 1 otherwise.
+ * layer in ascending order, all valid, n_phi * n_z <= 4096 and there are at
+ * least six (event, layer) ranges per compute unit, one block per (event,
+ * layer) sorts the call; otherwise the general kernels do, with the same
+ * result.  The environment variable KFTRACK_HIT_BIN_PATH=grouped (try the
+ * grouped path whatever the number of ranges) or =general overrides the
+ * choice.  Diagnostic: after the call, the int32 at byte offset
+ * hit_bin_workspace_bytes(...) - 256 of ws is 0 when the grouped path
+ * sorted the call and 1 otherwise.
  */
 int hit_bin(const kf_geometry* g, int32_t n_events, const int32_t* event_offsets, int32_t n_phi, int32_t n_z,
             int32_t n_hits, const int32_t* layer, const float* xyz, const float* cov, int32_t* offsets,

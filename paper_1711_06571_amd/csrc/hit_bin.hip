@@ -11,6 +11,9 @@
 // order inside each bin, whole hit records) -> rank (exact order inside
 // each bin) and write out.  A device flag selects the path, so the sequence
 // has no host decision in it and can be captured in a graph.
+#include <stdlib.h>
+#include <string.h>
+
 #include <algorithm>
 
 #include "kfhost.h"
@@ -575,6 +578,22 @@ size_t bin_ws_layout(int E, int L, int n_phi, int n_z, int n, char* base, BinWs*
 
 int grid_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 
+// One block per (event, layer) pays when there are many ranges to spread
+// over the device: at least six per CU (68 M hits in 3 400 ranges: 4.9 ms
+// grouped against 7.7 general; 12.7 M hits of 64 uneven events in 1 088
+// ranges: 3.7 against 1.8, the largest ranges' blocks finishing last).
+// KFTRACK_HIT_BIN_PATH=grouped or =general overrides the choice.
+bool use_grouped_path(int EL) {
+  const char* v = getenv("KFTRACK_HIT_BIN_PATH");
+  if (v && !strcmp(v, "grouped")) return true;
+  if (v && !strcmp(v, "general")) return false;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  return EL >= 6 * cus;
+}
+
 }  // namespace
 
 extern "C" size_t hit_bin_workspace_bytes(int32_t n_events, int32_t n_layers, int32_t n_phi, int32_t n_z,
@@ -607,8 +626,8 @@ int run_hit_bin(int L, const RowGeom& rg, int32_t n_events, const int32_t* event
   // clear (kernels, not memset nodes, so the sequence can be captured in a graph)
   if (out_bad) hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, out_bad, (int64_t)1, 0);
   // fast path (one block per event and layer); the flag starts raised where
-  // it cannot apply
-  const bool fast = nb <= kSegMaxBins;
+  // it cannot apply or would not pay
+  const bool fast = nb <= kSegMaxBins && use_grouped_path(EL);
   hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, w.flag, (int64_t)1, fast ? 0 : 1);
   if (fast)
     hipLaunchKernelGGL(seg_kernel, dim3(EL), dim3(kSegThreads), seg_lds_bytes(nb), s, n_hits, n_events, event_offsets,

@@ -82,7 +82,14 @@ def test_hit_bin_edge_cases(kf):
 # ---- the two sorting paths -------------------------------------------------
 # Input grouped by layer (all valid) is sorted by one block per (event,
 # layer); any other input by the general kernels.  The workspace's last 256
-# bytes hold the path flag (0: grouped path).
+# bytes hold the path flag (0: grouped path).  The grouped path is tried
+# when there are enough (event, layer) ranges, or when the environment asks
+# for it (as the tests below do, whatever the size).
+
+
+@pytest.fixture
+def grouped(monkeypatch):
+    monkeypatch.setenv("KFTRACK_HIT_BIN_PATH", "grouped")
 
 def _bin(kf, g, n_phi, n_z, layer, xyz, cov, eoff=None):
     E = 1 if eoff is None else len(eoff) - 1
@@ -101,7 +108,7 @@ def _event(seed=0):
     return w, ev.layer.astype(np.int32), ev.xyz.astype(np.float32), ev.cov.astype(np.float32)
 
 
-def test_grouped_input_takes_the_block_path(kf):
+def test_grouped_input_takes_the_block_path(kf, grouped):
     w, layer, xyz, cov = _event()
     assert np.all(np.diff(layer) >= 0)
     b, flag = _bin(kf, w.geometry, 63, 16, layer, xyz, cov)
@@ -110,7 +117,7 @@ def test_grouped_input_takes_the_block_path(kf):
     _check_event(w, b, 0, xyz, cov, layer, 0)
 
 
-def test_shuffled_input_takes_the_general_path(kf):
+def test_shuffled_input_takes_the_general_path(kf, grouped):
     """The same hits in a random order: general kernels, oracle order (the
     original index is the shuffled position)."""
     w, layer, xyz, cov = _event()
@@ -121,7 +128,7 @@ def test_shuffled_input_takes_the_general_path(kf):
     _check_event(w, b, 0, xyz, cov, layer, 0)
 
 
-def test_layers_in_descending_order_take_the_general_path(kf):
+def test_layers_in_descending_order_take_the_general_path(kf, grouped):
     w, layer, xyz, cov = _event()
     order = np.argsort(-layer, kind="stable")
     layer, xyz, cov = layer[order], np.ascontiguousarray(xyz[:, order]), np.ascontiguousarray(cov[:, order])
@@ -130,7 +137,7 @@ def test_layers_in_descending_order_take_the_general_path(kf):
     _check_event(w, b, 0, xyz, cov, layer, 0)
 
 
-def test_bin_above_the_tile_takes_the_general_path(kf):
+def test_bin_above_the_tile_takes_the_general_path(kf, grouped):
     """One bin per layer (more than 2048 hits each): the grouped path gives way."""
     w, layer, xyz, cov = _event()
     assert np.bincount(layer).min() > 2048
@@ -139,14 +146,14 @@ def test_bin_above_the_tile_takes_the_general_path(kf):
     _check_event(w, b, 0, xyz, cov, layer, 0, n_phi=1, n_z=1)
 
 
-def test_many_bins_take_the_general_path(kf):
+def test_many_bins_take_the_general_path(kf, grouped):
     w, layer, xyz, cov = _event()
     b, flag = _bin(kf, w.geometry, 128, 64, layer, xyz, cov)
     assert flag == 1
     _check_event(w, b, 0, xyz, cov, layer, 0, n_phi=128, n_z=64)
 
 
-def test_block_path_with_empty_layers_and_events(kf):
+def test_block_path_with_empty_layers_and_events(kf, grouped):
     """Grouped events where some layers (and one whole event) hold no hits;
     small bins (a tile of 2048 positions spans many bins), coarse bins (a
     tile ends inside a layer's range)."""
@@ -167,7 +174,7 @@ def test_block_path_with_empty_layers_and_events(kf):
                          np.ascontiguousarray(lay[sl]), eoff[e], n_phi=n_phi, n_z=n_z)
 
 
-def test_batch_of_events_takes_the_block_path(kf):
+def test_batch_of_events_takes_the_block_path(kf, grouped):
     w = presets.batch()
     eb = workloads.event_batch(w, range(6))
     b, flag = _bin(kf, w.geometry, 63, 16, eb.layer, eb.xyz, eb.cov, eoff=eb.hit_offsets)
@@ -177,3 +184,31 @@ def test_batch_of_events_takes_the_block_path(kf):
         sl = slice(eoff[e], eoff[e + 1])
         _check_event(w, b, e, np.ascontiguousarray(eb.xyz[:, sl]), np.ascontiguousarray(eb.cov[:, sl]),
                      np.ascontiguousarray(eb.layer[sl]), int(eoff[e]))
+
+
+def test_path_choice_follows_the_number_of_ranges(kf, monkeypatch):
+    """Without the override: one event (17 ranges) goes to the general
+    kernels; many small events (at least six ranges per compute unit) to the
+    grouped path; =general forces the general kernels.  Results equal the
+    oracle either way."""
+    monkeypatch.delenv("KFTRACK_HIT_BIN_PATH", raising=False)
+    w, layer, xyz, cov = _event()
+    b, flag = _bin(kf, w.geometry, 63, 16, layer, xyz, cov)
+    assert flag == 1
+    _check_event(w, b, 0, xyz, cov, layer, 0)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    E = -(-6 * cus // w.geometry.n_layers)
+    eb = workloads.event_batch(w, range(E), n_tracks=100)
+    b, flag = _bin(kf, w.geometry, 63, 16, eb.layer, eb.xyz, eb.cov, eoff=eb.hit_offsets)
+    assert flag == 0
+    eoff = eb.hit_offsets
+    for e in (0, E // 2, E - 1):
+        sl = slice(eoff[e], eoff[e + 1])
+        _check_event(w, b, e, np.ascontiguousarray(eb.xyz[:, sl]), np.ascontiguousarray(eb.cov[:, sl]),
+                     np.ascontiguousarray(eb.layer[sl]), int(eoff[e]))
+    monkeypatch.setenv("KFTRACK_HIT_BIN_PATH", "general")
+    b, flag = _bin(kf, w.geometry, 63, 16, eb.layer, eb.xyz, eb.cov, eoff=eb.hit_offsets)
+    assert flag == 1
+    sl = slice(eoff[1], eoff[2])
+    _check_event(w, b, 1, np.ascontiguousarray(eb.xyz[:, sl]), np.ascontiguousarray(eb.cov[:, sl]),
+                 np.ascontiguousarray(eb.layer[sl]), int(eoff[1]))
