@@ -107,14 +107,12 @@ struct BuildArgs {
 // positions ~ 1e-5 cm) stays far below the chi2 gaps (1e-3) and window-edge
 // distances (1e-4 cm) that separate decisions; the Kalman update of a
 // chosen hit runs in the arithmetic of the mode.
-// pairs per lane per round of the hit search
+// pairs per lane per round of the hit search (at most)
 constexpr int NP = 2;
-template <typename T>
+template <typename T, int NPT>
 __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, const T Xp[6], const T Pp[21],
                                  T dphi_w, T dz_w, TopList& tl, const AccBuf& ab, int lane) {
-  // NP pairs per lane and round in both arithmetics (FP64 builds spill a
-  // little more for it and still gain)
-  constexpr int NPT = NP;
+  static_assert(NPT >= 1 && NPT <= NP, "pairs per lane");
   const int nz = A.n_z, nf = A.n_phi * A.refine;
   const float inv = fine_inv(nf);
   const float tp = 6.283185307179586f;
@@ -388,6 +386,17 @@ __host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsi
 #define KF_BUILD_F64_LEARNED_WAVES 2
 #endif
 
+// Pairs per lane and round: NP in FP32 builds and plain FP64 builds (which
+// spill a little more for it and still gain: 26.80 -> 26.16 ms on 50
+// events); one in learned FP64 builds, whose network already holds registers
+// and whose narrow windows leave few pairs per round (32 events: 17.35 ->
+// 17.28 ms, hybrid state 18.58 -> 18.10 ms).
+#ifndef KF_LEARNED_F64_NPT
+#define KF_LEARNED_F64_NPT 1
+#endif
+template <typename T, bool LEARNED>
+constexpr int NPT_OF = (sizeof(T) == 8 && LEARNED) ? KF_LEARNED_F64_NPT : NP;
+
 template <typename T, bool LEARNED, bool HYB>
 __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
                                                        : (LEARNED ? KF_BUILD_F64_LEARNED_WAVES : KF_BUILD_F64_WAVES)))
@@ -592,7 +601,7 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
         }
       }
       const T dphi_w = pok ? w_rphi / R : T(0), dz_w = pok ? w_z : T(0);
-      coop_scan<T>(A, ev, l, pok, Xp, Pp, dphi_w, dz_w, tl, ab, lane);
+      coop_scan<T, NPT_OF<T, LEARNED>>(A, ev, l, pok, Xp, Pp, dphi_w, dz_w, tl, ab, lane);
       cnt_pred += live ? 1u : 0u;
       cnt_scan += (unsigned)tl.scanned;
       cnt_chi2 += (unsigned)tl.tested;
