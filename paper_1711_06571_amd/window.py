@@ -36,10 +36,14 @@ DEV = "cuda:0"
 SCALE = np.array([0.01, 0.1])   # output scales: arc cm, z cm
 FLOOR = (0.01, 0.1)
 # the network is consulted where a plain half-width lies above this quantile
-# of the training rows' (about an eighth of them): the wide windows, which scan
-# most of the hits
-GATE_QUANTILE = 0.9
-KAPPAS = [0.6, 0.7, 0.8, 0.9, 1.0, 1.1, 1.2, 1.35, 1.5, 1.75, 2.0, 2.5, 3.0]
+# of the training rows' (about 4 % of them): the widest windows, which scan
+# most of the hits.  Rarely gated candidates leave most waves without a
+# network tile to run (at the 0.9 quantile almost every wave ran one per
+# layer); much higher quantiles leave the network too few training rows.
+GATE_QUANTILE = 0.97
+# kappa values the calibration tries, smallest first (the first that keeps
+# the plain efficiency wins)
+KAPPAS = [round(0.3 + 0.05 * i, 2) for i in range(19)] + [1.35, 1.5, 1.75, 2.0, 2.5, 3.0]
 
 
 @dataclass
