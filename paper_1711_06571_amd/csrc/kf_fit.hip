@@ -296,14 +296,19 @@ namespace {
 // takes the built hit (event-local index) or, if none, a hole bit.  One lane
 // per (seed, layer): the rows and the built indices are read and written
 // coalesced along the seeds; the hit reads are the only scattered access.
-__global__ void __launch_bounds__(256) gather_kernel(int n_layers, int first_layer, int n, int ld,
+// Blocks are dispatched to the 8 XCDs in turn (block index mod 8): block b
+// takes seed chunk x * cpx + (k mod cpx) of layer first_layer + k / cpx
+// (x = b mod 8, k = b / 8, cpx chunks per XCD), so each XCD gathers for its
+// own eighth of the seeds, a few events at a time, whose hits stay in its L2.
+__global__ void __launch_bounds__(256) gather_kernel(int n_layers, int first_layer, int n, int ld, int cpx,
                                                      const int32_t* __restrict__ built,
                                                      const int32_t* __restrict__ seed_event,
                                                      const int32_t* __restrict__ event_offsets, int n_events,
                                                      int n_hits, const float* __restrict__ xyz,
                                                      const float* __restrict__ cov, float* __restrict__ fit_hits) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int l = first_layer + blockIdx.y;
+  const int x = blockIdx.x & 7, k = blockIdx.x >> 3;
+  const int i = (x * cpx + k % cpx) * blockDim.x + threadIdx.x;
+  const int l = first_layer + k / cpx;
   if (i >= n || l >= n_layers) return;
   const int e = seed_event ? seed_event[i] : 0;
   const bool ev_ok = e >= 0 && e < n_events;
@@ -359,9 +364,10 @@ extern "C" int kf_gather_hits(int32_t n_layers, int32_t first_layer, int32_t n_s
   if (n_seeds == 0) return KF_OK;
   if (!built_hits || !fit_hits || !hole_mask || (n_hits > 0 && (!xyz || !cov))) return KF_E_INVALID_ARG;
   const int bs = 256;
-  hipLaunchKernelGGL(gather_kernel, dim3((n_seeds + bs - 1) / bs, n_layers - first_layer), dim3(bs), 0,
-                     (hipStream_t)stream, n_layers, first_layer, n_seeds, ld, built_hits, seed_event, event_offsets,
-                     n_events, n_hits, xyz, cov, fit_hits);
+  const int chunks = (n_seeds + bs - 1) / bs, cpx = (chunks + 7) / 8;
+  hipLaunchKernelGGL(gather_kernel, dim3(8 * cpx * (n_layers - first_layer)), dim3(bs), 0, (hipStream_t)stream,
+                     n_layers, first_layer, n_seeds, ld, cpx, built_hits, seed_event, event_offsets, n_events, n_hits,
+                     xyz, cov, fit_hits);
   if (int rc = kf_check_launch()) return rc;
   hipLaunchKernelGGL(hole_mask_kernel, dim3((n_seeds + bs - 1) / bs), dim3(bs), 0, (hipStream_t)stream, n_layers,
                      first_layer, n_seeds, ld, built_hits, seed_event, event_offsets, n_events, n_hits, hole_mask);
