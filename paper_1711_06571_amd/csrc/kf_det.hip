@@ -433,12 +433,20 @@ __device__ inline void coop_scan_det(const DetBuildArgs& A, int ev, int lj, int 
   tl.tot = n_acc;
 }
 
-#ifndef KF_BUILD_DET_WAVES
-#define KF_BUILD_DET_WAVES 2
+// Waves per SIMD the register allocation aims at: the FP64 kernel at two
+// spilled 888 bytes per lane and ran slower than at one without spills
+// (16 lids events: 15.06 -> 13.26 ms); the FP32 kernel needs the second wave
+// (12.0 ms against 17.0 at one).
+#ifndef KF_BUILD_DET_F64_WAVES
+#define KF_BUILD_DET_F64_WAVES 1
+#endif
+#ifndef KF_BUILD_DET_F32_WAVES
+#define KF_BUILD_DET_F32_WAVES 2
 #endif
 
 template <typename T>
-__global__ void __launch_bounds__(256, KF_BUILD_DET_WAVES) build_det_kernel(DetBuildArgs A) {
+__global__ void __launch_bounds__(256, sizeof(T) == 8 ? KF_BUILD_DET_F64_WAVES : KF_BUILD_DET_F32_WAVES)
+    build_det_kernel(DetBuildArgs A) {
   const int S = A.cap;
   const int SEEDS = 64 / S;
   extern __shared__ __align__(16) uint32_t lds[];
