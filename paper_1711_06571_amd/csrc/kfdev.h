@@ -60,13 +60,22 @@ KFD inline double k_tan(double v) { return tan(v); }
 KFD inline float k_atan(float v) { return atanf(v); }
 KFD inline float k_log(float v) { return logf(v); }
 
-// FP64 arctangent written out from textbook identities: inside the build
-// kernels, which are short of registers, the library routine made the
-// compiler spill around every call (it cost 15 % of the FP64 build).  It
-// stays within 6 ulp of the correctly rounded value (a CPU test checks it
-// against the host library).  (A logarithm written the same way, for the
-// scattering term, ran slower than the library's: its eleven series
-// coefficients held registers of their own.)
+// A double constant materialised where it is used: the empty asm (scalar
+// registers) keeps the compiler from hoisting it out of the layer loop,
+// where every series coefficient would hold two registers throughout.
+KFD inline double kc(double c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+s"(c));
+#endif
+  return c;
+}
+
+// FP64 arctangent and logarithm written out from textbook identities: inside
+// the build kernels, which are short of registers, the library routines made
+// the compiler spill around every call (the arctangent alone cost 15 % of
+// the FP64 build).  Their series coefficients go through kc().  Both stay
+// within a few ulp of the correctly rounded value (a CPU test checks them
+// against the host library).
 //
 // atan: |x| > 1 folds to pi/2 - atan(1/|x|); arguments above 0.05 are
 // halved (at most four times) by atan(x) = 2 atan(x / (1 + sqrt(1 + x^2)));
@@ -85,17 +94,46 @@ KFD inline double k_atan(double v) {
   }
   const double u = x * x;
   double p = 1.0 / 13.0;
-  p = __builtin_fma(p, u, -1.0 / 11.0);
-  p = __builtin_fma(p, u, 1.0 / 9.0);
-  p = __builtin_fma(p, u, -1.0 / 7.0);
-  p = __builtin_fma(p, u, 1.0 / 5.0);
-  p = __builtin_fma(p, u, -1.0 / 3.0);
+  p = __builtin_fma(p, u, kc(-1.0 / 11.0));
+  p = __builtin_fma(p, u, kc(1.0 / 9.0));
+  p = __builtin_fma(p, u, kc(-1.0 / 7.0));
+  p = __builtin_fma(p, u, kc(1.0 / 5.0));
+  p = __builtin_fma(p, u, kc(-1.0 / 3.0));
   double r = scale * __builtin_fma(x * u, p, x);
   if (inv) r = 1.5707963267948966 - r;
   return __builtin_copysign(r, v);
 }
 
-KFD inline double k_log(double v) { return log(v); }
+// log: v = m 2^e with m in [sqrt(1/2), sqrt(2)), log m = 2 atanh(f) with
+// f = (m - 1) / (m + 1), |f| <= 0.172, the series 2 f sum f^2k / (2k + 1) to
+// f^23; e ln 2 added in two parts (Cody and Waite's split of ln 2, whose
+// leading part times a small integer is exact).  Zero, negative, infinite and
+// NaN arguments give the IEEE results.
+KFD inline double k_log(double v) {
+  if (!(v > 0.0)) return v == 0.0 ? -__builtin_inf() : __builtin_nan("");
+  if (!__builtin_isfinite(v)) return v;
+  int e = 0;
+  double m = __builtin_frexp(v, &e);
+  if (m < 0.70710678118654752440) {
+    m *= 2.0;
+    e -= 1;
+  }
+  const double f = (m - 1.0) / (m + 1.0), f2 = f * f;
+  double p = 1.0 / 23.0;
+  p = __builtin_fma(p, f2, kc(1.0 / 21.0));
+  p = __builtin_fma(p, f2, kc(1.0 / 19.0));
+  p = __builtin_fma(p, f2, kc(1.0 / 17.0));
+  p = __builtin_fma(p, f2, kc(1.0 / 15.0));
+  p = __builtin_fma(p, f2, kc(1.0 / 13.0));
+  p = __builtin_fma(p, f2, kc(1.0 / 11.0));
+  p = __builtin_fma(p, f2, kc(1.0 / 9.0));
+  p = __builtin_fma(p, f2, kc(1.0 / 7.0));
+  p = __builtin_fma(p, f2, kc(1.0 / 5.0));
+  p = __builtin_fma(p, f2, kc(1.0 / 3.0));
+  const double lm = 2.0 * __builtin_fma(f * f2, p, f);
+  const double ln2_hi = 6.93147180369123816490e-01, ln2_lo = 1.90821492927058770002e-10;
+  return (double)e * ln2_hi + ((double)e * ln2_lo + lm);
+}
 KFD inline bool k_finite(float v) { return __builtin_isfinite(v); }
 KFD inline bool k_finite(double v) { return __builtin_isfinite(v); }
 
