@@ -165,7 +165,8 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
   const int R = pok ? (iz1 - iz0 + 1) * nint : 0;
   const int Rmax = wave_max(R);
   int n_acc = 0;  // accepted hits of this lane's candidate
-  int held = 0;  // entries in the list
+  int held = 0;           // entries in the list
+  bool unsorted = false;  // entries appended out of order
   // the candidate's admission threshold: its last entry once its list is
   // full (before, +inf admits every accepted hit)
   float thr_c2 = __builtin_inff();
@@ -323,12 +324,13 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
           // the run of this lane's pair: from its candidate's mark to the next
           const unsigned long long above = sma[h] & ~((2ull << lane) - 1ull);
           const int rhi = above ? (int)__builtin_ctzll(above) : 64;
-          round_insert(tl, A.cap, lane, m, keep[h], c2[h], p[h], orig[h], c[h], my_lo[h], rhi, s0, e0, held, thr_c2,
-                       thr_o, ab.pub_c2, ab.pub_o);
+          round_insert(tl, A.cap, lane, m, keep[h], c2[h], p[h], orig[h], c[h], my_lo[h], rhi, s0, e0, held, unsorted,
+                       thr_c2, thr_o, ab.pub_c2, ab.pub_o);
         }
       }
     }
   }
+  if (unsorted) sort_own(tl, A.cap, held);
   tl.n = held;
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();

@@ -329,6 +329,7 @@ __device__ inline void coop_scan_det(const DetBuildArgs& A, int ev, int lj, int 
   const int Rmax = wave_max(R);
   int n_acc = 0;  // accepted hits of this lane's candidate
   int held = 0;
+  bool unsorted = false;  // entries appended out of order
   float thr_c2 = __builtin_inff();
   uint32_t thr_o = 0xFFFFFFFFu;
   const float cut = A.chi2_cut;
@@ -422,11 +423,12 @@ __device__ inline void coop_scan_det(const DetBuildArgs& A, int ev, int lj, int 
         // the run of this lane's pair: from its candidate's mark to the next
         const unsigned long long above = sma & ~((2ull << lane) - 1ull);
         const int rhi = above ? (int)__builtin_ctzll(above) : 64;
-        round_insert(tl, A.cap, lane, m, keep, c2, p, orig, c, my_lo, rhi, s0, e0, held, thr_c2, thr_o, ab.pub_c2,
-                     ab.pub_o);
+        round_insert(tl, A.cap, lane, m, keep, c2, p, orig, c, my_lo, rhi, s0, e0, held, unsorted, thr_c2, thr_o,
+                     ab.pub_c2, ab.pub_o);
       }
     }
   }
+  if (unsorted) sort_own(tl, A.cap, held);
   tl.n = held;
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();

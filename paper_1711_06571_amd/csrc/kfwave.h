@@ -122,18 +122,73 @@ __device__ inline unsigned long long run_mask(int lo, int hi) {
   return up & ~((1ull << lo) - 1ull);
 }
 
+// Sorts the first n entries of this lane's list by (chi2, hit index): the
+// entries go through registers and Batcher's odd-even merge network for
+// eight (19 comparators), positions from n on (and from cap on) as +inf.
+__device__ inline void sort_own(TopList& tl, int cap, int n) {
+  float v[8];
+  uint32_t o[8];
+  int32_t q[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (k < cap) {
+      v[k] = tl.c2[k * 64];
+      o[k] = tl.orig[k * 64];
+      q[k] = tl.pos[k * 64];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (!(k < n && k < cap)) {
+      v[k] = __builtin_inff();
+      o[k] = 0xFFFFFFFFu;
+      q[k] = 0;
+    }
+  }
+  constexpr int net[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6}, {5, 7}, {1, 2}, {5, 6},
+                              {0, 4}, {1, 5}, {2, 6}, {3, 7}, {2, 4}, {3, 5}, {1, 2}, {3, 4}, {5, 6}};
+#pragma unroll
+  for (int t = 0; t < 19; ++t) {
+    const int a = net[t][0], b = net[t][1];
+    const bool sw = top_before(v[b], o[b], v[a], o[a]);
+    const float tv = v[a];
+    const uint32_t to = o[a];
+    const int32_t tq = q[a];
+    v[a] = sw ? v[b] : v[a];
+    o[a] = sw ? o[b] : o[a];
+    q[a] = sw ? q[b] : q[a];
+    v[b] = sw ? tv : v[b];
+    o[b] = sw ? to : o[b];
+    q[b] = sw ? tq : q[b];
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (k < n && k < cap) {
+      tl.c2[k * 64] = v[k];
+      tl.orig[k * 64] = o[k];
+      tl.pos[k * 64] = q[k];
+    }
+  }
+}
+
 // One round's admissible hits into their candidates' lists, all at once.
 //
 // In a round of the cooperative hit search every lane holds one
 // (candidate, hit) pair, and the pairs of a candidate occupy a run of
 // consecutive lanes.  The new list of a candidate is the best cap of its
-// held entries and its admissible hits of the round.  Its admissible hits
-// are ranked in parallel: a hit's place is the number of held entries that
-// rank before it (the list is sorted) plus the number of the round's other
+// held entries and its admissible hits of the round.
+//
+// Where they all fit (held + admissible <= cap) the hits are appended, each
+// at held plus its index among the run's admissible lanes, and the list is
+// marked unsorted; a list that fills up this way is sorted at once (its
+// last entry is the admission threshold), and the caller sorts the others
+// at the end of the search.  Where they do not, the hits are ranked in
+// parallel against the (sorted) held entries: a hit's place is the number
+// of held entries that rank before it plus the number of the round's other
 // admissible hits of the candidate that rank before it (read from a
 // per-wave buffer the lanes publish to); a held entry moves down by the
 // number of new hits whose place among the held entries is at or before
-// its own (one ballot per list position).  Places at or past cap drop out.
+// its own (one ballot per list position); places at or past cap drop out.
 // The ranking is a total order, so the lists equal those of inserting the
 // hits one at a time.
 //
@@ -141,85 +196,113 @@ __device__ inline unsigned long long run_mask(int lo, int hi) {
 //   c, rlo, rhi           the pair's candidate lane and its run [rlo, rhi)
 //   s0, e0                this lane's own run as a candidate (empty if s0 >= e0)
 //   m                     ballot of keep (nonzero)
-//   held, thr_c2, thr_o   this lane's list: entries and admission threshold
+//   held, unsorted        this lane's list: entries, and whether they are out of order
+//   thr_c2, thr_o         its admission threshold (its last entry once full)
 //   pub_c2, pub_o         the wave's publish buffer, 64 entries each
 __device__ inline void round_insert(TopList& tl, int cap, int lane, unsigned long long m, bool keep, float c2,
                                     int pos, uint32_t orig, int c, int rlo, int rhi, int s0, int e0, int& held,
-                                    float& thr_c2, uint32_t& thr_o, float* pub_c2, uint32_t* pub_o) {
+                                    bool& unsorted, float& thr_c2, uint32_t& thr_o, float* pub_c2, uint32_t* pub_o) {
   float* wc2 = tl.c2 - lane;
   int32_t* wpos = tl.pos - lane;
   uint32_t* wor = tl.orig - lane;
-  if (keep) {
-    pub_c2[lane] = c2;
-    pub_o[lane] = orig;
-  }
-  asm volatile("" ::: "memory");
-  // place among the candidate's held entries
+  // the pair's candidate: entries held, admissible hits in the run
   const int hc = __shfl(held, c, 64);
-  int rl = 0;
-  if (keep) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (k < hc) rl += top_before(wc2[k * 64 + c], wor[k * 64 + c], c2, orig) ? 1 : 0;
-  }
-  // place among the round's admissible hits of the same candidate
-  int rank = rl;
-  unsigned long long M = keep ? (m & run_mask(rlo, rhi) & ~(1ull << lane)) : 0ull;
-  while (__any(M != 0ull)) {
-    int j[4];
-    bool v[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      v[u] = M != 0ull;
-      j[u] = v[u] ? (int)__builtin_ctzll(M) : lane;
-      M &= M - 1ull;
-    }
-    float sc[4];
-    uint32_t so[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      sc[u] = pub_c2[j[u]];
-      so[u] = pub_o[j[u]];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) rank += (v[u] && top_before(sc[u], so[u], c2, orig)) ? 1 : 0;
-  }
-  // held entries of this lane's list move down past the new hits before them
+  const unsigned long long runm = m & run_mask(rlo, rhi);
+  const bool app = keep && hc + __builtin_popcountll(runm) <= cap;
+  // this lane as a candidate
   const unsigned long long own = s0 < e0 ? run_mask(s0, e0) : 0ull;
   const int na = __builtin_popcountll(m & own);
-  int sh[8];
+  const bool ovf = na > 0 && held + na > cap;
+  if (app) {
+    const int idx = hc + __builtin_popcountll(runm & ((1ull << lane) - 1ull));
+    wc2[idx * 64 + c] = c2;
+    wpos[idx * 64 + c] = pos;
+    wor[idx * 64 + c] = orig;
+  }
+  if (__any(ovf)) {
+    if (ovf && unsorted) {
+      sort_own(tl, cap, held);
+      unsorted = false;
+    }
+    const bool rk = keep && !app;  // hits of overflowing candidates
+    if (rk) {
+      pub_c2[lane] = c2;
+      pub_o[lane] = orig;
+    }
+    asm volatile("" ::: "memory");
+    // place among the candidate's held entries
+    int rl = 0;
+    if (rk) {
 #pragma unroll
-  for (int k = 0; k < 8; ++k) sh[k] = k < cap ? __builtin_popcountll(__ballot(keep && rl <= k) & own) : 0;
-  if (na > 0) {
-    float ec[8];
-    int32_t ep[8];
-    uint32_t eo[8];
+      for (int k = 0; k < 8; ++k)
+        if (k < hc) rl += top_before(wc2[k * 64 + c], wor[k * 64 + c], c2, orig) ? 1 : 0;
+    }
+    // place among the round's admissible hits of the same candidate
+    int rank = rl;
+    unsigned long long M = rk ? (runm & ~(1ull << lane)) : 0ull;
+    while (__any(M != 0ull)) {
+      int j[4];
+      bool v[4];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      if (k < held && sh[k] > 0 && k + sh[k] < cap) {
-        ec[k] = tl.c2[k * 64];
-        ep[k] = tl.pos[k * 64];
-        eo[k] = tl.orig[k * 64];
+      for (int u = 0; u < 4; ++u) {
+        v[u] = M != 0ull;
+        j[u] = v[u] ? (int)__builtin_ctzll(M) : lane;
+        M &= M - 1ull;
+      }
+      float sc[4];
+      uint32_t so[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        sc[u] = pub_c2[j[u]];
+        so[u] = pub_o[j[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) rank += (v[u] && top_before(sc[u], so[u], c2, orig)) ? 1 : 0;
+    }
+    // held entries move down past the new hits before them
+    int sh[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[k] = k < cap ? __builtin_popcountll(__ballot(rk && rl <= k) & own) : 0;
+    if (ovf) {
+      float ec[8];
+      int32_t ep[8];
+      uint32_t eo[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (k < held && sh[k] > 0 && k + sh[k] < cap) {
+          ec[k] = tl.c2[k * 64];
+          ep[k] = tl.pos[k * 64];
+          eo[k] = tl.orig[k * 64];
+        }
+      }
+#pragma unroll
+      for (int k = 7; k >= 0; --k) {
+        if (k < held && sh[k] > 0 && k + sh[k] < cap) {
+          tl.c2[(k + sh[k]) * 64] = ec[k];
+          tl.pos[(k + sh[k]) * 64] = ep[k];
+          tl.orig[(k + sh[k]) * 64] = eo[k];
+        }
       }
     }
-#pragma unroll
-    for (int k = 7; k >= 0; --k) {
-      if (k < held && sh[k] > 0 && k + sh[k] < cap) {
-        tl.c2[(k + sh[k]) * 64] = ec[k];
-        tl.pos[(k + sh[k]) * 64] = ep[k];
-        tl.orig[(k + sh[k]) * 64] = eo[k];
-      }
+    asm volatile("" ::: "memory");
+    if (rk && rank < cap) {
+      wc2[rank * 64 + c] = c2;
+      wpos[rank * 64 + c] = pos;
+      wor[rank * 64 + c] = orig;
     }
   }
   asm volatile("" ::: "memory");
-  if (keep && rank < cap) {
-    wc2[rank * 64 + c] = c2;
-    wpos[rank * 64 + c] = pos;
-    wor[rank * 64 + c] = orig;
-  }
-  asm volatile("" ::: "memory");
   if (na > 0) {
-    held = held + na < cap ? held + na : cap;
+    if (ovf) {
+      held = cap;
+    } else {
+      held += na;
+      unsorted = true;
+      if (held == cap) {
+        sort_own(tl, cap, held);
+        unsorted = false;
+      }
+    }
     if (held == cap) {
       thr_c2 = tl.c2[(cap - 1) * 64];
       thr_o = tl.orig[(cap - 1) * 64];
