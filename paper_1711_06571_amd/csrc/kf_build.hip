@@ -107,6 +107,19 @@ struct BuildArgs {
 // positions ~ 1e-5 cm) stays far below the chi2 gaps (1e-3) and window-edge
 // distances (1e-4 cm) that separate decisions; the Kalman update of a
 // chosen hit runs in the arithmetic of the mode.
+// ku / kv in FP64 builds only: there, kernel arguments and per-seed values
+// that the layer loop uses are recomputed where they are used instead of
+// being hoisted out of the loop and spilled (the FP32 build does not spill;
+// the barriers would only cost it issue slots)
+template <typename T, typename U> __device__ inline U ku64(U v) {
+  if constexpr (sizeof(T) == 8) return ku(v);
+  else return v;
+}
+template <typename T, typename U> __device__ inline U kv64(U v) {
+  if constexpr (sizeof(T) == 8) return kv(v);
+  else return v;
+}
+
 // pairs per lane per round of the hit search (at most)
 constexpr int NP = 2;
 template <typename T, int NPT>
@@ -137,8 +150,8 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
     const float phip = wrap_2pi(atan2f(fy, fx));
     const float eps_phi = 1e-5f, eps_z = 1e-4f;
     const float dphi = fdphi + eps_phi, dz = fdz + eps_z;
-    iz0 = (int)floorf((fz - dz + zh) * (float)nz / (2.f * zh));
-    iz1 = (int)floorf((fz + dz + zh) * (float)nz / (2.f * zh));
+    iz0 = (int)floorf((fz - dz + zh) * (float)ku64<T>(A.n_z) / (2.f * zh));
+    iz1 = (int)floorf((fz + dz + zh) * (float)ku64<T>(A.n_z) / (2.f * zh));
     iz0 = iz0 < 0 ? 0 : (iz0 > nz - 1 ? nz - 1 : iz0);
     iz1 = iz1 < 0 ? 0 : (iz1 > nz - 1 ? nz - 1 : iz1);
     if (dphi >= 3.14159f) { a0 = 0.f; b0v = tp; }
@@ -407,7 +420,10 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
   const int SEEDS = 64 / S;      // seeds per wave
   extern __shared__ __align__(16) uint32_t lds[];
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  // the wave index as a uniform value in FP64 builds: the per-wave addresses
+  // derived from it then stay in scalar registers (the FP32 build, which
+  // does not spill, measured slower with it)
+  const int wave = sizeof(T) == 8 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : (int)(threadIdx.x >> 6);
   const int nwaves = blockDim.x >> 6;
   const int LB = A.n_layers - A.first_layer;  // searched layers
   const LdsPlan lp = lds_plan(LB, nwaves, S, (int)sizeof(T), LEARNED);
@@ -502,9 +518,11 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
       int rc = 1;
       if (live) {
         if constexpr (HYB)
-          rc = predict_hyb<T>(X, P, (T)A.r[l], (T)A.bz, (T)A.z_half, (T)A.x_over_x0, (T)A.mass, Xp, Pp);
+          rc = predict_hyb<T>(X, P, (T)A.r[l], (T)ku64<T>(A.bz), (T)ku64<T>(A.z_half), (T)ku64<T>(A.x_over_x0),
+                              (T)ku64<T>(A.mass), Xp, Pp);
         else
-          rc = predict<T>(X, P, q, (T)A.r[l], (T)A.bz, (T)A.z_half, (T)A.x_over_x0, (T)A.mass, Xp, Pp);
+          rc = predict<T>(X, P, kv64<T>(q), (T)A.r[l], (T)ku64<T>(A.bz), (T)ku64<T>(A.z_half),
+                          (T)ku64<T>(A.x_over_x0), (T)ku64<T>(A.mass), Xp, Pp);
       }
       else {
 #pragma unroll
@@ -528,10 +546,10 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
         const T rr = k_sqrt(Xp[0] * Xp[0] + Xp[1] * Xp[1]);
         const T tx = -Xp[1] / rr, ty = Xp[0] / rr;
         const T Suu = tx * tx * Pp[ut(0, 0)] + T(2) * tx * ty * Pp[ut(0, 1)] + ty * ty * Pp[ut(1, 1)] +
-                      (T)A.win_sig_rphi * (T)A.win_sig_rphi;
-        const T Sww = Pp[ut(2, 2)] + (T)A.win_sig_z * (T)A.win_sig_z;
-        w_rphi = (T)A.nsigma * k_sqrt(Suu);
-        w_z = (T)A.nsigma * k_sqrt(Sww);
+                      sq((T)ku64<T>(A.win_sig_rphi));
+        const T Sww = Pp[ut(2, 2)] + sq((T)ku64<T>(A.win_sig_z));
+        w_rphi = (T)ku64<T>(A.nsigma) * k_sqrt(Suu);
+        w_z = (T)ku64<T>(A.nsigma) * k_sqrt(Sww);
         if (A.dump && ontrack && A.true_hits) {
           const int th = A.true_hits[(size_t)l * A.ld + seed];
           if (th >= 0) {
@@ -603,10 +621,7 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
         }
       }
       const T dphi_w = pok ? w_rphi / R : T(0), dz_w = pok ? w_z : T(0);
-      coop_scan<T, NPT_OF<T, LEARNED>>(A, ev, l, pok, Xp, Pp, dphi_w, dz_w, tl, ab, lane);
-      cnt_pred += live ? 1u : 0u;
-      cnt_scan += (unsigned)tl.scanned;
-      cnt_chi2 += (unsigned)tl.tested;
+      coop_scan<T, NPT_OF<T, LEARNED>>(A, kv64<T>(ev), l, pok, Xp, Pp, dphi_w, dz_w, tl, ab, lane);
       const bool hole_ok = pok && holes < A.max_holes;
       const int nchild = tl.tot + (hole_ok ? 1 : 0);
       // finished candidates of this layer (live, no child) compete for the record
@@ -694,7 +709,6 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
           Innov<T> in;
           innovation<T>(Xn, Pn, hx, hy, hz, V, in);
           apply_update<T>(Xn, Pn, in);
-          cnt_upd += 1;
         }
 #pragma unroll
         for (int k = 0; k < 6; ++k) X[k] = Xn[k];
@@ -709,6 +723,10 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
         }
         hist[(l - A.first_layer) * 64 + lane] = pack_hist(my_parent, my_orig);
       }
+      cnt_pred += live ? 1u : 0u;
+      cnt_scan += (unsigned)tl.scanned;
+      cnt_chi2 += (unsigned)tl.tested;
+      cnt_upd += my_parent >= 0 && my_orig != kHoleIdx ? 1u : 0u;
       n_active = n_new;
     }
     if (A.counters) {

@@ -70,6 +70,27 @@ KFD inline double kc(double c) {
   return c;
 }
 
+// A kernel argument read where it is used (the empty asm on its scalar
+// register): what is computed from it in vector registers (an FP64
+// conversion, a square) is then recomputed inside the layer loop, not
+// hoisted out of it and spilled to scratch memory.
+template <typename U> KFD inline U ku(U v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+s"(v));
+#endif
+  return v;
+}
+
+// A per-lane value made opaque where it is used (the empty asm on its
+// vector register): what is computed from it is recomputed there, not held
+// through the layer loop (or spilled) as a loop-invariant value.
+template <typename U> KFD inline U kv(U v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(v));
+#endif
+  return v;
+}
+
 // FP64 arctangent and logarithm written out from textbook identities: inside
 // the build kernels, which are short of registers, the library routines made
 // the compiler spill around every call (the arctangent alone cost 15 % of
