@@ -359,16 +359,30 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
 //   publish  [64] f32 chi2, [64] u32 indices of a round's admissible hits
 //   mlp      activation buffer of the learned window (the network runs before
 //            the hit search, so the toplists of a learned build live in it)
+// FP64 builds without the network keep each candidate's state between
+// layers in LDS as doubles: the position and momentum and the last NPL
+// covariance entries (the rest of the covariance stays in registers, its
+// FP32 copy in the stash for the finished record).  Held in registers
+// through the layer loop, these values were spilled to scratch memory and
+// reloaded at every layer; the stash then needs only the covariance
+// entries not held in LDS.  NPL is what fits two blocks of four waves per
+// CU (the hybrid state, which spills more, takes all it can).
+__host__ __device__ constexpr int xs_npl(int tsize, bool learned, bool hyb) {
+  return (tsize == 8 && !learned) ? (hyb ? 20 : 12) : -6;
+}
 struct LdsPlan {
-  size_t stash, rec, recf, acc, pub, tl, tl_stride, mlp, total;
+  size_t stash, rec, recf, acc, pub, tl, tl_stride, mlp, xs, total;
 };
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
-__host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsize, bool learned) {
+__host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsize, bool learned, bool hyb) {
   const int seeds = 64 / cap;
+  const int npl = xs_npl(tsize, learned, hyb);
+  // FP32 values per lane in the stash: all 27 without the LDS state
+  const int nst = npl < 0 ? 27 : 21 - npl;
   LdsPlan p;
   (void)LB;
   p.stash = 0;
-  p.rec = align16(p.stash + (size_t)nwaves * 27 * 64 * 4);
+  p.rec = align16(p.stash + (size_t)nwaves * nst * 64 * 4);
   p.recf = align16(p.rec + (size_t)nwaves * seeds * 27 * 4);
   (void)tsize;
   const size_t tl_wave = (size_t)cap * 64 * 12;
@@ -384,6 +398,8 @@ __host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsi
     p.mlp = p.total = align16(p.tl + (size_t)nwaves * tl_wave);
     p.tl_stride = tl_wave;
   }
+  p.xs = p.total;
+  if (npl >= 0) p.total = align16(p.xs + (size_t)nwaves * (6 + npl) * 64 * 8);
   return p;
 }
 
@@ -426,12 +442,15 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
   const int wave = sizeof(T) == 8 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : (int)(threadIdx.x >> 6);
   const int nwaves = blockDim.x >> 6;
   const int LB = A.n_layers - A.first_layer;  // searched layers
-  const LdsPlan lp = lds_plan(LB, nwaves, S, (int)sizeof(T), LEARNED);
+  const LdsPlan lp = lds_plan(LB, nwaves, S, (int)sizeof(T), LEARNED, HYB);
+  constexpr int NPL = xs_npl((int)sizeof(T), LEARNED, HYB);
+  constexpr bool XS = NPL >= 0;  // state between layers in LDS
   char* base = (char*)lds;
   // this wave's back-pointer table (written once per new candidate and layer,
   // read once per seed at the end)
   uint32_t* hist = A.hist + ((size_t)blockIdx.x * nwaves + wave) * LB * 64;
-  float* stash = (float*)(base + lp.stash) + (size_t)wave * 27 * 64;
+  float* stash = (float*)(base + lp.stash) + (size_t)wave * (XS ? 21 - NPL : 27) * 64;
+  T* xs = (T*)(base + lp.xs) + (size_t)wave * (XS ? 6 + NPL : 0) * 64 + lane;
   float* fin = (float*)(base + lp.rec) + (size_t)wave * SEEDS * 27;
   int32_t* finm = (int32_t*)(base + lp.recf) + (size_t)wave * SEEDS * 5;
   // per wave: the network buffer, or (after the network has run) the toplists
@@ -498,6 +517,12 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
       }
       n_active = 0;
     }
+    if constexpr (XS) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) xs[k * 64] = X[k];
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) xs[(6 + k) * 64] = P[21 - NPL + k];
+    }
     T fin_chi2_reg = 0;  // chi2 of the finished record, kept by slot 0 of the seed
     unsigned cnt_pred = 0, cnt_scan = 0, cnt_chi2 = 0, cnt_upd = 0;
     int last_l = A.first_layer - 1;
@@ -506,13 +531,25 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
       if (!__any(n_active > 0)) break;
       last_l = l;
       const bool live = slot < n_active;
+      if constexpr (XS) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) X[k] = xs[k * 64];
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) P[21 - NPL + k] = xs[(6 + k) * 64];
+      }
       // the state before prediction is kept (in the output precision) for
-      // the finished record, so it need not stay in registers
+      // the finished record, so it need not stay in registers (the part held
+      // in LDS is read from there)
       if (live) {
+        if constexpr (XS) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) stash[k * 64 + lane] = (float)X[k];
+          for (int k = 0; k < 21 - NPL; ++k) stash[k * 64 + lane] = (float)P[k];
+        } else {
 #pragma unroll
-        for (int k = 0; k < 21; ++k) stash[(6 + k) * 64 + lane] = (float)P[k];
+          for (int k = 0; k < 6; ++k) stash[k * 64 + lane] = (float)X[k];
+#pragma unroll
+          for (int k = 0; k < 21; ++k) stash[(6 + k) * 64 + lane] = (float)P[k];
+        }
       }
       T Xp[6], Pp[21];
       int rc = 1;
@@ -642,7 +679,13 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
           const bool take = !fvalid || wn > fn || (wn == fn && wc2 < fc2);
           if (take) {
             if (slot == ws) {
-              for (int k = 0; k < 27; ++k) fin[sidx * 27 + k] = stash[k * 64 + lane];
+              if constexpr (XS) {
+                for (int k = 0; k < 6; ++k) fin[sidx * 27 + k] = (float)xs[k * 64];
+                for (int k = 0; k < 21 - NPL; ++k) fin[sidx * 27 + 6 + k] = stash[k * 64 + lane];
+                for (int k = 21 - NPL; k < 21; ++k) fin[sidx * 27 + 6 + k] = (float)xs[(6 + k - 21 + NPL) * 64];
+              } else {
+                for (int k = 0; k < 27; ++k) fin[sidx * 27 + k] = stash[k * 64 + lane];
+              }
               finm[sidx * 5 + 0] = 1; finm[sidx * 5 + 1] = wn; finm[sidx * 5 + 2] = wst;
               finm[sidx * 5 + 3] = l - 1; finm[sidx * 5 + 4] = ws;
             }
@@ -710,10 +753,19 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
           innovation<T>(Xn, Pn, hx, hy, hz, V, in);
           apply_update<T>(Xn, Pn, in);
         }
+        if constexpr (XS) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) X[k] = Xn[k];
+          for (int k = 0; k < 6; ++k) xs[k * 64] = Xn[k];
 #pragma unroll
-        for (int k = 0; k < 21; ++k) P[k] = Pn[k];
+          for (int k = 0; k < NPL; ++k) xs[(6 + k) * 64] = Pn[21 - NPL + k];
+#pragma unroll
+          for (int k = 0; k < 21 - NPL; ++k) P[k] = Pn[k];
+        } else {
+#pragma unroll
+          for (int k = 0; k < 6; ++k) X[k] = Xn[k];
+#pragma unroll
+          for (int k = 0; k < 21; ++k) P[k] = Pn[k];
+        }
         chi2 = is_hole ? pchi2 : pchi2 + my_c2;
         nhits = is_hole ? pnh : pnh + 1;
         holes = is_hole ? pho + 1 : pho;
@@ -762,8 +814,10 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? KF_BUILD_F32_WAVES
       if (seed_ok) {
         // state: the best lane writes its own; slot 0 writes the record
         if (!use_fin && slot == bslot) {
-          for (int k2 = 0; k2 < 6; ++k2) A.out_par[(size_t)k2 * A.ld + seed] = (float)X[k2];
-          for (int k2 = 0; k2 < 21; ++k2) A.out_cov[(size_t)k2 * A.ld + seed] = (float)P[k2];
+          for (int k2 = 0; k2 < 6; ++k2) A.out_par[(size_t)k2 * A.ld + seed] = (float)(XS ? xs[k2 * 64] : X[k2]);
+          for (int k2 = 0; k2 < 21; ++k2)
+            A.out_cov[(size_t)k2 * A.ld + seed] =
+                (float)(XS && k2 >= 21 - NPL ? xs[(6 + k2 - 21 + NPL) * 64] : P[k2]);
           A.out_chi2[seed] = (float)chi2;
           A.out_nhits[seed] = nhits;
           A.out_status[seed] = seed_status;
@@ -809,7 +863,7 @@ int launch(const BuildArgs& A, int lanes, int blocks, int hist_waves, hipStream_
   int dev = 0, max_lds = 0;
   if (kf_check(hipGetDevice(&dev))) return KF_E_HIP;
   if (kf_check(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev))) return KF_E_HIP;
-  auto plan = [&](int ln) { return lds_plan(LB, ln / 64, A.cap, (int)sizeof(T), LEARNED).total; };
+  auto plan = [&](int ln) { return lds_plan(LB, ln / 64, A.cap, (int)sizeof(T), LEARNED, HYB).total; };
   if (lanes == 0) {  // automatic: the widest block whose LDS fits
     lanes = 256;
     while (lanes > 64 && plan(lanes) > (size_t)max_lds) lanes /= 2;
