@@ -359,16 +359,17 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
 //   publish  [64] f32 chi2, [64] u32 indices of a round's admissible hits
 //   mlp      activation buffer of the learned window (the network runs before
 //            the hit search, so the toplists of a learned build live in it)
-// FP64 builds without the network keep each candidate's state between
-// layers in LDS as doubles: the position and momentum and the last NPL
-// covariance entries (the rest of the covariance stays in registers, its
-// FP32 copy in the stash for the finished record).  Held in registers
-// through the layer loop, these values were spilled to scratch memory and
-// reloaded at every layer; the stash then needs only the covariance
-// entries not held in LDS.  NPL is what fits two blocks of four waves per
-// CU (the hybrid state, which spills more, takes all it can).
+// FP64 builds keep each candidate's state between layers in LDS as
+// doubles: the position and momentum and the last NPL covariance entries
+// (the rest of the covariance stays in registers, its FP32 copy in the
+// stash for the finished record).  Held in registers through the layer
+// loop, these values were spilled to scratch memory and reloaded at every
+// layer; the stash then needs only the covariance entries not held in LDS.
+// NPL: what fits two blocks of four waves per CU (the learned builds' network
+// buffers leave room for 2; the hybrid state, which spills more, takes all
+// it can), 12 in the Cartesian state (measured best).
 __host__ __device__ constexpr int xs_npl(int tsize, bool learned, bool hyb) {
-  return (tsize == 8 && !learned) ? (hyb ? 20 : 12) : -6;
+  return tsize == 8 ? (learned ? 2 : hyb ? 20 : 12) : -6;
 }
 struct LdsPlan {
   size_t stash, rec, recf, acc, pub, tl, tl_stride, mlp, xs, total;
