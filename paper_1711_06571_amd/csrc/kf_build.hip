@@ -312,7 +312,8 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
             const float s11 = csww[h] + V[h][5];
             const float det = s00 * s11 - s01 * s01;
             if (s00 > 0.f && det > 0.f) {
-              c2[h] = (s11 * r0 * r0 - 2.f * s01 * r0 * r1 + s00 * r1 * r1) / det;
+              // (the hardware reciprocal: within a few ulp, no division sequence)
+              c2[h] = (s11 * r0 * r0 - 2.f * s01 * r0 * r1 + s00 * r1 * r1) * k_rcp(det);
               if (c2[h] < cut) {
                 acc[h] = true;
                 orig[h] = forig[h];

@@ -277,7 +277,7 @@ __device__ inline bool pair_chi2(const float Xa[6], const float Pa[21], int q, f
   }
   const float det = s00 * s11 - s01 * s01;
   if (!(s00 > 0.f) || !(det > 0.f)) return false;
-  c2 = (s11 * r0 * r0 - 2.f * s01 * r0 * r1 + s00 * r1 * r1) / det;
+  c2 = (s11 * r0 * r0 - 2.f * s01 * r0 * r1 + s00 * r1 * r1) * k_rcp(det);  // hardware reciprocal
   return true;
 }
 
