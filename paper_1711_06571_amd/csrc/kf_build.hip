@@ -419,13 +419,12 @@ __host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsi
 #define KF_BUILD_F64_LEARNED_WAVES 2
 #endif
 
-// Pairs per lane and round: NP in FP32 builds and plain FP64 builds (which
-// spill a little more for it and still gain: 26.80 -> 26.16 ms on 50
-// events); one in learned FP64 builds, whose network already holds registers
-// and whose narrow windows leave few pairs per round (32 events: 17.35 ->
-// 17.28 ms, hybrid state 18.58 -> 18.10 ms).
+// Pairs per lane and round: NP in every build.  Learned FP64 builds took
+// one while they spilled around the network (32 events: 17.35 -> 17.28 ms);
+// with their state between layers in LDS two pay (11.45 -> 10.79 ms, hybrid
+// state 11.40 -> 11.04 ms).  The macro allows a rebuild to compare.
 #ifndef KF_LEARNED_F64_NPT
-#define KF_LEARNED_F64_NPT 1
+#define KF_LEARNED_F64_NPT 2
 #endif
 template <typename T, bool LEARNED>
 constexpr int NPT_OF = (sizeof(T) == 8 && LEARNED) ? KF_LEARNED_F64_NPT : NP;
