@@ -123,14 +123,31 @@ __device__ inline unsigned long long run_mask(int lo, int hi) {
 }
 
 // Sorts the first n entries of this lane's list by (chi2, hit index): the
-// entries go through registers and Batcher's odd-even merge network for
-// eight (19 comparators), positions from n on (and from cap on) as +inf.
-__device__ inline void sort_own(TopList& tl, int cap, int n) {
-  float v[8];
-  uint32_t o[8];
-  int32_t q[8];
+// entries go through registers and a sorting network for N (positions from
+// n on, and from cap on, as +inf): N = 4 (5 comparators), 6 (12, depth 5)
+// or 8 (Batcher's odd-even merge, 19), the smallest that holds cap.
+template <int N> struct SortNet;
+template <> struct SortNet<4> {
+  static constexpr int len = 5;
+  static constexpr int c[5][2] = {{0, 1}, {2, 3}, {0, 2}, {1, 3}, {1, 2}};
+};
+template <> struct SortNet<6> {
+  static constexpr int len = 12;
+  static constexpr int c[12][2] = {{0, 5}, {1, 3}, {2, 4}, {1, 2}, {3, 4}, {0, 3},
+                                   {2, 5}, {0, 1}, {2, 3}, {4, 5}, {1, 2}, {3, 4}};
+};
+template <> struct SortNet<8> {
+  static constexpr int len = 19;
+  static constexpr int c[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6}, {5, 7}, {1, 2}, {5, 6},
+                                   {0, 4}, {1, 5}, {2, 6}, {3, 7}, {2, 4}, {3, 5}, {1, 2}, {3, 4}, {5, 6}};
+};
+template <int N>
+__device__ inline void sort_net(TopList& tl, int cap, int n) {
+  float v[N];
+  uint32_t o[N];
+  int32_t q[N];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < N; ++k) {
     if (k < cap) {
       v[k] = tl.c2[k * 64];
       o[k] = tl.orig[k * 64];
@@ -138,18 +155,16 @@ __device__ inline void sort_own(TopList& tl, int cap, int n) {
     }
   }
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < N; ++k) {
     if (!(k < n && k < cap)) {
       v[k] = __builtin_inff();
       o[k] = 0xFFFFFFFFu;
       q[k] = 0;
     }
   }
-  constexpr int net[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6}, {5, 7}, {1, 2}, {5, 6},
-                              {0, 4}, {1, 5}, {2, 6}, {3, 7}, {2, 4}, {3, 5}, {1, 2}, {3, 4}, {5, 6}};
 #pragma unroll
-  for (int t = 0; t < 19; ++t) {
-    const int a = net[t][0], b = net[t][1];
+  for (int t = 0; t < SortNet<N>::len; ++t) {
+    const int a = SortNet<N>::c[t][0], b = SortNet<N>::c[t][1];
     const bool sw = top_before(v[b], o[b], v[a], o[a]);
     const float tv = v[a];
     const uint32_t to = o[a];
@@ -162,13 +177,18 @@ __device__ inline void sort_own(TopList& tl, int cap, int n) {
     q[b] = sw ? tq : q[b];
   }
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < N; ++k) {
     if (k < n && k < cap) {
       tl.c2[k * 64] = v[k];
       tl.orig[k * 64] = o[k];
       tl.pos[k * 64] = q[k];
     }
   }
+}
+__device__ inline void sort_own(TopList& tl, int cap, int n) {
+  if (cap <= 4) sort_net<4>(tl, cap, n);
+  else if (cap <= 6) sort_net<6>(tl, cap, n);
+  else sort_net<8>(tl, cap, n);
 }
 
 // One round's admissible hits into their candidates' lists, all at once.
