@@ -582,7 +582,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? KF_BUILD_DET_F64_WAVES :
       const int nchild = pok ? tl.tot + (hole_ok ? 1 : 0) : 0;
       // candidates that stop here (no next layer, or no child) compete for
       // the seed's record with their state before this step
-      {
+      if (__any(live && nchild == 0)) {  // (most layers have none)
         const bool stopped = live && nchild == 0;
         const uint64_t fk = stopped ? make_key(nhits, (float)chi2, slot, 0) : kInfKey;
         const uint64_t best = group_min(fk, sbase, slot, S, lane_used);
@@ -606,8 +606,6 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? KF_BUILD_DET_F64_WAVES :
         }
       }
       // merge the seed's children, best first, into slots 0..cap-1
-      const int tot = group_sum(nchild, sbase, slot, S, lane_used);
-      if (tot > A.cap) seed_status |= KF_CAP_TRUNC;
       int ptr = 0;
       bool hole_left = hole_ok;
       int my_parent = -1, my_pos = -1;
@@ -643,6 +641,13 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? KF_BUILD_DET_F64_WAVES :
           my_c2 = wc2;
         }
         n_new = r + 1;
+      }
+      // children left after cap rounds (accepted hits beyond a full list
+      // included): the seed's candidates were cut to cap
+      {
+        const bool left = pok && tl.tot - ptr + (hole_left ? 1 : 0) > 0;
+        const unsigned long long lm = __ballot(left);
+        if (lane_used && ((lm >> sbase) & ((1ull << S) - 1ull)) != 0ull) seed_status |= KF_CAP_TRUNC;
       }
       // new slots pull the parent's state on the average surface, then
       // step 2 to their hit's surface and the update (or the hole's scattering)

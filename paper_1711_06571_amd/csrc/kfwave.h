@@ -45,8 +45,8 @@ __device__ inline double readlane_t(double v, int j) {
 }
 __device__ inline double shfl_t(double v, int src) { return shfl_d(v, src); }
 
-// Reductions over the S lanes base .. base+S-1 of one seed (S <= 8, any
-// value).  The minimum doubles a rotation: after the steps 1, 2, 4 a lane
+// The minimum over the S lanes base .. base+S-1 of one seed (S <= 8, any
+// value), doubling a rotation: after the steps 1, 2, 4 a lane
 // has seen the slots slot .. slot+7 (mod S), which covers the group.  Lanes
 // that hold no seed (used = false) only ever read themselves.
 __device__ inline int rot_lane(int base, int slot, int d, int S, bool used) {
@@ -59,14 +59,6 @@ __device__ inline uint64_t group_min(uint64_t k, int base, int slot, int S, bool
     k = o < k ? o : k;
   }
   return k;
-}
-__device__ inline int group_sum(int v, int base, int slot, int S, bool used) {
-  int acc = v;
-  for (int d = 1; d < S; ++d) {
-    const int o = __shfl(v, rot_lane(base, slot, d, S, used), 64);
-    acc += used ? o : 0;
-  }
-  return acc;
 }
 
 __device__ inline uint32_t chi2_bits(float c) {
