@@ -83,6 +83,19 @@ struct BuildArgs {
   int32_t* event_done;
 };
 
+// ku / kv in FP64 builds only: there, kernel arguments and per-seed values
+// that the layer loop uses are recomputed where they are used instead of
+// being hoisted out of the loop and spilled (the FP32 build does not spill;
+// the barriers would only cost it issue slots)
+template <typename T, typename U> __device__ inline U ku64(U v) {
+  if constexpr (sizeof(T) == 8) return ku(v);
+  else return v;
+}
+template <typename T, typename U> __device__ inline U kv64(U v) {
+  if constexpr (sizeof(T) == 8) return kv(v);
+  else return v;
+}
+
 // Hit search of every candidate of the wave, shared by all 64 lanes.
 //
 // Each live candidate's window covers, per z row it overlaps and per phi
@@ -107,19 +120,7 @@ struct BuildArgs {
 // positions ~ 1e-5 cm) stays far below the chi2 gaps (1e-3) and window-edge
 // distances (1e-4 cm) that separate decisions; the Kalman update of a
 // chosen hit runs in the arithmetic of the mode.
-// ku / kv in FP64 builds only: there, kernel arguments and per-seed values
-// that the layer loop uses are recomputed where they are used instead of
-// being hoisted out of the loop and spilled (the FP32 build does not spill;
-// the barriers would only cost it issue slots)
-template <typename T, typename U> __device__ inline U ku64(U v) {
-  if constexpr (sizeof(T) == 8) return ku(v);
-  else return v;
-}
-template <typename T, typename U> __device__ inline U kv64(U v) {
-  if constexpr (sizeof(T) == 8) return kv(v);
-  else return v;
-}
-
+//
 // pairs per lane per round of the hit search (at most)
 constexpr int NP = 2;
 template <typename T, int NPT>
@@ -386,7 +387,6 @@ __host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsi
   p.stash = 0;
   p.rec = align16(p.stash + (size_t)nwaves * nst * 64 * 4);
   p.recf = align16(p.rec + (size_t)nwaves * seeds * 27 * 4);
-  (void)tsize;
   const size_t tl_wave = (size_t)cap * 64 * 12;
   p.acc = align16(p.recf + (size_t)nwaves * seeds * 5 * 4);
   p.pub = align16(p.acc + (size_t)nwaves * 64 * NP * 4);
