@@ -29,6 +29,7 @@
 #include "kfdev.h"
 #include "kfhost.h"
 #include "kfmlp.h"
+#include "kfplan.h"
 #include "kfwave.h"
 
 using namespace kfdev;
@@ -119,10 +120,8 @@ template <typename T, typename U> __device__ inline U kv64(U v) {
 // prediction rounded to FP32: their rounding (chi2 ~ 3e-5 at the cut,
 // positions ~ 1e-5 cm) stays far below the chi2 gaps (1e-3) and window-edge
 // distances (1e-4 cm) that separate decisions; the Kalman update of a
-// chosen hit runs in the arithmetic of the mode.
-//
-// pairs per lane per round of the hit search (at most)
-constexpr int NP = 2;
+// chosen hit runs in the arithmetic of the mode.  NP (pairs per lane and
+// round at most) is defined with the LDS plan.
 template <typename T, int NPT>
 __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, const T Xp[6], const T Pp[21],
                                  T dphi_w, T dz_w, TopList& tl, const AccBuf& ab, int lane) {
@@ -352,58 +351,6 @@ __device__ inline void coop_scan(const BuildArgs& A, int ev, int l, bool pok, co
   tl.tot = n_acc;
 }
 
-// LDS of one block (byte offsets), per wave:
-//   stash    [27][64] f32      each slot's state before this layer's prediction
-//   record   [SEEDS][27] f32   best finished candidate of each seed
-//   recfield [SEEDS][5] i32    valid, nhits, status, last layer, slot
-//   toplist  [cap][64] f32 chi2, then [cap][64] i32 positions, [cap][64] u32 indices
-//   starts   [64 NP] i32 run starts of the cooperative hit search
-//   publish  [64] f32 chi2, [64] u32 indices of a round's admissible hits
-//   mlp      activation buffer of the learned window (the network runs before
-//            the hit search, so the toplists of a learned build live in it)
-// FP64 builds keep each candidate's state between layers in LDS as
-// doubles: the position and momentum and the last NPL covariance entries
-// (the rest of the covariance stays in registers, its FP32 copy in the
-// stash for the finished record).  Held in registers through the layer
-// loop, these values were spilled to scratch memory and reloaded at every
-// layer; the stash then needs only the covariance entries not held in LDS.
-// NPL: what fits two blocks of four waves per CU (the learned builds' network
-// buffers leave room for 2; the hybrid state, which spills more, takes all
-// it can), 12 in the Cartesian state (measured best).
-__host__ __device__ constexpr int xs_npl(int tsize, bool learned, bool hyb) {
-  return tsize == 8 ? (learned ? 2 : hyb ? 20 : 12) : -6;
-}
-struct LdsPlan {
-  size_t stash, rec, recf, acc, pub, tl, tl_stride, mlp, xs, total;
-};
-__host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
-__host__ __device__ inline LdsPlan lds_plan(int LB, int nwaves, int cap, int tsize, bool learned, bool hyb) {
-  const int seeds = 64 / cap;
-  const int npl = xs_npl(tsize, learned, hyb);
-  // FP32 values per lane in the stash: all 27 without the LDS state
-  const int nst = npl < 0 ? 27 : 21 - npl;
-  LdsPlan p;
-  (void)LB;
-  p.stash = 0;
-  p.rec = align16(p.stash + (size_t)nwaves * nst * 64 * 4);
-  p.recf = align16(p.rec + (size_t)nwaves * seeds * 27 * 4);
-  const size_t tl_wave = (size_t)cap * 64 * 12;
-  p.acc = align16(p.recf + (size_t)nwaves * seeds * 5 * 4);
-  p.pub = align16(p.acc + (size_t)nwaves * 64 * NP * 4);
-  p.tl = align16(p.pub + (size_t)nwaves * 64 * 8);
-  if (learned) {
-    const size_t per = tl_wave > KFMLP_LDS_BYTES ? tl_wave : (size_t)KFMLP_LDS_BYTES;
-    p.mlp = p.tl;
-    p.total = p.mlp + (size_t)nwaves * per;
-    p.tl_stride = per;
-  } else {
-    p.mlp = p.total = align16(p.tl + (size_t)nwaves * tl_wave);
-    p.tl_stride = tl_wave;
-  }
-  p.xs = p.total;
-  if (npl >= 0) p.total = align16(p.xs + (size_t)nwaves * (6 + npl) * 64 * 8);
-  return p;
-}
 
 // Waves per SIMD the register allocation aims at.  The build waits on
 // memory and LDS most of the time, so a second resident wave pays even where
