@@ -43,7 +43,7 @@ UNDECIDABLE_MAX_SMALL_SAMPLE = 0.25  # fewer than 100 seeds
 MISMATCH_MAX_FRACTION = 0.01
 
 
-def gpu_build_event(kf, w, ev, arith, cap=None, lanes=0, blocks=0, order=None, seeds=None, refine=0):
+def gpu_build_event(kf, w, ev, arith, cap=None, lanes=0, blocks=0, order=None, seeds=None, refine=0, state=None):
     xyz = ev.xyz.astype(np.float32)
     cov = ev.cov.astype(np.float32)
     b = kf.hit_bin(w.geometry, w.cuts.n_phi_bins, w.cuts.n_z_bins, to_dev(ev.layer), to_dev(xyz), to_dev(cov))
@@ -52,7 +52,7 @@ def gpu_build_event(kf, w, ev, arith, cap=None, lanes=0, blocks=0, order=None, s
     if seeds is None:
         seeds = kf.kf_seed(w.geometry, n, to_dev(H))
     bp = kf.build_params(w.cuts, cap=cap, lanes_per_block=lanes, persistent_blocks=blocks, arith=arith,
-                         phi_refine=refine)
+                         phi_refine=refine, **({} if state is None else {"state": state}))
     ex = kf.BuildExtra()
     keep = []
     if order is not None:
@@ -173,6 +173,38 @@ def test_build_launch_shape_and_order_invariance(kf):
                                refine=refine)
         for k in ref:
             assert np.array_equal(g[k][..., :n], ref[k][..., :n]), (k, lanes, blocks, refine)
+
+
+@pytest.mark.parametrize("hybrid", [False, True])
+def test_build_fp64_launch_shapes(kf, hybrid):
+    """FP64 builds keep each candidate's state between layers in the block's
+    LDS, at offsets that depend on the waves per block: blocks of one, two
+    and four waves, and a fixed small grid, give the default launch's
+    outputs bit for bit, in both states."""
+    w = presets.build()
+    ev = datagen.generate(w.geometry, w.gen, 15, 1500)
+    n = ev.n_tracks
+    st = kf.STATE_HYBRID if hybrid else kf.STATE_CARTESIAN
+    ref, sg = gpu_build_event(kf, w, ev, kf.ARITH_F64, state=st)
+    for lanes, blocks in [(64, 0), (128, 7), (256, 1)]:
+        g, _ = gpu_build_event(kf, w, ev, kf.ARITH_F64, lanes=lanes, blocks=blocks, seeds=sg, state=st)
+        for k in ref:
+            assert np.array_equal(g[k][..., :n], ref[k][..., :n]), (k, lanes, blocks, hybrid)
+
+
+@pytest.mark.parametrize("cap", [3, 8])
+def test_hybrid_state_build_other_caps(kf, cap):
+    """The hybrid FP64 build at other caps against the oracle (at cap 8 its
+    LDS state takes one block per CU)."""
+    w = presets.build()
+    ev = datagen.generate(w.geometry, w.gen, 16, 300)
+    n = ev.n_tracks
+    g, _ = gpu_build_event(kf, w, ev, kf.ARITH_F64, cap=cap, state=kf.STATE_HYBRID)
+    H = datagen.track_hits(ev)
+    so = oracle.seed(w.geometry, H, n)
+    o = oracle.build(w.geometry, w.cuts, ev.layer, ev.xyz, ev.cov, so["par"], so["cov"], so["q"], n, cap=cap,
+                     state=1)
+    print(f"hybrid cap {cap}", compare(g, o, n, ctx=f"hybrid cap {cap}", check_params=False))
 
 
 def test_build_noise_free_recovers_true_hits(kf):
